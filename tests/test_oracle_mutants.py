@@ -1,0 +1,112 @@
+"""Planted mistakes in copies of the oracle (CPU only): each must fail at least one pin.
+
+The pins in test_oracle_pins.py are only worth something if a plausible slip in
+the oracle trips them.  Each mutant below is one such slip (a sign, a factor,
+a transpose, the printed source-normal Jacobian, a dropped half in the central
+difference, the wrong depth cue); the checks are condensed versions of the
+pins: FD gradient, ground-truth residuals and the linear-ramp identity.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "pba_oracle.c")
+
+MUTANTS = {
+    "skew_sign": ("S[0] = 0;     S[1] = v[2];  S[2] = -v[1];", "S[0] = 0;     S[1] = -v[2];  S[2] = v[1];"),
+    "rot_factor": ("Ms[6*i+3+j] = 2.0 * L[3*i+j];", "Ms[6*i+3+j] = 1.0 * L[3*i+j];"),
+    "target_factor": ("Mt[6*i+3+j] = -2.0 * L[3*i+j];", "Mt[6*i+3+j] = 2.0 * L[3*i+j];"),
+    "warp_transpose": ("matvec3(RjT, w3, y);", "matvec3(Rj, w3, y);"),
+    "printed_normal_jacobian": ("matmul3(M_RotRjRi, Sn, A);",
+                                "{ double Sn0[9], RR[9]; const double nu[3] = {Ns[3*pix], Ns[3*pix+1], Ns[3*pix+2]};"
+                                " skewp(nu, Sn0); matmul3(RotT, Rj, RR); matmul3(RR, Ri, RR); matmul3(RR, ss->Ro, RR);"
+                                " matmul3(RR, Sn0, A); }"),
+    "central_diff_half": ("double gc00 = 0.5 * (T(y0, x0+1) - T(y0, x0-1));",
+                          "double gc00 = 1.0 * (T(y0, x0+1) - T(y0, x0-1));"),
+    "pinhole_jac_sign": ("-v[0] * iz2, 0, v[2] * iz2", "v[0] * iz2, 0, v[2] * iz2"),
+    "range_cue_as_depth": ("zeta[1] = st->model == 0 ? pbar[2] : range;", "zeta[1] = pbar[2];"),
+}
+
+
+def _fd_ok(p, prm):
+    X = p.init_poses
+    r = oracle.eval_pair(p, X, 1, 0, prm, grad_mode=1)
+    g = 2 * r["b12"]
+    fd = np.zeros(12)
+    h = 1e-8
+    for k in range(12):
+        dx = np.zeros(6 * p.n)
+        dx[6 + k if k < 6 else k - 6] = h
+        Fp = oracle.eval_pair(p, oracle.boxplus(X, dx), 1, 0, prm, grad_mode=1)["F"]
+        dx[6 + k if k < 6 else k - 6] = -h
+        Fm = oracle.eval_pair(p, oracle.boxplus(X, dx), 1, 0, prm, grad_mode=1)["F"]
+        fd[k] = (Fp - Fm) / (2 * h)
+    return np.abs(g - fd).max() < 2e-5 * np.abs(fd).max()
+
+
+def _gt_ok(p, prm):
+    r = oracle.eval_pair(p, p.gt_poses, 1, 0, prm, pixels=True)
+    v = r["status"] == 0
+    if v.sum() < 0.3 * r["n_eval"]:
+        return False
+    med = np.median(np.abs(r["res"][v]), 0)
+    return med[1] < 1e-3 and np.all(med[2:] < 1e-6)
+
+
+def _ramp_ok(p, prm):
+    H, W = p.depth[0].shape
+    rr, cc = np.mgrid[0:H, 0:W].astype(np.float64)
+    q = synth.Problem(p.name, p.sensors, p.kf_sensor, p.gt_poses, p.init_poses, p.pairs, p.params)
+    q.intensity = [(0.25 + cc / 512 - rr / 1024).astype(np.float32)] + list(p.intensity[1:])
+    q.depth = [(3.0 + cc / 128 + rr / 256).astype(np.float32)] + list(p.depth[1:])
+    q.normals = [np.stack([0.125 + cc / 1024, -0.25 + rr / 512, -0.875 + (cc + rr) / 2048], -1).astype(np.float32)] \
+        + list(p.normals[1:])
+    prm = dict(prm, occ_tau_pinhole=1e9, huber_delta=1e9)
+    a = oracle.eval_pair(q, q.init_poses, 1, 0, prm, grad_mode=0)
+    b = oracle.eval_pair(q, q.init_poses, 1, 0, prm, grad_mode=1)
+    return np.abs(a["H12"] - b["H12"]).max() <= 1e-9 * np.abs(b["H12"]).max()
+
+
+@pytest.fixture(scope="module")
+def problems():
+    rg = synth.make("rgbd_small")
+    rgc = synth.make("rgbd_small", noise=False)
+    li = synth.make("lidar128", kfs=[0, 1], H=32, W=512).subset([0, 1])
+    lic = synth.make("lidar128", kfs=[0, 1], H=32, W=512, noise=False).subset([0, 1])
+    return rg, rgc, li, lic
+
+
+def _checks(problems):
+    rg, rgc, li, lic = problems
+    p5 = dict(rg.params, channels=5)
+    l5 = dict(li.params, channels=5)
+    return {"fd_rgbd": _fd_ok(rg, p5), "fd_lidar": _fd_ok(li, l5), "gt_rgbd": _gt_ok(rgc, p5),
+            "gt_lidar": _gt_ok(lic, l5), "ramp": _ramp_ok(rg, p5)}
+
+
+def test_unmutated_oracle_passes_condensed_checks(problems):
+    oracle.use_library(oracle.build_lib())
+    assert all(_checks(problems).values())
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name, problems, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    mpath = tmp_path / ("oracle_%s.c" % name)
+    mpath.write_text(src.replace(old, new))
+    so = str(tmp_path / ("liboracle_%s.so" % name))
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-o", so,
+                           str(mpath), "-lm"])
+    try:
+        oracle.use_library(so)
+        res = _checks(problems)
+    finally:
+        oracle.use_library(os.path.join(os.path.dirname(SRC), "liboracle.so"))
+    assert not all(res.values()), (name, res)
