@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark: photometric BA iterations on one MI355X.
+
+Workload (default): 128x2048 spherical LiDAR keyframes, 300 of them on a seeded 2 km loop,
+2406 ordered pairs within 30 m, 5 channels (intensity, range, normal xyz), Levenberg-Marquardt.
+One step = one full iteration: damped FP64 Cholesky solve at the current poses, pose update,
+evaluation of residuals/Jacobians/H/b at the candidate over every pair and valid source pixel,
+device-side accept/reject.  Inputs are resident on the GPU before timing starts.
+
+Prints one JSON line on stdout.  value = px-pair evaluations per second over whole iterations
+(FP32 evaluation path); the FP64 path, the evaluation-kernel roofline and the FP64 CPU oracle
+on a bounded sample are reported beside it.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_px_pair(channels):
+    # source texel + one target texel per evaluation, FP32 channels
+    return 2 * 4 * channels
+
+
+def run_path(pba, prob, precision, warmup, steps):
+    import numpy as np
+    import torch
+    with pba.context_for_problem(prob, precision=precision) as ctx:
+        torch.cuda.synchronize()
+        if warmup:
+            ctx.iterate(warmup, use_lm=True, lambda0=1e-4)
+        ev = ctx.evaluate()                      # system at the current poses; counts per evaluation
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        logs = ctx.iterate(steps, use_lm=True, lambda0=0.0)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        # evaluation kernel alone, timed with HIP events on the library's stream
+        ctx.timings(reset=True)
+        n_eval_runs = 5
+        for _ in range(n_eval_runs):
+            ev2 = ctx.evaluate()
+        tm = ctx.timings(reset=True)
+        poses = ctx.get_poses()
+    return dict(elapsed=elapsed, logs=logs, n_evaluated=ev["n_evaluated"], n_valid=ev["n_valid"],
+                n_refined=ev2["n_refined"], eval_ms=tm["eval_ms"] / n_eval_runs, n_items=tm["n_items"],
+                items_px=tm["items_px"], grid=tm["grid"], poses=poses, F=logs[-1]["F"])
+
+
+def cpu_baseline(prob, target_s=15.0):
+    """The FP64 oracle, as it is, on a bounded sample of pairs of the same workload."""
+    import numpy as np
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    pairs = prob.pairs
+    n0 = min(len(pairs), max(threads, 8))
+    t0 = time.perf_counter()
+    r = oracle.eval_pairs(prob, prob.init_poses, pairs=pairs[:n0])
+    dt = time.perf_counter() - t0
+    px = int(r["n_eval"].sum())
+    n1 = int(min(len(pairs), max(n0, n0 * target_s / max(dt, 1e-3))))
+    if n1 > n0:
+        sel = pairs[n0:n1]
+        t0 = time.perf_counter()
+        r = oracle.eval_pairs(prob, prob.init_poses, pairs=sel)
+        dt = time.perf_counter() - t0
+        px = int(r["n_eval"].sum())
+        n0 = len(sel)
+    return dict(value=px / dt, unit="px-pair evals/s", cores=threads, kind="oracle",
+                sample="%d of %d pairs, one FP64 evaluation (residuals, Jacobians of both poses, 12x12 "
+                       "blocks), %.1f s" % (n0, len(pairs), dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="lidar128", choices=["lidar128", "lidar64", "rgbd_room", "rgbd_small"])
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2303_16878_amd as pba
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    pba.load_library()
+    t0 = time.perf_counter()
+    prob = synth.make(args.workload)
+    log("generated %s: %d keyframes, %d pairs in %.1f s" % (args.workload, prob.n, len(prob.pairs),
+                                                             time.perf_counter() - t0))
+    ch = prob.params["channels"]
+    sen = prob.sensors[0]
+
+    log("FP32 path: warmup %d, timed %d iterations" % (args.warmup, args.steps))
+    r32 = run_path(pba, prob, pba.PBA_F32, args.warmup, args.steps)
+    ms_step = 1e3 * r32["elapsed"] / args.steps
+    value = r32["n_evaluated"] * args.steps / r32["elapsed"]
+    eval_s = r32["eval_ms"] / 1e3
+    achieved = bytes_per_px_pair(ch) * r32["n_evaluated"] / eval_s / 1e9
+    log("FP32: %.2f ms/iter, %.3e px-pair/s; eval kernel %.3f ms (%.3e px-pair/s, %.0f GB/s algorithmic)" % (
+        ms_step, value, r32["eval_ms"], r32["n_evaluated"] / eval_s, achieved))
+
+    import oracle
+    out = {
+        "metric": "px residual+Jacobian evals/s and s/GN-iter, FP32 vs FP64 path, equal final RMSE",
+        "value": value,
+        "unit": "px-pair evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %s %dx%d, %d keyframes, %d ordered pairs, %d channels, LM iterations" % (
+                args.workload, "spherical" if sen["model"] == 1 else "pinhole", sen["H"], sen["W"], prob.n,
+                len(prob.pairs), ch),
+            "px_pairs_per_step": r32["n_evaluated"],
+            "valid_per_step": r32["n_valid"],
+            "work_items": r32["n_items"],
+            "items_px": r32["items_px"],
+            "grid": r32["grid"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "eval_kernel<float,5,sph,sph> (persistent)",
+            "kernel_ms": r32["eval_ms"],
+            "bytes_per_px_pair": bytes_per_px_pair(ch),
+        },
+        "s_per_iter": {"f32": r32["elapsed"] / args.steps},
+        "eval_px_pairs_per_s": {"f32": r32["n_evaluated"] / eval_s},
+        "final_ate_rmse": {"f32": oracle.ate_rmse(r32["poses"], prob.gt_poses),
+                           "init": oracle.ate_rmse(prob.init_poses, prob.gt_poses)},
+    }
+    if not args.no_fp64:
+        log("FP64 path: warmup %d, timed %d iterations" % (args.warmup, args.steps))
+        r64 = run_path(pba, prob, pba.PBA_F64, args.warmup, args.steps)
+        out["s_per_iter"]["f64"] = r64["elapsed"] / args.steps
+        out["eval_px_pairs_per_s"]["f64"] = r64["n_evaluated"] / (r64["eval_ms"] / 1e3)
+        out["fp64_value"] = r64["n_evaluated"] * args.steps / r64["elapsed"]
+        out["final_ate_rmse"]["f64"] = oracle.ate_rmse(r64["poses"], prob.gt_poses)
+        out["final_ate_rmse"]["abs_diff"] = abs(out["final_ate_rmse"]["f64"] - out["final_ate_rmse"]["f32"])
+        log("FP64: %.2f ms/iter" % (1e3 * r64["elapsed"] / args.steps))
+    if not args.no_cpu:
+        log("CPU oracle baseline (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * pba.h -- C ABI of the MI355X photometric bundle-adjustment library (libpba.so).
+ *
+ * The library evaluates, for every ordered keyframe pair (s, t) -- the paper's
+ * <i, j>, where the cloud of image i is warped into image j -- the multi-cue
+ * photometric residuals of every source pixel with valid depth, their Huber
+ * weights and SE(3) Jacobians, reduces them into the 6N x 6N normal equations
+ * H dx = -b over all N poses, solves for the Gauss-Newton / Levenberg-Marquardt
+ * step in FP64 and applies it as X <- X exp(dx).  All of it runs in HIP kernels
+ * on one GPU; the host only marshals arguments.
+ *
+ * Definitions followed (paper "Photometric LiDAR and RGB-D Bundle Adjustment"):
+ *   poses, inverse, projections pi_p / pi_s            Sec. III (Basics)
+ *   warp u' = pi(R_j^T (R_i pi^-1(u, d) + t_i - t_j))     Sec. IV-C, Eq. (uprime)
+ *   objective F = sum rho(|stacked cue residual|^2_Omega)  Sec. IV-C, Eq. (total-error-multicue)
+ *   perturbation dx = [dt, dq], X boxplus dx = X exp(dx)  Supplementary (first paragraph)
+ *   sensor offset, p_u, p_bar and all Jacobians           Supplementary
+ *
+ * Conventions (all arrays row-major, C order):
+ *   pose      12 doubles: R (3x3 row-major) then t; maps platform -> world.
+ *   offset    12 doubles, same layout; maps sensor -> platform.
+ *   images    [H][W] float32 per keyframe: intensity and depth (pinhole: depth
+ *             along the optical axis; spherical: range).  normals [H][W][3]
+ *             float32, sensor frame.  Pixel (col u, row v) has integer
+ *             coordinates at its centre.
+ *   pinhole   pixel u looks along ((u-cx)/fx, (v-cy)/fy, 1).
+ *   spherical pixel u looks along (cos el cos az, cos el sin az, sin el) with
+ *             az = (u-cx)/fx, el = (v-cy)/fy.
+ *   dx        6N doubles, per pose [dt (3), dq (3)]; dq is the imaginary part
+ *             of a unit quaternion, so a rotation by angle a has |dq| = sin(a/2).
+ *
+ * Ownership: every input is copied during the call; the library never keeps a
+ * caller pointer.  Outputs are caller-allocated.  `on_device` arguments say
+ * whether a caller pointer is device memory (1) or host memory (0).
+ *
+ * Errors: every call returns a pba_status; no C++ exception crosses the ABI.
+ * On error the context state is unchanged and pba_last_error() describes it.
+ *
+ * Streams: work is ordered on the stream given in pba_config (a borrowed
+ * hipStream_t; NULL = the null stream).  Calls that return host values
+ * synchronise that stream.  A context is not thread-safe.
+ */
+#ifndef PBA_H
+#define PBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pba_ctx pba_ctx;
+typedef int32_t pba_status;
+
+enum {
+    PBA_OK = 0,
+    PBA_EINVAL = -1,     /* bad argument: ids, sizes, NaN or non-orthonormal pose, shape mismatch */
+    PBA_ENOMEM = -2,     /* device allocation failed */
+    PBA_EDEVICE = -3,    /* HIP runtime error */
+    PBA_ESTATE = -4,     /* call out of order (e.g. evaluate before poses and pairs are set) */
+    PBA_ENOTPD = -5,     /* Gauss-Newton system not positive definite (lambda = 0) */
+    PBA_ENOVALID = -6    /* no valid correspondence at all */
+};
+
+enum { PBA_PINHOLE = 0, PBA_SPHERICAL = 1 };
+enum { PBA_F32 = 0, PBA_F64 = 1 };
+
+/* Length of one per-pair record written by pba_evaluate (pair_out):
+ * [0,144)  H12, 12x12 row-major over [dx_s (6); dx_t (6)]
+ * [144,156) b12
+ * 156 F (sum of rho), 157 evaluated source pixels, 158 valid correspondences,
+ * 159 pixels whose integer cell was decided in FP64 (FP32 path only). */
+#define PBA_PAIR_OUT_LEN 160
+
+/* A sensor model (Sec. III) and its rigid offset on the platform (Supplementary). */
+typedef struct {
+    int32_t model;               /* PBA_PINHOLE or PBA_SPHERICAL */
+    int32_t height, width;       /* image size H, W: >= 4 each and H * W * W < 2^32 */
+    int32_t pad;
+    double fx, fy, cx, cy;       /* K: focal / angular resolution and offsets, in pixels */
+    double min_depth, max_depth; /* valid depth (pinhole) or range (spherical) interval, metres */
+    double offset[12];           /* sensor -> platform, R row-major then t */
+} pba_sensor;
+
+typedef struct {
+    int32_t device;              /* HIP device ordinal */
+    int32_t precision;           /* PBA_F32: residual/Jacobian/H path in FP32 (solve FP64);
+                                    PBA_F64: the same kernels instantiated in FP64 */
+    int32_t channels;            /* 2: intensity + depth; 5: + normal xyz */
+    int32_t grad_mode;           /* image Jacobian: 0 = central differences at the 4 bilinear taps,
+                                    blended bilinearly (Supplementary); 1 = slope of the bilinear
+                                    interpolant (exact derivative of the sampled image) */
+    int32_t anchor;              /* pose held fixed (gauge) */
+    int32_t pad0;
+    void *stream;                /* borrowed hipStream_t, NULL = null stream */
+    double omega_intensity, omega_depth, omega_normal;  /* Omega^c, scalar per cue */
+    double huber_delta;          /* Huber threshold on sqrt(chi^2); <= 0: plain squares */
+    double occlusion_tau_pinhole, occlusion_tau_spherical;
+    /* every stencil tap's depth must be within tau of the predicted depth (Sec. IV-C,
+       occlusion suppression), chosen by the target sensor's model */
+    double refine_band;          /* FP32 path: a projected coordinate within this many pixels of an
+                                    integer is recomputed in FP64 before its cell is chosen; 0 = off */
+} pba_config;
+
+/* Fill *cfg with defaults: F32, 5 channels, grad_mode 0, anchor 0, Omega 1, Huber 0.1,
+ * tau 0.5 m (pinhole) / 1.0 m (spherical), refine band 2e-3 px. */
+void pba_config_default(pba_config *cfg);
+
+/* Create a context on cfg->device.  *out receives the handle. */
+pba_status pba_create(const pba_config *cfg, pba_ctx **out);
+pba_status pba_destroy(pba_ctx *ctx);
+
+/* Register a sensor; *sensor_id receives its index (0, 1, ...).  Before any keyframe is loaded. */
+pba_status pba_add_sensor(pba_ctx *ctx, const pba_sensor *sensor, int32_t *sensor_id);
+
+/* Load n keyframes (replacing any loaded before): per keyframe its sensor id and pointers to its
+ * intensity [H][W], depth [H][W] and normals [H][W][3] (normals may be NULL when channels == 2).
+ * Depth outside [min_depth, max_depth] or not finite marks the pixel invalid. */
+pba_status pba_load_keyframes(pba_ctx *ctx, int32_t n, const int32_t *sensor_id,
+                              const float *const *intensity, const float *const *depth,
+                              const float *const *normals, int32_t on_device);
+
+/* Poses of all n keyframes (n must equal the number loaded).  Rejects non-finite values and
+ * rotations with max |R^T R - I| > 1e-6. */
+pba_status pba_set_poses(pba_ctx *ctx, int32_t n, const double *poses, int32_t on_device);
+pba_status pba_get_poses(pba_ctx *ctx, double *poses, int32_t on_device);
+
+/* Ordered pairs (src[k] -> tgt[k]); ids in [0, n).  Replaces any previous set. */
+pba_status pba_set_pairs(pba_ctx *ctx, int32_t p, const int32_t *src, const int32_t *tgt);
+
+typedef struct {
+    double F;                    /* sum over pairs and pixels of rho(chi^2) */
+    int64_t n_evaluated;         /* (pair, source pixel with valid depth) evaluations */
+    int64_t n_valid;             /* valid correspondences */
+    int64_t n_refined;           /* cells decided in FP64 (FP32 path) */
+    double *H;                   /* nullable: 6N x 6N, raw (no gauge fix, no damping) */
+    double *b;                   /* nullable: 6N */
+    double *pair_out;            /* nullable: P x PBA_PAIR_OUT_LEN, in the platform frames */
+    int32_t on_device;           /* whether H, b, pair_out are device pointers */
+    int32_t pad;
+} pba_eval_out;
+
+/* Evaluate residuals, Jacobians and the normal equations at the current poses. */
+pba_status pba_evaluate(pba_ctx *ctx, pba_eval_out *out);
+
+/* Solve (H + lambda diag H) dx = -b at the current poses (anchor fixed), FP64 Cholesky.
+ * dx (6N, nullable) receives the step; it is also kept for pba_apply_step. */
+pba_status pba_solve_step(pba_ctx *ctx, double lambda, double *dx, int32_t on_device);
+
+/* X_k <- X_k exp(dx_k) for every pose; dx NULL applies the last solved step. */
+pba_status pba_apply_step(pba_ctx *ctx, const double *dx, int32_t on_device);
+
+typedef struct {
+    double F;                    /* objective after the iteration (at the accepted poses) */
+    double lambda;               /* damping after the iteration (0 for Gauss-Newton) */
+    double step_norm;            /* |dx| of the step tried */
+    int64_t n_valid;
+    int32_t accepted;            /* 1 if the step was taken */
+    int32_t pad;
+} pba_iter_log;
+
+/* Run n_iters Gauss-Newton (use_lm = 0: every solved step taken) or Levenberg-Marquardt
+ * iterations (use_lm = 1: a step is kept only if F decreases; lambda /= 10 (floor 1e-12) on
+ * accept, *= 10 on reject; lambda0 > 0 sets the initial damping, 0 continues from the damping
+ * the previous call ended with, 1e-4 if none).  Each iteration solves at the current poses,
+ * evaluates the candidate and decides on the device; the system at the current poses is
+ * evaluated first only if no call has left it.  log (n_iters entries, nullable) is copied back
+ * at the end.  Gauss-Newton returns PBA_ENOTPD if a system was not positive definite. */
+pba_status pba_iterate(pba_ctx *ctx, int32_t n_iters, int32_t use_lm, double lambda0, pba_iter_log *log);
+
+/* Per-pixel view of one pair for inspection (host outputs, each nullable, source-image sized):
+ * status (0 valid, 1 no depth, 2 not projectable, 3 outside, 4 invalid or occluded tap),
+ * uv (2 floats: projected column, row), cell (2 ints: integer cell x0, y0) and residuals
+ * (5 floats).  Same kernels as pba_evaluate. */
+pba_status pba_debug_pair(pba_ctx *ctx, int32_t pair, uint8_t *status, float *uv, int32_t *cell,
+                          float *residuals);
+
+typedef struct {
+    double eval_ms;              /* summed duration of the evaluation kernel launches (HIP events) */
+    int64_t eval_launches;
+    double iterate_ms;           /* summed duration of pba_iterate iterations */
+    int64_t iterations;
+    int64_t n_items;             /* work items of the evaluation queue */
+    int32_t items_px;            /* source pixels per work item */
+    int32_t grid;                /* workgroups of the persistent evaluation launch */
+} pba_timings;
+
+/* Kernel timing counters; reset = 1 clears them after reading. */
+pba_status pba_get_timings(pba_ctx *ctx, pba_timings *out, int32_t reset);
+
+const char *pba_status_string(pba_status status);
+const char *pba_last_error(const pba_ctx *ctx);   /* valid until the next call on ctx */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBA_H */

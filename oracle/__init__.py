@@ -52,7 +52,7 @@ class OrcParams(ctypes.Structure):
 
 class OrcPairOut(ctypes.Structure):
     _fields_ = [("H", ctypes.c_double * 144), ("b", ctypes.c_double * 12), ("F", ctypes.c_double),
-                ("n_eval", ctypes.c_int64), ("n_valid", ctypes.c_int64)]
+                ("n_eval", ctypes.c_int64), ("n_valid", ctypes.c_int64), ("babs", ctypes.c_double * 12)]
 
 
 class OrcFrame(ctypes.Structure):
@@ -88,7 +88,7 @@ def _load():
         lib.orc_eval_pair.restype = ctypes.c_int
         lib.orc_eval_pair.argtypes = [ctypes.POINTER(OrcSensor), vp, vp, vp, ctypes.POINTER(OrcSensor), vp, vp,
                                       vp, vp, vp, ctypes.POINTER(OrcParams), vp, vp,
-                                      ctypes.POINTER(OrcPairOut), vp, vp, vp]
+                                      ctypes.POINTER(OrcPairOut), vp, vp, vp, vp]
         lib.orc_eval_pairs.restype = ctypes.c_int
         lib.orc_eval_pairs.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, ctypes.POINTER(OrcParams),
                                        ctypes.POINTER(OrcParams), vp]
@@ -131,7 +131,9 @@ def _c(a, dtype):
 
 def eval_pair(prob, poses, s, t, params=None, force_valid=None, force_cell=None, pixels=False,
               grad_mode=0):
-    """One ordered pair (s -> t).  Returns dict(H12, b12, F, n_eval, n_valid[, status, uv, res])."""
+    """One ordered pair (s -> t).
+
+    Returns dict(H12, b12, babs12, F, n_eval, n_valid[, status, uv, res, margin])."""
     lib = _load()
     params = prob.params if params is None else params
     ss, st = prob.sensors[prob.kf_sensor[s]], prob.sensors[prob.kf_sensor[t]]
@@ -144,6 +146,7 @@ def eval_pair(prob, poses, s, t, params=None, force_valid=None, force_cell=None,
     status = np.empty((Hs, Ws), np.uint8) if pixels else None
     uv = np.empty((Hs, Ws, 2), np.float64) if pixels else None
     res = np.empty((Hs, Ws, 5), np.float64) if pixels else None
+    margin = np.empty((Hs, Ws), np.float64) if pixels else None
     fv = _c(force_valid, np.uint8) if force_valid is not None else None
     fc = _c(force_cell, np.int32) if force_cell is not None else None
     rc = lib.orc_eval_pair(ctypes.byref(sensor_struct(ss)), Is.ctypes.data, Ds.ctypes.data, Ns.ctypes.data,
@@ -154,13 +157,14 @@ def eval_pair(prob, poses, s, t, params=None, force_valid=None, force_cell=None,
                            ctypes.byref(out),
                            status.ctypes.data if pixels else None,
                            uv.ctypes.data if pixels else None,
-                           res.ctypes.data if pixels else None)
+                           res.ctypes.data if pixels else None,
+                           margin.ctypes.data if pixels else None)
     if rc != 0:
         raise RuntimeError("orc_eval_pair failed (%d)" % rc)
-    r = dict(H12=np.array(out.H).reshape(12, 12), b12=np.array(out.b), F=out.F, n_eval=out.n_eval,
-             n_valid=out.n_valid)
+    r = dict(H12=np.array(out.H).reshape(12, 12), b12=np.array(out.b), babs12=np.array(out.babs), F=out.F,
+             n_eval=out.n_eval, n_valid=out.n_valid)
     if pixels:
-        r.update(status=status, uv=uv, res=res)
+        r.update(status=status, uv=uv, res=res, margin=margin)
     return r
 
 

@@ -47,6 +47,7 @@ typedef struct {
     double b[12];
     double F;
     int64_t n_eval, n_valid;
+    double babs[12];            /* sum of |w Omega J e| per component: the scale b cancels against */
 } OrcPairOut;
 
 /* per-pixel status codes */
@@ -155,13 +156,16 @@ static inline double px(const float *img, int W, int r, int c) { return (double)
  * per-source-pixel validity and integer cell (x0, y0) instead of deciding
  * them here ("mask-forced" mode, for comparing sums on identical
  * correspondences).
- * Optional per-pixel outputs: status (uint8), uv (2 doubles), res (5 doubles).
+ * Optional per-pixel outputs: status (uint8), uv (2 doubles), res (5 doubles) and
+ * margin (1 double: min over the stencil taps of occ_tau - |depth_tap - zeta^d|,
+ * written for pixels that reach the occlusion test).
  */
 int orc_eval_pair(const OrcSensor *ss, const float *Is, const float *Ds, const float *Ns,
                   const OrcSensor *st, const float *It, const float *Dt, const float *Nt,
                   const double *Xs, const double *Xt, const OrcParams *prm,
                   const uint8_t *force_valid, const int32_t *force_cell,
-                  OrcPairOut *out, uint8_t *status_out, double *uv_out, double *res_out)
+                  OrcPairOut *out, uint8_t *status_out, double *uv_out, double *res_out,
+                  double *margin_out)
 {
     const int C = prm->channels;
     const int Hs = ss->H, Ws = ss->W, Ht = st->H, Wt = st->W;
@@ -180,6 +184,7 @@ int orc_eval_pair(const OrcSensor *ss, const float *Is, const float *Ds, const f
         if (status_out) status_out[pix] = ST_NODEPTH;
         if (uv_out) { uv_out[2*pix] = NAN; uv_out[2*pix+1] = NAN; }
         if (res_out) for (int k = 0; k < 5; ++k) res_out[5*pix+k] = NAN;
+        if (margin_out) margin_out[pix] = NAN;
 
         const double d = px(Ds, Ws, r, c);
         if (!depth_ok(d, ss)) continue;
@@ -275,7 +280,13 @@ int orc_eval_pair(const OrcSensor *ss, const float *Is, const float *Ds, const f
                 const int tr[12] = {y0, y0, y0, y0, y0+1, y0+1, y0+1, y0+1, y0-1, y0-1, y0+2, y0+2};
                 const int tc[12] = {x0-1, x0, x0+1, x0+2, x0-1, x0, x0+1, x0+2, x0, x0+1, x0, x0+1};
                 int vis = 1;
-                for (int k = 0; k < 12; ++k) vis &= fabs(px(Dt, Wt, tr[k], tc[k]) - zeta[1]) <= prm->occ_tau;
+                double margin = INFINITY;
+                for (int k = 0; k < 12; ++k) {
+                    const double m = prm->occ_tau - fabs(px(Dt, Wt, tr[k], tc[k]) - zeta[1]);
+                    vis &= m >= 0.0;
+                    if (m < margin) margin = m;
+                }
+                if (margin_out) margin_out[pix] = margin;
                 if (!vis) { status = ST_OCCLUDED; goto done; }
             }
             if (res_out) for (int ch = 0; ch < C; ++ch) res_out[5*pix+ch] = e[ch];
@@ -342,6 +353,7 @@ int orc_eval_pair(const OrcSensor *ss, const float *Is, const float *Ds, const f
                 for (int i = 0; i < 12; ++i) {
                     for (int j = 0; j < 12; ++j) out->H[12*i+j] += om * J[i] * J[j];
                     out->b[i] += om * J[i] * e[ch];
+                    out->babs[i] += fabs(om * J[i] * e[ch]);
                 }
             }
             out->F += rho;
@@ -371,7 +383,7 @@ int orc_eval_pairs(const OrcSensor *sensors, const OrcFrame *frames, const doubl
         const OrcParams *prm = st->model == 0 ? prm_pinhole : prm_spherical;
         int rc = orc_eval_pair(ss, fs->I, fs->D, fs->N, st, ft->I, ft->D, ft->N,
                                poses + 12 * (int64_t)src[p], poses + 12 * (int64_t)tgt[p], prm,
-                               NULL, NULL, &outs[p], NULL, NULL, NULL);
+                               NULL, NULL, &outs[p], NULL, NULL, NULL, NULL);
         if (rc) err |= 1;
     }
     return err ? -1 : 0;

@@ -1,0 +1,323 @@
+"""Python binding of libpba, the MI355X photometric bundle-adjustment library.
+
+The names mirror the C ABI in include/pba.h; this module only marshals
+arguments through ctypes.  Every step of the computation runs in the HIP
+kernels of libpba.so; if the library is not built, importing the binding's
+entry points raises instead of falling back to anything else.
+
+Arrays may be numpy arrays (host) or torch CUDA tensors (device memory; the
+library then reads them in place on the given stream).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpba.so")
+
+PBA_OK, PBA_EINVAL, PBA_ENOMEM, PBA_EDEVICE, PBA_ESTATE, PBA_ENOTPD, PBA_ENOVALID = 0, -1, -2, -3, -4, -5, -6
+PBA_PINHOLE, PBA_SPHERICAL = 0, 1
+PBA_F32, PBA_F64 = 0, 1
+PBA_PAIR_OUT_LEN = 160
+
+# names declared in include/pba.h
+ABI_FUNCTIONS = (
+    "pba_config_default", "pba_create", "pba_destroy", "pba_add_sensor", "pba_load_keyframes",
+    "pba_set_poses", "pba_get_poses", "pba_set_pairs", "pba_evaluate", "pba_solve_step",
+    "pba_apply_step", "pba_iterate", "pba_debug_pair", "pba_get_timings", "pba_status_string",
+    "pba_last_error",
+)
+
+
+class pba_sensor(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("min_depth", ctypes.c_double),
+                ("max_depth", ctypes.c_double), ("offset", ctypes.c_double * 12)]
+
+
+class pba_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("channels", ctypes.c_int32),
+                ("grad_mode", ctypes.c_int32), ("anchor", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("omega_intensity", ctypes.c_double),
+                ("omega_depth", ctypes.c_double), ("omega_normal", ctypes.c_double),
+                ("huber_delta", ctypes.c_double), ("occlusion_tau_pinhole", ctypes.c_double),
+                ("occlusion_tau_spherical", ctypes.c_double), ("refine_band", ctypes.c_double)]
+
+
+class pba_eval_out(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_double), ("n_evaluated", ctypes.c_int64), ("n_valid", ctypes.c_int64),
+                ("n_refined", ctypes.c_int64), ("H", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("pair_out", ctypes.c_void_p), ("on_device", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class pba_iter_log(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_double), ("lambda_", ctypes.c_double), ("step_norm", ctypes.c_double),
+                ("n_valid", ctypes.c_int64), ("accepted", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class pba_timings(ctypes.Structure):
+    _fields_ = [("eval_ms", ctypes.c_double), ("eval_launches", ctypes.c_int64), ("iterate_ms", ctypes.c_double),
+                ("iterations", ctypes.c_int64), ("n_items", ctypes.c_int64), ("items_px", ctypes.c_int32),
+                ("grid", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpba.so; raises if it has not been built (there is no other implementation)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libpba.so is not built (%s): run __graft_entry__.build() or "
+                           "python -m paper_2303_16878_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "pba_config_default": (None, [ctypes.POINTER(pba_config)]),
+        "pba_create": (i32, [ctypes.POINTER(pba_config), ctypes.POINTER(vp)]),
+        "pba_destroy": (i32, [vp]),
+        "pba_add_sensor": (i32, [vp, ctypes.POINTER(pba_sensor), ctypes.POINTER(i32)]),
+        "pba_load_keyframes": (i32, [vp, i32, vp, vp, vp, vp, i32]),
+        "pba_set_poses": (i32, [vp, i32, vp, i32]),
+        "pba_get_poses": (i32, [vp, vp, i32]),
+        "pba_set_pairs": (i32, [vp, i32, vp, vp]),
+        "pba_evaluate": (i32, [vp, ctypes.POINTER(pba_eval_out)]),
+        "pba_solve_step": (i32, [vp, f64, vp, i32]),
+        "pba_apply_step": (i32, [vp, vp, i32]),
+        "pba_iterate": (i32, [vp, i32, i32, f64, vp]),
+        "pba_debug_pair": (i32, [vp, i32, vp, vp, vp, vp]),
+        "pba_get_timings": (i32, [vp, ctypes.POINTER(pba_timings), i32]),
+        "pba_status_string": (ctypes.c_char_p, [i32]),
+        "pba_last_error": (ctypes.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class PbaError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (%d): %s" % (load_library().pba_status_string(status).decode(), status, message))
+        self.status = status
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype):
+    """(pointer, on_device, keepalive) for a numpy array or a torch tensor."""
+    if x is None:
+        return None, 0, None
+    if _is_torch(x):
+        import torch
+        tdt = {np.float32: torch.float32, np.float64: torch.float64, np.int32: torch.int32}[dtype]
+        if x.dtype != tdt or not x.is_contiguous():
+            raise TypeError("expected a contiguous %s tensor" % tdt)
+        return x.data_ptr(), int(x.is_cuda), x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data, 0, a
+
+
+def config_default():
+    cfg = pba_config()
+    load_library().pba_config_default(ctypes.byref(cfg))
+    return cfg
+
+
+class Context:
+    """Owns one pba_ctx.  Methods map one-to-one onto the C ABI calls."""
+
+    def __init__(self, device=0, precision=PBA_F32, channels=5, grad_mode=0, anchor=0, stream=None,
+                 omega_intensity=1.0, omega_depth=1.0, omega_normal=1.0, huber_delta=0.1,
+                 occlusion_tau_pinhole=0.5, occlusion_tau_spherical=1.0, refine_band=None):
+        self.lib = load_library()
+        cfg = config_default()
+        cfg.device, cfg.precision, cfg.channels, cfg.grad_mode, cfg.anchor = device, precision, channels, grad_mode, anchor
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream(device).cuda_stream
+            except ImportError:
+                stream = None
+        cfg.stream = stream
+        cfg.omega_intensity, cfg.omega_depth, cfg.omega_normal = omega_intensity, omega_depth, omega_normal
+        cfg.huber_delta = huber_delta
+        cfg.occlusion_tau_pinhole, cfg.occlusion_tau_spherical = occlusion_tau_pinhole, occlusion_tau_spherical
+        if refine_band is not None:
+            cfg.refine_band = refine_band
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        self._check(self.lib.pba_create(ctypes.byref(cfg), ctypes.byref(h)), ctx=None)
+        self.h = h
+        self.n = 0
+        self.p = 0
+        self.sensor_sizes = []
+        self.kf_sensor = None
+
+    def _check(self, st, ctx="self"):
+        if st != PBA_OK:
+            msg = self.lib.pba_last_error(self.h if ctx == "self" else None).decode()
+            raise PbaError(st, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pba_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def add_sensor(self, model, height, width, fx, fy, cx, cy, min_depth, max_depth, offset=None):
+        s = pba_sensor()
+        s.model, s.height, s.width = model, height, width
+        s.fx, s.fy, s.cx, s.cy, s.min_depth, s.max_depth = fx, fy, cx, cy, min_depth, max_depth
+        off = np.eye(3).reshape(-1).tolist() + [0.0, 0.0, 0.0] if offset is None else list(np.asarray(offset, float))
+        for i in range(12):
+            s.offset[i] = off[i]
+        sid = ctypes.c_int32()
+        self._check(self.lib.pba_add_sensor(self.h, ctypes.byref(s), ctypes.byref(sid)))
+        self.sensor_sizes.append((height, width))
+        return sid.value
+
+    def load_keyframes(self, sensor_ids, intensity, depth, normals=None):
+        n = len(sensor_ids)
+        keep = []
+        ptrs = {}
+        on_dev = None
+        for name, arrs in (("I", intensity), ("D", depth), ("N", normals)):
+            if arrs is None:
+                ptrs[name] = None
+                continue
+            ps = (ctypes.c_void_p * n)()
+            for k in range(n):
+                p, dev, ka = _ptr(arrs[k], np.float32)
+                keep.append(ka)
+                ps[k] = p
+                if on_dev is None:
+                    on_dev = dev
+                elif on_dev != dev:
+                    raise ValueError("mixing host and device images")
+            ptrs[name] = ps
+        sid = np.ascontiguousarray(sensor_ids, np.int32)
+        self._check(self.lib.pba_load_keyframes(
+            self.h, n, sid.ctypes.data, ctypes.cast(ptrs["I"], ctypes.c_void_p),
+            ctypes.cast(ptrs["D"], ctypes.c_void_p),
+            ctypes.cast(ptrs["N"], ctypes.c_void_p) if ptrs["N"] is not None else None, int(on_dev or 0)))
+        self.n = n
+        self.kf_sensor = sid.copy()
+
+    def set_poses(self, poses):
+        p, dev, ka = _ptr(poses, np.float64)
+        self._check(self.lib.pba_set_poses(self.h, self.n, p, dev))
+
+    def get_poses(self, out=None):
+        if out is None:
+            out = np.empty((self.n, 12), np.float64)
+        p, dev, ka = _ptr(out, np.float64)
+        self._check(self.lib.pba_get_poses(self.h, p, dev))
+        return out
+
+    def set_pairs(self, pairs):
+        pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+        s = np.ascontiguousarray(pairs[:, 0])
+        t = np.ascontiguousarray(pairs[:, 1])
+        self._check(self.lib.pba_set_pairs(self.h, len(pairs), s.ctypes.data, t.ctypes.data))
+        self.p = len(pairs)
+
+    def evaluate(self, want_system=False, want_pairs=False):
+        out = pba_eval_out()
+        H = b = po = None
+        if want_system:
+            H = np.empty((6 * self.n, 6 * self.n), np.float64)
+            b = np.empty(6 * self.n, np.float64)
+            out.H, out.b = H.ctypes.data, b.ctypes.data
+        if want_pairs:
+            po = np.empty((self.p, PBA_PAIR_OUT_LEN), np.float64)
+            out.pair_out = po.ctypes.data
+        out.on_device = 0
+        self._check(self.lib.pba_evaluate(self.h, ctypes.byref(out)))
+        r = dict(F=out.F, n_evaluated=out.n_evaluated, n_valid=out.n_valid, n_refined=out.n_refined)
+        if want_system:
+            r.update(H=H, b=b)
+        if want_pairs:
+            r["pairs"] = po
+        return r
+
+    def solve_step(self, lam=0.0):
+        dx = np.empty(6 * self.n, np.float64)
+        self._check(self.lib.pba_solve_step(self.h, float(lam), dx.ctypes.data, 0))
+        return dx
+
+    def apply_step(self, dx=None):
+        if dx is None:
+            self._check(self.lib.pba_apply_step(self.h, None, 0))
+        else:
+            p, dev, ka = _ptr(dx, np.float64)
+            self._check(self.lib.pba_apply_step(self.h, p, dev))
+
+    def iterate(self, n_iters, use_lm=False, lambda0=1e-4):
+        logs = (pba_iter_log * max(1, n_iters))()
+        self._check(self.lib.pba_iterate(self.h, int(n_iters), int(bool(use_lm)), float(lambda0),
+                                         ctypes.cast(logs, ctypes.c_void_p)))
+        return [dict(F=l.F, lam=l.lambda_, step=l.step_norm, n_valid=l.n_valid, accepted=bool(l.accepted))
+                for l in logs[:n_iters]]
+
+    def debug_pair(self, pair, src_shape):
+        H, W = src_shape
+        status = np.empty((H, W), np.uint8)
+        uv = np.empty((H, W, 2), np.float32)
+        cell = np.empty((H, W, 2), np.int32)
+        res = np.empty((H, W, 5), np.float32)
+        self._check(self.lib.pba_debug_pair(self.h, int(pair), status.ctypes.data, uv.ctypes.data,
+                                            cell.ctypes.data, res.ctypes.data))
+        return dict(status=status, uv=uv, cell=cell, res=res)
+
+    def timings(self, reset=False):
+        t = pba_timings()
+        self._check(self.lib.pba_get_timings(self.h, ctypes.byref(t), int(bool(reset))))
+        return dict(eval_ms=t.eval_ms, eval_launches=t.eval_launches, iterate_ms=t.iterate_ms,
+                    iterations=t.iterations, n_items=t.n_items, items_px=t.items_px, grid=t.grid)
+
+
+def context_for_problem(prob, precision=PBA_F32, channels=None, grad_mode=0, device=0, poses=None, images=None,
+                        **kw):
+    """Create a context holding a synthetic problem's sensors, keyframes, poses and pairs.
+
+    `prob` follows the layout of the seeded generator (sensors, kf_sensor, images, poses, pairs);
+    `images` optionally overrides the per-keyframe (intensity, depth, normals) lists (e.g. torch
+    CUDA tensors).  Only argument marshalling happens here."""
+    prm = prob.params
+    ch = channels if channels is not None else prm["channels"]
+    ctx = Context(device=device, precision=precision, channels=ch, grad_mode=grad_mode, anchor=prm.get("anchor", 0),
+                  omega_intensity=prm["omega_intensity"], omega_depth=prm["omega_depth"],
+                  omega_normal=prm["omega_normal"], huber_delta=prm["huber_delta"],
+                  occlusion_tau_pinhole=prm["occ_tau_pinhole"], occlusion_tau_spherical=prm["occ_tau_spherical"],
+                  **kw)
+    for s in prob.sensors:
+        ctx.add_sensor(s["model"], s["H"], s["W"], s["fx"], s["fy"], s["cx"], s["cy"], s["min_depth"],
+                       s["max_depth"], s["offset"])
+    I, D, N = images if images is not None else (prob.intensity, prob.depth, prob.normals)
+    ctx.load_keyframes(prob.kf_sensor, I, D, N if ch == 5 else None)
+    ctx.set_poses(prob.init_poses if poses is None else poses)
+    ctx.set_pairs(prob.pairs)
+    return ctx

@@ -1,0 +1,690 @@
+// Evaluation kernels: pair setup, per-pixel residuals/Jacobians/accumulation over a
+// persistent work queue, ordered per-pair reduction, pair expansion and assembly of
+// the 6N x 6N normal equations.
+//
+// Paper: warp Eq. (uprime) and objective Eq. (total-error-multicue) in Sec. IV-C;
+// projections in Sec. III; Jacobians, cue maps and sensor offsets in the
+// supplementary material.
+//
+// Frames.  For pair (s, t) the kernel works in the target *sensor* frame:
+//   q      = pi_s^-1(u, d)                   source sensor frame
+//   p_bar  = R q + t                          target sensor frame, with
+//   R      = R_ot^T R_t^T R_s R_os,  t = R_ot^T (R_t^T (R_s t_os + t_s - t_t) - t_ot)
+// and differentiates with respect to the target-pose perturbation expressed in the
+// target sensor axes, dx' = D dx_t with D = blockdiag(R_ot^T, R_ot^T):
+//   d p_bar / d dx' = [-I | 2 [y'']_x],  y'' = p_bar + R_ot^T t_ot
+// (the supplementary's -R_o^T [I  2 skewp(y)] rotated into sensor axes; skewp(v) w = w x v).
+// Rows for the platform perturbations follow per pair in FP64:
+//   J_t = J' D,   J_s = J_t A = J' (D A),  A = [[-R, 2 skewp(t) R], [0, -R]]
+// with (R, t) = X_t^-1 X_s; A is the exact algebraic relation between the two
+// supplementary point Jacobians.  So per pixel only the 6-vector J' of each cue
+// row is formed and 21 + 6 unique products are accumulated.
+
+#include "pba_internal.h"
+
+#include <type_traits>
+
+namespace pba {
+
+// ------------------------------------------------------------------ pair setup (FP64)
+
+__device__ static inline void mm3(const double *A, const double *B, double *C) {
+    double T[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) T[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+    for (int i = 0; i < 9; ++i) C[i] = T[i];
+}
+__device__ static inline void mtm3(const double *A, const double *B, double *C) {   // A^T B
+    double T[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) T[3 * i + j] = A[i] * B[j] + A[3 + i] * B[3 + j] + A[6 + i] * B[6 + j];
+    for (int i = 0; i < 9; ++i) C[i] = T[i];
+}
+__device__ static inline void mv3(const double *A, const double *v, double *o) {
+    double r0 = A[0] * v[0] + A[1] * v[1] + A[2] * v[2];
+    double r1 = A[3] * v[0] + A[4] * v[1] + A[5] * v[2];
+    double r2 = A[6] * v[0] + A[7] * v[1] + A[8] * v[2];
+    o[0] = r0; o[1] = r1; o[2] = r2;
+}
+__device__ static inline void mtv3(const double *A, const double *v, double *o) {   // A^T v
+    double r0 = A[0] * v[0] + A[3] * v[1] + A[6] * v[2];
+    double r1 = A[1] * v[0] + A[4] * v[1] + A[7] * v[2];
+    double r2 = A[2] * v[0] + A[5] * v[1] + A[8] * v[2];
+    o[0] = r0; o[1] = r1; o[2] = r2;
+}
+
+__global__ void pair_setup_kernel(const double *__restrict__ poses, const int2 *__restrict__ pairs, int P,
+                                  const SensorDev *__restrict__ sensors, const KfDev *__restrict__ kfs,
+                                  PairDev *__restrict__ out, uint32_t *counters, int ncounters)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < ncounters) counters[p] = 0u;
+    if (p >= P) return;
+    const int s = pairs[p].x, t = pairs[p].y;
+    const SensorDev &ss = sensors[kfs[s].sensor];
+    const SensorDev &st = sensors[kfs[t].sensor];
+    const double *Rs = poses + 12 * (int64_t)s, *ts = Rs + 9;
+    const double *Rt = poses + 12 * (int64_t)t, *tt = Rt + 9;
+    // platform-level relative pose X_t^-1 X_s
+    double Rp[9], tp[3], d3[3];
+    mtm3(Rt, Rs, Rp);
+    for (int k = 0; k < 3; ++k) d3[k] = ts[k] - tt[k];
+    mtv3(Rt, d3, tp);
+    // sensor-to-sensor transform
+    double M[9], R[9], tv[3], tw[3];
+    mm3(Rp, ss.Ro, M);
+    mtm3(st.Ro, M, R);
+    mv3(Rp, ss.to, tw);
+    for (int k = 0; k < 3; ++k) tw[k] += tp[k] - st.to[k];
+    mtv3(st.Ro, tw, tv);
+    double c[3];
+    mtv3(st.Ro, st.to, c);
+    PairDev &o = out[p];
+    for (int k = 0; k < 9; ++k) { o.Rd[k] = R[k]; o.R[k] = (float)R[k]; }
+    for (int k = 0; k < 3; ++k) { o.td[k] = tv[k]; o.t[k] = (float)tv[k]; o.c[k] = (float)c[k]; }
+    // D = R_ot^T ; A = [[-Rp, 2 skewp(tp) Rp], [0, -Rp]] ; E = blockdiag(D, D) A
+    double D[9];
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) D[3 * i + j] = st.Ro[3 * j + i];
+    for (int k = 0; k < 9; ++k) o.D[k] = D[k];
+    const double Sp[9] = {0, tp[2], -tp[1], -tp[2], 0, tp[0], tp[1], -tp[0], 0};
+    double A12[9], DR[9], DA12[9];
+    mm3(Sp, Rp, A12);
+    for (int k = 0; k < 9; ++k) A12[k] *= 2.0;
+    mm3(D, Rp, DR);
+    mm3(D, A12, DA12);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            o.E[6 * i + j] = -DR[3 * i + j];
+            o.E[6 * i + 3 + j] = DA12[3 * i + j];
+            o.E[6 * (3 + i) + j] = 0.0;
+            o.E[6 * (3 + i) + 3 + j] = -DR[3 * i + j];
+        }
+    o.src = s;
+    o.tgt = t;
+}
+
+void launch_pair_setup(const double *poses, const int2 *pairs, int P, const SensorDev *sensors, const KfDev *kfs,
+                       PairDev *out, uint32_t *counters, int ncounters, hipStream_t st)
+{
+    const int n = P > ncounters ? P : ncounters;
+    hipLaunchKernelGGL(pair_setup_kernel, dim3((n + 127) / 128), dim3(128), 0, st, poses, pairs, P, sensors, kfs,
+                       out, counters, ncounters);
+}
+
+// ------------------------------------------------------------------ per-pixel evaluation
+
+template <typename T>
+__device__ __forceinline__ T my_sqrt(T x) { return sqrt(x); }
+template <>
+__device__ __forceinline__ float my_sqrt<float>(float x) { return sqrtf(x); }
+template <typename T>
+__device__ __forceinline__ T my_atan2(T y, T x) { return atan2(y, x); }
+template <>
+__device__ __forceinline__ float my_atan2<float>(float y, float x) { return atan2f(y, x); }
+
+// value and image Jacobian [d/dcol, d/drow] of one channel at the bilinear point.
+// a0..a3: row y0, cols x0-1..x0+2; b0..b3: row y0+1; c1,c2: row y0-1, cols x0, x0+1;
+// d1,d2: row y0+2, cols x0, x0+1.
+template <typename T, int GM>
+__device__ __forceinline__ void sample_channel(T a0, T a1, T a2, T a3, T b0, T b1, T b2, T b3, T c1, T c2, T d1,
+                                               T d2, T w00, T w01, T w10, T w11, T al, T be, T &V, T &Gx, T &Gy)
+{
+    V = w00 * a1 + w01 * a2 + w10 * b1 + w11 * b2;
+    if (GM == 0) {
+        // central differences 1/2 (I[x+1] - I[x-1]) at each tap, blended with the bilinear weights
+        Gx = T(0.5) * (w00 * (a2 - a0) + w01 * (a3 - a1) + w10 * (b2 - b0) + w11 * (b3 - b1));
+        Gy = T(0.5) * (w00 * (b1 - c1) + w01 * (b2 - c2) + w10 * (d1 - a1) + w11 * (d2 - a2));
+    } else {
+        Gx = (T(1) - be) * (a2 - a1) + be * (b2 - b1);
+        Gy = (T(1) - al) * (b1 - a1) + al * (b2 - a2);
+    }
+}
+
+// acc += om * J J^T (upper triangle) and acc_b += om * e * J, accumulated in FP64 whatever the
+// evaluation precision: with FP32 operands every product om*J_i*J_j is formed exactly and each
+// addition rounds once in FP64.  The source-pose blocks are expanded from these sums by A, whose
+// lever arm (the pair baseline) amplifies relative errors of the sums by up to ~|t|^2 / range^2,
+// so FP32 accumulation would not hold the 1e-5 agreement on long baselines.
+template <typename T>
+__device__ __forceinline__ void accumulate_row(double *acc, const T (&J)[6], T e, T om)
+{
+    double jd[6], wj[6];
+    const double omd = (double)om;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        jd[i] = (double)J[i];
+        wj[i] = omd * jd[i];
+    }
+    int idx = ACC_H;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i; j < 6; ++j) { acc[idx] = fma(wj[i], jd[j], acc[idx]); ++idx; }
+    const double ed = (double)e;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[ACC_B + i] = fma(wj[i], ed, acc[ACC_B + i]);
+}
+
+// J' of a cue row whose point-space derivative is a = d e / d p_bar (up to sign conventions below):
+// J' = [-a ; 2 a x y'']  (translation, rotation), plus an optional rotation-only term z.
+template <typename T>
+__device__ __forceinline__ void row_from_a(T (&J)[6], T ax, T ay, T az, T y2x, T y2y, T y2z)
+{
+    J[0] = -ax;
+    J[1] = -ay;
+    J[2] = -az;
+    J[3] = ay * y2z - az * y2y;
+    J[4] = az * y2x - ax * y2z;
+    J[5] = ax * y2y - ay * y2x;
+}
+
+template <typename T>
+struct Lut;
+template <>
+struct Lut<float> {
+    typedef float2 type;
+    __device__ static const float2 *ptr(const EvalArgs &a) { return a.lut32; }
+};
+template <>
+struct Lut<double> {
+    typedef double2 type;
+    __device__ static const double2 *ptr(const EvalArgs &a) { return a.lut64; }
+};
+
+template <typename T, int NCH, int SM, int TM, int GM, bool DBG>
+__global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base, int n_items)
+{
+    __shared__ int s_item;
+    __shared__ double s_red[kBlock / 64][kAcc];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    typedef typename Lut<T>::type L2;
+    const L2 *lut = Lut<T>::ptr(a);
+
+    for (;;) {
+        if (tid == 0) s_item = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (it >= n_items) break;
+        const int item = item_base + it;
+        const int pair = __builtin_amdgcn_readfirstlane(a.item_pair[item]);
+        const int px0 = __builtin_amdgcn_readfirstlane(a.item_px0[item]);
+        const PairDev &pd = a.pairs[pair];
+        const KfDev ks = a.kfs[pd.src], kt = a.kfs[pd.tgt];
+        const SensorDev &ss = a.sensors[ks.sensor];
+        const SensorDev &st = a.sensors[kt.sensor];
+        const int Ws = ss.W, npx = ss.npx, Wt = st.W, Ht = st.H;
+        const uint32_t magic = ss.magic_w;
+        const int px1 = min(px0 + a.items_px, npx);
+
+        // pair constants in the evaluation precision
+        T R[9], tr[3], cc[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R[k] = std::is_same<T, double>::value ? (T)pd.Rd[k] : (T)pd.R[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            tr[k] = std::is_same<T, double>::value ? (T)pd.td[k] : (T)pd.t[k];
+            cc[k] = (T)pd.c[k];
+        }
+        if (std::is_same<T, double>::value) {
+            // c in FP64 from the target offset
+            double cd[3];
+            mtv3(st.Ro, st.to, cd);
+            for (int k = 0; k < 3; ++k) cc[k] = (T)cd[k];
+        }
+        const T fx = std::is_same<T, double>::value ? (T)st.fxd : (T)st.fx;
+        const T fy = std::is_same<T, double>::value ? (T)st.fyd : (T)st.fy;
+        const T cx = std::is_same<T, double>::value ? (T)st.cxd : (T)st.cx;
+        const T cy = std::is_same<T, double>::value ? (T)st.cyd : (T)st.cy;
+        const T dmin = std::is_same<T, double>::value ? (T)st.dmind : (T)st.dmin;
+        const T tau = std::is_same<T, double>::value ? (T)st.taud : (T)st.tau;
+        const T om_g = (T)a.omega_g, om_d = (T)a.omega_d, om_n = (T)a.omega_n, delta = (T)a.huber;
+        const float band = (float)a.refine_band;
+        const L2 *lcol = lut + ss.lut_col, *lrow = lut + ss.lut_row;
+        const float4 *sA4 = a.tex4 + ks.off, *tA4 = a.tex4 + kt.off;
+        const float *sB1 = a.tex1 + ks.off, *tB1 = a.tex1 + kt.off;
+        const float2 *sA2 = a.tex2 + ks.off, *tA2 = a.tex2 + kt.off;
+
+        double acc[ACC_USED];
+#pragma unroll
+        for (int k = 0; k < ACC_USED; ++k) acc[k] = 0.0;
+
+        for (int pix = px0 + tid; pix < px1; pix += kBlock) {
+            int row = (int)__umulhi((uint32_t)pix, magic);
+            int col = pix - row * Ws;
+            if (col < 0) { row -= 1; col += Ws; }   // the reciprocal can only round up
+            float Is, Ds, nsx = 0.f, nsy = 0.f, nsz = 0.f;
+            if (NCH == 5) {
+                const float4 s4 = sA4[pix];
+                Is = s4.x; Ds = s4.y; nsx = s4.z; nsy = s4.w;
+                nsz = sB1[pix];
+            } else {
+                const float2 s2 = sA2[pix];
+                Is = s2.x; Ds = s2.y;
+            }
+            if (DBG) a.dbg_status[pix] = 1;
+            if (!(Ds > 0.f)) continue;
+            acc[ACC_EVAL] += 1.0;
+            if (DBG) a.dbg_status[pix] = 2;
+
+            // unprojection q = d * ray(u) and transform into the target sensor frame
+            const L2 lc = lcol[col], lr = lrow[row];
+            const T d = (T)Ds;
+            T qx, qy, qz;
+            if (SM == MODEL_SPHERICAL) { qx = d * (lr.x * lc.x); qy = d * (lr.x * lc.y); qz = d * lr.y; }
+            else { qx = d * lc.x; qy = d * lr.x; qz = d; }
+            const T px = R[0] * qx + R[1] * qy + R[2] * qz + tr[0];
+            const T py = R[3] * qx + R[4] * qy + R[5] * qz + tr[1];
+            const T pz = R[6] * qx + R[7] * qy + R[8] * qz + tr[2];
+
+            // projection (Sec. III) and predicted depth/range cue
+            T u, v, zeta_d, r2 = T(0), rho = T(0), n2 = T(0), iz = T(0);
+            bool proj_ok;
+            if (TM == MODEL_PINHOLE) {
+                proj_ok = pz >= dmin;
+                iz = T(1) / pz;
+                u = fx * px * iz + cx;
+                v = fy * py * iz + cy;
+                zeta_d = pz;
+            } else {
+                r2 = px * px + py * py;
+                rho = my_sqrt(r2);
+                n2 = r2 + pz * pz;
+                proj_ok = (rho > T(0)) && (n2 >= dmin * dmin);
+                u = fx * my_atan2(py, px) + cx;
+                v = fy * my_atan2(pz, rho) + cy;
+                zeta_d = my_sqrt(n2);
+            }
+            if (!proj_ok) continue;
+            if (DBG) { a.dbg_status[pix] = 3; a.dbg_uv[pix] = make_float2((float)u, (float)v); }
+
+            // choose the integer cell; near a cell boundary the FP32 path decides it in FP64
+            int x0, y0;
+            T al, be;
+            bool refined = false;
+            if (std::is_same<T, float>::value && band > 0.f) {
+                const float fu = (float)u - floorf((float)u), fv = (float)v - floorf((float)v);
+                refined = fu < band || fu > 1.f - band || fv < band || fv > 1.f - band;
+            }
+            if (refined) {
+                const double2 lcd = a.lut64[ss.lut_col + col], lrd = a.lut64[ss.lut_row + row];
+                const double dd = (double)Ds;
+                double q0, q1, q2;
+                if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
+                else { q0 = dd * lcd.x; q1 = dd * lrd.x; q2 = dd; }
+                const double *Rd = pd.Rd, *td = pd.td;
+                const double X = Rd[0] * q0 + Rd[1] * q1 + Rd[2] * q2 + td[0];
+                const double Y = Rd[3] * q0 + Rd[4] * q1 + Rd[5] * q2 + td[1];
+                const double Z = Rd[6] * q0 + Rd[7] * q1 + Rd[8] * q2 + td[2];
+                double ud, vd;
+                if (TM == MODEL_PINHOLE) {
+                    ud = st.fxd * X / Z + st.cxd;
+                    vd = st.fyd * Y / Z + st.cyd;
+                } else {
+                    ud = st.fxd * atan2(Y, X) + st.cxd;
+                    vd = st.fyd * atan2(Z, sqrt(X * X + Y * Y)) + st.cyd;
+                }
+                if (!(ud >= 1.0 && ud < (double)(Wt - 2) && vd >= 1.0 && vd < (double)(Ht - 2))) continue;
+                const double fx0 = floor(ud), fy0 = floor(vd);
+                x0 = (int)fx0; y0 = (int)fy0;
+                al = (T)(ud - fx0); be = (T)(vd - fy0);
+                acc[ACC_REF] += 1.0;
+                if (DBG) a.dbg_uv[pix] = make_float2((float)ud, (float)vd);
+            } else {
+                if (!(u >= T(1) && u < (T)(Wt - 2) && v >= T(1) && v < (T)(Ht - 2))) continue;
+                x0 = (int)u; y0 = (int)v;
+                al = u - (T)x0; be = v - (T)y0;
+            }
+            if (DBG) { a.dbg_status[pix] = 4; a.dbg_cell[pix] = make_int2(x0, y0); }
+
+            // gather the 12-tap stencil of the target image
+            const int base = y0 * Wt + x0;
+            const int idx[12] = {base - 1, base, base + 1, base + 2,
+                                 base + Wt - 1, base + Wt, base + Wt + 1, base + Wt + 2,
+                                 base - Wt, base - Wt + 1, base + 2 * Wt, base + 2 * Wt + 1};
+            float tI[12], tD[12], tX[12], tY[12], tZ[12];
+            if (NCH == 5) {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    const float4 q4 = tA4[idx[k]];
+                    tI[k] = q4.x; tD[k] = q4.y; tX[k] = q4.z; tY[k] = q4.w;
+                }
+#pragma unroll
+                for (int k = 0; k < 12; ++k) tZ[k] = tB1[idx[k]];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    const float2 q2 = tA2[idx[k]];
+                    tI[k] = q2.x; tD[k] = q2.y;
+                }
+            }
+            // validity and occlusion suppression: every tap valid and on the predicted surface
+            bool vis = true;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) vis = vis && (tD[k] > 0.f) && (fabs((T)tD[k] - zeta_d) <= tau);
+            if (!vis) continue;
+
+            const T w00 = (T(1) - al) * (T(1) - be), w01 = al * (T(1) - be);
+            const T w10 = (T(1) - al) * be, w11 = al * be;
+#define SAMPLE(arr, V, GX, GY)                                                                             \
+    sample_channel<T, GM>((T)arr[0], (T)arr[1], (T)arr[2], (T)arr[3], (T)arr[4], (T)arr[5], (T)arr[6],      \
+                          (T)arr[7], (T)arr[8], (T)arr[9], (T)arr[10], (T)arr[11], w00, w01, w10, w11, al, \
+                          be, V, GX, GY)
+            T Vg, Gxg, Gyg, Vd, Gxd, Gyd;
+            SAMPLE(tI, Vg, Gxg, Gyg);
+            SAMPLE(tD, Vd, Gxd, Gyd);
+            const T eg = (T)Is - Vg;
+            const T ed = zeta_d - Vd;
+            T chi2 = om_g * eg * eg + om_d * ed * ed;
+            T en[3] = {T(0), T(0), T(0)}, nr[3] = {T(0), T(0), T(0)};
+            T Gxn[3] = {T(0), T(0), T(0)}, Gyn[3] = {T(0), T(0), T(0)};
+            if (NCH == 5) {
+                T Vn[3];
+                SAMPLE(tX, Vn[0], Gxn[0], Gyn[0]);
+                SAMPLE(tY, Vn[1], Gxn[1], Gyn[1]);
+                SAMPLE(tZ, Vn[2], Gxn[2], Gyn[2]);
+                // normal cue: the source normal rotated into the target sensor frame
+                const T n0 = nsx, n1 = nsy, n2s = nsz;
+                nr[0] = R[0] * n0 + R[1] * n1 + R[2] * n2s;
+                nr[1] = R[3] * n0 + R[4] * n1 + R[5] * n2s;
+                nr[2] = R[6] * n0 + R[7] * n1 + R[8] * n2s;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) { en[k] = nr[k] - Vn[k]; chi2 += om_n * en[k] * en[k]; }
+            }
+#undef SAMPLE
+            if (DBG) {
+                float *rr = a.dbg_res + 5 * (int64_t)pix;
+                rr[0] = (float)eg; rr[1] = (float)ed; rr[2] = (float)en[0]; rr[3] = (float)en[1]; rr[4] = (float)en[2];
+                a.dbg_status[pix] = 0;
+            }
+
+            // Huber on sqrt(chi^2): w = d rho / d chi^2
+            T w = T(1), rhov = chi2;
+            if (delta > T(0)) {
+                const T sq = my_sqrt(chi2);
+                if (sq > delta) { w = delta / sq; rhov = delta * (T(2) * sq - delta); }
+            }
+            acc[ACC_F] += (double)rhov;
+            acc[ACC_VALID] += 1.0;
+
+            // projective Jacobian rows Pi0 = d u / d p_bar, Pi1 = d v / d p_bar
+            T P00, P01, P02, P10, P11, P12;
+            if (TM == MODEL_PINHOLE) {
+                P00 = fx * iz; P01 = T(0); P02 = -fx * px * iz * iz;
+                P10 = T(0); P11 = fy * iz; P12 = -fy * py * iz * iz;
+            } else {
+                const T ir2 = T(1) / r2;
+                const T k1 = pz / (rho * n2);
+                P00 = -fx * py * ir2; P01 = fx * px * ir2; P02 = T(0);
+                P10 = -fy * px * k1; P11 = -fy * py * k1; P12 = fy * rho / n2;
+            }
+            const T y2x = T(2) * (px + cc[0]), y2y = T(2) * (py + cc[1]), y2z = T(2) * (pz + cc[2]);
+            T J[6];
+            // intensity: a = -(Gx Pi0 + Gy Pi1)
+            row_from_a(J, -(Gxg * P00 + Gyg * P10), -(Gxg * P01 + Gyg * P11), -(Gxg * P02 + Gyg * P12), y2x, y2y,
+                       y2z);
+            accumulate_row(acc, J, eg, w * om_g);
+            // depth / range: a = d zeta / d p_bar - (Gx Pi0 + Gy Pi1)
+            {
+                T zx, zy, zz;
+                if (TM == MODEL_PINHOLE) { zx = T(0); zy = T(0); zz = T(1); }
+                else { const T ir = T(1) / zeta_d; zx = px * ir; zy = py * ir; zz = pz * ir; }
+                row_from_a(J, zx - (Gxd * P00 + Gyd * P10), zy - (Gxd * P01 + Gyd * P11),
+                           zz - (Gxd * P02 + Gyd * P12), y2x, y2y, y2z);
+                accumulate_row(acc, J, ed, w * om_d);
+            }
+            if (NCH == 5) {
+                // normal rows: image term plus the rotation-only term 2 (e_k x n')
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    row_from_a(J, -(Gxn[k] * P00 + Gyn[k] * P10), -(Gxn[k] * P01 + Gyn[k] * P11),
+                               -(Gxn[k] * P02 + Gyn[k] * P12), y2x, y2y, y2z);
+                    if (k == 0) { J[4] -= T(2) * nr[2]; J[5] += T(2) * nr[1]; }
+                    if (k == 1) { J[3] += T(2) * nr[2]; J[5] -= T(2) * nr[0]; }
+                    if (k == 2) { J[3] -= T(2) * nr[1]; J[4] += T(2) * nr[0]; }
+                    accumulate_row(acc, J, en[k], w * om_n);
+                }
+            }
+        }
+
+        // workgroup reduction of the accumulators (fixed order: deterministic)
+#pragma unroll
+        for (int k = 0; k < ACC_USED; ++k) {
+            double v = acc[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) s_red[wave][k] = v;
+        }
+        __syncthreads();
+        if (tid < kAcc) {
+            double v = 0.0;
+            if (tid < ACC_USED) {
+#pragma unroll
+                for (int w = 0; w < kBlock / 64; ++w) v += s_red[w][tid];
+            }
+            static_cast<double *>(a.partials)[(int64_t)item * kAcc + tid] = v;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int NCH, int SM, int TM, int GM, bool DBG>
+static void launch_eval_t(const EvalArgs &a, int item_base, int n_items, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((eval_kernel<T, NCH, SM, TM, GM, DBG>), dim3(grid), dim3(kBlock), 0, st, a, item_base,
+                       n_items);
+}
+
+template <typename T, int NCH, int GM, bool DBG>
+static void launch_eval_models(const EvalArgs &a, int sm, int tm, int item_base, int n_items, int grid,
+                               hipStream_t st)
+{
+    if (sm == MODEL_PINHOLE && tm == MODEL_PINHOLE)
+        launch_eval_t<T, NCH, MODEL_PINHOLE, MODEL_PINHOLE, GM, DBG>(a, item_base, n_items, grid, st);
+    else if (sm == MODEL_PINHOLE)
+        launch_eval_t<T, NCH, MODEL_PINHOLE, MODEL_SPHERICAL, GM, DBG>(a, item_base, n_items, grid, st);
+    else if (tm == MODEL_PINHOLE)
+        launch_eval_t<T, NCH, MODEL_SPHERICAL, MODEL_PINHOLE, GM, DBG>(a, item_base, n_items, grid, st);
+    else
+        launch_eval_t<T, NCH, MODEL_SPHERICAL, MODEL_SPHERICAL, GM, DBG>(a, item_base, n_items, grid, st);
+}
+
+template <typename T, bool DBG>
+static void launch_eval_cfg(const EvalArgs &a, int channels, int gm, int sm, int tm, int item_base, int n_items,
+                            int grid, hipStream_t st)
+{
+    if (channels == 5) {
+        if (gm == 0) launch_eval_models<T, 5, 0, DBG>(a, sm, tm, item_base, n_items, grid, st);
+        else launch_eval_models<T, 5, 1, DBG>(a, sm, tm, item_base, n_items, grid, st);
+    } else {
+        if (gm == 0) launch_eval_models<T, 2, 0, DBG>(a, sm, tm, item_base, n_items, grid, st);
+        else launch_eval_models<T, 2, 1, DBG>(a, sm, tm, item_base, n_items, grid, st);
+    }
+}
+
+void launch_eval(const EvalArgs &a, int precision, int channels, int grad_mode, int src_model, int tgt_model,
+                 bool debug, int item_base, int n_items, int grid, hipStream_t st)
+{
+    if (precision == 1) {
+        if (debug) launch_eval_cfg<double, true>(a, channels, grad_mode, src_model, tgt_model, item_base, n_items, grid, st);
+        else launch_eval_cfg<double, false>(a, channels, grad_mode, src_model, tgt_model, item_base, n_items, grid, st);
+    } else {
+        if (debug) launch_eval_cfg<float, true>(a, channels, grad_mode, src_model, tgt_model, item_base, n_items, grid, st);
+        else launch_eval_cfg<float, false>(a, channels, grad_mode, src_model, tgt_model, item_base, n_items, grid, st);
+    }
+}
+
+// ------------------------------------------------------------------ per-pair reduction and expansion (FP64)
+
+// One wave per pair: sums the pair's FP64 item partials in item order, then expands S, beta
+// into the 12x12 / 12 blocks over [dx_s; dx_t]:
+//   H_tt = D^T S D, H_ss = E^T S E, H_st = E^T S D, H_ts = D^T S E, b_t = D^T beta, b_s = E^T beta
+// with D = blockdiag(R_ot^T, R_ot^T) and E = D A.
+__global__ void __launch_bounds__(64) reduce_pairs_kernel(const double *__restrict__ partials,
+                                                          const int32_t *__restrict__ ibeg,
+                                                          const int32_t *__restrict__ icnt,
+                                                          const PairDev *__restrict__ pairs,
+                                                          double *__restrict__ out, int P)
+{
+    const int p = blockIdx.x;
+    const int lane = threadIdx.x;
+    __shared__ double sums[kAcc];
+    __shared__ double S[36], beta[6], Dm[36], Em[36], SD[36], SE[36];
+    if (lane < kAcc) {
+        double s = 0.0;
+        const int b = ibeg[p], n = icnt[p];
+        for (int i = 0; i < n; ++i) s += partials[(int64_t)(b + i) * kAcc + lane];
+        sums[lane] = s;
+    }
+    __syncthreads();
+    const PairDev &pd = pairs[p];
+    if (lane < 36) {
+        const int i = lane / 6, j = lane % 6;
+        const int a = i < j ? i : j, c = i < j ? j : i;
+        // upper-triangular index of (a, c)
+        const int idx = a * 6 - a * (a - 1) / 2 + (c - a);
+        S[lane] = sums[ACC_H + idx];
+        // D = blockdiag(R_ot^T, R_ot^T)
+        double dv = 0.0;
+        if ((i < 3) == (j < 3)) dv = pd.D[3 * (i % 3) + (j % 3)];
+        Dm[lane] = dv;
+        Em[lane] = pd.E[lane];
+    }
+    if (lane < 6) beta[lane] = sums[ACC_B + lane];
+    __syncthreads();
+    if (lane < 36) {
+        const int i = lane / 6, j = lane % 6;
+        double sd = 0.0, se = 0.0;
+        for (int k = 0; k < 6; ++k) { sd += S[6 * i + k] * Dm[6 * k + j]; se += S[6 * i + k] * Em[6 * k + j]; }
+        SD[lane] = sd;
+        SE[lane] = se;
+    }
+    __syncthreads();
+    // symmetric by construction: each mirrored pair of entries is computed once
+    double *o = out + (int64_t)p * kPairOut;
+    if (lane < 36) {
+        const int i = lane / 6, j = lane % 6;
+        double st = 0;
+        for (int k = 0; k < 6; ++k) st += Em[6 * k + i] * SD[6 * k + j];
+        o[12 * i + 6 + j] = st;                 // H_st
+        o[12 * (6 + j) + i] = st;               // H_ts = H_st^T
+        if (i <= j) {
+            double ss = 0, tt = 0;
+            for (int k = 0; k < 6; ++k) {
+                ss += Em[6 * k + i] * SE[6 * k + j];
+                tt += Dm[6 * k + i] * SD[6 * k + j];
+            }
+            o[12 * i + j] = ss;
+            o[12 * j + i] = ss;
+            o[12 * (6 + i) + 6 + j] = tt;
+            o[12 * (6 + j) + 6 + i] = tt;
+        }
+    }
+    if (lane < 6) {
+        double bs = 0, bt = 0;
+        for (int k = 0; k < 6; ++k) { bs += Em[6 * k + lane] * beta[k]; bt += Dm[6 * k + lane] * beta[k]; }
+        o[144 + lane] = bs;
+        o[150 + lane] = bt;
+    }
+    if (lane == 0) {
+        o[156] = sums[ACC_F];
+        o[157] = sums[ACC_EVAL];
+        o[158] = sums[ACC_VALID];
+        o[159] = sums[ACC_REF];
+    }
+}
+
+void launch_reduce_pairs(const void *partials, int precision, const int32_t *ibeg, const int32_t *icnt,
+                         const PairDev *pairs, double *pair_out, int P, hipStream_t st)
+{
+    (void)precision;
+    if (P <= 0) return;
+    hipLaunchKernelGGL(reduce_pairs_kernel, dim3(P), dim3(64), 0, st, static_cast<const double *>(partials), ibeg,
+                       icnt, pairs, pair_out, P);
+}
+
+// ------------------------------------------------------------------ assembly of the 6N x 6N system
+
+__global__ void fill_kernel(double *p, int64_t n, double v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void launch_fill(double *p, int64_t n, double v, hipStream_t st)
+{
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+}
+
+// One workgroup per nonzero 6x6 block: sums its contributions in pair order.
+// blk_ent[k] = 4 * pair + quadrant (0 ss, 1 st, 2 ts, 3 tt).
+__global__ void __launch_bounds__(64) assemble_H_kernel(const double *__restrict__ pair_out,
+                                                        const int2 *__restrict__ blk_rc,
+                                                        const int32_t *__restrict__ blk_ptr,
+                                                        const int32_t *__restrict__ blk_ent, int n,
+                                                        double *__restrict__ H)
+{
+    const int blk = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (lane >= 36) return;
+    const int i = lane / 6, j = lane % 6;
+    double s = 0.0;
+    for (int k = blk_ptr[blk]; k < blk_ptr[blk + 1]; ++k) {
+        const int e = blk_ent[k];
+        const int p = e >> 2, q = e & 3;
+        const int ro = (q >> 1) * 6, co = (q & 1) * 6;
+        s += pair_out[(int64_t)p * kPairOut + 12 * (ro + i) + co + j];
+    }
+    const int2 rc = blk_rc[blk];
+    H[(int64_t)(6 * rc.x + i) * n + 6 * rc.y + j] = s;
+}
+
+// b per keyframe (bk_ent = 2 * pair + side, side 0 = source, 1 = target) and the totals
+// F, evaluated, valid, refined summed over pairs in order (one workgroup).
+__global__ void __launch_bounds__(256) assemble_b_kernel(const double *__restrict__ pair_out, int P,
+                                                         const int32_t *__restrict__ bk_ptr,
+                                                         const int32_t *__restrict__ bk_ent, int N,
+                                                         double *__restrict__ b, double *__restrict__ totals)
+{
+    const int tid = threadIdx.x;
+    for (int r = tid; r < 6 * N; r += blockDim.x) {
+        const int k = r / 6, j = r % 6;
+        double s = 0.0;
+        for (int e = bk_ptr[k]; e < bk_ptr[k + 1]; ++e) {
+            const int ent = bk_ent[e];
+            s += pair_out[(int64_t)(ent >> 1) * kPairOut + 144 + 6 * (ent & 1) + j];
+        }
+        b[r] = s;
+    }
+    __shared__ double red[4][256];
+    double acc[4] = {0, 0, 0, 0};
+    for (int p = tid; p < P; p += blockDim.x)
+        for (int k = 0; k < 4; ++k) acc[k] += pair_out[(int64_t)p * kPairOut + 156 + k];
+    for (int k = 0; k < 4; ++k) red[k][tid] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int k = 0; k < 4; ++k) red[k][tid] += red[k][tid + w];
+        __syncthreads();
+    }
+    if (tid < 4) totals[tid] = red[tid][0];
+}
+
+void launch_assemble(const double *pair_out, int P, const int2 *blk_rc, const int32_t *blk_ptr,
+                     const int32_t *blk_ent, int nblk, const int32_t *bk_ptr, const int32_t *bk_ent, int N,
+                     double *H, double *b, double *totals, hipStream_t st)
+{
+    const int n = 6 * N;
+    launch_fill(H, (int64_t)n * n, 0.0, st);
+    if (nblk > 0)
+        hipLaunchKernelGGL(assemble_H_kernel, dim3(nblk), dim3(64), 0, st, pair_out, blk_rc, blk_ptr, blk_ent, n, H);
+    hipLaunchKernelGGL(assemble_b_kernel, dim3(1), dim3(256), 0, st, pair_out, P, bk_ptr, bk_ent, N, b, totals);
+}
+
+void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
+
+}  // namespace pba

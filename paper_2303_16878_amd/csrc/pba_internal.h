@@ -1,0 +1,94 @@
+// Internal declarations shared by the HIP sources of libpba (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace pba {
+
+constexpr int kBlock = 256;      // threads per evaluation workgroup (4 wave64)
+constexpr int kAcc = 32;         // accumulator slots per work item
+// accumulator layout: 21 upper-triangular H terms, 6 b terms, F, valid, evaluated, refined
+enum { ACC_H = 0, ACC_B = 21, ACC_F = 27, ACC_VALID = 28, ACC_EVAL = 29, ACC_REF = 30, ACC_USED = 31 };
+constexpr int kPairOut = 160;    // PBA_PAIR_OUT_LEN
+enum { MODEL_PINHOLE = 0, MODEL_SPHERICAL = 1 };
+
+struct SensorDev {
+    int32_t model, H, W, npx;
+    uint32_t magic_w;            // ceil(2^32 / W): row = umulhi(pix, magic_w) for pix < 2^32 / W
+    float fx, fy, cx, cy, dmin, dmax, tau;
+    double fxd, fyd, cxd, cyd, dmind, dmaxd, taud;
+    double Ro[9], to[3];         // sensor -> platform
+    int64_t lut_col, lut_row;    // element offsets into the ray tables
+};
+
+struct KfDev {
+    int32_t sensor, H, W, pad;
+    int64_t off;                 // texel offset of this keyframe in the image arenas
+};
+
+// Per-pair transform from the source sensor frame to the target sensor frame,
+// p_bar = R q + t for q = pi_s^-1(u, d), and c = R_ot^T t_ot so that the target
+// platform point expressed in the target sensor axes is y'' = p_bar + c.
+struct alignas(16) PairDev {
+    float R[9], t[3], c[3], pad;
+    double Rd[9], td[3];
+    double D[9];                 // R_ot^T: target-sensor axes of the platform perturbation
+    double E[36];                // D A: source-pose rows follow as J_s = J' E (6x6 row-major)
+    int32_t src, tgt, pad2[2];
+};
+
+struct EvalArgs {
+    const SensorDev *sensors;
+    const KfDev *kfs;
+    const PairDev *pairs;
+    const float4 *tex4;          // 5 channels: {intensity, depth, nx, ny}
+    const float *tex1;           // 5 channels: nz
+    const float2 *tex2;          // 2 channels: {intensity, depth}
+    const float2 *lut32;         // ray tables, FP32
+    const double2 *lut64;        // ray tables, FP64
+    const int32_t *item_pair;
+    const int32_t *item_px0;
+    int32_t items_px;
+    int32_t pad;
+    uint32_t *counter;
+    void *partials;              // double[n_items][kAcc]
+    double omega_g, omega_d, omega_n, huber, refine_band;
+    // per-pixel inspection outputs (debug launches only)
+    uint8_t *dbg_status;
+    float2 *dbg_uv;
+    int2 *dbg_cell;
+    float *dbg_res;
+};
+
+// ---- launch wrappers (eval.hip)
+void launch_pair_setup(const double *poses, const int2 *pairs, int P, const SensorDev *sensors,
+                       const KfDev *kfs, PairDev *out, uint32_t *counters, int ncounters, hipStream_t st);
+void launch_eval(const EvalArgs &a, int precision, int channels, int grad_mode, int src_model, int tgt_model,
+                 bool debug, int item_base, int n_items, int grid, hipStream_t st);
+void launch_reduce_pairs(const void *partials, int precision, const int32_t *pair_item_begin,
+                         const int32_t *pair_item_count, const PairDev *pairs, double *pair_out, int P,
+                         hipStream_t st);
+void launch_assemble(const double *pair_out, int P, const int2 *blk_rc, const int32_t *blk_ptr,
+                     const int32_t *blk_ent, int nblk, const int32_t *bk_ptr, const int32_t *bk_ent, int N,
+                     double *H, double *b, double *totals, hipStream_t st);
+void launch_fill(double *p, int64_t n, double v, hipStream_t st);
+
+// ---- launch wrappers (solve.hip)
+struct LmState {
+    double lam, F_cur, F_cand, step_norm;
+    int64_t valid_cur, valid_cand;
+    int32_t fail, accepted, use_lm, iter;
+};
+void launch_damp_copy(const double *H, const double *b, double *A, double *rhs, int n, int anchor,
+                      const LmState *lm, double lam_override, hipStream_t st);
+void launch_cholesky(double *A, int n, int32_t *fail, hipStream_t st);
+void launch_chol_solve(const double *L, double *x, int n, const int32_t *fail, hipStream_t st);
+void launch_boxplus(const double *X, const double *dx, double *Xout, int N, const int32_t *fail,
+                    LmState *lm, hipStream_t st);
+void launch_lm_decide(LmState *lm, const double *totals_cand, int64_t nH, double *H_cur, const double *H_cand,
+                      double *b_cur, const double *b_cand, double *X_cur, const double *X_cand, int N,
+                      double *totals_cur, double *log_row, hipStream_t st);
+void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
+
+}  // namespace pba

@@ -1,0 +1,796 @@
+// libpba runtime: context, buffers, work queue, and the C-ABI entry points of include/pba.h.
+// The host only validates, marshals and orders launches; all arithmetic of the
+// evaluation, reduction, assembly, solve and update runs in the kernels of eval.hip
+// and solve.hip.
+
+#include "pba.h"
+#include "pba_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+using namespace pba;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct pba_ctx {
+    pba_config cfg;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    std::string err;
+
+    std::vector<pba_sensor> sensors;
+    std::vector<SensorDev> sensors_dev_h;
+    int N = 0, P = 0;
+    bool poses_set = false;
+    bool system_valid = false;   // H, b, totals[0..3] hold the system at the current poses
+    double lam_carry = -1.0;     // LM damping left by the previous pba_iterate call
+    std::vector<KfDev> kfs_h;
+    int64_t texels = 0;
+
+    // items
+    int items_px = 16384;
+    int n_items = 0;
+    struct Group { int sm, tm, base, count; };
+    std::vector<Group> groups;
+    std::vector<int32_t> pair_item_begin, pair_item_count;
+    int nblk = 0;
+
+    // device buffers
+    DevBuf sensors_d, kfs_d, tex4, tex1, tex2, lut32, lut64;
+    DevBuf poses, poses_cand, pairs_d, pair_dev, item_pair, item_px0, ibeg, icnt, counters, partials, pair_out;
+    DevBuf blk_rc, blk_ptr, blk_ent, bk_ptr, bk_ent;
+    DevBuf H, b, H_cand, b_cand, totals, A, dx, lm, fail, logbuf;
+    DevBuf dbg_status, dbg_uv, dbg_cell, dbg_res;
+
+    // timing
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double eval_ms = 0.0, iterate_ms = 0.0;
+    int64_t eval_launches = 0, iterations = 0;
+    int grid = 0;
+};
+
+namespace {
+
+pba_status fail(pba_ctx *c, pba_status s, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+pba_status fail(pba_ctx *c, pba_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HIP_OK(expr)                                                                                     \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return fail(c, PBA_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+pba_status ensure(pba_ctx *c, DevBuf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    if (b.bytes >= bytes) return PBA_OK;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return fail(c, PBA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    b.bytes = bytes;
+    return PBA_OK;
+}
+
+void release(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <typename T>
+T *P_(DevBuf &b) { return static_cast<T *>(b.p); }
+
+pba_status upload(pba_ctx *c, DevBuf &b, const void *src, size_t bytes)
+{
+    pba_status s = ensure(c, b, bytes);
+    if (s) return s;
+    if (bytes) HIP_OK(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, c->stream));
+    return PBA_OK;
+}
+
+bool pose_ok(const double *x)
+{
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(x[i])) return false;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += x[3 * k + i] * x[3 * k + j];
+            if (std::fabs(s - (i == j ? 1.0 : 0.0)) > 1e-6) return false;
+        }
+    return true;
+}
+
+int n_sys(const pba_ctx *c) { return 6 * c->N; }
+
+// texel preparation: sanitise depth (invalid -> 0) and interleave the channels
+__global__ void pack5_kernel(const float *__restrict__ I, const float *__restrict__ D, const float *__restrict__ Nn,
+                             float4 *__restrict__ A, float *__restrict__ B, int npx, float dmin, float dmax)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += gridDim.x * blockDim.x) {
+        const float d = D[i];
+        const bool ok = d > 0.f && d >= dmin && d <= dmax && isfinite(d);
+        const float in = I[i];
+        float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+        if (Nn) { n0 = Nn[3 * (int64_t)i]; n1 = Nn[3 * (int64_t)i + 1]; n2 = Nn[3 * (int64_t)i + 2]; }
+        A[i] = ok ? make_float4(in, d, n0, n1) : make_float4(0.f, 0.f, 0.f, 0.f);
+        B[i] = ok ? n2 : 0.f;
+    }
+}
+
+__global__ void pack2_kernel(const float *__restrict__ I, const float *__restrict__ D, float2 *__restrict__ A,
+                             int npx, float dmin, float dmax)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += gridDim.x * blockDim.x) {
+        const float d = D[i];
+        const bool ok = d > 0.f && d >= dmin && d <= dmax && isfinite(d);
+        A[i] = ok ? make_float2(I[i], d) : make_float2(0.f, 0.f);
+    }
+}
+
+pba_status build_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt)
+{
+    const int P = (int)src.size();
+    // work items: (pair, first source pixel); grouped by (source model, target model),
+    // ordered by target keyframe so items sharing a target image run close together
+    std::vector<int> order(P);
+    for (int p = 0; p < P; ++p) order[p] = p;
+    auto model_of = [&](int kf) { return c->sensors[c->kfs_h[kf].sensor].model; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int ka = model_of(src[a]) * 2 + model_of(tgt[a]), kb = model_of(src[b]) * 2 + model_of(tgt[b]);
+        if (ka != kb) return ka < kb;
+        return tgt[a] < tgt[b];
+    });
+    std::vector<int32_t> ipair, ipx;
+    c->pair_item_begin.assign(P, 0);
+    c->pair_item_count.assign(P, 0);
+    c->groups.clear();
+    for (int oi = 0; oi < P; ++oi) {
+        const int p = order[oi];
+        const int sm = model_of(src[p]), tm = model_of(tgt[p]);
+        if (c->groups.empty() || c->groups.back().sm != sm || c->groups.back().tm != tm)
+            c->groups.push_back({sm, tm, (int)ipair.size(), 0});
+        const int npx = c->kfs_h[src[p]].H * c->kfs_h[src[p]].W;
+        c->pair_item_begin[p] = (int32_t)ipair.size();
+        for (int px = 0; px < npx; px += c->items_px) {
+            ipair.push_back(p);
+            ipx.push_back(px);
+        }
+        c->pair_item_count[p] = (int32_t)ipair.size() - c->pair_item_begin[p];
+        c->groups.back().count = (int)ipair.size() - c->groups.back().base;
+    }
+    c->n_items = (int)ipair.size();
+    pba_status s;
+    if ((s = upload(c, c->item_pair, ipair.data(), ipair.size() * 4))) return s;
+    if ((s = upload(c, c->item_px0, ipx.data(), ipx.size() * 4))) return s;
+    if ((s = upload(c, c->ibeg, c->pair_item_begin.data(), P * 4))) return s;
+    if ((s = upload(c, c->icnt, c->pair_item_count.data(), P * 4))) return s;
+    if ((s = ensure(c, c->partials, (size_t)std::max(1, c->n_items) * kAcc * sizeof(double)))) return s;
+    if ((s = ensure(c, c->pair_out, (size_t)std::max(1, P) * kPairOut * 8))) return s;
+    if ((s = ensure(c, c->pair_dev, (size_t)std::max(1, P) * sizeof(PairDev)))) return s;
+
+    // assembly plan: contributions of each nonzero 6x6 block, in pair order
+    std::map<std::pair<int, int>, std::vector<int32_t>> blocks;
+    std::vector<std::vector<int32_t>> bk(c->N);
+    for (int p = 0; p < P; ++p) {
+        const int a = src[p], t = tgt[p];
+        blocks[{a, a}].push_back(4 * p + 0);
+        blocks[{a, t}].push_back(4 * p + 1);
+        blocks[{t, a}].push_back(4 * p + 2);
+        blocks[{t, t}].push_back(4 * p + 3);
+        bk[a].push_back(2 * p + 0);
+        bk[t].push_back(2 * p + 1);
+    }
+    std::vector<int2> rc;
+    std::vector<int32_t> ptr(1, 0), ent;
+    for (auto &kv : blocks) {
+        std::vector<int32_t> v = kv.second;
+        std::stable_sort(v.begin(), v.end());
+        rc.push_back(make_int2(kv.first.first, kv.first.second));
+        ent.insert(ent.end(), v.begin(), v.end());
+        ptr.push_back((int32_t)ent.size());
+    }
+    c->nblk = (int)rc.size();
+    std::vector<int32_t> bptr(1, 0), bent;
+    for (int k = 0; k < c->N; ++k) {
+        bent.insert(bent.end(), bk[k].begin(), bk[k].end());
+        bptr.push_back((int32_t)bent.size());
+    }
+    if ((s = upload(c, c->blk_rc, rc.data(), rc.size() * sizeof(int2)))) return s;
+    if ((s = upload(c, c->blk_ptr, ptr.data(), ptr.size() * 4))) return s;
+    if ((s = upload(c, c->blk_ent, ent.data(), ent.size() * 4))) return s;
+    if ((s = upload(c, c->bk_ptr, bptr.data(), bptr.size() * 4))) return s;
+    if ((s = upload(c, c->bk_ent, bent.data(), bent.size() * 4))) return s;
+    if ((s = ensure(c, c->counters, 64 * 4))) return s;
+    return PBA_OK;
+}
+
+EvalArgs make_args(pba_ctx *c)
+{
+    EvalArgs a{};
+    a.sensors = P_<SensorDev>(c->sensors_d);
+    a.kfs = P_<KfDev>(c->kfs_d);
+    a.pairs = P_<PairDev>(c->pair_dev);
+    a.tex4 = P_<float4>(c->tex4);
+    a.tex1 = P_<float>(c->tex1);
+    a.tex2 = P_<float2>(c->tex2);
+    a.lut32 = P_<float2>(c->lut32);
+    a.lut64 = P_<double2>(c->lut64);
+    a.item_pair = P_<int32_t>(c->item_pair);
+    a.item_px0 = P_<int32_t>(c->item_px0);
+    a.items_px = c->items_px;
+    a.partials = c->partials.p;
+    a.omega_g = c->cfg.omega_intensity;
+    a.omega_d = c->cfg.omega_depth;
+    a.omega_n = c->cfg.omega_normal;
+    a.huber = c->cfg.huber_delta;
+    a.refine_band = c->cfg.precision == PBA_F32 ? c->cfg.refine_band : 0.0;
+    return a;
+}
+
+// Evaluate at `poses` into (H, b, totals).  Launch order on the context stream:
+// pair setup (also clears the queue counters) -> persistent evaluation per model group
+// -> ordered per-pair reduction/expansion -> assembly.
+pba_status run_eval(pba_ctx *c, const double *poses, double *H, double *b, double *totals, bool timed)
+{
+    const int ncnt = (int)c->groups.size();
+    launch_pair_setup(poses, P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->sensors_d), P_<KfDev>(c->kfs_d),
+                      P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ncnt, c->stream);
+    EvalArgs a = make_args(c);
+    if (timed) HIP_OK(hipEventRecord(c->ev0, c->stream));
+    for (int g = 0; g < ncnt; ++g) {
+        const auto &G = c->groups[g];
+        a.counter = P_<uint32_t>(c->counters) + g;
+        const int grid = std::max(1, std::min(G.count, c->grid));
+        launch_eval(a, c->cfg.precision, c->cfg.channels, c->cfg.grad_mode, G.sm, G.tm, false, G.base, G.count, grid,
+                    c->stream);
+    }
+    if (timed) HIP_OK(hipEventRecord(c->ev1, c->stream));
+    HIP_OK(hipGetLastError());
+    launch_reduce_pairs(c->partials.p, c->cfg.precision, P_<int32_t>(c->ibeg), P_<int32_t>(c->icnt),
+                        P_<PairDev>(c->pair_dev), P_<double>(c->pair_out), c->P, c->stream);
+    launch_assemble(P_<double>(c->pair_out), c->P, P_<int2>(c->blk_rc), P_<int32_t>(c->blk_ptr),
+                    P_<int32_t>(c->blk_ent), c->nblk, P_<int32_t>(c->bk_ptr), P_<int32_t>(c->bk_ent), c->N, H, b,
+                    totals, c->stream);
+    HIP_OK(hipGetLastError());
+    return PBA_OK;
+}
+
+pba_status accumulate_eval_time(pba_ctx *c)
+{
+    HIP_OK(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->eval_ms += ms;
+    c->eval_launches += 1;
+    return PBA_OK;
+}
+
+pba_status check_ready(pba_ctx *c)
+{
+    if (c->N == 0) return fail(c, PBA_ESTATE, "no keyframes loaded");
+    if (!c->poses_set) return fail(c, PBA_ESTATE, "poses not set");
+    if (c->P == 0) return fail(c, PBA_ESTATE, "pairs not set");
+    return PBA_OK;
+}
+
+pba_status ensure_system(pba_ctx *c)
+{
+    const size_t n = (size_t)n_sys(c);
+    pba_status s;
+    if ((s = ensure(c, c->H, n * n * 8))) return s;
+    if ((s = ensure(c, c->b, n * 8))) return s;
+    if ((s = ensure(c, c->totals, 8 * 8))) return s;
+    if ((s = ensure(c, c->A, n * n * 8))) return s;
+    if ((s = ensure(c, c->dx, n * 8))) return s;
+    if ((s = ensure(c, c->lm, sizeof(LmState)))) return s;
+    if ((s = ensure(c, c->fail, 16))) return s;
+    return PBA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pba_config_default(pba_config *cfg)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->device = 0;
+    cfg->precision = PBA_F32;
+    cfg->channels = 5;
+    cfg->grad_mode = 0;
+    cfg->anchor = 0;
+    cfg->stream = nullptr;
+    cfg->omega_intensity = 1.0;
+    cfg->omega_depth = 1.0;
+    cfg->omega_normal = 1.0;
+    cfg->huber_delta = 0.1;
+    cfg->occlusion_tau_pinhole = 0.5;
+    cfg->occlusion_tau_spherical = 1.0;
+    cfg->refine_band = 2e-3;
+}
+
+const char *pba_status_string(pba_status s)
+{
+    switch (s) {
+    case PBA_OK: return "ok";
+    case PBA_EINVAL: return "invalid argument";
+    case PBA_ENOMEM: return "out of device memory";
+    case PBA_EDEVICE: return "HIP device error";
+    case PBA_ESTATE: return "call out of order";
+    case PBA_ENOTPD: return "system not positive definite";
+    case PBA_ENOVALID: return "no valid correspondence";
+    default: return "unknown status";
+    }
+}
+
+const char *pba_last_error(const pba_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+pba_status pba_create(const pba_config *cfg, pba_ctx **out)
+{
+    if (!cfg || !out) return PBA_EINVAL;
+    *out = nullptr;
+    if (cfg->precision != PBA_F32 && cfg->precision != PBA_F64) return PBA_EINVAL;
+    if (cfg->channels != 2 && cfg->channels != 5) return PBA_EINVAL;
+    if (cfg->grad_mode != 0 && cfg->grad_mode != 1) return PBA_EINVAL;
+    if (cfg->anchor < 0) return PBA_EINVAL;
+    if (!(cfg->refine_band >= 0.0 && cfg->refine_band < 0.5)) return PBA_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return PBA_EDEVICE;
+    if (hipSetDevice(cfg->device) != hipSuccess) return PBA_EDEVICE;
+    pba_ctx *c = new (std::nothrow) pba_ctx;
+    if (!c) return PBA_ENOMEM;
+    c->cfg = *cfg;
+    c->stream = static_cast<hipStream_t>(cfg->stream);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, cfg->device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cu = prop.multiProcessorCount;
+    c->grid = c->num_cu * 4;
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        delete c;
+        return PBA_EDEVICE;
+    }
+    *out = c;
+    return PBA_OK;
+}
+
+pba_status pba_destroy(pba_ctx *c)
+{
+    if (!c) return PBA_EINVAL;
+    (void)hipSetDevice(c->cfg.device);
+    (void)hipStreamSynchronize(c->stream);
+    DevBuf *bufs[] = {&c->sensors_d, &c->kfs_d, &c->tex4, &c->tex1, &c->tex2, &c->lut32, &c->lut64, &c->poses,
+                      &c->poses_cand, &c->pairs_d, &c->pair_dev, &c->item_pair, &c->item_px0, &c->ibeg, &c->icnt,
+                      &c->counters, &c->partials, &c->pair_out, &c->blk_rc, &c->blk_ptr, &c->blk_ent, &c->bk_ptr,
+                      &c->bk_ent, &c->H, &c->b, &c->H_cand, &c->b_cand, &c->totals, &c->A, &c->dx, &c->lm,
+                      &c->fail, &c->logbuf, &c->dbg_status, &c->dbg_uv, &c->dbg_cell, &c->dbg_res};
+    for (DevBuf *b : bufs) release(*b);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+    return PBA_OK;
+}
+
+pba_status pba_add_sensor(pba_ctx *c, const pba_sensor *s, int32_t *sensor_id)
+{
+    if (!c || !s) return fail(c, PBA_EINVAL, "null argument");
+    if (c->N > 0) return fail(c, PBA_ESTATE, "sensors must be added before keyframes are loaded");
+    if (s->model != PBA_PINHOLE && s->model != PBA_SPHERICAL) return fail(c, PBA_EINVAL, "unknown sensor model");
+    // the kernels split a pixel index into (row, col) with a 32-bit reciprocal multiply, exact
+    // while H * W^2 < 2^32
+    if (s->height < 4 || s->width < 4 || (uint64_t)s->height * s->width * s->width >= (1ull << 32))
+        return fail(c, PBA_EINVAL, "image size %d x %d out of range", s->height, s->width);
+    const double v[6] = {s->fx, s->fy, s->cx, s->cy, s->min_depth, s->max_depth};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(c, PBA_EINVAL, "non-finite intrinsics");
+    if (s->fx == 0.0 || s->fy == 0.0) return fail(c, PBA_EINVAL, "zero focal length / resolution");
+    if (!(s->min_depth > 0.0 && s->max_depth > s->min_depth)) return fail(c, PBA_EINVAL, "bad depth interval");
+    if (!pose_ok(s->offset)) return fail(c, PBA_EINVAL, "sensor offset is not a rigid transform");
+    c->sensors.push_back(*s);
+    if (sensor_id) *sensor_id = (int32_t)c->sensors.size() - 1;
+    return PBA_OK;
+}
+
+pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, const float *const *intensity,
+                              const float *const *depth, const float *const *normals, int32_t on_device)
+{
+    if (!c) return PBA_EINVAL;
+    if (n <= 0 || !sensor_id || !intensity || !depth) return fail(c, PBA_EINVAL, "bad keyframe arguments");
+    if (c->sensors.empty()) return fail(c, PBA_ESTATE, "no sensor registered");
+    if (c->cfg.channels == 5 && !normals) return fail(c, PBA_EINVAL, "5 channels need normals");
+    HIP_OK(hipSetDevice(c->cfg.device));
+    std::vector<KfDev> kfs(n);
+    int64_t off = 0;
+    for (int k = 0; k < n; ++k) {
+        const int sid = sensor_id[k];
+        if (sid < 0 || sid >= (int)c->sensors.size()) return fail(c, PBA_EINVAL, "keyframe %d: bad sensor id", k);
+        if (!intensity[k] || !depth[k] || (c->cfg.channels == 5 && !normals[k]))
+            return fail(c, PBA_EINVAL, "keyframe %d: null image", k);
+        kfs[k].sensor = sid;
+        kfs[k].H = c->sensors[sid].height;
+        kfs[k].W = c->sensors[sid].width;
+        kfs[k].off = off;
+        off += (int64_t)kfs[k].H * kfs[k].W;
+    }
+    pba_status s;
+    // sensors and ray tables (FP32 and FP64), computed once per sensor
+    std::vector<SensorDev> sd(c->sensors.size());
+    std::vector<float2> l32;
+    std::vector<double2> l64;
+    for (size_t i = 0; i < c->sensors.size(); ++i) {
+        const pba_sensor &S = c->sensors[i];
+        SensorDev &d = sd[i];
+        d.model = S.model; d.H = S.height; d.W = S.width; d.npx = S.height * S.width;
+        d.magic_w = (uint32_t)(((1ull << 32) + S.width - 1) / S.width);
+        d.fx = (float)S.fx; d.fy = (float)S.fy; d.cx = (float)S.cx; d.cy = (float)S.cy;
+        d.dmin = (float)S.min_depth; d.dmax = (float)S.max_depth;
+        d.fxd = S.fx; d.fyd = S.fy; d.cxd = S.cx; d.cyd = S.cy; d.dmind = S.min_depth; d.dmaxd = S.max_depth;
+        d.taud = S.model == PBA_PINHOLE ? c->cfg.occlusion_tau_pinhole : c->cfg.occlusion_tau_spherical;
+        d.tau = (float)d.taud;
+        for (int k = 0; k < 9; ++k) d.Ro[k] = S.offset[k];
+        for (int k = 0; k < 3; ++k) d.to[k] = S.offset[9 + k];
+        d.lut_col = (int64_t)l32.size();
+        for (int u = 0; u < S.width; ++u) {
+            double x, y;
+            if (S.model == PBA_SPHERICAL) { const double az = (u - S.cx) / S.fx; x = std::cos(az); y = std::sin(az); }
+            else { x = (u - S.cx) / S.fx; y = 0.0; }
+            l32.push_back(make_float2((float)x, (float)y));
+            l64.push_back(make_double2(x, y));
+        }
+        d.lut_row = (int64_t)l32.size();
+        for (int v = 0; v < S.height; ++v) {
+            double x, y;
+            if (S.model == PBA_SPHERICAL) { const double el = (v - S.cy) / S.fy; x = std::cos(el); y = std::sin(el); }
+            else { x = (v - S.cy) / S.fy; y = 0.0; }
+            l32.push_back(make_float2((float)x, (float)y));
+            l64.push_back(make_double2(x, y));
+        }
+    }
+    if ((s = upload(c, c->sensors_d, sd.data(), sd.size() * sizeof(SensorDev)))) return s;
+    if ((s = upload(c, c->lut32, l32.data(), l32.size() * sizeof(float2)))) return s;
+    if ((s = upload(c, c->lut64, l64.data(), l64.size() * sizeof(double2)))) return s;
+    if ((s = upload(c, c->kfs_d, kfs.data(), kfs.size() * sizeof(KfDev)))) return s;
+    if (c->cfg.channels == 5) {
+        if ((s = ensure(c, c->tex4, off * sizeof(float4)))) return s;
+        if ((s = ensure(c, c->tex1, off * sizeof(float)))) return s;
+    } else {
+        if ((s = ensure(c, c->tex2, off * sizeof(float2)))) return s;
+    }
+    // stage each keyframe on the device (copy if host) and pack
+    DevBuf stage;
+    for (int k = 0; k < n; ++k) {
+        const int npx = kfs[k].H * kfs[k].W;
+        const pba_sensor &S = c->sensors[kfs[k].sensor];
+        const float *dI = intensity[k], *dD = depth[k], *dN = c->cfg.channels == 5 ? normals[k] : nullptr;
+        if (!on_device) {
+            const size_t need = (size_t)npx * (c->cfg.channels == 5 ? 5 : 2) * 4;
+            if ((s = ensure(c, stage, need))) { release(stage); return s; }
+            float *base = P_<float>(stage);
+            HIP_OK(hipMemcpyAsync(base, intensity[k], (size_t)npx * 4, hipMemcpyHostToDevice, c->stream));
+            HIP_OK(hipMemcpyAsync(base + npx, depth[k], (size_t)npx * 4, hipMemcpyHostToDevice, c->stream));
+            if (dN) HIP_OK(hipMemcpyAsync(base + 2 * (size_t)npx, normals[k], (size_t)npx * 12, hipMemcpyHostToDevice,
+                                          c->stream));
+            dI = base; dD = base + npx; dN = dN ? base + 2 * (size_t)npx : nullptr;
+        }
+        const int blocks = std::min((npx + 255) / 256, 4096);
+        if (c->cfg.channels == 5)
+            hipLaunchKernelGGL(pack5_kernel, dim3(blocks), dim3(256), 0, c->stream, dI, dD, dN,
+                               P_<float4>(c->tex4) + kfs[k].off, P_<float>(c->tex1) + kfs[k].off, npx,
+                               (float)S.min_depth, (float)S.max_depth);
+        else
+            hipLaunchKernelGGL(pack2_kernel, dim3(blocks), dim3(256), 0, c->stream, dI, dD,
+                               P_<float2>(c->tex2) + kfs[k].off, npx, (float)S.min_depth, (float)S.max_depth);
+        if (!on_device) HIP_OK(hipStreamSynchronize(c->stream));   // stage is reused
+    }
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
+    release(stage);
+    c->kfs_h = kfs;
+    c->sensors_dev_h = sd;
+    c->texels = off;
+    c->N = n;
+    c->P = 0;
+    c->poses_set = false;
+    if ((s = ensure(c, c->poses, (size_t)n * 12 * 8))) return s;
+    if ((s = ensure(c, c->poses_cand, (size_t)n * 12 * 8))) return s;
+    if (c->cfg.anchor >= n) return fail(c, PBA_EINVAL, "anchor %d >= number of keyframes %d", c->cfg.anchor, n);
+    return PBA_OK;
+}
+
+pba_status pba_set_poses(pba_ctx *c, int32_t n, const double *poses, int32_t on_device)
+{
+    if (!c || !poses) return fail(c, PBA_EINVAL, "null argument");
+    if (n != c->N || n == 0) return fail(c, PBA_EINVAL, "expected %d poses, got %d", c->N, n);
+    std::vector<double> h((size_t)n * 12);
+    HIP_OK(hipSetDevice(c->cfg.device));
+    if (on_device) {
+        HIP_OK(hipMemcpyAsync(h.data(), poses, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+    } else {
+        std::memcpy(h.data(), poses, h.size() * 8);
+    }
+    for (int k = 0; k < n; ++k)
+        if (!pose_ok(&h[12 * (size_t)k])) return fail(c, PBA_EINVAL, "pose %d is not finite/orthonormal", k);
+    pba_status s = upload(c, c->poses, h.data(), h.size() * 8);
+    if (s) return s;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->poses_set = true;
+    c->system_valid = false;
+    c->lam_carry = -1.0;
+    return PBA_OK;
+}
+
+pba_status pba_get_poses(pba_ctx *c, double *poses, int32_t on_device)
+{
+    if (!c || !poses) return fail(c, PBA_EINVAL, "null argument");
+    if (!c->poses_set) return fail(c, PBA_ESTATE, "poses not set");
+    HIP_OK(hipSetDevice(c->cfg.device));
+    HIP_OK(hipMemcpyAsync(poses, c->poses.p, (size_t)c->N * 96, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return PBA_OK;
+}
+
+pba_status pba_set_pairs(pba_ctx *c, int32_t p, const int32_t *src, const int32_t *tgt)
+{
+    if (!c || (p > 0 && (!src || !tgt)) || p < 0) return fail(c, PBA_EINVAL, "bad pair arguments");
+    if (c->N == 0) return fail(c, PBA_ESTATE, "no keyframes loaded");
+    HIP_OK(hipSetDevice(c->cfg.device));
+    std::vector<int32_t> s(src, src + p), t(tgt, tgt + p);
+    for (int k = 0; k < p; ++k)
+        if (s[k] < 0 || s[k] >= c->N || t[k] < 0 || t[k] >= c->N)
+            return fail(c, PBA_EINVAL, "pair %d: keyframe id out of range", k);
+    std::vector<int2> pr(p);
+    for (int k = 0; k < p; ++k) pr[k] = make_int2(s[k], t[k]);
+    pba_status st;
+    if ((st = upload(c, c->pairs_d, pr.data(), pr.size() * sizeof(int2)))) return st;
+    if ((st = build_plan(c, s, t))) return st;
+    if ((st = ensure_system(c))) return st;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->P = p;
+    c->system_valid = false;
+    c->lam_carry = -1.0;
+    return PBA_OK;
+}
+
+pba_status pba_evaluate(pba_ctx *c, pba_eval_out *out)
+{
+    if (!c || !out) return fail(c, PBA_EINVAL, "null argument");
+    pba_status s;
+    if ((s = check_ready(c))) return s;
+    HIP_OK(hipSetDevice(c->cfg.device));
+    if ((s = run_eval(c, P_<double>(c->poses), P_<double>(c->H), P_<double>(c->b), P_<double>(c->totals), true)))
+        return s;
+    const size_t n = (size_t)n_sys(c);
+    const hipMemcpyKind k = out->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (out->H) HIP_OK(hipMemcpyAsync(out->H, c->H.p, n * n * 8, k, c->stream));
+    if (out->b) HIP_OK(hipMemcpyAsync(out->b, c->b.p, n * 8, k, c->stream));
+    if (out->pair_out) HIP_OK(hipMemcpyAsync(out->pair_out, c->pair_out.p, (size_t)c->P * kPairOut * 8, k, c->stream));
+    double tot[4];
+    HIP_OK(hipMemcpyAsync(tot, c->totals.p, sizeof tot, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if ((s = accumulate_eval_time(c))) return s;
+    c->system_valid = true;
+    out->F = tot[0];
+    out->n_evaluated = (int64_t)tot[1];
+    out->n_valid = (int64_t)tot[2];
+    out->n_refined = (int64_t)tot[3];
+    return PBA_OK;
+}
+
+pba_status pba_solve_step(pba_ctx *c, double lambda, double *dx, int32_t on_device)
+{
+    if (!c) return PBA_EINVAL;
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(c, PBA_EINVAL, "lambda must be finite and >= 0");
+    pba_status s;
+    if ((s = check_ready(c))) return s;
+    HIP_OK(hipSetDevice(c->cfg.device));
+    const int n = n_sys(c);
+    if (!c->system_valid) {
+        if ((s = run_eval(c, P_<double>(c->poses), P_<double>(c->H), P_<double>(c->b), P_<double>(c->totals),
+                          false)))
+            return s;
+        c->system_valid = true;
+    }
+    launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
+                     P_<LmState>(c->lm), lambda, c->stream);
+    launch_cholesky(P_<double>(c->A), n, P_<int32_t>(c->fail), c->stream);
+    launch_chol_solve(P_<double>(c->A), P_<double>(c->dx), n, P_<int32_t>(c->fail), c->stream);
+    HIP_OK(hipGetLastError());
+    int32_t f = 0;
+    HIP_OK(hipMemcpyAsync(&f, c->fail.p, 4, hipMemcpyDeviceToHost, c->stream));
+    if (dx) HIP_OK(hipMemcpyAsync(dx, c->dx.p, (size_t)n * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (f) return fail(c, PBA_ENOTPD, "damped system is not positive definite (lambda = %g)", lambda);
+    return PBA_OK;
+}
+
+pba_status pba_apply_step(pba_ctx *c, const double *dx, int32_t on_device)
+{
+    if (!c) return PBA_EINVAL;
+    pba_status s;
+    if ((s = check_ready(c))) return s;
+    HIP_OK(hipSetDevice(c->cfg.device));
+    const int n = n_sys(c);
+    if (dx) {
+        std::vector<double> h(n);
+        if (on_device) {
+            HIP_OK(hipMemcpyAsync(h.data(), dx, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+        } else {
+            std::memcpy(h.data(), dx, (size_t)n * 8);
+        }
+        for (double v : h)
+            if (!std::isfinite(v)) return fail(c, PBA_EINVAL, "non-finite step");
+        if ((s = upload(c, c->dx, h.data(), (size_t)n * 8))) return s;
+    }
+    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->N, nullptr, nullptr,
+                   c->stream);
+    launch_copy(P_<double>(c->poses), P_<double>(c->poses_cand), (int64_t)c->N * 12, c->stream);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->system_valid = false;
+    c->lam_carry = -1.0;
+    return PBA_OK;
+}
+
+pba_status pba_iterate(pba_ctx *c, int32_t n_iters, int32_t use_lm, double lambda0, pba_iter_log *log)
+{
+    if (!c) return PBA_EINVAL;
+    if (n_iters < 0) return fail(c, PBA_EINVAL, "negative iteration count");
+    if (use_lm && !(lambda0 >= 0.0 && std::isfinite(lambda0))) return fail(c, PBA_EINVAL, "bad lambda0");
+    pba_status s;
+    if ((s = check_ready(c))) return s;
+    if (n_iters == 0) return PBA_OK;
+    HIP_OK(hipSetDevice(c->cfg.device));
+    const int n = n_sys(c);
+    const size_t nn = (size_t)n * n;
+    if ((s = ensure(c, c->H_cand, nn * 8))) return s;
+    if ((s = ensure(c, c->b_cand, (size_t)n * 8))) return s;
+    if ((s = ensure(c, c->logbuf, (size_t)n_iters * 8 * 8))) return s;
+    double *totals = P_<double>(c->totals);   // [0..3] current, [4..7] candidate
+    // system at the current poses (reused if already evaluated there)
+    if (!c->system_valid) {
+        if ((s = run_eval(c, P_<double>(c->poses), P_<double>(c->H), P_<double>(c->b), totals, false))) return s;
+        c->system_valid = true;
+    }
+    double tot0[4];
+    HIP_OK(hipMemcpyAsync(tot0, totals, sizeof tot0, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    LmState lm{};
+    lm.lam = use_lm ? (lambda0 > 0.0 ? lambda0 : (c->lam_carry > 0.0 ? c->lam_carry : 1e-4)) : 0.0;
+    lm.F_cur = tot0[0];
+    lm.valid_cur = (int64_t)tot0[2];
+    lm.use_lm = use_lm ? 1 : 0;
+    HIP_OK(hipMemcpyAsync(c->lm.p, &lm, sizeof lm, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipEventRecord(c->ev0, c->stream));
+    for (int it = 0; it < n_iters; ++it) {
+        launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
+                         P_<LmState>(c->lm), -1.0, c->stream);
+        launch_cholesky(P_<double>(c->A), n, P_<int32_t>(c->fail), c->stream);
+        launch_chol_solve(P_<double>(c->A), P_<double>(c->dx), n, P_<int32_t>(c->fail), c->stream);
+        launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->N,
+                       P_<int32_t>(c->fail), P_<LmState>(c->lm), c->stream);
+        if ((s = run_eval(c, P_<double>(c->poses_cand), P_<double>(c->H_cand), P_<double>(c->b_cand), totals + 4,
+                          false)))
+            return s;
+        launch_lm_decide(P_<LmState>(c->lm), totals + 4, (int64_t)nn, P_<double>(c->H), P_<double>(c->H_cand),
+                         P_<double>(c->b), P_<double>(c->b_cand), P_<double>(c->poses), P_<double>(c->poses_cand),
+                         c->N, totals, P_<double>(c->logbuf) + 8 * it, c->stream);
+        HIP_OK(hipGetLastError());
+    }
+    HIP_OK(hipEventRecord(c->ev1, c->stream));
+    std::vector<double> lg((size_t)n_iters * 8);
+    HIP_OK(hipMemcpyAsync(lg.data(), c->logbuf.p, lg.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->iterate_ms += ms;
+    c->iterations += n_iters;
+    bool any_fail = false;
+    for (int it = 0; it < n_iters; ++it) {
+        const double *r = &lg[8 * (size_t)it];
+        if (log) {
+            log[it].F = r[0];
+            log[it].lambda = r[1];
+            log[it].step_norm = r[2];
+            log[it].n_valid = (int64_t)r[3];
+            log[it].accepted = r[4] != 0.0;
+            log[it].pad = 0;
+        }
+        if (r[5] != 0.0) any_fail = true;
+    }
+    if (use_lm) c->lam_carry = lg[8 * (size_t)(n_iters - 1) + 1];
+    if (any_fail && !use_lm) return fail(c, PBA_ENOTPD, "Gauss-Newton system not positive definite");
+    return PBA_OK;
+}
+
+pba_status pba_debug_pair(pba_ctx *c, int32_t pair, uint8_t *status, float *uv, int32_t *cell, float *residuals)
+{
+    if (!c) return PBA_EINVAL;
+    pba_status s;
+    if ((s = check_ready(c))) return s;
+    if (pair < 0 || pair >= c->P) return fail(c, PBA_EINVAL, "pair %d out of range", pair);
+    HIP_OK(hipSetDevice(c->cfg.device));
+    // pair transforms at the current poses
+    launch_pair_setup(P_<double>(c->poses), P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->sensors_d),
+                      P_<KfDev>(c->kfs_d), P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), 64, c->stream);
+    int2 pr;
+    HIP_OK(hipMemcpyAsync(&pr, P_<int2>(c->pairs_d) + pair, sizeof pr, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    const KfDev &ks = c->kfs_h[pr.x], &kt = c->kfs_h[pr.y];
+    const int npx = ks.H * ks.W;
+    if ((s = ensure(c, c->dbg_status, npx))) return s;
+    if ((s = ensure(c, c->dbg_uv, (size_t)npx * 8))) return s;
+    if ((s = ensure(c, c->dbg_cell, (size_t)npx * 8))) return s;
+    if ((s = ensure(c, c->dbg_res, (size_t)npx * 20))) return s;
+    launch_fill(P_<double>(c->dbg_res), (int64_t)npx * 20 / 8, 0.0, c->stream);
+    EvalArgs a = make_args(c);
+    a.counter = P_<uint32_t>(c->counters);
+    a.dbg_status = P_<uint8_t>(c->dbg_status);
+    a.dbg_uv = P_<float2>(c->dbg_uv);
+    a.dbg_cell = P_<int2>(c->dbg_cell);
+    a.dbg_res = P_<float>(c->dbg_res);
+    const int sm = c->sensors[ks.sensor].model, tm = c->sensors[kt.sensor].model;
+    const int base = c->pair_item_begin[pair], cnt = c->pair_item_count[pair];
+    launch_eval(a, c->cfg.precision, c->cfg.channels, c->cfg.grad_mode, sm, tm, true, base, cnt,
+                std::max(1, std::min(cnt, c->grid)), c->stream);
+    HIP_OK(hipGetLastError());
+    if (status) HIP_OK(hipMemcpyAsync(status, c->dbg_status.p, npx, hipMemcpyDeviceToHost, c->stream));
+    if (uv) HIP_OK(hipMemcpyAsync(uv, c->dbg_uv.p, (size_t)npx * 8, hipMemcpyDeviceToHost, c->stream));
+    if (cell) HIP_OK(hipMemcpyAsync(cell, c->dbg_cell.p, (size_t)npx * 8, hipMemcpyDeviceToHost, c->stream));
+    if (residuals) HIP_OK(hipMemcpyAsync(residuals, c->dbg_res.p, (size_t)npx * 20, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return PBA_OK;
+}
+
+pba_status pba_get_timings(pba_ctx *c, pba_timings *out, int32_t reset)
+{
+    if (!c || !out) return fail(c, PBA_EINVAL, "null argument");
+    out->eval_ms = c->eval_ms;
+    out->eval_launches = c->eval_launches;
+    out->iterate_ms = c->iterate_ms;
+    out->iterations = c->iterations;
+    out->n_items = c->n_items;
+    out->items_px = c->items_px;
+    out->grid = c->grid;
+    if (reset) {
+        c->eval_ms = c->iterate_ms = 0.0;
+        c->eval_launches = c->iterations = 0;
+    }
+    return PBA_OK;
+}
+
+}  // extern "C"

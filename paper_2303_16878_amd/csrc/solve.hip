@@ -1,0 +1,371 @@
+// FP64 solve and update kernels: gauge fix and Levenberg-Marquardt damping, blocked
+// Cholesky factorisation of the dense 6N x 6N system, the two triangular solves, the
+// pose update X <- X exp(dx) (Supplementary: exp(dx) = [R(dq), dt], R(dq) the rotation
+// of the unit quaternion with imaginary part dq) and the device-side accept/reject of a
+// step, so that a whole iteration runs without returning to the host.
+
+#include "pba_internal.h"
+
+namespace pba {
+
+constexpr int NB = 64;   // Cholesky block size
+
+// A = gauge-fixed H with Marquardt damping, rhs = -b (anchor rows zero).
+// lam_override >= 0 replaces the device-side lambda (direct solve calls).
+__global__ void damp_copy_kernel(const double *__restrict__ H, const double *__restrict__ b,
+                                 double *__restrict__ A, double *__restrict__ rhs, int n, int anchor,
+                                 const LmState *lm, double lam_override)
+{
+    const double lam = lam_override >= 0.0 ? lam_override : lm->lam;
+    const int a0 = 6 * anchor, a1 = a0 + 6;
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+        const bool ai = i >= a0 && i < a1, aj = j >= a0 && j < a1;
+        double v = H[e];
+        if (ai || aj) v = (i == j) ? 1.0 : 0.0;
+        if (i == j) v += lam * v;
+        A[e] = v;
+        if (j == 0) rhs[i] = ai ? 0.0 : -b[i];
+    }
+}
+
+void launch_damp_copy(const double *H, const double *b, double *A, double *rhs, int n, int anchor,
+                      const LmState *lm, double lam_override, hipStream_t st)
+{
+    int64_t nn = (int64_t)n * n;
+    int64_t blocks = (nn + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(damp_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st, H, b, A, rhs, n, anchor, lm,
+                       lam_override);
+}
+
+// ---- blocked right-looking Cholesky, lower triangle, A row-major n x n
+
+// Factor the diagonal block at k0 in LDS (one workgroup).
+__global__ void __launch_bounds__(256) chol_diag_kernel(double *A, int n, int k0, int32_t *fail)
+{
+    __shared__ double L[NB][NB + 1];
+    const int nb = min(NB, n - k0);
+    const int tid = threadIdx.x;
+    if (*fail) return;
+    for (int e = tid; e < nb * nb; e += blockDim.x) {
+        const int i = e / nb, j = e % nb;
+        L[i][j] = A[(int64_t)(k0 + i) * n + k0 + j];
+    }
+    __syncthreads();
+    __shared__ int bad;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (tid == 0) {
+            const double d = L[j][j];
+            if (!(d > 0.0)) bad = 1;
+            L[j][j] = d > 0.0 ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        const double ljj = L[j][j];
+        for (int i = j + 1 + tid; i < nb; i += blockDim.x) L[i][j] /= ljj;
+        __syncthreads();
+        // trailing update within the block: L[i][k] -= L[i][j] L[k][j], j < k <= i
+        const int m = nb - j - 1;
+        for (int e = tid; e < m * m; e += blockDim.x) {
+            const int i = j + 1 + e / m, k = j + 1 + e % m;
+            if (k <= i) L[i][k] -= L[i][j] * L[k][j];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < nb * nb; e += blockDim.x) {
+        const int i = e / nb, j = e % nb;
+        if (j <= i) A[(int64_t)(k0 + i) * n + k0 + j] = L[i][j];
+    }
+    if (tid == 0 && bad) *fail = 1;
+}
+
+// Panel below the diagonal block: X L_kk^T = A_ik (one row per thread, 64 rows per workgroup).
+__global__ void __launch_bounds__(64) chol_trsm_kernel(double *A, int n, int k0, const int32_t *fail)
+{
+    __shared__ double L[NB][NB + 1];
+    __shared__ double X[NB][NB + 1];
+    if (*fail) return;
+    const int nb = min(NB, n - k0);
+    const int tid = threadIdx.x;
+    const int r0 = k0 + nb + blockIdx.x * NB;
+    const int rows = min(NB, n - r0);
+    for (int e = tid; e < nb * nb; e += blockDim.x) {
+        const int i = e / nb, j = e % nb;
+        L[i][j] = A[(int64_t)(k0 + i) * n + k0 + j];
+    }
+    for (int e = tid; e < rows * nb; e += blockDim.x) {
+        const int i = e / nb, j = e % nb;
+        X[i][j] = A[(int64_t)(r0 + i) * n + k0 + j];
+    }
+    __syncthreads();
+    if (tid < rows) {
+        for (int j = 0; j < nb; ++j) {
+            double s = X[tid][j];
+            for (int m = 0; m < j; ++m) s -= X[tid][m] * L[j][m];
+            X[tid][j] = s / L[j][j];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < rows * nb; e += blockDim.x) {
+        const int i = e / nb, j = e % nb;
+        A[(int64_t)(r0 + i) * n + k0 + j] = X[i][j];
+    }
+}
+
+// Trailing update A_ij -= L_i L_j^T for block pairs i >= j below the panel.
+__global__ void __launch_bounds__(256) chol_update_kernel(double *A, int n, int k0, const int32_t *fail)
+{
+    __shared__ double Li[NB][NB + 1];
+    __shared__ double Lj[NB][NB + 1];
+    if (*fail) return;
+    const int nb = min(NB, n - k0);
+    const int t0 = k0 + nb;
+    // blockIdx.x -> (bi, bj) with bi >= bj over the trailing blocks
+    const int idx = blockIdx.x;
+    int bi = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= idx) ++bi;
+    while (bi * (bi + 1) / 2 > idx) --bi;
+    const int bj = idx - bi * (bi + 1) / 2;
+    const int ri = t0 + bi * NB, rj = t0 + bj * NB;
+    const int ni = min(NB, n - ri), nj = min(NB, n - rj);
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, k = e % NB;
+        Li[i][k] = (i < ni && k < nb) ? A[(int64_t)(ri + i) * n + k0 + k] : 0.0;
+        Lj[i][k] = (i < nj && k < nb) ? A[(int64_t)(rj + i) * n + k0 + k] : 0.0;
+    }
+    __syncthreads();
+    const int tx = tid & 15, ty = tid >> 4;
+    double c[4][4];
+    for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 4; ++q) c[a][q] = 0.0;
+    for (int k = 0; k < nb; ++k) {
+        double li[4], lj[4];
+        for (int a = 0; a < 4; ++a) li[a] = Li[ty * 4 + a][k];
+        for (int q = 0; q < 4; ++q) lj[q] = Lj[tx * 4 + q][k];
+        for (int a = 0; a < 4; ++a)
+            for (int q = 0; q < 4; ++q) c[a][q] += li[a] * lj[q];
+    }
+    for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 4; ++q) {
+            const int i = ty * 4 + a, j = tx * 4 + q;
+            if (i < ni && j < nj && (bi != bj || j <= i)) A[(int64_t)(ri + i) * n + rj + j] -= c[a][q];
+        }
+}
+
+__global__ void reset_flag_kernel(int32_t *f) { *f = 0; }
+
+void launch_cholesky(double *A, int n, int32_t *fail, hipStream_t st)
+{
+    hipLaunchKernelGGL(reset_flag_kernel, dim3(1), dim3(1), 0, st, fail);
+    for (int k0 = 0; k0 < n; k0 += NB) {
+        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, A, n, k0, fail);
+        const int rest = n - k0 - NB;
+        if (rest > 0) {
+            const int nbr = (rest + NB - 1) / NB;
+            hipLaunchKernelGGL(chol_trsm_kernel, dim3(nbr), dim3(64), 0, st, A, n, k0, fail);
+            hipLaunchKernelGGL(chol_update_kernel, dim3(nbr * (nbr + 1) / 2), dim3(256), 0, st, A, n, k0, fail);
+        }
+    }
+}
+
+// L y = rhs, then L^T x = y, in place on x (one workgroup of 1024 threads).
+__global__ void __launch_bounds__(1024) chol_solve_kernel(const double *__restrict__ L, double *__restrict__ x,
+                                                          int n, const int32_t *fail)
+{
+    __shared__ double yb[NB];
+    const int tid = threadIdx.x;
+    if (*fail) {
+        for (int i = tid; i < n; i += blockDim.x) x[i] = 0.0;
+        return;
+    }
+    const int nblk = (n + NB - 1) / NB;
+    // forward: right-looking over column blocks
+    for (int kb = 0; kb < nblk; ++kb) {
+        const int k0 = kb * NB, nb = min(NB, n - k0);
+        if (tid < 64) {
+            double v = tid < nb ? x[k0 + tid] : 0.0;
+            for (int j = 0; j < nb; ++j) {
+                double yj = __shfl(v, j, 64);
+                yj /= L[(int64_t)(k0 + j) * n + k0 + j];
+                if (tid == j) v = yj;
+                if (tid > j && tid < nb) v -= L[(int64_t)(k0 + tid) * n + k0 + j] * yj;
+            }
+            if (tid < nb) { x[k0 + tid] = v; yb[tid] = v; }
+        }
+        __syncthreads();
+        for (int i = k0 + nb + tid; i < n; i += blockDim.x) {
+            const double *Lr = L + (int64_t)i * n + k0;
+            double s = 0.0;
+            for (int j = 0; j < nb; ++j) s += Lr[j] * yb[j];
+            x[i] -= s;
+        }
+        __syncthreads();
+    }
+    // backward: L^T x = y, last block first
+    for (int kb = nblk - 1; kb >= 0; --kb) {
+        const int k0 = kb * NB, nb = min(NB, n - k0);
+        if (tid < 64) {
+            double v = tid < nb ? x[k0 + tid] : 0.0;
+            for (int j = nb - 1; j >= 0; --j) {
+                double xj = __shfl(v, j, 64);
+                xj /= L[(int64_t)(k0 + j) * n + k0 + j];
+                if (tid == j) v = xj;
+                if (tid < j) v -= L[(int64_t)(k0 + j) * n + k0 + tid] * xj;
+            }
+            if (tid < nb) { x[k0 + tid] = v; yb[tid] = v; }
+        }
+        __syncthreads();
+        for (int i = tid; i < k0; i += blockDim.x) {
+            double s = 0.0;
+            for (int j = 0; j < nb; ++j) s += L[(int64_t)(k0 + j) * n + i] * yb[j];
+            x[i] -= s;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_chol_solve(const double *L, double *x, int n, const int32_t *fail, hipStream_t st)
+{
+    hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(1024), 0, st, L, x, n, fail);
+}
+
+// ---- pose update
+
+__device__ static void quat_rot(double qx, double qy, double qz, double *R)
+{
+    double n2 = qx * qx + qy * qy + qz * qz, w;
+    if (n2 < 1.0) {
+        w = sqrt(1.0 - n2);
+    } else {
+        const double s = 1.0 / sqrt(1.0 + n2);
+        w = s; qx *= s; qy *= s; qz *= s;
+    }
+    R[0] = 1 - 2 * (qy * qy + qz * qz); R[1] = 2 * (qx * qy - qz * w);     R[2] = 2 * (qx * qz + qy * w);
+    R[3] = 2 * (qx * qy + qz * w);     R[4] = 1 - 2 * (qx * qx + qz * qz); R[5] = 2 * (qy * qz - qx * w);
+    R[6] = 2 * (qx * qz - qy * w);     R[7] = 2 * (qy * qz + qx * w);     R[8] = 1 - 2 * (qx * qx + qy * qy);
+}
+
+// Xout_k = X_k exp(dx_k); also the step norm into lm (one workgroup reduces it).
+__global__ void __launch_bounds__(256) boxplus_kernel(const double *__restrict__ X, const double *__restrict__ dx,
+                                                      double *__restrict__ Xo, int N, const int32_t *fail,
+                                                      LmState *lm)
+{
+    const int tid = threadIdx.x;
+    const bool f = fail && *fail;
+    __shared__ double red[256];
+    double ss = 0.0;
+    for (int k = tid; k < N; k += blockDim.x) {
+        const double *x = X + 12 * (int64_t)k;
+        double *o = Xo + 12 * (int64_t)k;
+        if (f) {
+            for (int i = 0; i < 12; ++i) o[i] = x[i];
+            continue;
+        }
+        const double *d = dx + 6 * (int64_t)k;
+        for (int i = 0; i < 6; ++i) ss += d[i] * d[i];
+        double E[9];
+        quat_rot(d[3], d[4], d[5], E);
+        double R[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) R[3 * i + j] = x[3 * i] * E[j] + x[3 * i + 1] * E[3 + j] + x[3 * i + 2] * E[6 + j];
+        for (int i = 0; i < 3; ++i) o[9 + i] = x[9 + i] + x[3 * i] * d[0] + x[3 * i + 1] * d[1] + x[3 * i + 2] * d[2];
+        for (int i = 0; i < 9; ++i) o[i] = R[i];
+    }
+    red[tid] = ss;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0 && lm) {
+        lm->step_norm = sqrt(red[0]);
+        lm->fail = f ? 1 : 0;
+    }
+}
+
+void launch_boxplus(const double *X, const double *dx, double *Xout, int N, const int32_t *fail, LmState *lm,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(boxplus_kernel, dim3(1), dim3(256), 0, st, X, dx, Xout, N, fail, lm);
+}
+
+// Accept/reject the candidate: totals_cand = {F, evaluated, valid, refined} at the candidate
+// poses.  Gauss-Newton (use_lm = 0) accepts every solved step; LM accepts if F decreases.
+// On accept the candidate system, gradient and poses become current.  Writes one log row
+// {F, lambda, step_norm, valid, accepted}.
+__global__ void __launch_bounds__(256) lm_decide_kernel(LmState *lm, const double *__restrict__ totals_cand,
+                                                        int64_t nH, double *H_cur, const double *H_cand,
+                                                        double *b_cur, const double *b_cand, int nb,
+                                                        double *X_cur, const double *X_cand, int nX,
+                                                        double *log_row)
+{
+    __shared__ int acc;
+    const double Fc = totals_cand[0];
+    const bool solved = !lm->fail;
+    const bool accept = solved && (!lm->use_lm || Fc < lm->F_cur);
+    if (threadIdx.x == 0) acc = accept;
+    __syncthreads();
+    if (acc) {
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nH; e += stride) H_cur[e] = H_cand[e];
+        for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nb; e += stride) b_cur[e] = b_cand[e];
+        for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nX; e += stride) X_cur[e] = X_cand[e];
+    }
+}
+
+// Scalar part of the decision, run after the copies (single thread).
+__global__ void lm_finish_kernel(LmState *lm, const double *__restrict__ totals_cand, double *totals_cur,
+                                 double *log_row)
+{
+    const double Fc = totals_cand[0];
+    const bool solved = !lm->fail;
+    const bool accept = solved && (!lm->use_lm || Fc < lm->F_cur);
+    if (accept) {
+        for (int k = 0; k < 4; ++k) totals_cur[k] = totals_cand[k];
+        lm->F_cur = Fc;
+        lm->valid_cur = (int64_t)totals_cand[2];
+        if (lm->use_lm) lm->lam = fmax(lm->lam / 10.0, 1e-12);
+    } else if (lm->use_lm) {
+        lm->lam *= 10.0;
+    }
+    lm->accepted = accept;
+    log_row[0] = lm->F_cur;
+    log_row[1] = lm->use_lm ? lm->lam : 0.0;
+    log_row[2] = solved ? lm->step_norm : 0.0;
+    log_row[3] = (double)lm->valid_cur;
+    log_row[4] = accept ? 1.0 : 0.0;
+    log_row[5] = solved ? 0.0 : 1.0;
+    lm->iter += 1;
+}
+
+void launch_lm_decide(LmState *lm, const double *totals_cand, int64_t nH, double *H_cur, const double *H_cand,
+                      double *b_cur, const double *b_cand, double *X_cur, const double *X_cand, int N,
+                      double *totals_cur, double *log_row, hipStream_t st)
+{
+    int64_t blocks = (nH + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(lm_decide_kernel, dim3((unsigned)blocks), dim3(256), 0, st, lm, totals_cand, nH, H_cur, H_cand,
+                       b_cur, b_cand, 6 * N, X_cur, X_cand, 12 * N, log_row);
+    hipLaunchKernelGGL(lm_finish_kernel, dim3(1), dim3(1), 0, st, lm, totals_cand, totals_cur, log_row);
+}
+
+__global__ void copy_kernel(double *__restrict__ dst, const double *__restrict__ src, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dst, src, n);
+}
+
+}  // namespace pba

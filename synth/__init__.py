@@ -451,7 +451,9 @@ def lidar_loop(name, seed, H, W, n_kf, radius=30.0, n_struct=5000, length=2000.0
     d = np.linalg.norm(pos[:, None] - pos[None], axis=2)
     pairs = np.array([(i, j) for i in range(n_kf) for j in range(n_kf) if i != j and d[i, j] < radius],
                      np.int32)
-    init = _perturb(gt, np.random.default_rng(100 + seed), 0.1, 3.0)
+    # 0.05 m / 1 deg: inside the single-resolution photometric basin at 128x2048 (a 3 deg start
+    # stalls without a coarse-to-fine pyramid)
+    init = _perturb(gt, np.random.default_rng(100 + seed), 0.05, 1.0)
     params = dict(DEFAULT_PARAMS, channels=5, iterations=10, lm=True)
     scene = dict(rects=rects, ground=1, ground_tex=_random_texture(rng), noise_i=0.01, noise_d=0.01,
                  seed=seed)

@@ -1,0 +1,230 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded inputs.
+
+Sizes: the 160x120 RGB-D set (19200 px per keyframe: 2 work items, the second one ragged) and
+3-keyframe 48x768 LiDAR sets (36864 px: 3 items, ragged tail), both through every pair; then the
+full 640x480 RGB-D and 128x2048 LiDAR configurations in the launch configuration bench.py uses,
+on sampled pairs.  Tolerances: masks exact outside the 1e-4 px band (counted); H/b within 1e-5
+relative (FP32 path), 1e-9 (FP64 path); poses after iterating within 1e-6 m / 1e-6 rad.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import compare_pair_masks, compare_pair_sums, forced_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pba():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2303_16878_amd as pba
+    pba.load_library()
+    return pba
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [
+    ("rgbd_small", "F64", 2, 0),
+    ("rgbd_small", "F32", 2, 0),
+    ("rgbd_small", "F32", 5, 0),
+    ("rgbd_small", "F32", 5, 1),
+    ("lidar_mini", "F32", 5, 0),
+    ("lidar_mini", "F64", 5, 0),
+    ("lidar_mini", "F32", 5, 1),
+    ("lidar_mini", "F32", 2, 0),
+]
+
+
+@pytest.mark.parametrize("fixture,prec,ch,gm", CASES)
+def test_pairs_match_oracle(fixture, prec, ch, gm, request, pba):
+    prob = request.getfixturevalue(fixture)
+    params = dict(prob.params, channels=ch)
+    precision = pba.PBA_F64 if prec == "F64" else pba.PBA_F32
+    _log("case", fixture, prec, ch, gm)
+    with pba.context_for_problem(prob, precision=precision, channels=ch, grad_mode=gm) as ctx:
+        ev = ctx.evaluate(want_system=True, want_pairs=True)
+        tol = 1e-9 if prec == "F64" else 1e-5
+        tot_band = 0
+        for k in range(len(prob.pairs)):
+            m = compare_pair_masks(ctx, prob, prob.init_poses, k, params=params, grad_mode=gm)
+            assert m["n_bad"] == 0, (k, m["n_mismatch"], m["bad_idx"])
+            assert m["n_code"] == 0, k
+            tot_band += m["n_band"]
+            if prec == "F64":
+                assert m["n_mismatch"] == 0
+            fo = forced_oracle(prob, prob.init_poses, k, m["gpu"], params=params, grad_mode=gm)
+            c = compare_pair_sums(ev["pairs"][k], fo, tol)
+            assert c["ok"], (k, c)
+        _log("  band mismatches", tot_band, "refined", ev["n_refined"], "valid", ev["n_valid"])
+        # the assembled system against the oracle's own assembly (unforced)
+        o = oracle.evaluate(prob, prob.init_poses, params, grad_mode=gm)
+        assert ev["n_evaluated"] == o["n_eval"]
+        if prec == "F64":
+            assert ev["n_valid"] == o["n_valid"]
+            sc = np.abs(o["H"]).max()
+            assert np.abs(ev["H"] - o["H"]).max() <= 1e-9 * sc
+            np.testing.assert_allclose(ev["F"], o["F"], rtol=1e-10)
+        assert np.array_equal(ev["H"], ev["H"].T)
+
+
+def test_evaluation_is_deterministic(lidar_mini, pba):
+    with pba.context_for_problem(lidar_mini) as ctx:
+        a = ctx.evaluate(want_system=True, want_pairs=True)
+        b = ctx.evaluate(want_system=True, want_pairs=True)
+        assert np.array_equal(a["pairs"], b["pairs"]) and np.array_equal(a["H"], b["H"])
+        assert a["F"] == b["F"]
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_solve_step_matches_dense_solve(rgbd_small, prec, pba):
+    precision = pba.PBA_F64 if prec == "F64" else pba.PBA_F32
+    with pba.context_for_problem(rgbd_small, precision=precision) as ctx:
+        ev = ctx.evaluate(want_system=True)
+        for lam in (0.0, 1e-3):
+            dx = ctx.solve_step(lam)
+            ref, ok = oracle.solve_step(ev["H"], ev["b"], lam, anchor=0)
+            assert ok
+            assert np.abs(dx - ref).max() <= 1e-8 * np.abs(ref).max()
+        # apply it and compare with the oracle's boxplus
+        X0 = ctx.get_poses()
+        ctx.apply_step()
+        np.testing.assert_allclose(ctx.get_poses(), oracle.boxplus(X0, dx), atol=1e-14)
+
+
+def _pose_err(A, B):
+    dt = np.abs(A[:, 9:] - B[:, 9:]).max()
+    dr = 0.0
+    for a, b in zip(A, B):
+        Ra, Rb = a[:9].reshape(3, 3), b[:9].reshape(3, 3)
+        c = np.clip((np.trace(Ra.T @ Rb) - 1) / 2, -1, 1)
+        dr = max(dr, math.acos(c) if c < 1 else 0.0)
+    return dt, dr
+
+
+def test_gauss_newton_iterations_match_oracle(rgbd_small, pba):
+    prob = rgbd_small
+    X_or, log_or = oracle.optimize(prob, prob.init_poses, iters=10, lm=False)
+    finals = {}
+    for prec in ("F64", "F32"):
+        precision = pba.PBA_F64 if prec == "F64" else pba.PBA_F32
+        with pba.context_for_problem(prob, precision=precision) as ctx:
+            logs = ctx.iterate(10, use_lm=False)
+            X = ctx.get_poses()
+        dt, dr = _pose_err(X, X_or)
+        _log(prec, "GN pose diff vs oracle: %.3g m %.3g rad" % (dt, dr), "F", logs[-1]["F"], log_or[-1]["F"])
+        if prec == "F64":
+            assert dt < 1e-6 and dr < 1e-6
+            for lg, lo in zip(logs, log_or):
+                assert abs(lg["F"] - lo["F"]) <= 1e-8 * lo["F"]
+        finals[prec] = oracle.ate_rmse(X, prob.gt_poses)
+    assert abs(finals["F32"] - finals["F64"]) < 1e-6
+    assert finals["F64"] < oracle.ate_rmse(prob.init_poses, prob.gt_poses) / 20
+
+
+def test_levenberg_marquardt_matches_oracle(lidar_mini, pba):
+    prob = lidar_mini
+    X_or, log_or = oracle.optimize(prob, prob.init_poses, iters=6, lm=True, lam0=1e-4)
+    with pba.context_for_problem(prob, precision=pba.PBA_F64) as ctx:
+        logs = ctx.iterate(6, use_lm=True, lambda0=1e-4)
+        X = ctx.get_poses()
+    assert [l["accepted"] for l in logs] == [l["accepted"] for l in log_or]
+    dt, dr = _pose_err(X, X_or)
+    _log("LM pose diff vs oracle: %.3g m %.3g rad" % (dt, dr))
+    assert dt < 1e-6 and dr < 1e-6
+    for lg, lo in zip(logs, log_or):
+        assert abs(lg["F"] - lo["F"]) <= 1e-8 * lo["F"]
+        assert abs(lg["lam"] - lo["lam"]) <= 1e-12 * max(lo["lam"], 1e-300)
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_identity_pair_and_invalid_keyframe(rgbd_small, pba):
+    prob = synth.Problem(rgbd_small.name, rgbd_small.sensors, np.zeros(3, np.int32), rgbd_small.gt_poses[:3].copy(),
+                         rgbd_small.init_poses[:3].copy(), np.array([[0, 0], [1, 2], [2, 1], [0, 1]], np.int32),
+                         dict(rgbd_small.params))
+    prob.intensity = list(rgbd_small.intensity[:3])
+    prob.depth = [rgbd_small.depth[0], np.zeros_like(rgbd_small.depth[1]), rgbd_small.depth[2]]
+    prob.normals = list(rgbd_small.normals[:3])
+    for precision in (pba.PBA_F32, pba.PBA_F64):
+        with pba.context_for_problem(prob, precision=precision) as ctx:
+            ev = ctx.evaluate(want_pairs=True)
+            po = ev["pairs"]
+            assert po[0, 158] > 0 and abs(po[0, 156]) < 1e-6 * po[0, 158]     # identity pair: e == 0
+            assert po[1, 157] == 0 and po[1, 158] == 0                         # source without depth
+            assert po[2, 158] == 0 and po[2, 157] > 0                          # target without depth
+            for k in range(len(prob.pairs)):
+                m = compare_pair_masks(ctx, prob, prob.init_poses, k)
+                assert m["n_bad"] == 0, (precision, k, m["n_mismatch"], m["bad_idx"])
+
+
+def test_error_paths(rgbd_small, pba):
+    prob = rgbd_small
+    ctx = pba.Context(channels=2)
+    s = prob.sensors[0]
+    with pytest.raises(pba.PbaError) as e:
+        ctx.add_sensor(7, s["H"], s["W"], s["fx"], s["fy"], s["cx"], s["cy"], 0.1, 10.0)
+    assert e.value.status == pba.PBA_EINVAL
+    ctx.add_sensor(s["model"], s["H"], s["W"], s["fx"], s["fy"], s["cx"], s["cy"], s["min_depth"], s["max_depth"])
+    with pytest.raises(pba.PbaError) as e:
+        ctx.evaluate()
+    assert e.value.status == pba.PBA_ESTATE
+    ctx.load_keyframes(prob.kf_sensor, prob.intensity, prob.depth)
+    with pytest.raises(pba.PbaError) as e:
+        ctx.evaluate()
+    assert e.value.status == pba.PBA_ESTATE
+    bad = prob.init_poses.copy()
+    bad[2, 0] = np.nan
+    with pytest.raises(pba.PbaError) as e:
+        ctx.set_poses(bad)
+    assert e.value.status == pba.PBA_EINVAL
+    bad = prob.init_poses.copy()
+    bad[1, :9] *= 1.01
+    with pytest.raises(pba.PbaError):
+        ctx.set_poses(bad)
+    ctx.set_poses(prob.init_poses)
+    with pytest.raises(pba.PbaError) as e:
+        ctx.set_pairs(np.array([[0, 5]]))
+    assert e.value.status == pba.PBA_EINVAL
+    with pytest.raises(pba.PbaError) as e:
+        ctx.evaluate()
+    assert e.value.status == pba.PBA_ESTATE
+    ctx.set_pairs(prob.pairs)
+    ev = ctx.evaluate()
+    assert ev["n_valid"] > 0
+    with pytest.raises(pba.PbaError) as e:
+        ctx.solve_step(-1.0)
+    assert e.value.status == pba.PBA_EINVAL
+    with pytest.raises(pba.PbaError) as e:
+        ctx.debug_pair(len(prob.pairs), (s["H"], s["W"]))
+    assert e.value.status == pba.PBA_EINVAL
+    ctx.close()
+
+
+# ---------------------------------------------------------------- full-size configurations, sampled pairs
+
+@pytest.mark.parametrize("name,sample", [("rgbd_room", [0, 17, 333, 640, 999]),
+                                         ("lidar128", [0, 401, 1202, 1800, 2405])])
+def test_full_size_sampled_pairs(name, sample, pba):
+    prob = synth.make(name)
+    _log("generated", name, prob.n, "keyframes", len(prob.pairs), "pairs")
+    with pba.context_for_problem(prob) as ctx:
+        ev = ctx.evaluate(want_pairs=True)
+        _log("  valid", ev["n_valid"], "of", ev["n_evaluated"], "refined", ev["n_refined"])
+        for k in sample:
+            m = compare_pair_masks(ctx, prob, prob.init_poses, k)
+            assert m["n_bad"] == 0, (k, m["n_mismatch"], m["bad_idx"])
+            fo = forced_oracle(prob, prob.init_poses, k, m["gpu"])
+            c = compare_pair_sums(ev["pairs"][k], fo, 1e-5)
+            _log("  pair", k, "band", m["n_band"], "H err %.2e b err %.2e" % (c["H"], c["b"]))
+            assert c["ok"], (k, c)

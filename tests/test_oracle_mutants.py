@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 import synth
+from test_oracle_pins import fd_grad_F
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "pba_oracle.c")
 
@@ -37,15 +38,7 @@ def _fd_ok(p, prm):
     X = p.init_poses
     r = oracle.eval_pair(p, X, 1, 0, prm, grad_mode=1)
     g = 2 * r["b12"]
-    fd = np.zeros(12)
-    h = 1e-8
-    for k in range(12):
-        dx = np.zeros(6 * p.n)
-        dx[6 + k if k < 6 else k - 6] = h
-        Fp = oracle.eval_pair(p, oracle.boxplus(X, dx), 1, 0, prm, grad_mode=1)["F"]
-        dx[6 + k if k < 6 else k - 6] = -h
-        Fm = oracle.eval_pair(p, oracle.boxplus(X, dx), 1, 0, prm, grad_mode=1)["F"]
-        fd[k] = (Fp - Fm) / (2 * h)
+    fd, _ = fd_grad_F(p, X, 1, 0, prm)
     return np.abs(g - fd).max() < 2e-5 * np.abs(fd).max()
 
 
