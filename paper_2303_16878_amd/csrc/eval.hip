@@ -191,15 +191,30 @@ struct Lut<double> {
     __device__ static const double2 *ptr(const EvalArgs &a) { return a.lut64; }
 };
 
+// Per-wave queue of valid correspondences found by phase 1, consumed by phase 2.
+// Structure of arrays, 128 slots per wave (a chunk appends at most 64; phase 2 drains 64 at a time).
+constexpr int kQ = 128;
+template <typename T>
+struct WaveQueue {
+    int pix[kQ];
+    int cell[kQ];          // x0 | y0 << 16
+    T al[kQ], be[kQ];      // bilinear fractions
+    T px[kQ], py[kQ], pz[kQ];   // p_bar
+    T ed[kQ], gxd[kQ], gyd[kQ]; // depth residual and depth-channel image Jacobian
+};
+
 template <typename T, int NCH, int SM, int TM, int GM, bool DBG>
 __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base, int n_items)
 {
     __shared__ int s_item;
     __shared__ double s_red[kBlock / 64][kAcc];
+    __shared__ WaveQueue<T> s_q[kBlock / 64];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
+    WaveQueue<T> &Q = s_q[wave];
     typedef typename Lut<T>::type L2;
     const L2 *lut = Lut<T>::ptr(a);
+    constexpr bool F32 = std::is_same<T, float>::value;
 
     for (;;) {
         if (tid == 0) s_item = (int)atomicAdd(a.counter, 1u);
@@ -221,184 +236,92 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         // pair constants in the evaluation precision
         T R[9], tr[3], cc[3];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) R[k] = std::is_same<T, double>::value ? (T)pd.Rd[k] : (T)pd.R[k];
+        for (int k = 0; k < 9; ++k) R[k] = F32 ? (T)pd.R[k] : (T)pd.Rd[k];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            tr[k] = std::is_same<T, double>::value ? (T)pd.td[k] : (T)pd.t[k];
+            tr[k] = F32 ? (T)pd.t[k] : (T)pd.td[k];
             cc[k] = (T)pd.c[k];
         }
-        if (std::is_same<T, double>::value) {
-            // c in FP64 from the target offset
+        if (!F32) {
             double cd[3];
             mtv3(st.Ro, st.to, cd);
             for (int k = 0; k < 3; ++k) cc[k] = (T)cd[k];
         }
-        const T fx = std::is_same<T, double>::value ? (T)st.fxd : (T)st.fx;
-        const T fy = std::is_same<T, double>::value ? (T)st.fyd : (T)st.fy;
-        const T cx = std::is_same<T, double>::value ? (T)st.cxd : (T)st.cx;
-        const T cy = std::is_same<T, double>::value ? (T)st.cyd : (T)st.cy;
-        const T dmin = std::is_same<T, double>::value ? (T)st.dmind : (T)st.dmin;
-        const T tau = std::is_same<T, double>::value ? (T)st.taud : (T)st.tau;
+        const T fx = F32 ? (T)st.fx : (T)st.fxd, fy = F32 ? (T)st.fy : (T)st.fyd;
+        const T cx = F32 ? (T)st.cx : (T)st.cxd, cy = F32 ? (T)st.cy : (T)st.cyd;
+        const T dmin = F32 ? (T)st.dmin : (T)st.dmind;
+        const T tau = F32 ? (T)st.tau : (T)st.taud;
         const T om_g = (T)a.omega_g, om_d = (T)a.omega_d, om_n = (T)a.omega_n, delta = (T)a.huber;
         const float band = (float)a.refine_band;
         const L2 *lcol = lut + ss.lut_col, *lrow = lut + ss.lut_row;
-        const float4 *sA4 = a.tex4 + ks.off, *tA4 = a.tex4 + kt.off;
-        const float *sB1 = a.tex1 + ks.off, *tB1 = a.tex1 + kt.off;
-        const float2 *sA2 = a.tex2 + ks.off, *tA2 = a.tex2 + kt.off;
+        const float *sdep = a.dep + ks.off, *tdep = a.dep + kt.off;
+        const float4 *satt4 = a.att4 + ks.off, *tatt4 = a.att4 + kt.off;
+        const float *satt1 = a.att1 + ks.off, *tatt1 = a.att1 + kt.off;
 
-        double acc[ACC_USED];
+        double acc[ACC_F + 1];
 #pragma unroll
-        for (int k = 0; k < ACC_USED; ++k) acc[k] = 0.0;
+        for (int k = 0; k <= ACC_F; ++k) acc[k] = 0.0;
+        int n_eval = 0, n_valid = 0, n_ref = 0;
+        int head = 0, tail = 0;   // wave-uniform queue positions
 
-        for (int pix = px0 + tid; pix < px1; pix += kBlock) {
-            int row = (int)__umulhi((uint32_t)pix, magic);
-            int col = pix - row * Ws;
-            if (col < 0) { row -= 1; col += Ws; }   // the reciprocal can only round up
-            float Is, Ds, nsx = 0.f, nsy = 0.f, nsz = 0.f;
-            if (NCH == 5) {
-                const float4 s4 = sA4[pix];
-                Is = s4.x; Ds = s4.y; nsx = s4.z; nsy = s4.w;
-                nsz = sB1[pix];
-            } else {
-                const float2 s2 = sA2[pix];
-                Is = s2.x; Ds = s2.y;
-            }
-            if (DBG) a.dbg_status[pix] = 1;
-            if (!(Ds > 0.f)) continue;
-            acc[ACC_EVAL] += 1.0;
-            if (DBG) a.dbg_status[pix] = 2;
-
-            // unprojection q = d * ray(u) and transform into the target sensor frame
-            const L2 lc = lcol[col], lr = lrow[row];
-            const T d = (T)Ds;
-            T qx, qy, qz;
-            if (SM == MODEL_SPHERICAL) { qx = d * (lr.x * lc.x); qy = d * (lr.x * lc.y); qz = d * lr.y; }
-            else { qx = d * lc.x; qy = d * lr.x; qz = d; }
-            const T px = R[0] * qx + R[1] * qy + R[2] * qz + tr[0];
-            const T py = R[3] * qx + R[4] * qy + R[5] * qz + tr[1];
-            const T pz = R[6] * qx + R[7] * qy + R[8] * qz + tr[2];
-
-            // projection (Sec. III) and predicted depth/range cue
-            T u, v, zeta_d, r2 = T(0), rho = T(0), n2 = T(0), iz = T(0);
-            bool proj_ok;
-            if (TM == MODEL_PINHOLE) {
-                proj_ok = pz >= dmin;
-                iz = T(1) / pz;
-                u = fx * px * iz + cx;
-                v = fy * py * iz + cy;
-                zeta_d = pz;
-            } else {
-                r2 = px * px + py * py;
-                rho = my_sqrt(r2);
-                n2 = r2 + pz * pz;
-                proj_ok = (rho > T(0)) && (n2 >= dmin * dmin);
-                u = fx * my_atan2(py, px) + cx;
-                v = fy * my_atan2(pz, rho) + cy;
-                zeta_d = my_sqrt(n2);
-            }
-            if (!proj_ok) continue;
-            if (DBG) { a.dbg_status[pix] = 3; a.dbg_uv[pix] = make_float2((float)u, (float)v); }
-
-            // choose the integer cell; near a cell boundary the FP32 path decides it in FP64
-            int x0, y0;
-            T al, be;
-            bool refined = false;
-            if (std::is_same<T, float>::value && band > 0.f) {
-                const float fu = (float)u - floorf((float)u), fv = (float)v - floorf((float)v);
-                refined = fu < band || fu > 1.f - band || fv < band || fv > 1.f - band;
-            }
-            if (refined) {
-                const double2 lcd = a.lut64[ss.lut_col + col], lrd = a.lut64[ss.lut_row + row];
-                const double dd = (double)Ds;
-                double q0, q1, q2;
-                if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
-                else { q0 = dd * lcd.x; q1 = dd * lrd.x; q2 = dd; }
-                const double *Rd = pd.Rd, *td = pd.td;
-                const double X = Rd[0] * q0 + Rd[1] * q1 + Rd[2] * q2 + td[0];
-                const double Y = Rd[3] * q0 + Rd[4] * q1 + Rd[5] * q2 + td[1];
-                const double Z = Rd[6] * q0 + Rd[7] * q1 + Rd[8] * q2 + td[2];
-                double ud, vd;
-                if (TM == MODEL_PINHOLE) {
-                    ud = st.fxd * X / Z + st.cxd;
-                    vd = st.fyd * Y / Z + st.cyd;
-                } else {
-                    ud = st.fxd * atan2(Y, X) + st.cxd;
-                    vd = st.fyd * atan2(Z, sqrt(X * X + Y * Y)) + st.cyd;
-                }
-                if (!(ud >= 1.0 && ud < (double)(Wt - 2) && vd >= 1.0 && vd < (double)(Ht - 2))) continue;
-                const double fx0 = floor(ud), fy0 = floor(vd);
-                x0 = (int)fx0; y0 = (int)fy0;
-                al = (T)(ud - fx0); be = (T)(vd - fy0);
-                acc[ACC_REF] += 1.0;
-                if (DBG) a.dbg_uv[pix] = make_float2((float)ud, (float)vd);
-            } else {
-                if (!(u >= T(1) && u < (T)(Wt - 2) && v >= T(1) && v < (T)(Ht - 2))) continue;
-                x0 = (int)u; y0 = (int)v;
-                al = u - (T)x0; be = v - (T)y0;
-            }
-            if (DBG) { a.dbg_status[pix] = 4; a.dbg_cell[pix] = make_int2(x0, y0); }
-
-            // gather the 12-tap stencil of the target image
+        // phase 2: residuals, weights, Jacobian rows and accumulation of queue slot `slot`
+        auto consume = [&](int slot) {
+            const int pix = Q.pix[slot];
+            const int cellv = Q.cell[slot];
+            const int x0 = cellv & 0xffff, y0 = cellv >> 16;
+            const T al = Q.al[slot], be = Q.be[slot];
+            const T px = Q.px[slot], py = Q.py[slot], pz = Q.pz[slot];
+            const T ed = Q.ed[slot], Gxd = Q.gxd[slot], Gyd = Q.gyd[slot];
             const int base = y0 * Wt + x0;
             const int idx[12] = {base - 1, base, base + 1, base + 2,
                                  base + Wt - 1, base + Wt, base + Wt + 1, base + Wt + 2,
                                  base - Wt, base - Wt + 1, base + 2 * Wt, base + 2 * Wt + 1};
-            float tI[12], tD[12], tX[12], tY[12], tZ[12];
-            if (NCH == 5) {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    const float4 q4 = tA4[idx[k]];
-                    tI[k] = q4.x; tD[k] = q4.y; tX[k] = q4.z; tY[k] = q4.w;
-                }
-#pragma unroll
-                for (int k = 0; k < 12; ++k) tZ[k] = tB1[idx[k]];
-            } else {
-#pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    const float2 q2 = tA2[idx[k]];
-                    tI[k] = q2.x; tD[k] = q2.y;
-                }
-            }
-            // validity and occlusion suppression: every tap valid and on the predicted surface
-            bool vis = true;
-#pragma unroll
-            for (int k = 0; k < 12; ++k) vis = vis && (tD[k] > 0.f) && (fabs((T)tD[k] - zeta_d) <= tau);
-            if (!vis) continue;
-
             const T w00 = (T(1) - al) * (T(1) - be), w01 = al * (T(1) - be);
             const T w10 = (T(1) - al) * be, w11 = al * be;
+            T Is, ns0 = T(0), ns1 = T(0), ns2 = T(0);
+            T Vg, Gxg, Gyg;
+            T Vn[3] = {T(0), T(0), T(0)}, Gxn[3] = {T(0), T(0), T(0)}, Gyn[3] = {T(0), T(0), T(0)};
+            if (NCH == 5) {
+                const float4 s4 = satt4[pix];
+                Is = s4.x; ns0 = s4.y; ns1 = s4.z; ns2 = s4.w;
+                float tI[12], tX[12], tY[12], tZ[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    const float4 q4 = tatt4[idx[k]];
+                    tI[k] = q4.x; tX[k] = q4.y; tY[k] = q4.z; tZ[k] = q4.w;
+                }
 #define SAMPLE(arr, V, GX, GY)                                                                             \
     sample_channel<T, GM>((T)arr[0], (T)arr[1], (T)arr[2], (T)arr[3], (T)arr[4], (T)arr[5], (T)arr[6],      \
                           (T)arr[7], (T)arr[8], (T)arr[9], (T)arr[10], (T)arr[11], w00, w01, w10, w11, al, \
                           be, V, GX, GY)
-            T Vg, Gxg, Gyg, Vd, Gxd, Gyd;
-            SAMPLE(tI, Vg, Gxg, Gyg);
-            SAMPLE(tD, Vd, Gxd, Gyd);
-            const T eg = (T)Is - Vg;
-            const T ed = zeta_d - Vd;
-            T chi2 = om_g * eg * eg + om_d * ed * ed;
-            T en[3] = {T(0), T(0), T(0)}, nr[3] = {T(0), T(0), T(0)};
-            T Gxn[3] = {T(0), T(0), T(0)}, Gyn[3] = {T(0), T(0), T(0)};
-            if (NCH == 5) {
-                T Vn[3];
+                SAMPLE(tI, Vg, Gxg, Gyg);
                 SAMPLE(tX, Vn[0], Gxn[0], Gyn[0]);
                 SAMPLE(tY, Vn[1], Gxn[1], Gyn[1]);
                 SAMPLE(tZ, Vn[2], Gxn[2], Gyn[2]);
+            } else {
+                Is = satt1[pix];
+                float tI[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) tI[k] = tatt1[idx[k]];
+                SAMPLE(tI, Vg, Gxg, Gyg);
+#undef SAMPLE
+            }
+            const T eg = Is - Vg;
+            T chi2 = om_g * eg * eg + om_d * ed * ed;
+            T en[3] = {T(0), T(0), T(0)}, nr[3] = {T(0), T(0), T(0)};
+            if (NCH == 5) {
                 // normal cue: the source normal rotated into the target sensor frame
-                const T n0 = nsx, n1 = nsy, n2s = nsz;
-                nr[0] = R[0] * n0 + R[1] * n1 + R[2] * n2s;
-                nr[1] = R[3] * n0 + R[4] * n1 + R[5] * n2s;
-                nr[2] = R[6] * n0 + R[7] * n1 + R[8] * n2s;
+                nr[0] = R[0] * ns0 + R[1] * ns1 + R[2] * ns2;
+                nr[1] = R[3] * ns0 + R[4] * ns1 + R[5] * ns2;
+                nr[2] = R[6] * ns0 + R[7] * ns1 + R[8] * ns2;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) { en[k] = nr[k] - Vn[k]; chi2 += om_n * en[k] * en[k]; }
             }
-#undef SAMPLE
             if (DBG) {
                 float *rr = a.dbg_res + 5 * (int64_t)pix;
                 rr[0] = (float)eg; rr[1] = (float)ed; rr[2] = (float)en[0]; rr[3] = (float)en[1]; rr[4] = (float)en[2];
                 a.dbg_status[pix] = 0;
             }
-
             // Huber on sqrt(chi^2): w = d rho / d chi^2
             T w = T(1), rhov = chi2;
             if (delta > T(0)) {
@@ -406,18 +329,20 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 if (sq > delta) { w = delta / sq; rhov = delta * (T(2) * sq - delta); }
             }
             acc[ACC_F] += (double)rhov;
-            acc[ACC_VALID] += 1.0;
-
+            n_valid += 1;
             // projective Jacobian rows Pi0 = d u / d p_bar, Pi1 = d v / d p_bar
-            T P00, P01, P02, P10, P11, P12;
+            T P00, P01, P02, P10, P11, P12, zx, zy, zz;
             if (TM == MODEL_PINHOLE) {
+                const T iz = T(1) / pz;
                 P00 = fx * iz; P01 = T(0); P02 = -fx * px * iz * iz;
                 P10 = T(0); P11 = fy * iz; P12 = -fy * py * iz * iz;
+                zx = T(0); zy = T(0); zz = T(1);
             } else {
-                const T ir2 = T(1) / r2;
-                const T k1 = pz / (rho * n2);
+                const T r2 = px * px + py * py, rho = my_sqrt(r2), n2 = r2 + pz * pz;
+                const T ir2 = T(1) / r2, k1 = pz / (rho * n2), ir = T(1) / my_sqrt(n2);
                 P00 = -fx * py * ir2; P01 = fx * px * ir2; P02 = T(0);
                 P10 = -fy * px * k1; P11 = -fy * py * k1; P12 = fy * rho / n2;
+                zx = px * ir; zy = py * ir; zz = pz * ir;
             }
             const T y2x = T(2) * (px + cc[0]), y2y = T(2) * (py + cc[1]), y2z = T(2) * (pz + cc[2]);
             T J[6];
@@ -426,14 +351,9 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                        y2z);
             accumulate_row(acc, J, eg, w * om_g);
             // depth / range: a = d zeta / d p_bar - (Gx Pi0 + Gy Pi1)
-            {
-                T zx, zy, zz;
-                if (TM == MODEL_PINHOLE) { zx = T(0); zy = T(0); zz = T(1); }
-                else { const T ir = T(1) / zeta_d; zx = px * ir; zy = py * ir; zz = pz * ir; }
-                row_from_a(J, zx - (Gxd * P00 + Gyd * P10), zy - (Gxd * P01 + Gyd * P11),
-                           zz - (Gxd * P02 + Gyd * P12), y2x, y2y, y2z);
-                accumulate_row(acc, J, ed, w * om_d);
-            }
+            row_from_a(J, zx - (Gxd * P00 + Gyd * P10), zy - (Gxd * P01 + Gyd * P11), zz - (Gxd * P02 + Gyd * P12),
+                       y2x, y2y, y2z);
+            accumulate_row(acc, J, ed, w * om_d);
             if (NCH == 5) {
                 // normal rows: image term plus the rotation-only term 2 (e_k x n')
 #pragma unroll
@@ -446,12 +366,142 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                     accumulate_row(acc, J, en[k], w * om_n);
                 }
             }
+        };
+
+        for (int cbase = px0 + wave * 64; cbase < px1; cbase += kBlock) {
+            // ---------------- phase 1: projection, cell, validity and occlusion, depth channel
+            const int pix = cbase + lane;
+            bool valid = false;
+            int x0 = 0, y0 = 0;
+            T al = T(0), be = T(0), px = T(0), py = T(0), pz = T(0), edv = T(0), gxd = T(0), gyd = T(0);
+            const float Ds = pix < px1 ? sdep[pix] : 0.f;
+            if (DBG && pix < px1) a.dbg_status[pix] = 1;
+            if (Ds > 0.f) {
+                ++n_eval;
+                if (DBG) a.dbg_status[pix] = 2;
+                int row = (int)__umulhi((uint32_t)pix, magic);
+                int col = pix - row * Ws;
+                if (col < 0) { row -= 1; col += Ws; }   // the reciprocal can only round up
+                // unprojection q = d * ray(u) and transform into the target sensor frame
+                const L2 lc = lcol[col], lr = lrow[row];
+                const T d = (T)Ds;
+                T qx, qy, qz;
+                if (SM == MODEL_SPHERICAL) { qx = d * (lr.x * lc.x); qy = d * (lr.x * lc.y); qz = d * lr.y; }
+                else { qx = d * lc.x; qy = d * lr.x; qz = d; }
+                px = R[0] * qx + R[1] * qy + R[2] * qz + tr[0];
+                py = R[3] * qx + R[4] * qy + R[5] * qz + tr[1];
+                pz = R[6] * qx + R[7] * qy + R[8] * qz + tr[2];
+                // projection (Sec. III) and predicted depth/range cue
+                T u, v, zeta_d;
+                bool ok;
+                if (TM == MODEL_PINHOLE) {
+                    ok = pz >= dmin;
+                    const T iz = T(1) / pz;
+                    u = fx * px * iz + cx;
+                    v = fy * py * iz + cy;
+                    zeta_d = pz;
+                } else {
+                    const T r2 = px * px + py * py, rho = my_sqrt(r2), n2 = r2 + pz * pz;
+                    ok = (rho > T(0)) && (n2 >= dmin * dmin);
+                    u = fx * my_atan2(py, px) + cx;
+                    v = fy * my_atan2(pz, rho) + cy;
+                    zeta_d = my_sqrt(n2);
+                }
+                if (ok) {
+                    if (DBG) { a.dbg_status[pix] = 3; a.dbg_uv[pix] = make_float2((float)u, (float)v); }
+                    // choose the integer cell; near a cell boundary the FP32 path decides it in FP64
+                    bool refined = false;
+                    if (F32 && band > 0.f) {
+                        const float fu = (float)u - floorf((float)u), fv = (float)v - floorf((float)v);
+                        refined = fu < band || fu > 1.f - band || fv < band || fv > 1.f - band;
+                    }
+                    if (refined) {
+                        const double2 lcd = a.lut64[ss.lut_col + col], lrd = a.lut64[ss.lut_row + row];
+                        const double dd = (double)Ds;
+                        double q0, q1, q2;
+                        if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
+                        else { q0 = dd * lcd.x; q1 = dd * lrd.x; q2 = dd; }
+                        const double *Rd = pd.Rd, *td = pd.td;
+                        const double X = Rd[0] * q0 + Rd[1] * q1 + Rd[2] * q2 + td[0];
+                        const double Y = Rd[3] * q0 + Rd[4] * q1 + Rd[5] * q2 + td[1];
+                        const double Z = Rd[6] * q0 + Rd[7] * q1 + Rd[8] * q2 + td[2];
+                        double ud, vd;
+                        if (TM == MODEL_PINHOLE) {
+                            ud = st.fxd * X / Z + st.cxd;
+                            vd = st.fyd * Y / Z + st.cyd;
+                        } else {
+                            ud = st.fxd * atan2(Y, X) + st.cxd;
+                            vd = st.fyd * atan2(Z, sqrt(X * X + Y * Y)) + st.cyd;
+                        }
+                        ++n_ref;
+                        if (DBG) a.dbg_uv[pix] = make_float2((float)ud, (float)vd);
+                        ok = ud >= 1.0 && ud < (double)(Wt - 2) && vd >= 1.0 && vd < (double)(Ht - 2);
+                        if (ok) {
+                            const double fx0 = floor(ud), fy0 = floor(vd);
+                            x0 = (int)fx0; y0 = (int)fy0;
+                            al = (T)(ud - fx0); be = (T)(vd - fy0);
+                        }
+                    } else {
+                        ok = u >= T(1) && u < (T)(Wt - 2) && v >= T(1) && v < (T)(Ht - 2);
+                        if (ok) {
+                            x0 = (int)u; y0 = (int)v;
+                            al = u - (T)x0; be = v - (T)y0;
+                        }
+                    }
+                    if (ok) {
+                        if (DBG) { a.dbg_status[pix] = 4; a.dbg_cell[pix] = make_int2(x0, y0); }
+                        // the 12-tap depth stencil: validity and occlusion suppression -- every tap
+                        // valid and on the surface the point lands on
+                        const int base = y0 * Wt + x0;
+                        float tD[12];
+                        tD[0] = tdep[base - 1]; tD[1] = tdep[base]; tD[2] = tdep[base + 1]; tD[3] = tdep[base + 2];
+                        tD[4] = tdep[base + Wt - 1]; tD[5] = tdep[base + Wt]; tD[6] = tdep[base + Wt + 1];
+                        tD[7] = tdep[base + Wt + 2]; tD[8] = tdep[base - Wt]; tD[9] = tdep[base - Wt + 1];
+                        tD[10] = tdep[base + 2 * Wt]; tD[11] = tdep[base + 2 * Wt + 1];
+                        bool vis = true;
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) vis = vis && (tD[k] > 0.f) && (fabs((T)tD[k] - zeta_d) <= tau);
+                        if (vis) {
+                            const T w00 = (T(1) - al) * (T(1) - be), w01 = al * (T(1) - be);
+                            const T w10 = (T(1) - al) * be, w11 = al * be;
+                            T Vd;
+                            sample_channel<T, GM>((T)tD[0], (T)tD[1], (T)tD[2], (T)tD[3], (T)tD[4], (T)tD[5],
+                                                  (T)tD[6], (T)tD[7], (T)tD[8], (T)tD[9], (T)tD[10], (T)tD[11],
+                                                  w00, w01, w10, w11, al, be, Vd, gxd, gyd);
+                            edv = zeta_d - Vd;
+                            valid = true;
+                        }
+                    }
+                }
+            }
+            // append the valid lanes to the wave's queue in lane (= pixel) order
+            const uint64_t mask = __ballot(valid);
+            if (valid) {
+                const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                const int slot = (tail + rank) & (kQ - 1);
+                Q.pix[slot] = pix;
+                Q.cell[slot] = x0 | (y0 << 16);
+                Q.al[slot] = al; Q.be[slot] = be;
+                Q.px[slot] = px; Q.py[slot] = py; Q.pz[slot] = pz;
+                Q.ed[slot] = edv; Q.gxd[slot] = gxd; Q.gyd[slot] = gyd;
+            }
+            tail += __popcll(mask);
+            __builtin_amdgcn_wave_barrier();
+            // ---------------- phase 2: drain full waves of queued correspondences
+            if (tail - head >= 64) {
+                consume((head + lane) & (kQ - 1));
+                head += 64;
+                __builtin_amdgcn_wave_barrier();
+            }
         }
+        if (lane < tail - head) consume((head + lane) & (kQ - 1));
 
         // workgroup reduction of the accumulators (fixed order: deterministic)
 #pragma unroll
         for (int k = 0; k < ACC_USED; ++k) {
-            double v = acc[k];
+            double v = k <= ACC_F ? acc[k] : (k == ACC_VALID ? (double)n_valid : (k == ACC_EVAL ? (double)n_eval
+                                                                                                   : (double)n_ref));
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
             if (lane == 0) s_red[wave][k] = v;

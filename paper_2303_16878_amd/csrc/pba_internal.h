@@ -42,9 +42,9 @@ struct EvalArgs {
     const SensorDev *sensors;
     const KfDev *kfs;
     const PairDev *pairs;
-    const float4 *tex4;          // 5 channels: {intensity, depth, nx, ny}
-    const float *tex1;           // 5 channels: nz
-    const float2 *tex2;          // 2 channels: {intensity, depth}
+    const float *dep;            // depth plane (invalid pixels hold 0)
+    const float4 *att4;          // 5 channels: {intensity, nx, ny, nz}
+    const float *att1;           // 2 channels: intensity
     const float2 *lut32;         // ray tables, FP32
     const double2 *lut64;        // ray tables, FP64
     const int32_t *item_pair;

@@ -51,7 +51,7 @@ struct pba_ctx {
     int nblk = 0;
 
     // device buffers
-    DevBuf sensors_d, kfs_d, tex4, tex1, tex2, lut32, lut64;
+    DevBuf sensors_d, kfs_d, dep, att4, att1, lut32, lut64;
     DevBuf poses, poses_cand, pairs_d, pair_dev, item_pair, item_px0, ibeg, icnt, counters, partials, pair_out;
     DevBuf blk_rc, blk_ptr, blk_ent, bk_ptr, bk_ent;
     DevBuf H, b, H_cand, b_cand, totals, A, dx, lm, fail, logbuf;
@@ -133,28 +133,23 @@ bool pose_ok(const double *x)
 
 int n_sys(const pba_ctx *c) { return 6 * c->N; }
 
-// texel preparation: sanitise depth (invalid -> 0) and interleave the channels
-__global__ void pack5_kernel(const float *__restrict__ I, const float *__restrict__ D, const float *__restrict__ Nn,
-                             float4 *__restrict__ A, float *__restrict__ B, int npx, float dmin, float dmax)
+// texel preparation: sanitise depth (invalid -> 0; the depth test is made in FP64, as the
+// sensor's limits are given) and split into the depth plane and the attribute plane
+__global__ void pack_kernel(const float *__restrict__ I, const float *__restrict__ D, const float *__restrict__ Nn,
+                            float *__restrict__ dep, float4 *__restrict__ att4, float *__restrict__ att1, int npx,
+                            double dmin, double dmax)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += gridDim.x * blockDim.x) {
         const float d = D[i];
-        const bool ok = d > 0.f && d >= dmin && d <= dmax && isfinite(d);
+        const bool ok = isfinite(d) && d > 0.f && (double)d >= dmin && (double)d <= dmax;
         const float in = I[i];
-        float n0 = 0.f, n1 = 0.f, n2 = 0.f;
-        if (Nn) { n0 = Nn[3 * (int64_t)i]; n1 = Nn[3 * (int64_t)i + 1]; n2 = Nn[3 * (int64_t)i + 2]; }
-        A[i] = ok ? make_float4(in, d, n0, n1) : make_float4(0.f, 0.f, 0.f, 0.f);
-        B[i] = ok ? n2 : 0.f;
-    }
-}
-
-__global__ void pack2_kernel(const float *__restrict__ I, const float *__restrict__ D, float2 *__restrict__ A,
-                             int npx, float dmin, float dmax)
-{
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += gridDim.x * blockDim.x) {
-        const float d = D[i];
-        const bool ok = d > 0.f && d >= dmin && d <= dmax && isfinite(d);
-        A[i] = ok ? make_float2(I[i], d) : make_float2(0.f, 0.f);
+        dep[i] = ok ? d : 0.f;
+        if (att4) {
+            const float n0 = Nn[3 * (int64_t)i], n1 = Nn[3 * (int64_t)i + 1], n2 = Nn[3 * (int64_t)i + 2];
+            att4[i] = ok ? make_float4(in, n0, n1, n2) : make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            att1[i] = ok ? in : 0.f;
+        }
     }
 }
 
@@ -241,9 +236,9 @@ EvalArgs make_args(pba_ctx *c)
     a.sensors = P_<SensorDev>(c->sensors_d);
     a.kfs = P_<KfDev>(c->kfs_d);
     a.pairs = P_<PairDev>(c->pair_dev);
-    a.tex4 = P_<float4>(c->tex4);
-    a.tex1 = P_<float>(c->tex1);
-    a.tex2 = P_<float2>(c->tex2);
+    a.dep = P_<float>(c->dep);
+    a.att4 = P_<float4>(c->att4);
+    a.att1 = P_<float>(c->att1);
     a.lut32 = P_<float2>(c->lut32);
     a.lut64 = P_<double2>(c->lut64);
     a.item_pair = P_<int32_t>(c->item_pair);
@@ -390,7 +385,7 @@ pba_status pba_destroy(pba_ctx *c)
     if (!c) return PBA_EINVAL;
     (void)hipSetDevice(c->cfg.device);
     (void)hipStreamSynchronize(c->stream);
-    DevBuf *bufs[] = {&c->sensors_d, &c->kfs_d, &c->tex4, &c->tex1, &c->tex2, &c->lut32, &c->lut64, &c->poses,
+    DevBuf *bufs[] = {&c->sensors_d, &c->kfs_d, &c->dep, &c->att4, &c->att1, &c->lut32, &c->lut64, &c->poses,
                       &c->poses_cand, &c->pairs_d, &c->pair_dev, &c->item_pair, &c->item_px0, &c->ibeg, &c->icnt,
                       &c->counters, &c->partials, &c->pair_out, &c->blk_rc, &c->blk_ptr, &c->blk_ent, &c->bk_ptr,
                       &c->bk_ent, &c->H, &c->b, &c->H_cand, &c->b_cand, &c->totals, &c->A, &c->dx, &c->lm,
@@ -481,11 +476,11 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
     if ((s = upload(c, c->lut32, l32.data(), l32.size() * sizeof(float2)))) return s;
     if ((s = upload(c, c->lut64, l64.data(), l64.size() * sizeof(double2)))) return s;
     if ((s = upload(c, c->kfs_d, kfs.data(), kfs.size() * sizeof(KfDev)))) return s;
+    if ((s = ensure(c, c->dep, off * sizeof(float)))) return s;
     if (c->cfg.channels == 5) {
-        if ((s = ensure(c, c->tex4, off * sizeof(float4)))) return s;
-        if ((s = ensure(c, c->tex1, off * sizeof(float)))) return s;
+        if ((s = ensure(c, c->att4, off * sizeof(float4)))) return s;
     } else {
-        if ((s = ensure(c, c->tex2, off * sizeof(float2)))) return s;
+        if ((s = ensure(c, c->att1, off * sizeof(float)))) return s;
     }
     // stage each keyframe on the device (copy if host) and pack
     DevBuf stage;
@@ -504,13 +499,10 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
             dI = base; dD = base + npx; dN = dN ? base + 2 * (size_t)npx : nullptr;
         }
         const int blocks = std::min((npx + 255) / 256, 4096);
-        if (c->cfg.channels == 5)
-            hipLaunchKernelGGL(pack5_kernel, dim3(blocks), dim3(256), 0, c->stream, dI, dD, dN,
-                               P_<float4>(c->tex4) + kfs[k].off, P_<float>(c->tex1) + kfs[k].off, npx,
-                               (float)S.min_depth, (float)S.max_depth);
-        else
-            hipLaunchKernelGGL(pack2_kernel, dim3(blocks), dim3(256), 0, c->stream, dI, dD,
-                               P_<float2>(c->tex2) + kfs[k].off, npx, (float)S.min_depth, (float)S.max_depth);
+        const bool five = c->cfg.channels == 5;
+        hipLaunchKernelGGL(pack_kernel, dim3(blocks), dim3(256), 0, c->stream, dI, dD, five ? dN : nullptr,
+                           P_<float>(c->dep) + kfs[k].off, five ? P_<float4>(c->att4) + kfs[k].off : nullptr,
+                           five ? nullptr : P_<float>(c->att1) + kfs[k].off, npx, S.min_depth, S.max_depth);
         if (!on_device) HIP_OK(hipStreamSynchronize(c->stream));   // stage is reused
     }
     HIP_OK(hipGetLastError());

@@ -228,3 +228,24 @@ def test_full_size_sampled_pairs(name, sample, pba):
             c = compare_pair_sums(ev["pairs"][k], fo, 1e-5)
             _log("  pair", k, "band", m["n_band"], "H err %.2e b err %.2e" % (c["H"], c["b"]))
             assert c["ok"], (k, c)
+
+
+def test_multiblock_solve_and_lm(pba):
+    """A 40-keyframe LiDAR segment at 32x512: n = 240 spans four 64-wide Cholesky blocks (ragged
+    last block); the solve matches a dense solve of the same system and LM matches the oracle."""
+    full = synth.make("lidar128", kfs=range(40), H=32, W=512)
+    prob = full.subset(range(40))
+    with pba.context_for_problem(prob, precision=pba.PBA_F64) as ctx:
+        ev = ctx.evaluate(want_system=True)
+        for lam in (0.0, 1e-4):
+            dx = ctx.solve_step(lam)
+            ref, ok = oracle.solve_step(ev["H"], ev["b"], lam, anchor=0)
+            assert ok
+            assert np.abs(dx - ref).max() <= 1e-8 * np.abs(ref).max(), lam
+        logs = ctx.iterate(3, use_lm=True, lambda0=1e-4)
+        X = ctx.get_poses()
+    X_or, log_or = oracle.optimize(prob, prob.init_poses, iters=3, lm=True, lam0=1e-4)
+    dt, dr = _pose_err(X, X_or)
+    _log("multiblock LM pose diff vs oracle: %.3g m %.3g rad" % (dt, dr))
+    assert [l["accepted"] for l in logs] == [l["accepted"] for l in log_or]
+    assert dt < 1e-6 and dr < 1e-6
