@@ -80,8 +80,17 @@ __global__ void pair_setup_kernel(const double *__restrict__ poses, const int2 *
     double c[3];
     mtv3(st.Ro, st.to, c);
     PairDev &o = out[p];
-    for (int k = 0; k < 9; ++k) { o.Rd[k] = R[k]; o.R[k] = (float)R[k]; }
-    for (int k = 0; k < 3; ++k) { o.td[k] = tv[k]; o.t[k] = (float)tv[k]; o.c[k] = (float)c[k]; }
+    for (int k = 0; k < 9; ++k) {
+        o.Rd[k] = R[k];
+        o.R[k] = (float)R[k];
+        o.Rlo[k] = (float)(R[k] - (double)o.R[k]);
+    }
+    for (int k = 0; k < 3; ++k) {
+        o.td[k] = tv[k];
+        o.t[k] = (float)tv[k];
+        o.tlo[k] = (float)(tv[k] - (double)o.t[k]);
+        o.c[k] = (float)c[k];
+    }
     // D = R_ot^T ; A = [[-Rp, 2 skewp(tp) Rp], [0, -Rp]] ; E = blockdiag(D, D) A
     double D[9];
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) D[3 * i + j] = st.Ro[3 * j + i];
@@ -233,13 +242,17 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         const uint32_t magic = ss.magic_w;
         const int px1 = min(px0 + a.items_px, npx);
 
-        // pair constants in the evaluation precision
-        T R[9], tr[3], cc[3];
+        // pair constants in the evaluation precision (FP32: leading part plus correction)
+        T R[9], tr[3], cc[3], Rl[9], tl[3];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) R[k] = F32 ? (T)pd.R[k] : (T)pd.Rd[k];
+        for (int k = 0; k < 9; ++k) {
+            R[k] = F32 ? (T)pd.R[k] : (T)pd.Rd[k];
+            Rl[k] = F32 ? (T)pd.Rlo[k] : T(0);
+        }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             tr[k] = F32 ? (T)pd.t[k] : (T)pd.td[k];
+            tl[k] = F32 ? (T)pd.tlo[k] : T(0);
             cc[k] = (T)pd.c[k];
         }
         if (!F32) {
@@ -314,6 +327,11 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 nr[0] = R[0] * ns0 + R[1] * ns1 + R[2] * ns2;
                 nr[1] = R[3] * ns0 + R[4] * ns1 + R[5] * ns2;
                 nr[2] = R[6] * ns0 + R[7] * ns1 + R[8] * ns2;
+                if (F32) {
+                    nr[0] += Rl[0] * ns0 + Rl[1] * ns1 + Rl[2] * ns2;
+                    nr[1] += Rl[3] * ns0 + Rl[4] * ns1 + Rl[5] * ns2;
+                    nr[2] += Rl[6] * ns0 + Rl[7] * ns1 + Rl[8] * ns2;
+                }
 #pragma unroll
                 for (int k = 0; k < 3; ++k) { en[k] = nr[k] - Vn[k]; chi2 += om_n * en[k] * en[k]; }
             }
@@ -391,6 +409,11 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 px = R[0] * qx + R[1] * qy + R[2] * qz + tr[0];
                 py = R[3] * qx + R[4] * qy + R[5] * qz + tr[1];
                 pz = R[6] * qx + R[7] * qy + R[8] * qz + tr[2];
+                if (F32) {
+                    px += Rl[0] * qx + Rl[1] * qy + Rl[2] * qz + tl[0];
+                    py += Rl[3] * qx + Rl[4] * qy + Rl[5] * qz + tl[1];
+                    pz += Rl[6] * qx + Rl[7] * qy + Rl[8] * qz + tl[2];
+                }
                 // projection (Sec. III) and predicted depth/range cue
                 T u, v, zeta_d;
                 bool ok;

@@ -32,6 +32,8 @@ struct KfDev {
 // platform point expressed in the target sensor axes is y'' = p_bar + c.
 struct alignas(16) PairDev {
     float R[9], t[3], c[3], pad;
+    float Rlo[9], tlo[3];        // FP32 path: R = R + Rlo, t = t + tlo to ~48 bits, so that the
+                                 // rounding of the pair transform does not shift every point alike
     double Rd[9], td[3];
     double D[9];                 // R_ot^T: target-sensor axes of the platform perturbation
     double E[36];                // D A: source-pose rows follow as J_s = J' E (6x6 row-major)
@@ -82,8 +84,8 @@ struct LmState {
 };
 void launch_damp_copy(const double *H, const double *b, double *A, double *rhs, int n, int anchor,
                       const LmState *lm, double lam_override, hipStream_t st);
-void launch_cholesky(double *A, int n, int32_t *fail, hipStream_t st);
-void launch_chol_solve(const double *L, double *x, int n, const int32_t *fail, hipStream_t st);
+void launch_cholesky(double *A, int n, double *Winv, int32_t *fail, hipStream_t st);
+void launch_chol_solve(const double *L, const double *Winv, double *x, int n, const int32_t *fail, hipStream_t st);
 void launch_boxplus(const double *X, const double *dx, double *Xout, int N, const int32_t *fail,
                     LmState *lm, hipStream_t st);
 void launch_lm_decide(LmState *lm, const double *totals_cand, int64_t nH, double *H_cur, const double *H_cand,

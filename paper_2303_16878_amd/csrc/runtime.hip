@@ -54,7 +54,7 @@ struct pba_ctx {
     DevBuf sensors_d, kfs_d, dep, att4, att1, lut32, lut64;
     DevBuf poses, poses_cand, pairs_d, pair_dev, item_pair, item_px0, ibeg, icnt, counters, partials, pair_out;
     DevBuf blk_rc, blk_ptr, blk_ent, bk_ptr, bk_ent;
-    DevBuf H, b, H_cand, b_cand, totals, A, dx, lm, fail, logbuf;
+    DevBuf H, b, H_cand, b_cand, totals, A, Winv, dx, lm, fail, logbuf;
     DevBuf dbg_status, dbg_uv, dbg_cell, dbg_res;
 
     // timing
@@ -307,6 +307,7 @@ pba_status ensure_system(pba_ctx *c)
     if ((s = ensure(c, c->b, n * 8))) return s;
     if ((s = ensure(c, c->totals, 8 * 8))) return s;
     if ((s = ensure(c, c->A, n * n * 8))) return s;
+    if ((s = ensure(c, c->Winv, ((n + 63) / 64) * 64 * 64 * 8))) return s;
     if ((s = ensure(c, c->dx, n * 8))) return s;
     if ((s = ensure(c, c->lm, sizeof(LmState)))) return s;
     if ((s = ensure(c, c->fail, 16))) return s;
@@ -388,7 +389,7 @@ pba_status pba_destroy(pba_ctx *c)
     DevBuf *bufs[] = {&c->sensors_d, &c->kfs_d, &c->dep, &c->att4, &c->att1, &c->lut32, &c->lut64, &c->poses,
                       &c->poses_cand, &c->pairs_d, &c->pair_dev, &c->item_pair, &c->item_px0, &c->ibeg, &c->icnt,
                       &c->counters, &c->partials, &c->pair_out, &c->blk_rc, &c->blk_ptr, &c->blk_ent, &c->bk_ptr,
-                      &c->bk_ent, &c->H, &c->b, &c->H_cand, &c->b_cand, &c->totals, &c->A, &c->dx, &c->lm,
+                      &c->bk_ent, &c->H, &c->b, &c->H_cand, &c->b_cand, &c->totals, &c->A, &c->Winv, &c->dx, &c->lm,
                       &c->fail, &c->logbuf, &c->dbg_status, &c->dbg_uv, &c->dbg_cell, &c->dbg_res};
     for (DevBuf *b : bufs) release(*b);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -617,8 +618,8 @@ pba_status pba_solve_step(pba_ctx *c, double lambda, double *dx, int32_t on_devi
     }
     launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
                      P_<LmState>(c->lm), lambda, c->stream);
-    launch_cholesky(P_<double>(c->A), n, P_<int32_t>(c->fail), c->stream);
-    launch_chol_solve(P_<double>(c->A), P_<double>(c->dx), n, P_<int32_t>(c->fail), c->stream);
+    launch_cholesky(P_<double>(c->A), n, P_<double>(c->Winv), P_<int32_t>(c->fail), c->stream);
+    launch_chol_solve(P_<double>(c->A), P_<double>(c->Winv), P_<double>(c->dx), n, P_<int32_t>(c->fail), c->stream);
     HIP_OK(hipGetLastError());
     int32_t f = 0;
     HIP_OK(hipMemcpyAsync(&f, c->fail.p, 4, hipMemcpyDeviceToHost, c->stream));
@@ -691,8 +692,8 @@ pba_status pba_iterate(pba_ctx *c, int32_t n_iters, int32_t use_lm, double lambd
     for (int it = 0; it < n_iters; ++it) {
         launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
                          P_<LmState>(c->lm), -1.0, c->stream);
-        launch_cholesky(P_<double>(c->A), n, P_<int32_t>(c->fail), c->stream);
-        launch_chol_solve(P_<double>(c->A), P_<double>(c->dx), n, P_<int32_t>(c->fail), c->stream);
+        launch_cholesky(P_<double>(c->A), n, P_<double>(c->Winv), P_<int32_t>(c->fail), c->stream);
+        launch_chol_solve(P_<double>(c->A), P_<double>(c->Winv), P_<double>(c->dx), n, P_<int32_t>(c->fail), c->stream);
         launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->N,
                        P_<int32_t>(c->fail), P_<LmState>(c->lm), c->stream);
         if ((s = run_eval(c, P_<double>(c->poses_cand), P_<double>(c->H_cand), P_<double>(c->b_cand), totals + 4,

@@ -40,79 +40,92 @@ void launch_damp_copy(const double *H, const double *b, double *A, double *rhs, 
                        lam_override);
 }
 
-// ---- blocked right-looking Cholesky, lower triangle, A row-major n x n
+// ---- blocked right-looking Cholesky, lower triangle, A row-major n x n.
+// Per 64-wide block column: factor the diagonal block and invert its factor (one wave),
+// form the panel below as X = B W^T with W = L_kk^-1 (tiled product), then update the
+// trailing lower triangle.  The inverted diagonal blocks are kept for the solves.
 
-// Factor the diagonal block at k0 in LDS (one workgroup).
-__global__ void __launch_bounds__(256) chol_diag_kernel(double *A, int n, int k0, int32_t *fail)
+// Factor the diagonal block at k0 in LDS and write L_kk (lower) to A and W = L_kk^-1 (lower,
+// row-major 64 x 64, zero above the diagonal) to Winv.  One wave: lane i owns row i.
+__global__ void __launch_bounds__(64) chol_diag_kernel(double *A, int n, int k0, double *Winv, int32_t *fail)
 {
     __shared__ double L[NB][NB + 1];
-    const int nb = min(NB, n - k0);
-    const int tid = threadIdx.x;
+    __shared__ double W[NB][NB + 1];
     if (*fail) return;
-    for (int e = tid; e < nb * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
-        L[i][j] = A[(int64_t)(k0 + i) * n + k0 + j];
-    }
+    const int nb = min(NB, n - k0);
+    const int lane = threadIdx.x;
+    for (int i = 0; i < nb; ++i) L[i][lane] = lane < nb ? A[(int64_t)(k0 + i) * n + k0 + lane] : 0.0;
+    __builtin_amdgcn_wave_barrier();
     __syncthreads();
-    __shared__ int bad;
-    if (tid == 0) bad = 0;
-    __syncthreads();
+    bool bad = false;
     for (int j = 0; j < nb; ++j) {
-        if (tid == 0) {
-            const double d = L[j][j];
-            if (!(d > 0.0)) bad = 1;
-            L[j][j] = d > 0.0 ? sqrt(d) : 1.0;
-        }
+        const double d = L[j][j];
+        bad = bad || !(d > 0.0);
+        const double sd = d > 0.0 ? sqrt(d) : 1.0;
         __syncthreads();
-        const double ljj = L[j][j];
-        for (int i = j + 1 + tid; i < nb; i += blockDim.x) L[i][j] /= ljj;
+        if (lane == j) L[j][j] = sd;
+        if (lane > j && lane < nb) L[lane][j] /= sd;
         __syncthreads();
-        // trailing update within the block: L[i][k] -= L[i][j] L[k][j], j < k <= i
-        const int m = nb - j - 1;
-        for (int e = tid; e < m * m; e += blockDim.x) {
-            const int i = j + 1 + e / m, k = j + 1 + e % m;
-            if (k <= i) L[i][k] -= L[i][j] * L[k][j];
+        if (lane > j && lane < nb) {
+            const double lij = L[lane][j];
+            for (int k = j + 1; k <= lane; ++k) L[lane][k] -= lij * L[k][j];
         }
         __syncthreads();
     }
-    for (int e = tid; e < nb * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
-        if (j <= i) A[(int64_t)(k0 + i) * n + k0 + j] = L[i][j];
+    // W = L^-1, column c by lane c (forward substitution on the unit vector e_c)
+    if (lane < nb) {
+        const int c = lane;
+        for (int i = 0; i < c; ++i) W[i][c] = 0.0;
+        W[c][c] = 1.0 / L[c][c];
+        for (int i = c + 1; i < nb; ++i) {
+            double s = 0.0;
+            for (int m = c; m < i; ++m) s += L[i][m] * W[m][c];
+            W[i][c] = -s / L[i][i];
+        }
     }
-    if (tid == 0 && bad) *fail = 1;
+    __syncthreads();
+    double *Wb = Winv + (int64_t)(k0 / NB) * NB * NB;
+    for (int i = 0; i < NB; ++i) {
+        Wb[i * NB + lane] = (i < nb && lane < nb) ? W[i][lane] : 0.0;
+        if (i < nb && lane <= i) A[(int64_t)(k0 + i) * n + k0 + lane] = L[i][lane];
+    }
+    if (lane == 0 && bad) *fail = 1;
 }
 
-// Panel below the diagonal block: X L_kk^T = A_ik (one row per thread, 64 rows per workgroup).
-__global__ void __launch_bounds__(64) chol_trsm_kernel(double *A, int n, int k0, const int32_t *fail)
+// Panel below the diagonal block: X = B W^T for 64 rows per workgroup (16 x 16 threads, 4 x 4 each).
+__global__ void __launch_bounds__(256) chol_trsm_kernel(double *A, int n, int k0, const double *Winv,
+                                                        const int32_t *fail)
 {
-    __shared__ double L[NB][NB + 1];
-    __shared__ double X[NB][NB + 1];
+    __shared__ double Bs[NB][NB + 1];
+    __shared__ double Ws[NB][NB + 1];
     if (*fail) return;
     const int nb = min(NB, n - k0);
-    const int tid = threadIdx.x;
     const int r0 = k0 + nb + blockIdx.x * NB;
     const int rows = min(NB, n - r0);
-    for (int e = tid; e < nb * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
-        L[i][j] = A[(int64_t)(k0 + i) * n + k0 + j];
-    }
-    for (int e = tid; e < rows * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
-        X[i][j] = A[(int64_t)(r0 + i) * n + k0 + j];
+    const int tid = threadIdx.x;
+    const double *Wb = Winv + (int64_t)(k0 / NB) * NB * NB;
+    for (int e = tid; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, k = e % NB;
+        Bs[i][k] = (i < rows && k < nb) ? A[(int64_t)(r0 + i) * n + k0 + k] : 0.0;
+        Ws[i][k] = Wb[e];
     }
     __syncthreads();
-    if (tid < rows) {
-        for (int j = 0; j < nb; ++j) {
-            double s = X[tid][j];
-            for (int m = 0; m < j; ++m) s -= X[tid][m] * L[j][m];
-            X[tid][j] = s / L[j][j];
+    const int tx = tid & 15, ty = tid >> 4;
+    double c[4][4];
+    for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 4; ++q) c[a][q] = 0.0;
+    for (int k = 0; k < nb; ++k) {
+        double b[4], w[4];
+        for (int a = 0; a < 4; ++a) b[a] = Bs[ty * 4 + a][k];
+        for (int q = 0; q < 4; ++q) w[q] = Ws[tx * 4 + q][k];
+        for (int a = 0; a < 4; ++a)
+            for (int q = 0; q < 4; ++q) c[a][q] += b[a] * w[q];
+    }
+    for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 4; ++q) {
+            const int i = ty * 4 + a, j = tx * 4 + q;
+            if (i < rows && j < nb) A[(int64_t)(r0 + i) * n + k0 + j] = c[a][q];
         }
-    }
-    __syncthreads();
-    for (int e = tid; e < rows * nb; e += blockDim.x) {
-        const int i = e / nb, j = e % nb;
-        A[(int64_t)(r0 + i) * n + k0 + j] = X[i][j];
-    }
 }
 
 // Trailing update A_ij -= L_i L_j^T for block pairs i >= j below the panel.
@@ -158,79 +171,80 @@ __global__ void __launch_bounds__(256) chol_update_kernel(double *A, int n, int 
 
 __global__ void reset_flag_kernel(int32_t *f) { *f = 0; }
 
-void launch_cholesky(double *A, int n, int32_t *fail, hipStream_t st)
+void launch_cholesky(double *A, int n, double *Winv, int32_t *fail, hipStream_t st)
 {
     hipLaunchKernelGGL(reset_flag_kernel, dim3(1), dim3(1), 0, st, fail);
     for (int k0 = 0; k0 < n; k0 += NB) {
-        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, A, n, k0, fail);
+        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(64), 0, st, A, n, k0, Winv, fail);
         const int rest = n - k0 - NB;
         if (rest > 0) {
             const int nbr = (rest + NB - 1) / NB;
-            hipLaunchKernelGGL(chol_trsm_kernel, dim3(nbr), dim3(64), 0, st, A, n, k0, fail);
+            hipLaunchKernelGGL(chol_trsm_kernel, dim3(nbr), dim3(256), 0, st, A, n, k0, Winv, fail);
             hipLaunchKernelGGL(chol_update_kernel, dim3(nbr * (nbr + 1) / 2), dim3(256), 0, st, A, n, k0, fail);
         }
     }
 }
 
-// L y = rhs, then L^T x = y, in place on x (one workgroup of 1024 threads).
-__global__ void __launch_bounds__(1024) chol_solve_kernel(const double *__restrict__ L, double *__restrict__ x,
-                                                          int n, const int32_t *fail)
+// L y = rhs, then L^T x = y, in place on x, with the inverted diagonal blocks W_kk.
+// One workgroup of 1024 threads (16 waves); rows of L are read with consecutive lanes on
+// consecutive columns.
+__global__ void __launch_bounds__(1024) chol_solve_kernel(const double *__restrict__ L, const double *__restrict__ Winv,
+                                                          double *__restrict__ x, int n, const int32_t *fail)
 {
-    __shared__ double yb[NB];
-    const int tid = threadIdx.x;
+    __shared__ double sv[NB];
+    __shared__ double part[16][NB];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (*fail) {
         for (int i = tid; i < n; i += blockDim.x) x[i] = 0.0;
         return;
     }
     const int nblk = (n + NB - 1) / NB;
-    // forward: right-looking over column blocks
+    // forward: y_k = W_kk (r_k - sum_{j < k0} L[k0 + i][j] y_j)
     for (int kb = 0; kb < nblk; ++kb) {
         const int k0 = kb * NB, nb = min(NB, n - k0);
-        if (tid < 64) {
-            double v = tid < nb ? x[k0 + tid] : 0.0;
-            for (int j = 0; j < nb; ++j) {
-                double yj = __shfl(v, j, 64);
-                yj /= L[(int64_t)(k0 + j) * n + k0 + j];
-                if (tid == j) v = yj;
-                if (tid > j && tid < nb) v -= L[(int64_t)(k0 + tid) * n + k0 + j] * yj;
-            }
-            if (tid < nb) { x[k0 + tid] = v; yb[tid] = v; }
+        for (int i = wv; i < nb; i += 16) {
+            const double *Lr = L + (int64_t)(k0 + i) * n;
+            double s = 0.0;
+            for (int j = lane; j < k0; j += 64) s += Lr[j] * x[j];
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+            if (lane == 0) sv[i] = x[k0 + i] - s;
         }
         __syncthreads();
-        for (int i = k0 + nb + tid; i < n; i += blockDim.x) {
-            const double *Lr = L + (int64_t)i * n + k0;
-            double s = 0.0;
-            for (int j = 0; j < nb; ++j) s += Lr[j] * yb[j];
-            x[i] -= s;
+        const double *Wb = Winv + (int64_t)kb * NB * NB;
+        for (int i = wv; i < nb; i += 16) {
+            double s = lane < nb ? Wb[i * NB + lane] * sv[lane] : 0.0;
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+            if (lane == 0) x[k0 + i] = s;
         }
         __syncthreads();
     }
-    // backward: L^T x = y, last block first
+    // backward: x_k = W_kk^T (y_k - sum_{j >= k0 + nb} L[j][k0 + c] x_j)
     for (int kb = nblk - 1; kb >= 0; --kb) {
         const int k0 = kb * NB, nb = min(NB, n - k0);
-        if (tid < 64) {
-            double v = tid < nb ? x[k0 + tid] : 0.0;
-            for (int j = nb - 1; j >= 0; --j) {
-                double xj = __shfl(v, j, 64);
-                xj /= L[(int64_t)(k0 + j) * n + k0 + j];
-                if (tid == j) v = xj;
-                if (tid < j) v -= L[(int64_t)(k0 + j) * n + k0 + tid] * xj;
-            }
-            if (tid < nb) { x[k0 + tid] = v; yb[tid] = v; }
+        double s = 0.0;
+        if (lane < nb)
+            for (int j = k0 + nb + wv; j < n; j += 16) s += L[(int64_t)j * n + k0 + lane] * x[j];
+        part[wv][lane] = s;
+        __syncthreads();
+        if (wv == 0) {
+            double t = 0.0;
+            for (int w = 0; w < 16; ++w) t += part[w][lane];
+            sv[lane] = lane < nb ? x[k0 + lane] - t : 0.0;
         }
         __syncthreads();
-        for (int i = tid; i < k0; i += blockDim.x) {
-            double s = 0.0;
-            for (int j = 0; j < nb; ++j) s += L[(int64_t)(k0 + j) * n + i] * yb[j];
-            x[i] -= s;
+        const double *Wb = Winv + (int64_t)kb * NB * NB;
+        if (wv == 0 && lane < nb) {
+            double t = 0.0;
+            for (int i = lane; i < nb; ++i) t += Wb[i * NB + lane] * sv[i];
+            x[k0 + lane] = t;
         }
         __syncthreads();
     }
 }
 
-void launch_chol_solve(const double *L, double *x, int n, const int32_t *fail, hipStream_t st)
+void launch_chol_solve(const double *L, const double *Winv, double *x, int n, const int32_t *fail, hipStream_t st)
 {
-    hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(1024), 0, st, L, x, n, fail);
+    hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(1024), 0, st, L, Winv, x, n, fail);
 }
 
 // ---- pose update

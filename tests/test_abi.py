@@ -82,3 +82,18 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(pba, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         pba.load_library(str(tmp_path / "nope.so"))
+
+
+def test_product_ate_matches_oracle_alignment():
+    """The library's trajectory metric (orthonormal-matrix form) agrees with the oracle's
+    quaternion form of Horn's alignment."""
+    import numpy as np
+    import oracle
+    from paper_2303_16878_amd.metrics import ate_rmse
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        A = np.zeros((30, 12))
+        A[:, 9:] = rng.normal(size=(30, 3)) * 10
+        B = A.copy()
+        B[:, 9:] = A[:, 9:] @ np.linalg.qr(rng.normal(size=(3, 3)))[0].T + rng.normal(size=(30, 3)) * 0.1
+        assert abs(ate_rmse(A, B) - oracle.ate_rmse(A, B)) < 1e-12
