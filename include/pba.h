@@ -92,7 +92,8 @@ typedef struct {
                                     blended bilinearly (Supplementary); 1 = slope of the bilinear
                                     interpolant (exact derivative of the sampled image) */
     int32_t anchor;              /* pose held fixed (gauge) */
-    int32_t pad0;
+    int32_t use_graph;           /* 1: pba_iterate replays one captured HIP graph per iteration;
+                                    0: launches the same kernels one by one */
     void *stream;                /* borrowed hipStream_t, NULL = null stream */
     double omega_intensity, omega_depth, omega_normal;  /* Omega^c, scalar per cue */
     double huber_delta;          /* Huber threshold on sqrt(chi^2); <= 0: plain squares */
@@ -103,8 +104,8 @@ typedef struct {
                                     integer is recomputed in FP64 before its cell is chosen; 0 = off */
 } pba_config;
 
-/* Fill *cfg with defaults: F32, 5 channels, grad_mode 0, anchor 0, Omega 1, Huber 0.1,
- * tau 0.5 m (pinhole) / 1.0 m (spherical), refine band 2e-3 px. */
+/* Fill *cfg with defaults: F32, 5 channels, grad_mode 0, anchor 0, graphs on, Omega 1,
+ * Huber 0.1, tau 0.5 m (pinhole) / 1.0 m (spherical), refine band 2e-3 px. */
 void pba_config_default(pba_config *cfg);
 
 /* Create a context on cfg->device.  *out receives the handle. */

@@ -55,6 +55,11 @@ class OrcPairOut(ctypes.Structure):
                 ("n_eval", ctypes.c_int64), ("n_valid", ctypes.c_int64), ("babs", ctypes.c_double * 12)]
 
 
+class OrcImageGrad(ctypes.Structure):
+    _fields_ = [("gIs", ctypes.c_void_p), ("gDs", ctypes.c_void_p), ("gNs", ctypes.c_void_p),
+                ("gIt", ctypes.c_void_p), ("gDt", ctypes.c_void_p), ("gNt", ctypes.c_void_p)]
+
+
 class OrcFrame(ctypes.Structure):
     _fields_ = [("I", ctypes.c_void_p), ("D", ctypes.c_void_p), ("N", ctypes.c_void_p),
                 ("sensor", ctypes.c_int32), ("pad", ctypes.c_int32)]
@@ -89,6 +94,8 @@ def _load():
         lib.orc_eval_pair.argtypes = [ctypes.POINTER(OrcSensor), vp, vp, vp, ctypes.POINTER(OrcSensor), vp, vp,
                                       vp, vp, vp, ctypes.POINTER(OrcParams), vp, vp,
                                       ctypes.POINTER(OrcPairOut), vp, vp, vp, vp]
+        lib.orc_eval_pair_grad.restype = ctypes.c_int
+        lib.orc_eval_pair_grad.argtypes = lib.orc_eval_pair.argtypes + [ctypes.POINTER(OrcImageGrad)]
         lib.orc_eval_pairs.restype = ctypes.c_int
         lib.orc_eval_pairs.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, ctypes.POINTER(OrcParams),
                                        ctypes.POINTER(OrcParams), vp]
@@ -338,3 +345,59 @@ def ate_rmse(est_poses, gt_poses):
     R, t = horn_align(P, Q)
     d = (P @ R.T + t) - Q
     return float(np.sqrt(np.mean(np.sum(d * d, axis=1))))
+
+
+# ------------------------------------------------------------------ loss and its gradient
+
+def quat_right_jacobian(dq):
+    """L(q) with R(q + dq') = R(q) R(L(q) dq') to first order: the body-frame quaternion increment
+    vec(Q* (x) dQ) of the unit quaternion Q = (w, q), w = sqrt(1 - |q|^2)."""
+    q = np.asarray(dq, np.float64)
+    w = math.sqrt(1.0 - float(q @ q))
+    S = np.array([[0, -q[2], q[1]], [q[2], 0, -q[0]], [-q[1], q[0], 0]])
+    return w * np.eye(3) + np.outer(q, q) / w - S
+
+
+def loss_and_grad(prob, poses0, delta, params=None, pairs=None):
+    """F(X0 boxplus delta) = sum of rho over pairs and valid pixels, and its exact gradients.
+
+    delta: [N, 6] per pose [dt, dq].  Returns dict(F, g_delta [N,6], gI, gD, gN per keyframe).
+    The derivative of F is taken with the slope of the bilinear interpolant (the sampled images
+    are what F depends on); masks and integer cells are those of the evaluation at X."""
+    lib = _load()
+    params = prob.params if params is None else params
+    pairs = prob.pairs if pairs is None else np.asarray(pairs, np.int32)
+    delta = np.asarray(delta, np.float64).reshape(prob.n, 6)
+    X = boxplus(poses0, delta.reshape(-1))
+    gI = [np.zeros(prob.depth[k].shape) for k in range(prob.n)]
+    gD = [np.zeros(prob.depth[k].shape) for k in range(prob.n)]
+    gN = [np.zeros(prob.depth[k].shape + (3,)) for k in range(prob.n)]
+    b = np.zeros(6 * prob.n)
+    F = 0.0
+    for (s, t) in pairs:
+        s, t = int(s), int(t)
+        ss, st = prob.sensors[prob.kf_sensor[s]], prob.sensors[prob.kf_sensor[t]]
+        imgs = [_c(a, np.float32) for a in (prob.intensity[s], prob.depth[s], prob.normals[s],
+                                             prob.intensity[t], prob.depth[t], prob.normals[t])]
+        ig = OrcImageGrad(gI[s].ctypes.data, gD[s].ctypes.data, gN[s].ctypes.data,
+                          gI[t].ctypes.data, gD[t].ctypes.data, gN[t].ctypes.data)
+        out = OrcPairOut()
+        Xs, Xt = _c(X[s], np.float64), _c(X[t], np.float64)
+        rc = lib.orc_eval_pair_grad(ctypes.byref(sensor_struct(ss)), imgs[0].ctypes.data, imgs[1].ctypes.data,
+                                    imgs[2].ctypes.data, ctypes.byref(sensor_struct(st)), imgs[3].ctypes.data,
+                                    imgs[4].ctypes.data, imgs[5].ctypes.data, Xs.ctypes.data, Xt.ctypes.data,
+                                    ctypes.byref(params_struct(params, st["model"], 1)), None, None,
+                                    ctypes.byref(out), None, None, None, None, ctypes.byref(ig))
+        if rc != 0:
+            raise RuntimeError("orc_eval_pair_grad failed (%d)" % rc)
+        F += out.F
+        bb = np.array(out.b)
+        b[6 * s:6 * s + 6] += bb[:6]
+        b[6 * t:6 * t + 6] += bb[6:]
+    # dF/d(right perturbation at X) = 2 b; chain rule through X0 boxplus delta
+    g = np.zeros((prob.n, 6))
+    for k in range(prob.n):
+        q = delta[k, 3:]
+        g[k, :3] = quat_rot(q) @ (2.0 * b[6 * k:6 * k + 3])
+        g[k, 3:] = quat_right_jacobian(q).T @ (2.0 * b[6 * k + 3:6 * k + 6])
+    return dict(F=F, g_delta=g, gI=gI, gD=gD, gN=gN)

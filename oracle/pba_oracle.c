@@ -160,12 +160,39 @@ static inline double px(const float *img, int W, int r, int c) { return (double)
  * margin (1 double: min over the stencil taps of occ_tau - |depth_tap - zeta^d|,
  * written for pixels that reach the occlusion test).
  */
+/* Gradients of F with respect to the images (loss adjoint), accumulated when non-NULL:
+ * source and target intensity [H][W], depth [H][W], normals [H][W][3].  The masks, the
+ * integer cells and the occlusion decisions are held fixed; F is then a smooth function
+ * of the image values through the bilinear samples V^c, the source intensity and normal,
+ * and the source depth through the warped point p_bar. */
+typedef struct {
+    double *gIs, *gDs, *gNs, *gIt, *gDt, *gNt;
+} OrcImageGrad;
+
+int orc_eval_pair_grad(const OrcSensor *ss, const float *Is, const float *Ds, const float *Ns,
+                       const OrcSensor *st, const float *It, const float *Dt, const float *Nt,
+                       const double *Xs, const double *Xt, const OrcParams *prm,
+                       const uint8_t *force_valid, const int32_t *force_cell,
+                       OrcPairOut *out, uint8_t *status_out, double *uv_out, double *res_out,
+                       double *margin_out, const OrcImageGrad *ig);
+
 int orc_eval_pair(const OrcSensor *ss, const float *Is, const float *Ds, const float *Ns,
                   const OrcSensor *st, const float *It, const float *Dt, const float *Nt,
                   const double *Xs, const double *Xt, const OrcParams *prm,
                   const uint8_t *force_valid, const int32_t *force_cell,
                   OrcPairOut *out, uint8_t *status_out, double *uv_out, double *res_out,
                   double *margin_out)
+{
+    return orc_eval_pair_grad(ss, Is, Ds, Ns, st, It, Dt, Nt, Xs, Xt, prm, force_valid, force_cell, out,
+                              status_out, uv_out, res_out, margin_out, NULL);
+}
+
+int orc_eval_pair_grad(const OrcSensor *ss, const float *Is, const float *Ds, const float *Ns,
+                       const OrcSensor *st, const float *It, const float *Dt, const float *Nt,
+                       const double *Xs, const double *Xt, const OrcParams *prm,
+                       const uint8_t *force_valid, const int32_t *force_cell,
+                       OrcPairOut *out, uint8_t *status_out, double *uv_out, double *res_out,
+                       double *margin_out, const OrcImageGrad *ig)
 {
     const int C = prm->channels;
     const int Hs = ss->H, Ws = ss->W, Ht = st->H, Wt = st->W;
@@ -358,6 +385,49 @@ int orc_eval_pair(const OrcSensor *ss, const float *Is, const float *Ds, const f
             }
             out->F += rho;
             out->n_valid++;
+
+            if (ig) {
+                /* dF/de^c = 2 w Omega^c e^c */
+                double k[5];
+                for (int ch = 0; ch < C; ++ch) k[ch] = 2.0 * wgt * prm->omega[ch < 2 ? ch : 2] * e[ch];
+                /* target channels: e^c = zeta^c - V^c, V^c = sum of bilinear weights x taps */
+                const double wt[4] = {(1-a) * (1-bb), a * (1-bb), (1-a) * bb, a * bb};
+                const int64_t ti[4] = {(int64_t)y0 * Wt + x0, (int64_t)y0 * Wt + x0 + 1,
+                                       (int64_t)(y0+1) * Wt + x0, (int64_t)(y0+1) * Wt + x0 + 1};
+                for (int q = 0; q < 4; ++q) {
+                    if (ig->gIt) ig->gIt[ti[q]] -= k[0] * wt[q];
+                    if (ig->gDt) ig->gDt[ti[q]] -= k[1] * wt[q];
+                    if (ig->gNt) for (int ch = 2; ch < C; ++ch) ig->gNt[3*ti[q] + ch - 2] -= k[ch] * wt[q];
+                }
+                /* source intensity: e^g = I_s(u) - V^g */
+                if (ig->gIs) ig->gIs[pix] += k[0];
+                /* source normal: e^n = R_ot^T R_t^T R_s R_os n_u - V^n */
+                if (ig->gNs && C == 5) {
+                    double RR[9];
+                    matmul3(M_RotRjRi, ss->Ro, RR);
+                    for (int j = 0; j < 3; ++j)
+                        ig->gNs[3*pix + j] += k[2] * RR[j] + k[3] * RR[3+j] + k[4] * RR[6+j];
+                }
+                /* source depth: p_bar moves along R_ot^T R_t^T R_s R_os ray(u) per unit of d, and
+                 * every e^c depends on p_bar through zeta^c (depth/range) and through u' = pi(p_bar) */
+                if (ig->gDs) {
+                    double ray[3], RR[9], dp[3];
+                    unproject(ss, (double)c, (double)r, 1.0, ray);
+                    matmul3(M_RotRjRi, ss->Ro, RR);
+                    matvec3(RR, ray, dp);
+                    double dz[3];
+                    if (st->model == 0) { dz[0] = 0; dz[1] = 0; dz[2] = 1; }
+                    else { dz[0] = pbar[0] / range; dz[1] = pbar[1] / range; dz[2] = pbar[2] / range; }
+                    double g = 0.0;
+                    for (int ch = 0; ch < C; ++ch) {
+                        double ac[3];
+                        for (int j = 0; j < 3; ++j) ac[j] = -(G[ch][0] * P[j] + G[ch][1] * P[3+j]);
+                        if (ch == 1) for (int j = 0; j < 3; ++j) ac[j] += dz[j];
+                        g += k[ch] * (ac[0] * dp[0] + ac[1] * dp[1] + ac[2] * dp[2]);
+                    }
+                    ig->gDs[pix] += g;
+                }
+            }
         }
 done:
         if (status_out) status_out[pix] = status;

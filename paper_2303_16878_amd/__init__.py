@@ -41,7 +41,7 @@ class pba_sensor(ctypes.Structure):
 
 class pba_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("channels", ctypes.c_int32),
-                ("grad_mode", ctypes.c_int32), ("anchor", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("grad_mode", ctypes.c_int32), ("anchor", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("omega_intensity", ctypes.c_double),
                 ("omega_depth", ctypes.c_double), ("omega_normal", ctypes.c_double),
                 ("huber_delta", ctypes.c_double), ("occlusion_tau_pinhole", ctypes.c_double),
@@ -139,10 +139,11 @@ class Context:
 
     def __init__(self, device=0, precision=PBA_F32, channels=5, grad_mode=0, anchor=0, stream=None,
                  omega_intensity=1.0, omega_depth=1.0, omega_normal=1.0, huber_delta=0.1,
-                 occlusion_tau_pinhole=0.5, occlusion_tau_spherical=1.0, refine_band=None):
+                 occlusion_tau_pinhole=0.5, occlusion_tau_spherical=1.0, refine_band=None, use_graph=True):
         self.lib = load_library()
         cfg = config_default()
         cfg.device, cfg.precision, cfg.channels, cfg.grad_mode, cfg.anchor = device, precision, channels, grad_mode, anchor
+        cfg.use_graph = int(bool(use_graph))
         if stream is None:
             try:
                 import torch

@@ -90,7 +90,7 @@ void launch_boxplus(const double *X, const double *dx, double *Xout, int N, cons
                     LmState *lm, hipStream_t st);
 void launch_lm_decide(LmState *lm, const double *totals_cand, int64_t nH, double *H_cur, const double *H_cand,
                       double *b_cur, const double *b_cand, double *X_cur, const double *X_cand, int N,
-                      double *totals_cur, double *log_row, hipStream_t st);
+                      double *totals_cur, double *logbuf, int log_cap, hipStream_t st);
 void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
 
 }  // namespace pba

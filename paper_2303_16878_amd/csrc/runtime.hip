@@ -57,6 +57,13 @@ struct pba_ctx {
     DevBuf H, b, H_cand, b_cand, totals, A, Winv, dx, lm, fail, logbuf;
     DevBuf dbg_status, dbg_uv, dbg_cell, dbg_res;
 
+    // one captured LM iteration (replayed by pba_iterate)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_valid = false;
+    int log_cap = 0;
+
     // timing
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double eval_ms = 0.0, iterate_ms = 0.0;
@@ -256,27 +263,59 @@ EvalArgs make_args(pba_ctx *c)
 // Evaluate at `poses` into (H, b, totals).  Launch order on the context stream:
 // pair setup (also clears the queue counters) -> persistent evaluation per model group
 // -> ordered per-pair reduction/expansion -> assembly.
-pba_status run_eval(pba_ctx *c, const double *poses, double *H, double *b, double *totals, bool timed)
+pba_status run_eval(pba_ctx *c, const double *poses, double *H, double *b, double *totals, bool timed,
+                    hipStream_t st)
 {
     const int ncnt = (int)c->groups.size();
     launch_pair_setup(poses, P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->sensors_d), P_<KfDev>(c->kfs_d),
-                      P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ncnt, c->stream);
+                      P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ncnt, st);
     EvalArgs a = make_args(c);
-    if (timed) HIP_OK(hipEventRecord(c->ev0, c->stream));
+    if (timed) HIP_OK(hipEventRecord(c->ev0, st));
     for (int g = 0; g < ncnt; ++g) {
         const auto &G = c->groups[g];
         a.counter = P_<uint32_t>(c->counters) + g;
         const int grid = std::max(1, std::min(G.count, c->grid));
         launch_eval(a, c->cfg.precision, c->cfg.channels, c->cfg.grad_mode, G.sm, G.tm, false, G.base, G.count, grid,
-                    c->stream);
+                    st);
     }
-    if (timed) HIP_OK(hipEventRecord(c->ev1, c->stream));
+    if (timed) HIP_OK(hipEventRecord(c->ev1, st));
     HIP_OK(hipGetLastError());
     launch_reduce_pairs(c->partials.p, c->cfg.precision, P_<int32_t>(c->ibeg), P_<int32_t>(c->icnt),
-                        P_<PairDev>(c->pair_dev), P_<double>(c->pair_out), c->P, c->stream);
+                        P_<PairDev>(c->pair_dev), P_<double>(c->pair_out), c->P, st);
     launch_assemble(P_<double>(c->pair_out), c->P, P_<int2>(c->blk_rc), P_<int32_t>(c->blk_ptr),
                     P_<int32_t>(c->blk_ent), c->nblk, P_<int32_t>(c->bk_ptr), P_<int32_t>(c->bk_ent), c->N, H, b,
-                    totals, c->stream);
+                    totals, st);
+    HIP_OK(hipGetLastError());
+    return PBA_OK;
+}
+
+void drop_graph(pba_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->graph_valid = false;
+}
+
+// Enqueue one LM / GN iteration on `st`: damped solve at the current poses, candidate poses,
+// evaluation at the candidate, device-side accept/reject.  Identical launches every iteration.
+pba_status enqueue_iteration(pba_ctx *c, hipStream_t st)
+{
+    const int n = 6 * c->N;
+    double *totals = P_<double>(c->totals);   // [0..3] current, [4..7] candidate
+    launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
+                     P_<LmState>(c->lm), -1.0, st);
+    launch_cholesky(P_<double>(c->A), n, P_<double>(c->Winv), P_<int32_t>(c->fail), st);
+    launch_chol_solve(P_<double>(c->A), P_<double>(c->Winv), P_<double>(c->dx), n, P_<int32_t>(c->fail), st);
+    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->N, P_<int32_t>(c->fail),
+                   P_<LmState>(c->lm), st);
+    pba_status s = run_eval(c, P_<double>(c->poses_cand), P_<double>(c->H_cand), P_<double>(c->b_cand), totals + 4,
+                            false, st);
+    if (s) return s;
+    launch_lm_decide(P_<LmState>(c->lm), totals + 4, (int64_t)n * n, P_<double>(c->H), P_<double>(c->H_cand),
+                     P_<double>(c->b), P_<double>(c->b_cand), P_<double>(c->poses), P_<double>(c->poses_cand), c->N,
+                     totals, P_<double>(c->logbuf), c->log_cap, st);
     HIP_OK(hipGetLastError());
     return PBA_OK;
 }
@@ -307,6 +346,8 @@ pba_status ensure_system(pba_ctx *c)
     if ((s = ensure(c, c->b, n * 8))) return s;
     if ((s = ensure(c, c->totals, 8 * 8))) return s;
     if ((s = ensure(c, c->A, n * n * 8))) return s;
+    if ((s = ensure(c, c->H_cand, n * n * 8))) return s;
+    if ((s = ensure(c, c->b_cand, n * 8))) return s;
     if ((s = ensure(c, c->Winv, ((n + 63) / 64) * 64 * 64 * 8))) return s;
     if ((s = ensure(c, c->dx, n * 8))) return s;
     if ((s = ensure(c, c->lm, sizeof(LmState)))) return s;
@@ -327,6 +368,7 @@ void pba_config_default(pba_config *cfg)
     cfg->channels = 5;
     cfg->grad_mode = 0;
     cfg->anchor = 0;
+    cfg->use_graph = 1;
     cfg->stream = nullptr;
     cfg->omega_intensity = 1.0;
     cfg->omega_depth = 1.0;
@@ -391,6 +433,8 @@ pba_status pba_destroy(pba_ctx *c)
                       &c->counters, &c->partials, &c->pair_out, &c->blk_rc, &c->blk_ptr, &c->blk_ent, &c->bk_ptr,
                       &c->bk_ent, &c->H, &c->b, &c->H_cand, &c->b_cand, &c->totals, &c->A, &c->Winv, &c->dx, &c->lm,
                       &c->fail, &c->logbuf, &c->dbg_status, &c->dbg_uv, &c->dbg_cell, &c->dbg_res};
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) release(*b);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -509,6 +553,7 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(c->stream));
     release(stage);
+    drop_graph(c);
     c->kfs_h = kfs;
     c->sensors_dev_h = sd;
     c->texels = off;
@@ -566,6 +611,7 @@ pba_status pba_set_pairs(pba_ctx *c, int32_t p, const int32_t *src, const int32_
             return fail(c, PBA_EINVAL, "pair %d: keyframe id out of range", k);
     std::vector<int2> pr(p);
     for (int k = 0; k < p; ++k) pr[k] = make_int2(s[k], t[k]);
+    drop_graph(c);
     pba_status st;
     if ((st = upload(c, c->pairs_d, pr.data(), pr.size() * sizeof(int2)))) return st;
     if ((st = build_plan(c, s, t))) return st;
@@ -583,7 +629,7 @@ pba_status pba_evaluate(pba_ctx *c, pba_eval_out *out)
     pba_status s;
     if ((s = check_ready(c))) return s;
     HIP_OK(hipSetDevice(c->cfg.device));
-    if ((s = run_eval(c, P_<double>(c->poses), P_<double>(c->H), P_<double>(c->b), P_<double>(c->totals), true)))
+    if ((s = run_eval(c, P_<double>(c->poses), P_<double>(c->H), P_<double>(c->b), P_<double>(c->totals), true, c->stream)))
         return s;
     const size_t n = (size_t)n_sys(c);
     const hipMemcpyKind k = out->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -612,7 +658,7 @@ pba_status pba_solve_step(pba_ctx *c, double lambda, double *dx, int32_t on_devi
     const int n = n_sys(c);
     if (!c->system_valid) {
         if ((s = run_eval(c, P_<double>(c->poses), P_<double>(c->H), P_<double>(c->b), P_<double>(c->totals),
-                          false)))
+                          false, c->stream)))
             return s;
         c->system_valid = true;
     }
@@ -668,15 +714,18 @@ pba_status pba_iterate(pba_ctx *c, int32_t n_iters, int32_t use_lm, double lambd
     if ((s = check_ready(c))) return s;
     if (n_iters == 0) return PBA_OK;
     HIP_OK(hipSetDevice(c->cfg.device));
-    const int n = n_sys(c);
-    const size_t nn = (size_t)n * n;
-    if ((s = ensure(c, c->H_cand, nn * 8))) return s;
-    if ((s = ensure(c, c->b_cand, (size_t)n * 8))) return s;
-    if ((s = ensure(c, c->logbuf, (size_t)n_iters * 8 * 8))) return s;
+    if (n_iters > c->log_cap) {
+        const int cap = std::max(n_iters, 64);
+        release(c->logbuf);
+        if ((s = ensure(c, c->logbuf, (size_t)cap * 8 * 8))) return s;
+        c->log_cap = cap;
+        drop_graph(c);   // the graph refers to the log buffer
+    }
     double *totals = P_<double>(c->totals);   // [0..3] current, [4..7] candidate
     // system at the current poses (reused if already evaluated there)
     if (!c->system_valid) {
-        if ((s = run_eval(c, P_<double>(c->poses), P_<double>(c->H), P_<double>(c->b), totals, false))) return s;
+        if ((s = run_eval(c, P_<double>(c->poses), P_<double>(c->H), P_<double>(c->b), totals, false, c->stream)))
+            return s;
         c->system_valid = true;
     }
     double tot0[4];
@@ -689,20 +738,24 @@ pba_status pba_iterate(pba_ctx *c, int32_t n_iters, int32_t use_lm, double lambd
     lm.use_lm = use_lm ? 1 : 0;
     HIP_OK(hipMemcpyAsync(c->lm.p, &lm, sizeof lm, hipMemcpyHostToDevice, c->stream));
     HIP_OK(hipEventRecord(c->ev0, c->stream));
-    for (int it = 0; it < n_iters; ++it) {
-        launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
-                         P_<LmState>(c->lm), -1.0, c->stream);
-        launch_cholesky(P_<double>(c->A), n, P_<double>(c->Winv), P_<int32_t>(c->fail), c->stream);
-        launch_chol_solve(P_<double>(c->A), P_<double>(c->Winv), P_<double>(c->dx), n, P_<int32_t>(c->fail), c->stream);
-        launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->N,
-                       P_<int32_t>(c->fail), P_<LmState>(c->lm), c->stream);
-        if ((s = run_eval(c, P_<double>(c->poses_cand), P_<double>(c->H_cand), P_<double>(c->b_cand), totals + 4,
-                          false)))
-            return s;
-        launch_lm_decide(P_<LmState>(c->lm), totals + 4, (int64_t)nn, P_<double>(c->H), P_<double>(c->H_cand),
-                         P_<double>(c->b), P_<double>(c->b_cand), P_<double>(c->poses), P_<double>(c->poses_cand),
-                         c->N, totals, P_<double>(c->logbuf) + 8 * it, c->stream);
-        HIP_OK(hipGetLastError());
+    if (c->cfg.use_graph) {
+        if (!c->graph_valid) {
+            if (!c->cap_stream) HIP_OK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            drop_graph(c);
+            HIP_OK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            pba_status cs = enqueue_iteration(c, c->cap_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+            if (cs) { if (g) (void)hipGraphDestroy(g); return cs; }
+            if (e != hipSuccess) return fail(c, PBA_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+            c->graph = g;
+            HIP_OK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+            c->graph_valid = true;
+        }
+        for (int it = 0; it < n_iters; ++it) HIP_OK(hipGraphLaunch(c->gexec, c->stream));
+    } else {
+        for (int it = 0; it < n_iters; ++it)
+            if ((s = enqueue_iteration(c, c->stream))) return s;
     }
     HIP_OK(hipEventRecord(c->ev1, c->stream));
     std::vector<double> lg((size_t)n_iters * 8);

@@ -314,8 +314,7 @@ void launch_boxplus(const double *X, const double *dx, double *Xout, int N, cons
 __global__ void __launch_bounds__(256) lm_decide_kernel(LmState *lm, const double *__restrict__ totals_cand,
                                                         int64_t nH, double *H_cur, const double *H_cand,
                                                         double *b_cur, const double *b_cand, int nb,
-                                                        double *X_cur, const double *X_cand, int nX,
-                                                        double *log_row)
+                                                        double *X_cur, const double *X_cand, int nX)
 {
     __shared__ int acc;
     const double Fc = totals_cand[0];
@@ -333,8 +332,10 @@ __global__ void __launch_bounds__(256) lm_decide_kernel(LmState *lm, const doubl
 
 // Scalar part of the decision, run after the copies (single thread).
 __global__ void lm_finish_kernel(LmState *lm, const double *__restrict__ totals_cand, double *totals_cur,
-                                 double *log_row)
+                                 double *logbuf, int log_cap)
 {
+    // the row is chosen on the device so that every iteration launches identical arguments
+    double *log_row = logbuf + 8 * (int64_t)min(lm->iter, log_cap - 1);
     const double Fc = totals_cand[0];
     const bool solved = !lm->fail;
     const bool accept = solved && (!lm->use_lm || Fc < lm->F_cur);
@@ -358,14 +359,14 @@ __global__ void lm_finish_kernel(LmState *lm, const double *__restrict__ totals_
 
 void launch_lm_decide(LmState *lm, const double *totals_cand, int64_t nH, double *H_cur, const double *H_cand,
                       double *b_cur, const double *b_cand, double *X_cur, const double *X_cand, int N,
-                      double *totals_cur, double *log_row, hipStream_t st)
+                      double *totals_cur, double *logbuf, int log_cap, hipStream_t st)
 {
     int64_t blocks = (nH + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(lm_decide_kernel, dim3((unsigned)blocks), dim3(256), 0, st, lm, totals_cand, nH, H_cur, H_cand,
-                       b_cur, b_cand, 6 * N, X_cur, X_cand, 12 * N, log_row);
-    hipLaunchKernelGGL(lm_finish_kernel, dim3(1), dim3(1), 0, st, lm, totals_cand, totals_cur, log_row);
+                       b_cur, b_cand, 6 * N, X_cur, X_cand, 12 * N);
+    hipLaunchKernelGGL(lm_finish_kernel, dim3(1), dim3(1), 0, st, lm, totals_cand, totals_cur, logbuf, log_cap);
 }
 
 __global__ void copy_kernel(double *__restrict__ dst, const double *__restrict__ src, int64_t n)

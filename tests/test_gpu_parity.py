@@ -249,3 +249,18 @@ def test_multiblock_solve_and_lm(pba):
     _log("multiblock LM pose diff vs oracle: %.3g m %.3g rad" % (dt, dr))
     assert [l["accepted"] for l in logs] == [l["accepted"] for l in log_or]
     assert dt < 1e-6 and dr < 1e-6
+
+
+def test_graph_replays_match_eager_iterations(lidar_mini, pba):
+    """Each replay of the captured iteration graph gives bitwise the same poses and log as the
+    same kernels launched one by one; the host reads results between replays."""
+    prob = lidar_mini
+    with pba.context_for_problem(prob, use_graph=True) as cg, pba.context_for_problem(prob, use_graph=False) as ce:
+        for it in range(4):
+            lg = cg.iterate(1, use_lm=True, lambda0=1e-4 if it == 0 else 0.0)
+            le = ce.iterate(1, use_lm=True, lambda0=1e-4 if it == 0 else 0.0)
+            Xg, Xe = cg.get_poses(), ce.get_poses()
+            assert np.array_equal(Xg, Xe), it
+            assert lg == le, it
+        eg, ee = cg.evaluate(want_system=True), ce.evaluate(want_system=True)
+        assert np.array_equal(eg["H"], ee["H"])

@@ -3,8 +3,9 @@
 The pins in test_oracle_pins.py are only worth something if a plausible slip in
 the oracle trips them.  Each mutant below is one such slip (a sign, a factor,
 a transpose, the printed source-normal Jacobian, a dropped half in the central
-difference, the wrong depth cue); the checks are condensed versions of the
-pins: FD gradient, ground-truth residuals and the linear-ramp identity.
+difference, the wrong depth cue, two slips in the loss adjoint); the checks are
+condensed versions of the pins: FD gradient, ground-truth residuals, the
+linear-ramp identity and FD of the image gradients.
 """
 import os
 import subprocess
@@ -31,6 +32,10 @@ MUTANTS = {
                           "double gc00 = 1.0 * (T(y0, x0+1) - T(y0, x0-1));"),
     "pinhole_jac_sign": ("-v[0] * iz2, 0, v[2] * iz2", "v[0] * iz2, 0, v[2] * iz2"),
     "range_cue_as_depth": ("zeta[1] = st->model == 0 ? pbar[2] : range;", "zeta[1] = pbar[2];"),
+    "adjoint_depth_sign": ("g += k[ch] * (ac[0] * dp[0] + ac[1] * dp[1] + ac[2] * dp[2]);",
+                           "g -= k[ch] * (ac[0] * dp[0] + ac[1] * dp[1] + ac[2] * dp[2]);"),
+    "adjoint_normal_transpose": ("k[2] * RR[j] + k[3] * RR[3+j] + k[4] * RR[6+j];",
+                                 "k[2] * RR[3*j] + k[3] * RR[3*j+1] + k[4] * RR[3*j+2];"),
 }
 
 
@@ -65,6 +70,29 @@ def _ramp_ok(p, prm):
     return np.abs(a["H12"] - b["H12"]).max() <= 1e-9 * np.abs(b["H12"]).max()
 
 
+def _adj_ok(p, prm):
+    q = synth.Problem(p.name, p.sensors, p.kf_sensor, p.gt_poses, p.init_poses, p.pairs, prm)
+    q.intensity, q.depth, q.normals = list(p.intensity), list(p.depth), list(p.normals)
+    delta = np.zeros((q.n, 6))
+    r = oracle.loss_and_grad(q, q.init_poses, delta)
+    for arr, garr in (("depth", "gD"), ("normals", "gN")):
+        g = r[garr][1]
+        for i in np.argsort(-np.abs(g).ravel())[:2]:
+            imgs = getattr(q, arr)
+            orig = imgs[1]
+            vals = []
+            for sgn in (1, -1):
+                a = orig.copy()
+                a.ravel()[i] += sgn * 1e-4
+                imgs[1] = a
+                vals.append(oracle.evaluate(q, q.init_poses)["F"])
+            imgs[1] = orig
+            hp = float(np.float32(orig.ravel()[i] + 1e-4) - np.float32(orig.ravel()[i] - 1e-4))
+            if abs((vals[0] - vals[1]) / hp - g.ravel()[i]) > 1e-2 * abs(g.ravel()[i]):
+                return False
+    return True
+
+
 @pytest.fixture(scope="module")
 def problems():
     rg = synth.make("rgbd_small")
@@ -79,7 +107,7 @@ def _checks(problems):
     p5 = dict(rg.params, channels=5)
     l5 = dict(li.params, channels=5)
     return {"fd_rgbd": _fd_ok(rg, p5), "fd_lidar": _fd_ok(li, l5), "gt_rgbd": _gt_ok(rgc, p5),
-            "gt_lidar": _gt_ok(lic, l5), "ramp": _ramp_ok(rg, p5)}
+            "gt_lidar": _gt_ok(lic, l5), "ramp": _ramp_ok(rg, p5), "adjoint": _adj_ok(rg, p5)}
 
 
 def test_unmutated_oracle_passes_condensed_checks(problems):

@@ -391,3 +391,72 @@ def test_levenberg_marquardt_lidar_monotone(lidar_mini):
         e0 = np.linalg.norm(p.init_poses[k, 9:] - p.gt_poses[k, 9:])
         e1 = np.linalg.norm(X[k, 9:] - p.gt_poses[k, 9:])
         assert e1 < e0 / 3
+
+
+# ---------------------------------------------------------------- loss gradient (adjoint)
+
+def _loss_fd_delta(p, delta, k, j, h=1e-8):
+    dp, dm = delta.copy(), delta.copy()
+    dp[k, j] += h
+    dm[k, j] -= h
+    ep = oracle.evaluate(p, oracle.boxplus(p.init_poses, dp.ravel()))
+    em = oracle.evaluate(p, oracle.boxplus(p.init_poses, dm.ravel()))
+    if ep["n_valid"] != em["n_valid"]:
+        return None
+    return (ep["F"] - em["F"]) / (2 * h)
+
+
+@pytest.mark.parametrize("fixture", ["rgbd_small", "lidar_mini"])
+def test_loss_gradient_wrt_delta_matches_fd(fixture, request):
+    """dF/d delta of F(X0 boxplus delta) at a non-zero delta: chain rule through R(q) and the
+    quaternion right Jacobian L(q), checked by central differences."""
+    p = request.getfixturevalue(fixture)
+    prm = _params(p, **CH5)
+    q = synth.Problem(p.name, p.sensors, p.kf_sensor, p.gt_poses, p.init_poses, p.pairs, prm)
+    q.intensity, q.depth, q.normals = p.intensity, p.depth, p.normals
+    delta = np.random.default_rng(0).normal(size=(q.n, 6)) * 1e-3
+    r = oracle.loss_and_grad(q, q.init_poses, delta)
+    scale = np.abs(r["g_delta"]).max()
+    checked = 0
+    for k in range(q.n):
+        for j in range(6):
+            fd = _loss_fd_delta(q, delta, k, j)
+            if fd is None:
+                continue
+            checked += 1
+            assert abs(fd - r["g_delta"][k, j]) < 2e-5 * scale, (k, j, fd, r["g_delta"][k, j])
+    assert checked >= 6 * q.n - 2
+
+
+@pytest.mark.parametrize("fixture", ["rgbd_small", "lidar_mini"])
+def test_loss_gradient_wrt_images_matches_fd(fixture, request):
+    """dF/d(image texel) for intensity, depth and normals of a source and a target keyframe, at
+    the texels with the largest gradients, by central differences (masks frozen: cases where
+    the perturbation changes a mask are skipped)."""
+    p = request.getfixturevalue(fixture)
+    q = synth.Problem(p.name, p.sensors, p.kf_sensor, p.gt_poses, p.init_poses, p.pairs, _params(p, **CH5))
+    q.intensity, q.depth, q.normals = list(p.intensity), list(p.depth), list(p.normals)
+    delta = np.random.default_rng(1).normal(size=(q.n, 6)) * 1e-3
+    r = oracle.loss_and_grad(q, q.init_poses, delta)
+    X = oracle.boxplus(q.init_poses, delta.ravel())
+    checked = 0
+    for arr, garr in (("intensity", "gI"), ("depth", "gD"), ("normals", "gN")):
+        for kf in (0, 1):
+            g = r[garr][kf]
+            for i in np.argsort(-np.abs(g).ravel())[:3]:
+                imgs = getattr(q, arr)
+                orig = imgs[kf]
+                vals = []
+                for sgn in (1, -1):
+                    a = orig.copy()
+                    a.ravel()[i] += sgn * 1e-4
+                    imgs[kf] = a
+                    vals.append(oracle.evaluate(q, X))
+                imgs[kf] = orig
+                if vals[0]["n_valid"] != vals[1]["n_valid"]:
+                    continue
+                hp = float(np.float32(orig.ravel()[i] + 1e-4) - np.float32(orig.ravel()[i] - 1e-4))
+                fd = (vals[0]["F"] - vals[1]["F"]) / hp
+                assert abs(fd - g.ravel()[i]) < 1e-3 * abs(g.ravel()[i]), (arr, kf, i, fd, g.ravel()[i])
+                checked += 1
+    assert checked >= 15
