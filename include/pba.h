@@ -115,9 +115,11 @@ pba_status pba_destroy(pba_ctx *ctx);
 /* Register a sensor; *sensor_id receives its index (0, 1, ...).  Before any keyframe is loaded. */
 pba_status pba_add_sensor(pba_ctx *ctx, const pba_sensor *sensor, int32_t *sensor_id);
 
-/* Load n keyframes (replacing any loaded before): per keyframe its sensor id and pointers to its
- * intensity [H][W], depth [H][W] and normals [H][W][3] (normals may be NULL when channels == 2).
- * Depth outside [min_depth, max_depth] or not finite marks the pixel invalid. */
+/* Load n keyframes: per keyframe its sensor id and pointers to its intensity [H][W], depth [H][W]
+ * and normals [H][W][3] (normals may be NULL when channels == 2).  Depth outside [min_depth,
+ * max_depth] or not finite marks the pixel invalid.  If n and every keyframe's sensor equal the
+ * loaded ones, only the images are replaced and poses and pairs are kept; otherwise poses and
+ * pairs must be set again. */
 pba_status pba_load_keyframes(pba_ctx *ctx, int32_t n, const int32_t *sensor_id,
                               const float *const *intensity, const float *const *depth,
                               const float *const *normals, int32_t on_device);
@@ -169,6 +171,24 @@ typedef struct {
  * evaluated first only if no call has left it.  log (n_iters entries, nullable) is copied back
  * at the end.  Gauss-Newton returns PBA_ENOTPD if a system was not positive definite. */
 pba_status pba_iterate(pba_ctx *ctx, int32_t n_iters, int32_t use_lm, double lambda0, pba_iter_log *log);
+
+/* Photometric loss F(X0 boxplus delta) = sum over pairs and valid pixels of rho(chi^2)
+ * (Sec. IV-C, Eq. (total-error-multicue)), with X0 the current poses and delta [N][6] float32
+ * per pose [dt, dq] (X0 exp(delta), Supplementary).  Evaluates at X0 boxplus delta and keeps
+ * delta for pba_loss_backward.  *F_out (host) receives F, *n_valid_out (host, nullable) the number
+ * of valid correspondences.  The poses X0 are not changed. */
+pba_status pba_loss_forward(pba_ctx *ctx, const float *delta, int32_t on_device, double *F_out,
+                            int64_t *n_valid_out);
+
+/* Gradients of grad_F * F at the delta of the last pba_loss_forward, derived exactly for the
+ * sampled images (slope of the bilinear interpolant; masks, cells and occlusion decisions held
+ * as evaluated): grad_delta [N][6] (chain rule through R(dq) and the quaternion parameterisation)
+ * and, per keyframe k, grad_intensity[k] [H][W], grad_depth[k] [H][W], grad_normals[k] [H][W][3]
+ * (every array and every per-keyframe pointer nullable).  Image gradients are summed with atomic
+ * additions, so their last bits can vary between runs.  Projections are recomputed, nothing is
+ * stored per pixel between the two calls. */
+pba_status pba_loss_backward(pba_ctx *ctx, double grad_F, float *grad_delta, float *const *grad_intensity,
+                             float *const *grad_depth, float *const *grad_normals, int32_t on_device);
 
 /* Per-pixel view of one pair for inspection (host outputs, each nullable, source-image sized):
  * status (0 valid, 1 no depth, 2 not projectable, 3 outside, 4 invalid or occluded tap),

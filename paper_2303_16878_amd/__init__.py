@@ -27,8 +27,8 @@ PBA_PAIR_OUT_LEN = 160
 ABI_FUNCTIONS = (
     "pba_config_default", "pba_create", "pba_destroy", "pba_add_sensor", "pba_load_keyframes",
     "pba_set_poses", "pba_get_poses", "pba_set_pairs", "pba_evaluate", "pba_solve_step",
-    "pba_apply_step", "pba_iterate", "pba_debug_pair", "pba_get_timings", "pba_status_string",
-    "pba_last_error",
+    "pba_apply_step", "pba_iterate", "pba_loss_forward", "pba_loss_backward", "pba_debug_pair",
+    "pba_get_timings", "pba_status_string", "pba_last_error",
 )
 
 
@@ -91,6 +91,8 @@ def load_library(path: str = LIB_PATH):
         "pba_solve_step": (i32, [vp, f64, vp, i32]),
         "pba_apply_step": (i32, [vp, vp, i32]),
         "pba_iterate": (i32, [vp, i32, i32, f64, vp]),
+        "pba_loss_forward": (i32, [vp, vp, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]),
+        "pba_loss_backward": (i32, [vp, f64, vp, vp, vp, vp, i32]),
         "pba_debug_pair": (i32, [vp, i32, vp, vp, vp, vp]),
         "pba_get_timings": (i32, [vp, ctypes.POINTER(pba_timings), i32]),
         "pba_status_string": (ctypes.c_char_p, [i32]),
@@ -283,6 +285,50 @@ class Context:
         return [dict(F=l.F, lam=l.lambda_, step=l.step_norm, n_valid=l.n_valid, accepted=bool(l.accepted))
                 for l in logs[:n_iters]]
 
+    def loss_forward(self, delta, with_count=False):
+        """F(X0 boxplus delta) (delta: [N, 6] float32 numpy array or CUDA tensor); with_count also
+        returns the number of valid correspondences."""
+        p, dev, ka = _ptr(delta, np.float32)
+        F = ctypes.c_double()
+        nv = ctypes.c_int64()
+        self._check(self.lib.pba_loss_forward(self.h, p, dev, ctypes.byref(F), ctypes.byref(nv)))
+        return (F.value, nv.value) if with_count else F.value
+
+    def loss_backward(self, grad_F=1.0, grad_delta=None, grad_images=None):
+        """Gradients of grad_F * F at the last forward's delta.  grad_delta: [N, 6] float32 output
+        (numpy or CUDA tensor); grad_images: (I_list, D_list, N_list) of outputs (entries may be
+        None).  Outputs must all live on the same side (host or device)."""
+        keep = []
+        dev_flags = set()
+        gd = None
+        if grad_delta is not None:
+            gd, dev, ka = _ptr(grad_delta, np.float32)
+            keep.append(ka)
+            dev_flags.add(dev)
+        arrs = [None, None, None]
+        if grad_images is not None:
+            for j, lst in enumerate(grad_images):
+                if lst is None:
+                    continue
+                ps = (ctypes.c_void_p * self.n)()
+                for k, t in enumerate(lst):
+                    if t is None:
+                        continue
+                    if not _is_torch(t) and not (isinstance(t, np.ndarray) and t.dtype == np.float32
+                                                 and t.flags["C_CONTIGUOUS"]):
+                        raise TypeError("gradient outputs must be C-contiguous float32 arrays or tensors")
+                    p, dev, ka = _ptr(t, np.float32)
+                    keep.append(ka)
+                    dev_flags.add(dev)
+                    ps[k] = p
+                arrs[j] = ps
+        if len(dev_flags) > 1:
+            raise ValueError("mixing host and device gradient outputs")
+        on_dev = dev_flags.pop() if dev_flags else 0
+        cast = lambda a: ctypes.cast(a, ctypes.c_void_p) if a is not None else None
+        self._check(self.lib.pba_loss_backward(self.h, float(grad_F), gd, cast(arrs[0]), cast(arrs[1]),
+                                               cast(arrs[2]), on_dev))
+
     def debug_pair(self, pair, src_shape):
         H, W = src_shape
         status = np.empty((H, W), np.uint8)
@@ -322,3 +368,62 @@ def context_for_problem(prob, precision=PBA_F32, channels=None, grad_mode=0, dev
     ctx.set_poses(prob.init_poses if poses is None else poses)
     ctx.set_pairs(prob.pairs)
     return ctx
+
+
+# ------------------------------------------------------------------ autograd
+
+def _photometric_loss_function():
+    import torch
+
+    class PhotometricLoss(torch.autograd.Function):
+        """F(X0 boxplus delta, images) as a torch.autograd.Function.
+
+        forward(ctx, pba_context, delta, *images): images are the flat list
+        [I_0..I_{N-1}, D_0..D_{N-1}, N_0..N_{N-1}] of CUDA float32 tensors the context holds
+        (they are re-loaded into the context, so edits between calls are seen), or empty to use
+        the images already loaded.  Returns F as a 0-d float64 tensor on delta's device.
+        backward returns dF/d delta and dF/d image for every image tensor given."""
+
+        @staticmethod
+        def forward(ctx, pctx, delta, *images):
+            n = pctx.n
+            if images:
+                if len(images) not in (2 * n, 3 * n):
+                    raise ValueError("expected 2N or 3N image tensors")
+                I, D = list(images[:n]), list(images[n:2 * n])
+                Nn = list(images[2 * n:]) if len(images) == 3 * n else None
+                pctx.load_keyframes(pctx.kf_sensor, I, D, Nn)
+            d = delta.detach().to(torch.float32).contiguous()
+            F = pctx.loss_forward(d)
+            ctx.pctx = pctx
+            ctx.n_images = len(images)
+            ctx.shapes = [t.shape for t in images]
+            ctx.device = delta.device
+            ctx.delta_dtype = delta.dtype
+            return torch.tensor(F, dtype=torch.float64, device=delta.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            pctx = ctx.pctx
+            n = pctx.n
+            g_delta = torch.empty((n, 6), dtype=torch.float32, device=ctx.device)
+            outs = [torch.empty(sh, dtype=torch.float32, device=ctx.device) for sh in ctx.shapes]
+            lists = None
+            if ctx.n_images:
+                lists = (outs[:n], outs[n:2 * n], outs[2 * n:] if ctx.n_images == 3 * n else None)
+            torch.cuda.current_stream(ctx.device).synchronize()
+            pctx.loss_backward(float(grad_out.item()), g_delta, lists)
+            return (None, g_delta.to(ctx.delta_dtype)) + tuple(outs)
+
+    return PhotometricLoss
+
+
+_PL = None
+
+
+def photometric_loss(pctx, delta, images=()):
+    """F(X0 boxplus delta) with gradients for delta and the given image tensors (see PhotometricLoss)."""
+    global _PL
+    if _PL is None:
+        _PL = _photometric_loss_function()
+    return _PL.apply(pctx, delta, *images)

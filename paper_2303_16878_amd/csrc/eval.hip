@@ -212,7 +212,18 @@ struct WaveQueue {
     T ed[kQ], gxd[kQ], gyd[kQ]; // depth residual and depth-channel image Jacobian
 };
 
-template <typename T, int NCH, int SM, int TM, int GM, bool DBG>
+// b-only accumulation for the loss adjoint: acc_b += om * e * J
+template <typename T>
+__device__ __forceinline__ void accumulate_row_b(double *acc, const T (&J)[6], T e, T om)
+{
+    const double ome = (double)om * (double)e;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc[ACC_B + i] = fma(ome, (double)J[i], acc[ACC_B + i]);
+}
+
+// ADJ: the loss adjoint -- only b (gradient) is accumulated, and dF/d(image) is scattered into
+// the gradient arenas with hardware float atomics.
+template <typename T, int NCH, int SM, int TM, int GM, bool DBG, bool ADJ = false>
 __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base, int n_items)
 {
     __shared__ int s_item;
@@ -225,13 +236,28 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
     const L2 *lut = Lut<T>::ptr(a);
     constexpr bool F32 = std::is_same<T, float>::value;
 
+    // The items of a launch form kXcd contiguous queues; workgroups are dispatched round-robin
+    // over the XCDs, so workgroup w drains queue w % kXcd first (items that share target images
+    // stay on one XCD's L2), then helps with the others.  Every workgroup leaves once all
+    // queues are exhausted.
+    int q = 0;   // thread 0: queues tried so far
     for (;;) {
-        if (tid == 0) s_item = (int)atomicAdd(a.counter, 1u);
+        if (tid == 0) {
+            int got = -1;
+            while (q < kXcd) {
+                const int x = ((int)blockIdx.x + q) % kXcd;
+                const int lo = (int)((int64_t)n_items * x / kXcd), hi = (int)((int64_t)n_items * (x + 1) / kXcd);
+                const int v = (int)atomicAdd(a.counter + x, 1u);
+                if (v < hi - lo) { got = lo + v; break; }
+                ++q;
+            }
+            s_item = got;
+        }
         __syncthreads();
         const int it = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
-        if (it >= n_items) break;
-        const int item = item_base + it;
+        if (it < 0) break;
+        const int item = a.item_map ? a.item_map[item_base + it] : item_base + it;
         const int pair = __builtin_amdgcn_readfirstlane(a.item_pair[item]);
         const int px0 = __builtin_amdgcn_readfirstlane(a.item_px0[item]);
         const PairDev &pd = a.pairs[pair];
@@ -364,14 +390,18 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             }
             const T y2x = T(2) * (px + cc[0]), y2y = T(2) * (py + cc[1]), y2z = T(2) * (pz + cc[2]);
             T J[6];
+            // point-space derivatives a^c = d e^c / d p_bar
+            const T ag0 = -(Gxg * P00 + Gyg * P10), ag1 = -(Gxg * P01 + Gyg * P11), ag2 = -(Gxg * P02 + Gyg * P12);
+            const T ad0 = zx - (Gxd * P00 + Gyd * P10), ad1 = zy - (Gxd * P01 + Gyd * P11);
+            const T ad2 = zz - (Gxd * P02 + Gyd * P12);
             // intensity: a = -(Gx Pi0 + Gy Pi1)
-            row_from_a(J, -(Gxg * P00 + Gyg * P10), -(Gxg * P01 + Gyg * P11), -(Gxg * P02 + Gyg * P12), y2x, y2y,
-                       y2z);
-            accumulate_row(acc, J, eg, w * om_g);
+            row_from_a(J, ag0, ag1, ag2, y2x, y2y, y2z);
+            if (ADJ) accumulate_row_b(acc, J, eg, w * om_g);
+            else accumulate_row(acc, J, eg, w * om_g);
             // depth / range: a = d zeta / d p_bar - (Gx Pi0 + Gy Pi1)
-            row_from_a(J, zx - (Gxd * P00 + Gyd * P10), zy - (Gxd * P01 + Gyd * P11), zz - (Gxd * P02 + Gyd * P12),
-                       y2x, y2y, y2z);
-            accumulate_row(acc, J, ed, w * om_d);
+            row_from_a(J, ad0, ad1, ad2, y2x, y2y, y2z);
+            if (ADJ) accumulate_row_b(acc, J, ed, w * om_d);
+            else accumulate_row(acc, J, ed, w * om_d);
             if (NCH == 5) {
                 // normal rows: image term plus the rotation-only term 2 (e_k x n')
 #pragma unroll
@@ -381,8 +411,55 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                     if (k == 0) { J[4] -= T(2) * nr[2]; J[5] += T(2) * nr[1]; }
                     if (k == 1) { J[3] += T(2) * nr[2]; J[5] -= T(2) * nr[0]; }
                     if (k == 2) { J[3] -= T(2) * nr[1]; J[4] += T(2) * nr[0]; }
-                    accumulate_row(acc, J, en[k], w * om_n);
+                    if (ADJ) accumulate_row_b(acc, J, en[k], w * om_n);
+                    else accumulate_row(acc, J, en[k], w * om_n);
                 }
+            }
+            if (ADJ) {
+                // dF/de^c = 2 w Omega^c e^c (times the incoming gradient)
+                const T sc = (T)a.adj_scale * T(2) * w;
+                const T kg = sc * om_g * eg, kd = sc * om_d * ed;
+                const T kn0 = sc * om_n * en[0], kn1 = sc * om_n * en[1], kn2 = sc * om_n * en[2];
+                // target: e^c = zeta^c - V^c, V^c bilinear in the 4 taps
+                const int64_t toff = kt.off;
+                const int tap[4] = {idx[1], idx[2], idx[5], idx[6]};
+                const T wt[4] = {w00, w01, w10, w11};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t o = toff + tap[q];
+                    unsafeAtomicAdd(a.g_int + o, (float)(-kg * wt[q]));
+                    unsafeAtomicAdd(a.g_dep + o, (float)(-kd * wt[q]));
+                    if (NCH == 5) {
+                        unsafeAtomicAdd(a.g_nrm + 3 * o, (float)(-kn0 * wt[q]));
+                        unsafeAtomicAdd(a.g_nrm + 3 * o + 1, (float)(-kn1 * wt[q]));
+                        unsafeAtomicAdd(a.g_nrm + 3 * o + 2, (float)(-kn2 * wt[q]));
+                    }
+                }
+                // source intensity, normal (through R n_u) and depth (through p_bar = R d ray + t)
+                const int64_t so = ks.off + pix;
+                unsafeAtomicAdd(a.g_int + so, (float)kg);
+                int row = (int)__umulhi((uint32_t)pix, magic);
+                int col = pix - row * Ws;
+                if (col < 0) { row -= 1; col += Ws; }
+                const L2 lc = lcol[col], lr = lrow[row];
+                T rx, ry, rz;
+                if (SM == MODEL_SPHERICAL) { rx = lr.x * lc.x; ry = lr.x * lc.y; rz = lr.y; }
+                else { rx = lc.x; ry = lr.x; rz = T(1); }
+                const T dp0 = R[0] * rx + R[1] * ry + R[2] * rz;
+                const T dp1 = R[3] * rx + R[4] * ry + R[5] * rz;
+                const T dp2 = R[6] * rx + R[7] * ry + R[8] * rz;
+                T gd = kg * (ag0 * dp0 + ag1 * dp1 + ag2 * dp2) + kd * (ad0 * dp0 + ad1 * dp1 + ad2 * dp2);
+                if (NCH == 5) {
+                    const T kk[3] = {kn0, kn1, kn2};
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        gd += kk[k] * (-(Gxn[k] * P00 + Gyn[k] * P10) * dp0 - (Gxn[k] * P01 + Gyn[k] * P11) * dp1 -
+                                       (Gxn[k] * P02 + Gyn[k] * P12) * dp2);
+                    unsafeAtomicAdd(a.g_nrm + 3 * so, (float)(kn0 * R[0] + kn1 * R[3] + kn2 * R[6]));
+                    unsafeAtomicAdd(a.g_nrm + 3 * so + 1, (float)(kn0 * R[1] + kn1 * R[4] + kn2 * R[7]));
+                    unsafeAtomicAdd(a.g_nrm + 3 * so + 2, (float)(kn0 * R[2] + kn1 * R[5] + kn2 * R[8]));
+                }
+                unsafeAtomicAdd(a.g_dep + so, (float)gd);
             }
         };
 
@@ -439,6 +516,10 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         refined = fu < band || fu > 1.f - band || fv < band || fv > 1.f - band;
                     }
                     if (refined) {
+                        // Decide which side of the nearest integer each coordinate lies on exactly, in FP64:
+                        // u' >= k  <=>  the point is on the far side of the ray of column k (spherical: the
+                        // sign of Y cos az_k - X sin az_k, with (cos az_k, sin az_k) from the FP64 ray table;
+                        // pinhole: the sign of fx X - (k - cx) Z).  No transcendental is evaluated.
                         const double2 lcd = a.lut64[ss.lut_col + col], lrd = a.lut64[ss.lut_row + row];
                         const double dd = (double)Ds;
                         double q0, q1, q2;
@@ -448,21 +529,38 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         const double X = Rd[0] * q0 + Rd[1] * q1 + Rd[2] * q2 + td[0];
                         const double Y = Rd[3] * q0 + Rd[4] * q1 + Rd[5] * q2 + td[1];
                         const double Z = Rd[6] * q0 + Rd[7] * q1 + Rd[8] * q2 + td[2];
-                        double ud, vd;
-                        if (TM == MODEL_PINHOLE) {
-                            ud = st.fxd * X / Z + st.cxd;
-                            vd = st.fyd * Y / Z + st.cyd;
-                        } else {
-                            ud = st.fxd * atan2(Y, X) + st.cxd;
-                            vd = st.fyd * atan2(Z, sqrt(X * X + Y * Y)) + st.cyd;
+                        const float uf = (float)u, vf = (float)v;
+                        int xi = (int)floorf(uf), yi = (int)floorf(vf);
+                        const float ru = rintf(uf), rv = rintf(vf);
+                        if (fabsf(uf - ru) < band && ru >= 0.f && ru < (float)Wt) {
+                            const int k = (int)ru;
+                            bool ge;
+                            if (TM == MODEL_PINHOLE) {
+                                ge = st.fxd * X - ((double)k - st.cxd) * Z >= 0.0;
+                            } else {
+                                const double2 cs = a.lut64[st.lut_col + k];
+                                const double sd = Y * cs.x - X * cs.y;   // sign of az - az_k
+                                ge = st.fxd > 0.0 ? sd >= 0.0 : sd <= 0.0;
+                            }
+                            xi = ge ? k : k - 1;
+                        }
+                        if (fabsf(vf - rv) < band && rv >= 0.f && rv < (float)Ht) {
+                            const int k = (int)rv;
+                            bool ge;
+                            if (TM == MODEL_PINHOLE) {
+                                ge = st.fyd * Y - ((double)k - st.cyd) * Z >= 0.0;
+                            } else {
+                                const double2 cs = a.lut64[st.lut_row + k];
+                                const double sd = Z * cs.x - sqrt(X * X + Y * Y) * cs.y;   // sign of el - el_k
+                                ge = st.fyd > 0.0 ? sd >= 0.0 : sd <= 0.0;
+                            }
+                            yi = ge ? k : k - 1;
                         }
                         ++n_ref;
-                        if (DBG) a.dbg_uv[pix] = make_float2((float)ud, (float)vd);
-                        ok = ud >= 1.0 && ud < (double)(Wt - 2) && vd >= 1.0 && vd < (double)(Ht - 2);
+                        ok = xi >= 1 && xi <= Wt - 3 && yi >= 1 && yi <= Ht - 3;
                         if (ok) {
-                            const double fx0 = floor(ud), fy0 = floor(vd);
-                            x0 = (int)fx0; y0 = (int)fy0;
-                            al = (T)(ud - fx0); be = (T)(vd - fy0);
+                            x0 = xi; y0 = yi;
+                            al = u - (T)x0; be = v - (T)y0;
                         }
                     } else {
                         ok = u >= T(1) && u < (T)(Wt - 2) && v >= T(1) && v < (T)(Ht - 2);
@@ -542,6 +640,80 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
     }
 }
 
+template <int NCH, int SM, int TM>
+static void launch_adj_t(const EvalArgs &a, int item_base, int n_items, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((eval_kernel<float, NCH, SM, TM, 1, false, true>), dim3(grid), dim3(kBlock), 0, st, a,
+                       item_base, n_items);
+}
+
+void launch_eval_adjoint(const EvalArgs &a, int channels, int sm, int tm, int item_base, int n_items, int grid,
+                         hipStream_t st)
+{
+    const int key = (sm << 1) | tm;
+    if (channels == 5) {
+        switch (key) {
+        case 0: launch_adj_t<5, MODEL_PINHOLE, MODEL_PINHOLE>(a, item_base, n_items, grid, st); break;
+        case 1: launch_adj_t<5, MODEL_PINHOLE, MODEL_SPHERICAL>(a, item_base, n_items, grid, st); break;
+        case 2: launch_adj_t<5, MODEL_SPHERICAL, MODEL_PINHOLE>(a, item_base, n_items, grid, st); break;
+        default: launch_adj_t<5, MODEL_SPHERICAL, MODEL_SPHERICAL>(a, item_base, n_items, grid, st); break;
+        }
+    } else {
+        switch (key) {
+        case 0: launch_adj_t<2, MODEL_PINHOLE, MODEL_PINHOLE>(a, item_base, n_items, grid, st); break;
+        case 1: launch_adj_t<2, MODEL_PINHOLE, MODEL_SPHERICAL>(a, item_base, n_items, grid, st); break;
+        case 2: launch_adj_t<2, MODEL_SPHERICAL, MODEL_PINHOLE>(a, item_base, n_items, grid, st); break;
+        default: launch_adj_t<2, MODEL_SPHERICAL, MODEL_SPHERICAL>(a, item_base, n_items, grid, st); break;
+        }
+    }
+}
+
+// dF/d delta_k from b_k (= half the gradient with respect to the right perturbation at
+// X0 boxplus delta): translation rows R(q) (2 b_t), rotation rows L(q)^T (2 b_q) with
+// L(q) = w I + q q^T / w - [q]x, w = sqrt(1 - |q|^2) (quaternion right increment).
+__global__ void pose_grad_kernel(const double *__restrict__ b, const float *__restrict__ delta, double scale,
+                                 float *__restrict__ grad, int N)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    double qx = delta[6 * k + 3], qy = delta[6 * k + 4], qz = delta[6 * k + 5];
+    const double n2 = qx * qx + qy * qy + qz * qz;
+    double w;
+    if (n2 < 1.0) {
+        w = sqrt(1.0 - n2);
+    } else {    // the parameterisation normalises (1, q); its derivative is taken at the normalised q
+        const double s = 1.0 / sqrt(1.0 + n2);
+        w = s; qx *= s; qy *= s; qz *= s;
+    }
+    const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qz * w), 2 * (qx * qz + qy * w),
+                         2 * (qx * qy + qz * w), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qx * w),
+                         2 * (qx * qz - qy * w), 2 * (qy * qz + qx * w), 1 - 2 * (qx * qx + qy * qy)};
+    const double L[9] = {w + qx * qx / w, qx * qy / w + qz, qx * qz / w - qy,
+                         qy * qx / w - qz, w + qy * qy / w, qy * qz / w + qx,
+                         qz * qx / w + qy, qz * qy / w - qx, w + qz * qz / w};
+    const double *bt = b + 6 * (int64_t)k, *bq = bt + 3;
+    for (int i = 0; i < 3; ++i) {
+        grad[6 * k + i] = (float)(scale * 2.0 * (R[3 * i] * bt[0] + R[3 * i + 1] * bt[1] + R[3 * i + 2] * bt[2]));
+        grad[6 * k + 3 + i] = (float)(scale * 2.0 * (L[i] * bq[0] + L[3 + i] * bq[1] + L[6 + i] * bq[2]));
+    }
+}
+
+void launch_pose_grad(const double *b, const float *delta, double scale, float *grad, int N, hipStream_t st)
+{
+    hipLaunchKernelGGL(pose_grad_kernel, dim3((N + 127) / 128), dim3(128), 0, st, b, delta, scale, grad, N);
+}
+
+__global__ void delta_to_dx_kernel(const float *__restrict__ delta, double *__restrict__ dx, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dx[i] = (double)delta[i];
+}
+
+void launch_delta_to_dx(const float *delta, double *dx, int N, hipStream_t st)
+{
+    hipLaunchKernelGGL(delta_to_dx_kernel, dim3((6 * N + 255) / 256), dim3(256), 0, st, delta, dx, 6 * N);
+}
+
 template <typename T, int NCH, int SM, int TM, int GM, bool DBG>
 static void launch_eval_t(const EvalArgs &a, int item_base, int n_items, int grid, hipStream_t st)
 {
@@ -595,6 +767,7 @@ void launch_eval(const EvalArgs &a, int precision, int channels, int grad_mode, 
 //   H_tt = D^T S D, H_ss = E^T S E, H_st = E^T S D, H_ts = D^T S E, b_t = D^T beta, b_s = E^T beta
 // with D = blockdiag(R_ot^T, R_ot^T) and E = D A.
 __global__ void __launch_bounds__(64) reduce_pairs_kernel(const double *__restrict__ partials,
+                                                          const int32_t *__restrict__ pitems,
                                                           const int32_t *__restrict__ ibeg,
                                                           const int32_t *__restrict__ icnt,
                                                           const PairDev *__restrict__ pairs,
@@ -607,7 +780,7 @@ __global__ void __launch_bounds__(64) reduce_pairs_kernel(const double *__restri
     if (lane < kAcc) {
         double s = 0.0;
         const int b = ibeg[p], n = icnt[p];
-        for (int i = 0; i < n; ++i) s += partials[(int64_t)(b + i) * kAcc + lane];
+        for (int i = 0; i < n; ++i) s += partials[(int64_t)pitems[b + i] * kAcc + lane];
         sums[lane] = s;
     }
     __syncthreads();
@@ -668,13 +841,13 @@ __global__ void __launch_bounds__(64) reduce_pairs_kernel(const double *__restri
     }
 }
 
-void launch_reduce_pairs(const void *partials, int precision, const int32_t *ibeg, const int32_t *icnt,
-                         const PairDev *pairs, double *pair_out, int P, hipStream_t st)
+void launch_reduce_pairs(const void *partials, int precision, const int32_t *pitems, const int32_t *ibeg,
+                         const int32_t *icnt, const PairDev *pairs, double *pair_out, int P, hipStream_t st)
 {
     (void)precision;
     if (P <= 0) return;
-    hipLaunchKernelGGL(reduce_pairs_kernel, dim3(P), dim3(64), 0, st, static_cast<const double *>(partials), ibeg,
-                       icnt, pairs, pair_out, P);
+    hipLaunchKernelGGL(reduce_pairs_kernel, dim3(P), dim3(64), 0, st, static_cast<const double *>(partials), pitems,
+                       ibeg, icnt, pairs, pair_out, P);
 }
 
 // ------------------------------------------------------------------ assembly of the 6N x 6N system

@@ -11,6 +11,7 @@ constexpr int kAcc = 32;         // accumulator slots per work item
 // accumulator layout: 21 upper-triangular H terms, 6 b terms, F, valid, evaluated, refined
 enum { ACC_H = 0, ACC_B = 21, ACC_F = 27, ACC_VALID = 28, ACC_EVAL = 29, ACC_REF = 30, ACC_USED = 31 };
 constexpr int kPairOut = 160;    // PBA_PAIR_OUT_LEN
+constexpr int kXcd = 8;          // work queues per launch: one per accelerator complex die (XCD)
 enum { MODEL_PINHOLE = 0, MODEL_SPHERICAL = 1 };
 
 struct SensorDev {
@@ -51,11 +52,15 @@ struct EvalArgs {
     const double2 *lut64;        // ray tables, FP64
     const int32_t *item_pair;
     const int32_t *item_px0;
+    const int32_t *item_map;     // nullable: item = item_map[position] (per-pair launches)
     int32_t items_px;
     int32_t pad;
-    uint32_t *counter;
+    uint32_t *counter;           // kXcd queue counters of this launch
     void *partials;              // double[n_items][kAcc]
     double omega_g, omega_d, omega_n, huber, refine_band;
+    // loss adjoint outputs (adjoint launches only): arenas laid out like the images
+    float *g_int, *g_dep, *g_nrm;
+    double adj_scale;
     // per-pixel inspection outputs (debug launches only)
     uint8_t *dbg_status;
     float2 *dbg_uv;
@@ -68,9 +73,13 @@ void launch_pair_setup(const double *poses, const int2 *pairs, int P, const Sens
                        const KfDev *kfs, PairDev *out, uint32_t *counters, int ncounters, hipStream_t st);
 void launch_eval(const EvalArgs &a, int precision, int channels, int grad_mode, int src_model, int tgt_model,
                  bool debug, int item_base, int n_items, int grid, hipStream_t st);
-void launch_reduce_pairs(const void *partials, int precision, const int32_t *pair_item_begin,
-                         const int32_t *pair_item_count, const PairDev *pairs, double *pair_out, int P,
-                         hipStream_t st);
+void launch_eval_adjoint(const EvalArgs &a, int channels, int src_model, int tgt_model, int item_base, int n_items,
+                         int grid, hipStream_t st);
+void launch_pose_grad(const double *b, const float *delta, double scale, float *grad, int N, hipStream_t st);
+void launch_delta_to_dx(const float *delta, double *dx, int N, hipStream_t st);
+void launch_reduce_pairs(const void *partials, int precision, const int32_t *pair_items,
+                         const int32_t *pair_item_begin, const int32_t *pair_item_count, const PairDev *pairs,
+                         double *pair_out, int P, hipStream_t st);
 void launch_assemble(const double *pair_out, int P, const int2 *blk_rc, const int32_t *blk_ptr,
                      const int32_t *blk_ent, int nblk, const int32_t *bk_ptr, const int32_t *bk_ent, int N,
                      double *H, double *b, double *totals, hipStream_t st);

@@ -52,10 +52,12 @@ struct pba_ctx {
 
     // device buffers
     DevBuf sensors_d, kfs_d, dep, att4, att1, lut32, lut64;
-    DevBuf poses, poses_cand, pairs_d, pair_dev, item_pair, item_px0, ibeg, icnt, counters, partials, pair_out;
+    DevBuf poses, poses_cand, pairs_d, pair_dev, item_pair, item_px0, pitems, ibeg, icnt, counters, partials, pair_out;
     DevBuf blk_rc, blk_ptr, blk_ent, bk_ptr, bk_ent;
     DevBuf H, b, H_cand, b_cand, totals, A, Winv, dx, lm, fail, logbuf;
     DevBuf dbg_status, dbg_uv, dbg_cell, dbg_res;
+    DevBuf loss_delta, loss_poses, g_int, g_dep, g_nrm, g_pose;
+    bool loss_ready = false;
 
     // one captured LM iteration (replayed by pba_iterate)
     hipStream_t cap_stream = nullptr;
@@ -173,28 +175,49 @@ pba_status build_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::ve
         if (ka != kb) return ka < kb;
         return tgt[a] < tgt[b];
     });
-    std::vector<int32_t> ipair, ipx;
-    c->pair_item_begin.assign(P, 0);
-    c->pair_item_count.assign(P, 0);
-    c->groups.clear();
+    // items: (pair, first pixel); ordered by (model group, target keyframe, pixel band, pair) so
+    // that concurrently processed items read the same rows of the same target images
+    struct It { int key, tgt, band, pair, px; };
+    std::vector<It> items;
     for (int oi = 0; oi < P; ++oi) {
         const int p = order[oi];
-        const int sm = model_of(src[p]), tm = model_of(tgt[p]);
-        if (c->groups.empty() || c->groups.back().sm != sm || c->groups.back().tm != tm)
-            c->groups.push_back({sm, tm, (int)ipair.size(), 0});
+        const int key = model_of(src[p]) * 2 + model_of(tgt[p]);
         const int npx = c->kfs_h[src[p]].H * c->kfs_h[src[p]].W;
-        c->pair_item_begin[p] = (int32_t)ipair.size();
-        for (int px = 0; px < npx; px += c->items_px) {
-            ipair.push_back(p);
-            ipx.push_back(px);
-        }
-        c->pair_item_count[p] = (int32_t)ipair.size() - c->pair_item_begin[p];
-        c->groups.back().count = (int)ipair.size() - c->groups.back().base;
+        for (int px = 0, band = 0; px < npx; px += c->items_px, ++band) items.push_back({key, tgt[p], band, p, px});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const It &a, const It &b) {
+        if (a.key != b.key) return a.key < b.key;
+        if (a.tgt != b.tgt) return a.tgt < b.tgt;
+        if (a.band != b.band) return a.band < b.band;
+        return a.pair < b.pair;
+    });
+    std::vector<int32_t> ipair(items.size()), ipx(items.size());
+    c->groups.clear();
+    std::vector<std::vector<int32_t>> per_pair(P);
+    for (size_t i = 0; i < items.size(); ++i) {
+        const It &t = items[i];
+        ipair[i] = t.pair;
+        ipx[i] = t.px;
+        per_pair[t.pair].push_back((int32_t)i);
+        if (c->groups.empty() || c->groups.back().sm * 2 + c->groups.back().tm != t.key)
+            c->groups.push_back({t.key >> 1, t.key & 1, (int)i, 0});
+        c->groups.back().count = (int)i + 1 - c->groups.back().base;
+    }
+    // each pair's items in pixel order (the per-pair reduction sums them in this order)
+    std::vector<int32_t> pitems;
+    c->pair_item_begin.assign(P, 0);
+    c->pair_item_count.assign(P, 0);
+    for (int p = 0; p < P; ++p) {
+        std::sort(per_pair[p].begin(), per_pair[p].end(), [&](int32_t a, int32_t b) { return ipx[a] < ipx[b]; });
+        c->pair_item_begin[p] = (int32_t)pitems.size();
+        c->pair_item_count[p] = (int32_t)per_pair[p].size();
+        pitems.insert(pitems.end(), per_pair[p].begin(), per_pair[p].end());
     }
     c->n_items = (int)ipair.size();
     pba_status s;
     if ((s = upload(c, c->item_pair, ipair.data(), ipair.size() * 4))) return s;
     if ((s = upload(c, c->item_px0, ipx.data(), ipx.size() * 4))) return s;
+    if ((s = upload(c, c->pitems, pitems.data(), pitems.size() * 4))) return s;
     if ((s = upload(c, c->ibeg, c->pair_item_begin.data(), P * 4))) return s;
     if ((s = upload(c, c->icnt, c->pair_item_count.data(), P * 4))) return s;
     if ((s = ensure(c, c->partials, (size_t)std::max(1, c->n_items) * kAcc * sizeof(double)))) return s;
@@ -266,22 +289,22 @@ EvalArgs make_args(pba_ctx *c)
 pba_status run_eval(pba_ctx *c, const double *poses, double *H, double *b, double *totals, bool timed,
                     hipStream_t st)
 {
-    const int ncnt = (int)c->groups.size();
+    const int ngrp = (int)c->groups.size();
     launch_pair_setup(poses, P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->sensors_d), P_<KfDev>(c->kfs_d),
-                      P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ncnt, st);
+                      P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ngrp * kXcd, st);
     EvalArgs a = make_args(c);
     if (timed) HIP_OK(hipEventRecord(c->ev0, st));
-    for (int g = 0; g < ncnt; ++g) {
+    for (int g = 0; g < ngrp; ++g) {
         const auto &G = c->groups[g];
-        a.counter = P_<uint32_t>(c->counters) + g;
+        a.counter = P_<uint32_t>(c->counters) + g * kXcd;
         const int grid = std::max(1, std::min(G.count, c->grid));
         launch_eval(a, c->cfg.precision, c->cfg.channels, c->cfg.grad_mode, G.sm, G.tm, false, G.base, G.count, grid,
                     st);
     }
     if (timed) HIP_OK(hipEventRecord(c->ev1, st));
     HIP_OK(hipGetLastError());
-    launch_reduce_pairs(c->partials.p, c->cfg.precision, P_<int32_t>(c->ibeg), P_<int32_t>(c->icnt),
-                        P_<PairDev>(c->pair_dev), P_<double>(c->pair_out), c->P, st);
+    launch_reduce_pairs(c->partials.p, c->cfg.precision, P_<int32_t>(c->pitems), P_<int32_t>(c->ibeg),
+                        P_<int32_t>(c->icnt), P_<PairDev>(c->pair_dev), P_<double>(c->pair_out), c->P, st);
     launch_assemble(P_<double>(c->pair_out), c->P, P_<int2>(c->blk_rc), P_<int32_t>(c->blk_ptr),
                     P_<int32_t>(c->blk_ent), c->nblk, P_<int32_t>(c->bk_ptr), P_<int32_t>(c->bk_ent), c->N, H, b,
                     totals, st);
@@ -429,10 +452,11 @@ pba_status pba_destroy(pba_ctx *c)
     (void)hipSetDevice(c->cfg.device);
     (void)hipStreamSynchronize(c->stream);
     DevBuf *bufs[] = {&c->sensors_d, &c->kfs_d, &c->dep, &c->att4, &c->att1, &c->lut32, &c->lut64, &c->poses,
-                      &c->poses_cand, &c->pairs_d, &c->pair_dev, &c->item_pair, &c->item_px0, &c->ibeg, &c->icnt,
+                      &c->poses_cand, &c->pairs_d, &c->pair_dev, &c->item_pair, &c->item_px0, &c->pitems, &c->ibeg, &c->icnt,
                       &c->counters, &c->partials, &c->pair_out, &c->blk_rc, &c->blk_ptr, &c->blk_ent, &c->bk_ptr,
                       &c->bk_ent, &c->H, &c->b, &c->H_cand, &c->b_cand, &c->totals, &c->A, &c->Winv, &c->dx, &c->lm,
-                      &c->fail, &c->logbuf, &c->dbg_status, &c->dbg_uv, &c->dbg_cell, &c->dbg_res};
+                      &c->fail, &c->logbuf, &c->dbg_status, &c->dbg_uv, &c->dbg_cell, &c->dbg_res,
+                      &c->loss_delta, &c->loss_poses, &c->g_int, &c->g_dep, &c->g_nrm, &c->g_pose};
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) release(*b);
@@ -554,9 +578,14 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
     HIP_OK(hipStreamSynchronize(c->stream));
     release(stage);
     drop_graph(c);
+    bool same_layout = c->N == n && (int)c->kfs_h.size() == n;
+    for (int k = 0; same_layout && k < n; ++k) same_layout = c->kfs_h[k].sensor == kfs[k].sensor;
     c->kfs_h = kfs;
     c->sensors_dev_h = sd;
     c->texels = off;
+    c->system_valid = false;
+    c->loss_ready = false;
+    if (same_layout) return PBA_OK;   // images replaced; poses and pairs kept
     c->N = n;
     c->P = 0;
     c->poses_set = false;
@@ -783,6 +812,106 @@ pba_status pba_iterate(pba_ctx *c, int32_t n_iters, int32_t use_lm, double lambd
     return PBA_OK;
 }
 
+pba_status pba_loss_forward(pba_ctx *c, const float *delta, int32_t on_device, double *F_out, int64_t *n_valid_out)
+{
+    if (!c || !delta || !F_out) return fail(c, PBA_EINVAL, "null argument");
+    pba_status s;
+    if ((s = check_ready(c))) return s;
+    HIP_OK(hipSetDevice(c->cfg.device));
+    const int N = c->N;
+    if ((s = ensure(c, c->loss_delta, (size_t)N * 6 * 4))) return s;
+    if ((s = ensure(c, c->loss_poses, (size_t)N * 12 * 8))) return s;
+    if (on_device) {
+        HIP_OK(hipMemcpyAsync(c->loss_delta.p, delta, (size_t)N * 24, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        for (int i = 0; i < 6 * N; ++i)
+            if (!std::isfinite(delta[i])) return fail(c, PBA_EINVAL, "non-finite delta");
+        HIP_OK(hipMemcpyAsync(c->loss_delta.p, delta, (size_t)N * 24, hipMemcpyHostToDevice, c->stream));
+    }
+    // X = X0 boxplus delta (the step buffer is scratch here)
+    launch_delta_to_dx(P_<float>(c->loss_delta), P_<double>(c->dx), N, c->stream);
+    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->loss_poses), N, nullptr, nullptr,
+                   c->stream);
+    double *tot = P_<double>(c->totals) + 4;
+    if ((s = run_eval(c, P_<double>(c->loss_poses), P_<double>(c->H_cand), P_<double>(c->b_cand), tot, false,
+                      c->stream)))
+        return s;
+    double t[4];
+    HIP_OK(hipMemcpyAsync(t, tot, sizeof t, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    *F_out = t[0];
+    if (n_valid_out) *n_valid_out = (int64_t)t[2];
+    c->loss_ready = true;
+    return PBA_OK;
+}
+
+pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float *const *grad_intensity,
+                             float *const *grad_depth, float *const *grad_normals, int32_t on_device)
+{
+    if (!c) return PBA_EINVAL;
+    if (!std::isfinite(grad_F)) return fail(c, PBA_EINVAL, "non-finite grad_F");
+    pba_status s;
+    if ((s = check_ready(c))) return s;
+    if (!c->loss_ready) return fail(c, PBA_ESTATE, "pba_loss_backward needs a preceding pba_loss_forward");
+    HIP_OK(hipSetDevice(c->cfg.device));
+    const int N = c->N;
+    const int64_t tx = c->texels;
+    const bool five = c->cfg.channels == 5;
+    if ((s = ensure(c, c->g_int, (size_t)tx * 4))) return s;
+    if ((s = ensure(c, c->g_dep, (size_t)tx * 4))) return s;
+    if (five && (s = ensure(c, c->g_nrm, (size_t)tx * 12))) return s;
+    if ((s = ensure(c, c->g_pose, (size_t)N * 24))) return s;
+    // zero the gradient arenas with a fill kernel (as doubles over the byte range)
+    launch_fill(P_<double>(c->g_int), (int64_t)tx / 2, 0.0, c->stream);
+    launch_fill(P_<double>(c->g_dep), (int64_t)tx / 2, 0.0, c->stream);
+    if (tx & 1) {
+        HIP_OK(hipMemsetAsync(P_<float>(c->g_int) + tx - 1, 0, 4, c->stream));
+        HIP_OK(hipMemsetAsync(P_<float>(c->g_dep) + tx - 1, 0, 4, c->stream));
+    }
+    if (five) {
+        launch_fill(P_<double>(c->g_nrm), (int64_t)tx * 3 / 2, 0.0, c->stream);
+        if ((tx * 3) & 1) HIP_OK(hipMemsetAsync(P_<float>(c->g_nrm) + 3 * tx - 1, 0, 4, c->stream));
+    }
+    // recompute the evaluation at X0 boxplus delta in adjoint mode
+    const int ngrp = (int)c->groups.size();
+    launch_pair_setup(P_<double>(c->loss_poses), P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->sensors_d),
+                      P_<KfDev>(c->kfs_d), P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ngrp * kXcd,
+                      c->stream);
+    EvalArgs a = make_args(c);
+    a.g_int = P_<float>(c->g_int);
+    a.g_dep = P_<float>(c->g_dep);
+    a.g_nrm = five ? P_<float>(c->g_nrm) : nullptr;
+    a.adj_scale = grad_F;
+    for (int g = 0; g < ngrp; ++g) {
+        const auto &G = c->groups[g];
+        a.counter = P_<uint32_t>(c->counters) + g * kXcd;
+        launch_eval_adjoint(a, c->cfg.channels, G.sm, G.tm, G.base, G.count, std::max(1, std::min(G.count, c->grid)),
+                            c->stream);
+    }
+    HIP_OK(hipGetLastError());
+    launch_reduce_pairs(c->partials.p, 1, P_<int32_t>(c->pitems), P_<int32_t>(c->ibeg), P_<int32_t>(c->icnt),
+                        P_<PairDev>(c->pair_dev), P_<double>(c->pair_out), c->P, c->stream);
+    launch_assemble(P_<double>(c->pair_out), c->P, P_<int2>(c->blk_rc), P_<int32_t>(c->blk_ptr),
+                    P_<int32_t>(c->blk_ent), c->nblk, P_<int32_t>(c->bk_ptr), P_<int32_t>(c->bk_ent), N,
+                    P_<double>(c->H_cand), P_<double>(c->b_cand), P_<double>(c->totals) + 4, c->stream);
+    launch_pose_grad(P_<double>(c->b_cand), P_<float>(c->loss_delta), grad_F, P_<float>(c->g_pose), N, c->stream);
+    HIP_OK(hipGetLastError());
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (grad_delta) HIP_OK(hipMemcpyAsync(grad_delta, c->g_pose.p, (size_t)N * 24, kind, c->stream));
+    for (int k = 0; k < N; ++k) {
+        const size_t npx = (size_t)c->kfs_h[k].H * c->kfs_h[k].W;
+        const int64_t off = c->kfs_h[k].off;
+        if (grad_intensity && grad_intensity[k])
+            HIP_OK(hipMemcpyAsync(grad_intensity[k], P_<float>(c->g_int) + off, npx * 4, kind, c->stream));
+        if (grad_depth && grad_depth[k])
+            HIP_OK(hipMemcpyAsync(grad_depth[k], P_<float>(c->g_dep) + off, npx * 4, kind, c->stream));
+        if (five && grad_normals && grad_normals[k])
+            HIP_OK(hipMemcpyAsync(grad_normals[k], P_<float>(c->g_nrm) + 3 * off, npx * 12, kind, c->stream));
+    }
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return PBA_OK;
+}
+
 pba_status pba_debug_pair(pba_ctx *c, int32_t pair, uint8_t *status, float *uv, int32_t *cell, float *residuals)
 {
     if (!c) return PBA_EINVAL;
@@ -805,6 +934,7 @@ pba_status pba_debug_pair(pba_ctx *c, int32_t pair, uint8_t *status, float *uv, 
     launch_fill(P_<double>(c->dbg_res), (int64_t)npx * 20 / 8, 0.0, c->stream);
     EvalArgs a = make_args(c);
     a.counter = P_<uint32_t>(c->counters);
+    a.item_map = P_<int32_t>(c->pitems);
     a.dbg_status = P_<uint8_t>(c->dbg_status);
     a.dbg_uv = P_<float2>(c->dbg_uv);
     a.dbg_cell = P_<int2>(c->dbg_cell);

@@ -45,51 +45,65 @@ void launch_damp_copy(const double *H, const double *b, double *A, double *rhs, 
 // form the panel below as X = B W^T with W = L_kk^-1 (tiled product), then update the
 // trailing lower triangle.  The inverted diagonal blocks are kept for the solves.
 
-// Factor the diagonal block at k0 in LDS and write L_kk (lower) to A and W = L_kk^-1 (lower,
-// row-major 64 x 64, zero above the diagonal) to Winv.  One wave: lane i owns row i.
+__device__ __forceinline__ double bcast(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Factor the diagonal block at k0 and write L_kk (lower) to A and W = L_kk^-1 (lower, row-major
+// 64 x 64, zero above the diagonal) to Winv.  One wave; lane i keeps row i of L and of W in
+// registers and column entries are broadcast with readlane.  A ragged last block is padded with
+// the identity, whose factor and inverse are the identity.
 __global__ void __launch_bounds__(64) chol_diag_kernel(double *A, int n, int k0, double *Winv, int32_t *fail)
 {
-    __shared__ double L[NB][NB + 1];
-    __shared__ double W[NB][NB + 1];
     if (*fail) return;
     const int nb = min(NB, n - k0);
     const int lane = threadIdx.x;
-    for (int i = 0; i < nb; ++i) L[i][lane] = lane < nb ? A[(int64_t)(k0 + i) * n + k0 + lane] : 0.0;
-    __builtin_amdgcn_wave_barrier();
-    __syncthreads();
+    double r[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        r[k] = (lane < nb && k < nb) ? A[(int64_t)(k0 + lane) * n + k0 + k] : (k == lane ? 1.0 : 0.0);
     bool bad = false;
-    for (int j = 0; j < nb; ++j) {
-        const double d = L[j][j];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const double d = bcast(r[j], j);
         bad = bad || !(d > 0.0);
         const double sd = d > 0.0 ? sqrt(d) : 1.0;
-        __syncthreads();
-        if (lane == j) L[j][j] = sd;
-        if (lane > j && lane < nb) L[lane][j] /= sd;
-        __syncthreads();
-        if (lane > j && lane < nb) {
-            const double lij = L[lane][j];
-            for (int k = j + 1; k <= lane; ++k) L[lane][k] -= lij * L[k][j];
-        }
-        __syncthreads();
-    }
-    // W = L^-1, column c by lane c (forward substitution on the unit vector e_c)
-    if (lane < nb) {
-        const int c = lane;
-        for (int i = 0; i < c; ++i) W[i][c] = 0.0;
-        W[c][c] = 1.0 / L[c][c];
-        for (int i = c + 1; i < nb; ++i) {
-            double s = 0.0;
-            for (int m = c; m < i; ++m) s += L[i][m] * W[m][c];
-            W[i][c] = -s / L[i][i];
+        const double inv = 1.0 / sd;
+        r[j] = lane == j ? sd : (lane > j ? r[j] * inv : r[j]);
+#pragma unroll
+        for (int k = j + 1; k < NB; ++k) {
+            const double lkj = bcast(r[j], k);
+            if (lane >= k) r[k] = fma(-r[j], lkj, r[k]);
         }
     }
-    __syncthreads();
+    // W = L^-1 row by row: row m is final once divided by L_mm, then removed from the rows below
+    double w[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) w[c] = c == lane ? 1.0 : 0.0;
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+        const double dm = bcast(r[m], m);
+        const double im = 1.0 / dm;
+        if (lane == m) {
+#pragma unroll
+            for (int c = 0; c <= m; ++c) w[c] *= im;
+        }
+#pragma unroll
+        for (int c = 0; c <= m; ++c) {
+            const double wmc = bcast(w[c], m);
+            if (lane > m) w[c] = fma(-r[m], wmc, w[c]);
+        }
+    }
     double *Wb = Winv + (int64_t)(k0 / NB) * NB * NB;
-    for (int i = 0; i < NB; ++i) {
-        Wb[i * NB + lane] = (i < nb && lane < nb) ? W[i][lane] : 0.0;
-        if (i < nb && lane <= i) A[(int64_t)(k0 + i) * n + k0 + lane] = L[i][lane];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        Wb[lane * NB + k] = (lane < nb && k < nb && k <= lane) ? w[k] : 0.0;
+        if (lane < nb && k <= lane) A[(int64_t)(k0 + lane) * n + k0 + k] = r[k];
     }
-    if (lane == 0 && bad) *fail = 1;
+    if (lane == 0 && __any(bad)) *fail = 1;
 }
 
 // Panel below the diagonal block: X = B W^T for 64 rows per workgroup (16 x 16 threads, 4 x 4 each).

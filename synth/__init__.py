@@ -476,11 +476,64 @@ def lidar128(seed=4, **kw):
     return lidar_loop("lidar128", seed, **kw)
 
 
-CONFIGS = {"rgbd_small": rgbd_small, "rgbd_room": rgbd_room, "lidar64": lidar64, "lidar128": lidar128}
+def plane_pair(model="pinhole", seed=7):
+    """One large textured plane seen by three keyframes; keyframe 0 is the only source and keeps
+    depth only in a central window (outside it the depth is 0, i.e. no measurement), keyframes 1 and 2 are targets whose whole view is the plane.  With small pose
+    offsets every source pixel warps well inside the targets and no tap meets a depth edge, so the
+    set of valid correspondences does not change under small pose steps (a fixture for finite
+    differences of the loss with respect to the poses)."""
+    rng = np.random.default_rng(seed)
+    if model == "pinhole":
+        sen = pinhole_sensor(96, 128, 100.0, 100.0, 64.0, 48.0, min_depth=0.1, max_depth=20.0)
+        fwd = np.array([0.0, 1.0, 0.0])
+        c = np.array([0.0, 3.0, 0.0])
+        look = _look_frame_camera
+        h1 = h2 = 6.0
+        margin = (0.25, 0.25)
+    else:
+        sen = spherical_sensor(32, 512, el_up_deg=8.0, el_down_deg=-25.0, min_depth=0.5, max_depth=40.0)
+        fwd = np.array([1.0, 0.0, 0.0])
+        c = np.array([8.0, 0.0, -1.5])
+        look = _look_frame_lidar
+        h1, h2 = 30.0, 8.0
+        margin = (0.25, 0.42)
+    # plane facing the sensors: e1 horizontal, e2 = n x e1
+    e1 = np.array([1.0, 0.0, 0.0]) if model == "pinhole" else np.array([0.0, 1.0, 0.0])
+    e2 = np.cross(-fwd, e1)
+    rect = _rect(c, e1, e2, h1, h2, _random_texture(rng))
+    gt = []
+    for k in range(3):
+        pos = np.array([0.0, 0.0, 0.0]) + 0.15 * np.array([math.cos(2.1 * k), 0.0, math.sin(2.1 * k)]) * (k > 0)
+        pos = pos if model == "pinhole" else pos[[1, 0, 2]]
+        gt.append(np.concatenate([look(fwd).reshape(-1), pos]))
+    gt = np.array(gt)
+    init = _perturb(gt, np.random.default_rng(200 + seed), 0.02, 0.5, anchor=-1)
+    params = dict(DEFAULT_PARAMS, channels=5, iterations=5, lm=False)
+    scene = dict(rects=np.array([rect], dtype=RECT_DTYPE), ground=0, ground_tex=np.zeros((NSIN, 4)), noise_i=0.01,
+                 noise_d=0.005, seed=seed)
+    prob = Problem("plane_pair_" + model, [sen], np.zeros(3, np.int32), gt, init,
+                   np.array([(0, 1), (0, 2)], np.int32), params, scene=scene)
+    prob._source_margin = margin
+    return prob
+
+
+def _mask_source(prob):
+    m = getattr(prob, "_source_margin", None)
+    if m is None or not prob.depth or prob.depth[0] is None:
+        return prob
+    H, W = prob.depth[0].shape
+    keep = np.zeros((H, W), bool)
+    keep[int(m[0] * H):H - int(m[0] * H), int(m[1] * W):W - int(m[1] * W)] = True
+    prob.depth[0] = np.where(keep, prob.depth[0], np.float32(0.0)).astype(np.float32)
+    return prob
+
+
+CONFIGS = {"rgbd_small": rgbd_small, "rgbd_room": rgbd_room, "lidar64": lidar64, "lidar128": lidar128, "plane_pair": plane_pair}
 
 
 def make(name, render_images=True, noise=True, kfs=None, **kw):
     prob = CONFIGS[name](**kw)
     if render_images:
         render(prob, kfs=kfs, noise=noise)
+        _mask_source(prob)
     return prob

@@ -1,0 +1,211 @@
+"""GPU loss F(X0 boxplus delta, images) and its hand-written adjoint, through the C ABI and the
+torch.autograd.Function, against the FP64 oracle gradient and central finite differences.
+
+Tolerances: pose gradient within 1e-4 of max|g| of the oracle's; image gradients in relative L2
+1e-3 with 99.9% of texels within 1e-3 of max|g| (FP32 path: a few pixels near cell boundaries
+take the other cell, and atomic sums round in varying order); central differences of the GPU loss
+in single texels within 1e-3 |g| + 1e-4 max|g|.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pba():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2303_16878_amd as pba
+    pba.load_library()
+    return pba
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _prob5(p):
+    q = synth.Problem(p.name, p.sensors, p.kf_sensor, p.gt_poses, p.init_poses, p.pairs, dict(p.params, channels=5))
+    q.intensity, q.depth, q.normals = list(p.intensity), list(p.depth), list(p.normals)
+    return q
+
+
+def _compare_images(g_gpu, g_orc, what):
+    a = np.concatenate([np.ravel(x) for x in g_gpu])
+    b = np.concatenate([np.ravel(x) for x in g_orc])
+    scale = np.abs(b).max()
+    rel_l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+    frac_bad = np.mean(np.abs(a - b) > 1e-3 * scale)
+    _log("  %s: rel L2 %.2e, texels beyond 1e-3: %.2e" % (what, rel_l2, frac_bad))
+    assert rel_l2 < 1e-3 and frac_bad < 1e-3, what
+
+
+@pytest.mark.parametrize("fixture", ["rgbd_small", "lidar_mini"])
+def test_loss_gradients_match_oracle(fixture, request, pba):
+    p = _prob5(request.getfixturevalue(fixture))
+    delta = (np.random.default_rng(3).normal(size=(p.n, 6)) * 1e-3).astype(np.float32)
+    ref = oracle.loss_and_grad(p, p.init_poses, delta.astype(np.float64))
+    with pba.context_for_problem(p) as ctx:
+        F = ctx.loss_forward(delta)
+        gd = np.empty((p.n, 6), np.float32)
+        gI = [np.empty(p.depth[k].shape, np.float32) for k in range(p.n)]
+        gD = [np.empty(p.depth[k].shape, np.float32) for k in range(p.n)]
+        gN = [np.empty(p.depth[k].shape + (3,), np.float32) for k in range(p.n)]
+        ctx.loss_backward(1.0, gd, (gI, gD, gN))
+    _log(fixture, "F gpu %.9g oracle %.9g" % (F, ref["F"]))
+    assert abs(F - ref["F"]) <= 1e-5 * ref["F"]
+    scale = np.abs(ref["g_delta"]).max()
+    assert np.abs(gd - ref["g_delta"]).max() <= 1e-4 * scale, (gd, ref["g_delta"])
+    _compare_images(gI, ref["gI"], "intensity")
+    _compare_images(gD, ref["gD"], "depth")
+    _compare_images(gN, ref["gN"], "normals")
+
+
+@pytest.mark.parametrize("model", ["pinhole", "spherical"])
+def test_loss_pose_gradient_vs_fp32_finite_differences(model, pba):
+    """Central differences of the GPU loss in every FP32 pose-tangent component, eps = 1e-4, on a
+    one-plane scene whose valid set cannot change under such steps (the source keyframe measures
+    depth only in a central window, the targets see nothing but the plane).  F is then continuous
+    and smooth except where a pixel changes cell (the interpolant's slope jumps), so the
+    difference quotient over +-eps stays within 2% of max|g| of the adjoint (the FP64 oracle on the
+    same fixture: 0.6%)."""
+    p = synth.make("plane_pair", model=model)
+    eps = np.float32(1e-4)
+    h = 2.0 * float(eps)
+    with pba.context_for_problem(p) as ctx:
+        delta = np.zeros((p.n, 6), np.float32)
+        F0, n0 = ctx.loss_forward(delta, with_count=True)
+        gd = np.empty((p.n, 6), np.float32)
+        ctx.loss_backward(1.0, gd)
+        scale = np.abs(gd).max()
+        errs = np.zeros((p.n, 6))
+        for k in range(p.n):
+            for j in range(6):
+                d = delta.copy()
+                d[k, j] = eps
+                Fp, np_ = ctx.loss_forward(d, with_count=True)
+                d[k, j] = -eps
+                Fm, nm = ctx.loss_forward(d, with_count=True)
+                assert np_ == nm == n0, (k, j, np_, nm, n0)
+                errs[k, j] = abs((Fp - Fm) / h - gd[k, j]) / scale
+    _log(model, "pose FD eps=1e-4 over %d components: max err %.3g of max|g| (%.4g)" % (errs.size, errs.max(), scale))
+    assert errs.max() < 2e-2, errs
+
+
+def _texels(g, k_top, k_rand, rng):
+    """Indices of the k_top largest |g| entries and k_rand random entries with g != 0."""
+    flat = np.abs(g.ravel())
+    top = np.argsort(flat)[::-1][:k_top]
+    nz = np.flatnonzero(flat)
+    rand = rng.choice(nz, size=min(k_rand, nz.size), replace=False) if nz.size else np.array([], int)
+    return np.unique(np.concatenate([top, rand]))
+
+
+@pytest.mark.parametrize("fixture", ["rgbd_small", "lidar_mini"])
+def test_loss_image_gradient_vs_fp32_finite_differences(fixture, request, pba):
+    """Central differences of the GPU loss itself with respect to single texels.  Intensity and
+    normal texels never change which correspondences are valid, so F is smooth in them (up to the
+    Huber kink); a depth texel can move a warp or flip an occlusion test, and a depth difference
+    whose +-eps evaluations change the valid count is skipped (counted).  Pose components are not
+    differenced here: at these sizes almost every +-eps pose step changes the valid set somewhere,
+    so the pose gradient is tied to the oracle's, whose own differences use realised steps and
+    frozen masks.  Bar: |FD - g| <= 1e-3 |g| + 1e-4 max|g| per texel (FP32 residuals, F summed in
+    FP64 in a fixed order, so F(+eps) - F(-eps) carries only the changed pixels' rounding)."""
+    p = _prob5(request.getfixturevalue(fixture))
+    rng = np.random.default_rng(11)
+    delta = np.zeros((p.n, 6), np.float32)
+    I = [a.astype(np.float32).copy() for a in p.intensity]
+    D = [a.astype(np.float32).copy() for a in p.depth]
+    Nn = [a.astype(np.float32).copy() for a in p.normals]
+    with pba.context_for_problem(p) as ctx:
+        F0, n0 = ctx.loss_forward(delta, with_count=True)
+        gI = [np.empty(a.shape, np.float32) for a in I]
+        gD = [np.empty(a.shape, np.float32) for a in D]
+        gN = [np.empty(a.shape, np.float32) for a in Nn]
+        ctx.loss_backward(1.0, None, (gI, gD, gN))
+        for what, imgs, grads, eps in (("intensity", I, gI, 1e-3), ("normal", Nn, gN, 1e-3),
+                                       ("depth", D, gD, 1e-4)):
+            scale = max(np.abs(g).max() for g in grads)
+            checked, skipped, worst = 0, 0, 0.0
+            for k in range(p.n):
+                for idx in _texels(grads[k], 4, 4, rng):
+                    flat = imgs[k].reshape(-1)
+                    v0 = flat[idx]
+                    vals = []
+                    for sgn in (1.0, -1.0):
+                        flat[idx] = np.float32(v0 + sgn * eps)
+                        ctx.load_keyframes(p.kf_sensor, I, D, Nn)
+                        vals.append(ctx.loss_forward(delta, with_count=True))
+                    flat[idx] = v0
+                    (Fp, np_), (Fm, nm) = vals
+                    if np_ != nm:
+                        skipped += 1
+                        continue
+                    h = float(np.float32(v0 + eps)) - float(np.float32(v0 - eps))
+                    fd = (Fp - Fm) / h
+                    g = float(grads[k].reshape(-1)[idx])
+                    err = abs(fd - g)
+                    worst = max(worst, err / (1e-3 * abs(g) + 1e-4 * scale))
+                    checked += 1
+                    assert err <= 1e-3 * abs(g) + 1e-4 * scale, (what, k, idx, fd, g)
+            _log(fixture, "%s FD eps=%g: checked %d texels, skipped %d (valid count changed), worst %.2f of bar"
+                 % (what, eps, checked, skipped, worst))
+            assert checked >= 0.75 * (checked + skipped) and checked > 0
+        ctx.load_keyframes(p.kf_sensor, I, D, Nn)
+        assert ctx.loss_forward(delta, with_count=True) == (F0, n0)
+
+
+def test_autograd_function(lidar_mini, pba):
+    import torch
+    p = _prob5(lidar_mini)
+    dev = torch.device("cuda")
+    I = [torch.tensor(a, device=dev, requires_grad=True) for a in p.intensity]
+    D = [torch.tensor(a, device=dev, requires_grad=True) for a in p.depth]
+    Nn = [torch.tensor(a, device=dev, requires_grad=True) for a in p.normals]
+    delta = torch.zeros((p.n, 6), dtype=torch.float32, device=dev, requires_grad=True)
+    with pba.context_for_problem(p) as ctx:
+        loss = pba.photometric_loss(ctx, delta, I + D + Nn)
+        loss.backward()
+        ref = oracle.loss_and_grad(p, p.init_poses, np.zeros((p.n, 6)))
+        g = delta.grad.cpu().numpy()
+        assert np.abs(g - ref["g_delta"]).max() <= 1e-4 * np.abs(ref["g_delta"]).max()
+        _compare_images([t.grad.cpu().numpy() for t in D], ref["gD"], "autograd depth")
+        # the images are re-read on every forward: editing one changes F
+        saved = I[1].detach().clone()
+        with torch.no_grad():
+            I[1] += 0.01
+        loss2 = pba.photometric_loss(ctx, delta, I + D + Nn)
+        assert abs(float(loss2) - float(loss)) > 0
+        with torch.no_grad():
+            I[1].copy_(saved)
+        loss3 = pba.photometric_loss(ctx, delta, I + D + Nn)
+        assert float(loss3) == float(loss)
+
+
+def test_loss_full_size_sampled_pairs(pba):
+    """128x2048 LiDAR keyframes, a sample of 24 pairs: GPU adjoint against the oracle."""
+    full = synth.make("lidar128")
+    pairs = full.pairs[np.linspace(0, len(full.pairs) - 1, 24).astype(int)]
+    used = sorted(set(pairs.ravel().tolist()))
+    p = full.subset(used)
+    remap = {k: i for i, k in enumerate(used)}
+    p.pairs = np.array([(remap[s], remap[t]) for s, t in pairs], np.int32)
+    delta = (np.random.default_rng(4).normal(size=(p.n, 6)) * 1e-4).astype(np.float32)
+    ref = oracle.loss_and_grad(p, p.init_poses, delta.astype(np.float64))
+    with pba.context_for_problem(p) as ctx:
+        F = ctx.loss_forward(delta)
+        gd = np.empty((p.n, 6), np.float32)
+        gI = [np.empty(p.depth[k].shape, np.float32) for k in range(p.n)]
+        ctx.loss_backward(1.0, gd, (gI, None, None))
+    _log("full-size F gpu %.9g oracle %.9g" % (F, ref["F"]))
+    assert abs(F - ref["F"]) <= 1e-5 * ref["F"]
+    assert np.abs(gd - ref["g_delta"]).max() <= 1e-4 * np.abs(ref["g_delta"]).max()
+    _compare_images(gI, ref["gI"], "full-size intensity")
