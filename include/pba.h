@@ -76,7 +76,7 @@ enum { PBA_F32 = 0, PBA_F64 = 1 };
 /* A sensor model (Sec. III) and its rigid offset on the platform (Supplementary). */
 typedef struct {
     int32_t model;               /* PBA_PINHOLE or PBA_SPHERICAL */
-    int32_t height, width;       /* image size H, W: >= 4 each and H * W * W < 2^32 */
+    int32_t height, width;       /* image size H, W: >= 4 each, H * W * W < 2^32, H * W <= 2^26 */
     int32_t pad;
     double fx, fy, cx, cy;       /* K: focal / angular resolution and offsets, in pixels */
     double min_depth, max_depth; /* valid depth (pinhole) or range (spherical) interval, metres */
@@ -189,6 +189,38 @@ pba_status pba_loss_forward(pba_ctx *ctx, const float *delta, int32_t on_device,
  * stored per pixel between the two calls. */
 pba_status pba_loss_backward(pba_ctx *ctx, double grad_F, float *grad_delta, float *const *grad_intensity,
                              float *const *grad_depth, float *const *grad_normals, int32_t on_device);
+
+/* Coarse-to-fine image pyramid (Sec. IV-A: every keyframe is kept at several resolutions, each
+ * half the one below; Sec. IV-C: optimisation runs from the coarsest level to the finest).
+ * Builds n_levels levels (1..8; level 0 = the loaded images) on the device: level l + 1 takes
+ * each 2x2 block of level l (odd last row/column dropped) -- depth: the block mean if all four
+ * depths are valid and within the occlusion tau of each other, else no measurement; intensity:
+ * the mean; normals: the mean scaled to unit length.  Level intrinsics: fx/2, fy/2,
+ * (cx - 1/2)/2, (cy - 1/2)/2, floor(H/2) x floor(W/2) (pixel centres at integer coordinates).
+ * Poses and pairs are shared by all levels.  PBA_ESTATE without keyframes; PBA_EINVAL if
+ * n_levels is out of range or a level would be smaller than 4 x 4.  Loading keyframes drops the
+ * pyramid.  The active level stays selected if it still exists, else level 0 becomes active. */
+pba_status pba_build_pyramid(pba_ctx *ctx, int32_t n_levels);
+
+/* Select the level that pba_evaluate, pba_solve_step, pba_iterate, the loss calls and
+ * pba_debug_pair work on (image-sized outputs then have that level's size).  The system held
+ * for the previous level is dropped; LM damping restarts at the next lambda0 > 0. */
+pba_status pba_set_level(pba_ctx *ctx, int32_t level);
+
+/* Coarse-to-fine optimisation (Sec. IV-C): for level = n_levels - 1 down to 0, select the level
+ * and run up to iters[level] iterations (pba_iterate semantics, damping restarting at lambda0
+ * on every level); move to the next finer level as soon as an accepted iteration lowers F by
+ * less than rel_tol relative to F before it.  log (nullable, sum(iters) entries) receives the
+ * iterations run, level_of (nullable, same length) their level, *n_done (nullable) their
+ * number.  Level 0 is active afterwards. */
+pba_status pba_optimize_pyramid(pba_ctx *ctx, const int32_t *iters, double rel_tol, int32_t use_lm, double lambda0,
+                                pba_iter_log *log, int32_t *level_of, int32_t *n_done);
+
+/* Inspection: one keyframe's images at a level, in the caller's layout (host arrays, each
+ * nullable): intensity [H][W], depth [H][W] (0 where there is no measurement), normals
+ * [H][W][3]; dims (nullable) receives {H, W} of that level. */
+pba_status pba_get_level_image(pba_ctx *ctx, int32_t level, int32_t kf, float *intensity, float *depth,
+                               float *normals, int32_t *dims);
 
 /* Per-pixel view of one pair for inspection (host outputs, each nullable, source-image sized):
  * status (0 valid, 1 no depth, 2 not projectable, 3 outside, 4 invalid or occluded tap),

@@ -312,6 +312,108 @@ def optimize(prob, poses0, iters=10, lm=False, params=None, lam0=1e-4, anchor=0,
     return X, log
 
 
+# ------------------------------------------------------------------ image pyramid
+
+def level_sensor(sen):
+    """Intrinsics of the half-resolution level above `sen` (Sec. IV-A: each pyramid level has
+    half the resolution of the one below).  Texel j of the new level covers texels 2j and 2j + 1
+    of the old one, whose centres lie at 2j and 2j + 1, so the coordinates are related by
+    u_old = 2 u_new + 1/2.  Both projections are affine in the image coordinates (pinhole K,
+    spherical K_[1,2]), so the new level keeps the model with fx/2, fy/2, (cx - 1/2)/2,
+    (cy - 1/2)/2 and floor(H/2) x floor(W/2) texels; depth limits and offset are unchanged."""
+    out = dict(sen)
+    out["H"], out["W"] = int(sen["H"]) // 2, int(sen["W"]) // 2
+    out["fx"], out["fy"] = sen["fx"] / 2.0, sen["fy"] / 2.0
+    out["cx"], out["cy"] = (sen["cx"] - 0.5) / 2.0, (sen["cy"] - 0.5) / 2.0
+    return out
+
+
+def downsample_keyframe(I, D, N, sen, tau):
+    """One level up: each 2x2 block of texels becomes one (an odd last row or column is dropped).
+
+    Depth: the block's mean if all four depths are valid (finite, inside the sensor's depth
+    interval) and their spread max - min is at most tau, else no measurement (0): a block that
+    straddles a depth edge has no single surface to stand for.  Intensity: the mean of the four.
+    Normals: the mean of the four scaled to unit length.  Texels without depth get intensity and
+    normal 0; they are never read (a source pixel needs depth, and so does every target tap).
+    Means are taken in FP64 and rounded once to FP32."""
+    H2, W2 = D.shape[0] // 2, D.shape[1] // 2
+    d = np.asarray(D, np.float64)[:2 * H2, :2 * W2]
+    ok = np.isfinite(d) & (d > 0) & (d >= sen["min_depth"]) & (d <= sen["max_depth"])
+    blocks = lambda a: np.stack([a[0::2, 0::2], a[0::2, 1::2], a[1::2, 0::2], a[1::2, 1::2]], 0)
+    db, okb = blocks(np.where(ok, d, 0.0)), blocks(ok)
+    valid = okb.all(0) & ((db.max(0) - db.min(0)) <= tau)
+    D2 = np.where(valid, db.sum(0) / 4.0, 0.0)
+    I2 = np.where(valid, blocks(np.asarray(I, np.float64)[:2 * H2, :2 * W2]).sum(0) / 4.0, 0.0)
+    N2 = np.zeros((H2, W2, 3))
+    if N is not None:
+        n = np.asarray(N, np.float64)[:2 * H2, :2 * W2]
+        mean = np.stack([blocks(n[..., k]).sum(0) / 4.0 for k in range(3)], -1)
+        norm = np.sqrt(np.sum(mean * mean, -1))
+        good = valid & (norm > 0)
+        N2[good] = mean[good] / norm[good][:, None]
+    return I2.astype(np.float32), D2.astype(np.float32), N2.astype(np.float32)
+
+
+def pyramid(prob, n_levels):
+    """[level 0 (= prob), level 1, ...]: copies of the problem with downsampled keyframes and
+    level intrinsics; poses and pairs are shared."""
+    import copy
+    levels = [prob]
+    for _ in range(1, n_levels):
+        lo = levels[-1]
+        up = copy.copy(lo)
+        up.sensors = [level_sensor(sn) for sn in lo.sensors]
+        up.intensity, up.depth, up.normals = [], [], []
+        for k in range(lo.n):
+            sn = lo.sensors[lo.kf_sensor[k]]
+            tau = lo.params["occ_tau_pinhole"] if sn["model"] == 0 else lo.params["occ_tau_spherical"]
+            i2, d2, n2 = downsample_keyframe(lo.intensity[k], lo.depth[k],
+                                             lo.normals[k] if lo.normals else None, sn, tau)
+            up.intensity.append(i2)
+            up.depth.append(d2)
+            up.normals.append(n2)
+        levels.append(up)
+    return levels
+
+
+def optimize_coarse_to_fine(prob, poses0, n_levels=3, iters=(2, 5, 10), rel_tol=1e-3, lm=True, params=None,
+                            lam0=1e-4, anchor=0):
+    """Sec. IV-C: optimise the coarsest level first and move one level finer when the error stops
+    changing -- here when an accepted iteration lowers F by less than rel_tol relative, or after
+    iters[level] iterations (iters[0] is the finest level).  LM (or GN) as in optimize(); lambda
+    restarts at lam0 on every level.  Returns (poses, log) with the level in each log row."""
+    levels = pyramid(prob, n_levels)
+    X = np.array(poses0, np.float64, copy=True)
+    log = []
+    for lev in range(n_levels - 1, -1, -1):
+        pl = levels[lev]
+        ev = evaluate(pl, X, params)
+        lam = lam0 if lm else 0.0
+        for it in range(iters[lev]):
+            dx, ok = solve_step(ev["H"], ev["b"], lam, anchor)
+            if not ok:
+                if not lm:
+                    raise np.linalg.LinAlgError("GN system not positive definite")
+                lam *= 10.0
+                log.append(dict(level=lev, F=ev["F"], lam=lam, accepted=False, step=0.0))
+                continue
+            Xc = boxplus(X, dx)
+            evc = evaluate(pl, Xc, params)
+            accept = (not lm) or (evc["F"] < ev["F"])
+            drop = (ev["F"] - evc["F"]) / ev["F"] if ev["F"] > 0 else 0.0
+            if accept:
+                X, ev = Xc, evc
+                if lm:
+                    lam = max(lam / 10.0, 1e-12)
+            else:
+                lam *= 10.0
+            log.append(dict(level=lev, F=ev["F"], lam=lam, accepted=accept, step=float(np.linalg.norm(dx))))
+            if accept and drop < rel_tol:
+                break
+    return X, log
+
+
 # ------------------------------------------------------------------ trajectory error
 
 def horn_align(P, Q):

@@ -27,7 +27,8 @@ PBA_PAIR_OUT_LEN = 160
 ABI_FUNCTIONS = (
     "pba_config_default", "pba_create", "pba_destroy", "pba_add_sensor", "pba_load_keyframes",
     "pba_set_poses", "pba_get_poses", "pba_set_pairs", "pba_evaluate", "pba_solve_step",
-    "pba_apply_step", "pba_iterate", "pba_loss_forward", "pba_loss_backward", "pba_debug_pair",
+    "pba_apply_step", "pba_iterate", "pba_loss_forward", "pba_loss_backward", "pba_build_pyramid",
+    "pba_set_level", "pba_optimize_pyramid", "pba_get_level_image", "pba_debug_pair",
     "pba_get_timings", "pba_status_string", "pba_last_error",
 )
 
@@ -93,6 +94,10 @@ def load_library(path: str = LIB_PATH):
         "pba_iterate": (i32, [vp, i32, i32, f64, vp]),
         "pba_loss_forward": (i32, [vp, vp, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]),
         "pba_loss_backward": (i32, [vp, f64, vp, vp, vp, vp, i32]),
+        "pba_build_pyramid": (i32, [vp, i32]),
+        "pba_set_level": (i32, [vp, i32]),
+        "pba_optimize_pyramid": (i32, [vp, vp, f64, i32, f64, vp, vp, vp]),
+        "pba_get_level_image": (i32, [vp, i32, i32, vp, vp, vp, vp]),
         "pba_debug_pair": (i32, [vp, i32, vp, vp, vp, vp]),
         "pba_get_timings": (i32, [vp, ctypes.POINTER(pba_timings), i32]),
         "pba_status_string": (ctypes.c_char_p, [i32]),
@@ -284,6 +289,41 @@ class Context:
                                          ctypes.cast(logs, ctypes.c_void_p)))
         return [dict(F=l.F, lam=l.lambda_, step=l.step_norm, n_valid=l.n_valid, accepted=bool(l.accepted))
                 for l in logs[:n_iters]]
+
+    def build_pyramid(self, n_levels):
+        """Levels 1 .. n_levels - 1 as 2x2 reductions of the loaded images (level 0)."""
+        self._check(self.lib.pba_build_pyramid(self.h, int(n_levels)))
+        self.n_levels = int(n_levels)
+
+    def set_level(self, level):
+        self._check(self.lib.pba_set_level(self.h, int(level)))
+
+    def optimize_pyramid(self, iters, rel_tol=1e-3, use_lm=True, lambda0=1e-4):
+        """Coarse to fine over the built levels; iters[l] bounds the iterations of level l
+        (iters[0] is the finest).  Returns the log rows, each with its level."""
+        it = np.ascontiguousarray(iters, np.int32)
+        total = max(1, int(it.sum()))
+        logs = (pba_iter_log * total)()
+        lev = np.zeros(total, np.int32)
+        done = ctypes.c_int32()
+        self._check(self.lib.pba_optimize_pyramid(self.h, it.ctypes.data, float(rel_tol), int(bool(use_lm)),
+                                                  float(lambda0), ctypes.cast(logs, ctypes.c_void_p),
+                                                  lev.ctypes.data, ctypes.byref(done)))
+        return [dict(level=int(lev[i]), F=logs[i].F, lam=logs[i].lambda_, step=logs[i].step_norm,
+                     n_valid=logs[i].n_valid, accepted=bool(logs[i].accepted)) for i in range(done.value)]
+
+    def get_level_image(self, level, kf):
+        """(intensity [H,W], depth [H,W] (0 = no measurement), normals [H,W,3]) of keyframe kf at
+        a pyramid level, copied to the host."""
+        dims = np.zeros(2, np.int32)
+        self._check(self.lib.pba_get_level_image(self.h, int(level), int(kf), None, None, None, dims.ctypes.data))
+        H, W = int(dims[0]), int(dims[1])
+        I = np.empty((H, W), np.float32)
+        D = np.empty((H, W), np.float32)
+        N = np.empty((H, W, 3), np.float32)
+        self._check(self.lib.pba_get_level_image(self.h, int(level), int(kf), I.ctypes.data, D.ctypes.data,
+                                                 N.ctypes.data, None))
+        return I, D, N
 
     def loss_forward(self, delta, with_count=False):
         """F(X0 boxplus delta) (delta: [N, 6] float32 numpy array or CUDA tensor); with_count also

@@ -11,6 +11,9 @@ constexpr int kAcc = 32;         // accumulator slots per work item
 // accumulator layout: 21 upper-triangular H terms, 6 b terms, F, valid, evaluated, refined
 enum { ACC_H = 0, ACC_B = 21, ACC_F = 27, ACC_VALID = 28, ACC_EVAL = 29, ACC_REF = 30, ACC_USED = 31 };
 constexpr int kPairOut = 160;    // PBA_PAIR_OUT_LEN
+// packed depth of a pixel without a valid measurement: negative, so it fails any depth test
+// and every occlusion bound |D - zeta| <= tau
+constexpr float kNoDepth = -1e30f;
 constexpr int kXcd = 8;          // work queues per launch: one per accelerator complex die (XCD)
 enum { MODEL_PINHOLE = 0, MODEL_SPHERICAL = 1 };
 
@@ -94,7 +97,12 @@ struct LmState {
 void launch_damp_copy(const double *H, const double *b, double *A, double *rhs, int n, int anchor,
                       const LmState *lm, double lam_override, hipStream_t st);
 void launch_cholesky(double *A, int n, double *Winv, int32_t *fail, hipStream_t st);
-void launch_chol_solve(const double *L, const double *Winv, double *x, int n, const int32_t *fail, hipStream_t st);
+void launch_downsample(const float *dep, const float4 *att4, const float *att1, int H, int W, float *dep2,
+                       float4 *att4_2, float *att1_2, int H2, int W2, double tau, hipStream_t st);
+void launch_unpack(const float *dep, const float4 *att4, const float *att1, int npx, float *I, float *D, float *N,
+                   hipStream_t st);
+// Winv: the inverted diagonal blocks followed by n doubles of workspace.
+void launch_chol_solve(const double *L, double *Winv, double *x, int n, const int32_t *fail, hipStream_t st);
 void launch_boxplus(const double *X, const double *dx, double *Xout, int N, const int32_t *fail,
                     LmState *lm, hipStream_t st);
 void launch_lm_decide(LmState *lm, const double *totals_cand, int64_t nH, double *H_cur, const double *H_cand,

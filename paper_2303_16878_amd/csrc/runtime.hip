@@ -27,20 +27,32 @@ struct DevBuf {
 
 }  // namespace
 
+// One resolution level of every keyframe: the level's sensors (intrinsics), ray tables, keyframe
+// layout and packed image planes.  Level 0 holds the loaded images; level l + 1 is the 2x2
+// reduction of level l.
+struct ImageSet {
+    std::vector<pba_sensor> sensors;
+    std::vector<SensorDev> sensors_dev_h;
+    std::vector<KfDev> kfs_h;
+    int64_t texels = 0;
+    DevBuf sensors_d, kfs_d, dep, att4, att1, lut32, lut64;
+};
+
 struct pba_ctx {
     pba_config cfg;
     hipStream_t stream = nullptr;
     int num_cu = 256;
     std::string err;
 
-    std::vector<pba_sensor> sensors;
-    std::vector<SensorDev> sensors_dev_h;
+    std::vector<pba_sensor> sensors;   // as registered (level 0)
+    std::vector<ImageSet> lv = std::vector<ImageSet>(1);
+    int level = 0;                     // the level evaluate / iterate / loss work on
+    ImageSet &L() { return lv[level]; }
+    std::vector<int32_t> src_h, tgt_h; // the pairs as set
     int N = 0, P = 0;
     bool poses_set = false;
     bool system_valid = false;   // H, b, totals[0..3] hold the system at the current poses
     double lam_carry = -1.0;     // LM damping left by the previous pba_iterate call
-    std::vector<KfDev> kfs_h;
-    int64_t texels = 0;
 
     // items
     int items_px = 16384;
@@ -51,7 +63,6 @@ struct pba_ctx {
     int nblk = 0;
 
     // device buffers
-    DevBuf sensors_d, kfs_d, dep, att4, att1, lut32, lut64;
     DevBuf poses, poses_cand, pairs_d, pair_dev, item_pair, item_px0, pitems, ibeg, icnt, counters, partials, pair_out;
     DevBuf blk_rc, blk_ptr, blk_ent, bk_ptr, bk_ent;
     DevBuf H, b, H_cand, b_cand, totals, A, Winv, dx, lm, fail, logbuf;
@@ -152,7 +163,7 @@ __global__ void pack_kernel(const float *__restrict__ I, const float *__restrict
         const float d = D[i];
         const bool ok = isfinite(d) && d > 0.f && (double)d >= dmin && (double)d <= dmax;
         const float in = I[i];
-        dep[i] = ok ? d : 0.f;
+        dep[i] = ok ? d : kNoDepth;
         if (att4) {
             const float n0 = Nn[3 * (int64_t)i], n1 = Nn[3 * (int64_t)i + 1], n2 = Nn[3 * (int64_t)i + 2];
             att4[i] = ok ? make_float4(in, n0, n1, n2) : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -162,6 +173,77 @@ __global__ void pack_kernel(const float *__restrict__ I, const float *__restrict
     }
 }
 
+void release_images(ImageSet &is)
+{
+    DevBuf *bufs[] = {&is.sensors_d, &is.kfs_d, &is.dep, &is.att4, &is.att1, &is.lut32, &is.lut64};
+    for (DevBuf *b : bufs) release(*b);
+}
+
+// Device form of the sensors of one level and their ray tables (FP32 and FP64): per column
+// (cos az, sin az) or ((u - cx) / fx, 0), per row (cos el, sin el) or ((v - cy) / fy, 0).
+pba_status sensor_tables(pba_ctx *c, ImageSet &is)
+{
+    std::vector<SensorDev> sd(is.sensors.size());
+    std::vector<float2> l32;
+    std::vector<double2> l64;
+    for (size_t i = 0; i < is.sensors.size(); ++i) {
+        const pba_sensor &S = is.sensors[i];
+        SensorDev &d = sd[i];
+        d.model = S.model; d.H = S.height; d.W = S.width; d.npx = S.height * S.width;
+        d.magic_w = (uint32_t)(((1ull << 32) + S.width - 1) / S.width);
+        d.fx = (float)S.fx; d.fy = (float)S.fy; d.cx = (float)S.cx; d.cy = (float)S.cy;
+        d.dmin = (float)S.min_depth; d.dmax = (float)S.max_depth;
+        d.fxd = S.fx; d.fyd = S.fy; d.cxd = S.cx; d.cyd = S.cy; d.dmind = S.min_depth; d.dmaxd = S.max_depth;
+        d.taud = S.model == PBA_PINHOLE ? c->cfg.occlusion_tau_pinhole : c->cfg.occlusion_tau_spherical;
+        d.tau = (float)d.taud;
+        for (int k = 0; k < 9; ++k) d.Ro[k] = S.offset[k];
+        for (int k = 0; k < 3; ++k) d.to[k] = S.offset[9 + k];
+        d.lut_col = (int64_t)l32.size();
+        for (int u = 0; u < S.width; ++u) {
+            double x, y;
+            if (S.model == PBA_SPHERICAL) { const double az = (u - S.cx) / S.fx; x = std::cos(az); y = std::sin(az); }
+            else { x = (u - S.cx) / S.fx; y = 0.0; }
+            l32.push_back(make_float2((float)x, (float)y));
+            l64.push_back(make_double2(x, y));
+        }
+        d.lut_row = (int64_t)l32.size();
+        for (int v = 0; v < S.height; ++v) {
+            double x, y;
+            if (S.model == PBA_SPHERICAL) { const double el = (v - S.cy) / S.fy; x = std::cos(el); y = std::sin(el); }
+            else { x = (v - S.cy) / S.fy; y = 0.0; }
+            l32.push_back(make_float2((float)x, (float)y));
+            l64.push_back(make_double2(x, y));
+        }
+    }
+    pba_status s;
+    if ((s = upload(c, is.sensors_d, sd.data(), sd.size() * sizeof(SensorDev)))) return s;
+    if ((s = upload(c, is.lut32, l32.data(), l32.size() * sizeof(float2)))) return s;
+    if ((s = upload(c, is.lut64, l64.data(), l64.size() * sizeof(double2)))) return s;
+    is.sensors_dev_h = sd;
+    return PBA_OK;
+}
+
+// Keyframe layout of one level: keyframes back to back in each plane.
+pba_status image_layout(pba_ctx *c, ImageSet &is, const std::vector<int32_t> &sensor_of)
+{
+    is.kfs_h.assign(sensor_of.size(), KfDev{});
+    int64_t off = 0;
+    for (size_t k = 0; k < sensor_of.size(); ++k) {
+        KfDev &f = is.kfs_h[k];
+        f.sensor = sensor_of[k];
+        f.H = is.sensors[f.sensor].height;
+        f.W = is.sensors[f.sensor].width;
+        f.off = off;
+        off += (int64_t)f.H * f.W;
+    }
+    is.texels = off;
+    pba_status s;
+    if ((s = upload(c, is.kfs_d, is.kfs_h.data(), is.kfs_h.size() * sizeof(KfDev)))) return s;
+    if ((s = ensure(c, is.dep, off * sizeof(float)))) return s;
+    if (c->cfg.channels == 5) return ensure(c, is.att4, off * sizeof(float4));
+    return ensure(c, is.att1, off * sizeof(float));
+}
+
 pba_status build_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt)
 {
     const int P = (int)src.size();
@@ -169,7 +251,7 @@ pba_status build_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::ve
     // ordered by target keyframe so items sharing a target image run close together
     std::vector<int> order(P);
     for (int p = 0; p < P; ++p) order[p] = p;
-    auto model_of = [&](int kf) { return c->sensors[c->kfs_h[kf].sensor].model; };
+    auto model_of = [&](int kf) { return c->sensors[c->L().kfs_h[kf].sensor].model; };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         const int ka = model_of(src[a]) * 2 + model_of(tgt[a]), kb = model_of(src[b]) * 2 + model_of(tgt[b]);
         if (ka != kb) return ka < kb;
@@ -182,7 +264,7 @@ pba_status build_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::ve
     for (int oi = 0; oi < P; ++oi) {
         const int p = order[oi];
         const int key = model_of(src[p]) * 2 + model_of(tgt[p]);
-        const int npx = c->kfs_h[src[p]].H * c->kfs_h[src[p]].W;
+        const int npx = c->L().kfs_h[src[p]].H * c->L().kfs_h[src[p]].W;
         for (int px = 0, band = 0; px < npx; px += c->items_px, ++band) items.push_back({key, tgt[p], band, p, px});
     }
     std::stable_sort(items.begin(), items.end(), [](const It &a, const It &b) {
@@ -263,14 +345,14 @@ pba_status build_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::ve
 EvalArgs make_args(pba_ctx *c)
 {
     EvalArgs a{};
-    a.sensors = P_<SensorDev>(c->sensors_d);
-    a.kfs = P_<KfDev>(c->kfs_d);
+    a.sensors = P_<SensorDev>(c->L().sensors_d);
+    a.kfs = P_<KfDev>(c->L().kfs_d);
     a.pairs = P_<PairDev>(c->pair_dev);
-    a.dep = P_<float>(c->dep);
-    a.att4 = P_<float4>(c->att4);
-    a.att1 = P_<float>(c->att1);
-    a.lut32 = P_<float2>(c->lut32);
-    a.lut64 = P_<double2>(c->lut64);
+    a.dep = P_<float>(c->L().dep);
+    a.att4 = P_<float4>(c->L().att4);
+    a.att1 = P_<float>(c->L().att1);
+    a.lut32 = P_<float2>(c->L().lut32);
+    a.lut64 = P_<double2>(c->L().lut64);
     a.item_pair = P_<int32_t>(c->item_pair);
     a.item_px0 = P_<int32_t>(c->item_px0);
     a.items_px = c->items_px;
@@ -290,7 +372,7 @@ pba_status run_eval(pba_ctx *c, const double *poses, double *H, double *b, doubl
                     hipStream_t st)
 {
     const int ngrp = (int)c->groups.size();
-    launch_pair_setup(poses, P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->sensors_d), P_<KfDev>(c->kfs_d),
+    launch_pair_setup(poses, P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->L().sensors_d), P_<KfDev>(c->L().kfs_d),
                       P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ngrp * kXcd, st);
     EvalArgs a = make_args(c);
     if (timed) HIP_OK(hipEventRecord(c->ev0, st));
@@ -371,7 +453,8 @@ pba_status ensure_system(pba_ctx *c)
     if ((s = ensure(c, c->A, n * n * 8))) return s;
     if ((s = ensure(c, c->H_cand, n * n * 8))) return s;
     if ((s = ensure(c, c->b_cand, n * 8))) return s;
-    if ((s = ensure(c, c->Winv, ((n + 63) / 64) * 64 * 64 * 8))) return s;
+    // inverted diagonal blocks, then n doubles of triangular-solve workspace
+    if ((s = ensure(c, c->Winv, ((n + 63) / 64) * 64 * 64 * 8 + (size_t)n * 8))) return s;
     if ((s = ensure(c, c->dx, n * 8))) return s;
     if ((s = ensure(c, c->lm, sizeof(LmState)))) return s;
     if ((s = ensure(c, c->fail, 16))) return s;
@@ -451,8 +534,8 @@ pba_status pba_destroy(pba_ctx *c)
     if (!c) return PBA_EINVAL;
     (void)hipSetDevice(c->cfg.device);
     (void)hipStreamSynchronize(c->stream);
-    DevBuf *bufs[] = {&c->sensors_d, &c->kfs_d, &c->dep, &c->att4, &c->att1, &c->lut32, &c->lut64, &c->poses,
-                      &c->poses_cand, &c->pairs_d, &c->pair_dev, &c->item_pair, &c->item_px0, &c->pitems, &c->ibeg, &c->icnt,
+    for (ImageSet &is : c->lv) release_images(is);
+    DevBuf *bufs[] = {&c->poses, &c->poses_cand, &c->pairs_d, &c->pair_dev, &c->item_pair, &c->item_px0, &c->pitems, &c->ibeg, &c->icnt,
                       &c->counters, &c->partials, &c->pair_out, &c->blk_rc, &c->blk_ptr, &c->blk_ent, &c->bk_ptr,
                       &c->bk_ent, &c->H, &c->b, &c->H_cand, &c->b_cand, &c->totals, &c->A, &c->Winv, &c->dx, &c->lm,
                       &c->fail, &c->logbuf, &c->dbg_status, &c->dbg_uv, &c->dbg_cell, &c->dbg_res,
@@ -472,8 +555,10 @@ pba_status pba_add_sensor(pba_ctx *c, const pba_sensor *s, int32_t *sensor_id)
     if (c->N > 0) return fail(c, PBA_ESTATE, "sensors must be added before keyframes are loaded");
     if (s->model != PBA_PINHOLE && s->model != PBA_SPHERICAL) return fail(c, PBA_EINVAL, "unknown sensor model");
     // the kernels split a pixel index into (row, col) with a 32-bit reciprocal multiply, exact
-    // while H * W^2 < 2^32
-    if (s->height < 4 || s->width < 4 || (uint64_t)s->height * s->width * s->width >= (1ull << 32))
+    // while H * W^2 < 2^32, and address one keyframe plane (16 B per texel) with 32-bit byte
+    // offsets, so H * W <= 2^26
+    if (s->height < 4 || s->width < 4 || (uint64_t)s->height * s->width * s->width >= (1ull << 32) ||
+        (uint64_t)s->height * s->width > (1ull << 26))
         return fail(c, PBA_EINVAL, "image size %d x %d out of range", s->height, s->width);
     const double v[6] = {s->fx, s->fy, s->cx, s->cy, s->min_depth, s->max_depth};
     for (double x : v)
@@ -494,63 +579,28 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
     if (c->sensors.empty()) return fail(c, PBA_ESTATE, "no sensor registered");
     if (c->cfg.channels == 5 && !normals) return fail(c, PBA_EINVAL, "5 channels need normals");
     HIP_OK(hipSetDevice(c->cfg.device));
-    std::vector<KfDev> kfs(n);
-    int64_t off = 0;
+    std::vector<int32_t> sensor_of(n);
     for (int k = 0; k < n; ++k) {
         const int sid = sensor_id[k];
         if (sid < 0 || sid >= (int)c->sensors.size()) return fail(c, PBA_EINVAL, "keyframe %d: bad sensor id", k);
         if (!intensity[k] || !depth[k] || (c->cfg.channels == 5 && !normals[k]))
             return fail(c, PBA_EINVAL, "keyframe %d: null image", k);
-        kfs[k].sensor = sid;
-        kfs[k].H = c->sensors[sid].height;
-        kfs[k].W = c->sensors[sid].width;
-        kfs[k].off = off;
-        off += (int64_t)kfs[k].H * kfs[k].W;
+        sensor_of[k] = sid;
     }
     pba_status s;
-    // sensors and ray tables (FP32 and FP64), computed once per sensor
-    std::vector<SensorDev> sd(c->sensors.size());
-    std::vector<float2> l32;
-    std::vector<double2> l64;
-    for (size_t i = 0; i < c->sensors.size(); ++i) {
-        const pba_sensor &S = c->sensors[i];
-        SensorDev &d = sd[i];
-        d.model = S.model; d.H = S.height; d.W = S.width; d.npx = S.height * S.width;
-        d.magic_w = (uint32_t)(((1ull << 32) + S.width - 1) / S.width);
-        d.fx = (float)S.fx; d.fy = (float)S.fy; d.cx = (float)S.cx; d.cy = (float)S.cy;
-        d.dmin = (float)S.min_depth; d.dmax = (float)S.max_depth;
-        d.fxd = S.fx; d.fyd = S.fy; d.cxd = S.cx; d.cyd = S.cy; d.dmind = S.min_depth; d.dmaxd = S.max_depth;
-        d.taud = S.model == PBA_PINHOLE ? c->cfg.occlusion_tau_pinhole : c->cfg.occlusion_tau_spherical;
-        d.tau = (float)d.taud;
-        for (int k = 0; k < 9; ++k) d.Ro[k] = S.offset[k];
-        for (int k = 0; k < 3; ++k) d.to[k] = S.offset[9 + k];
-        d.lut_col = (int64_t)l32.size();
-        for (int u = 0; u < S.width; ++u) {
-            double x, y;
-            if (S.model == PBA_SPHERICAL) { const double az = (u - S.cx) / S.fx; x = std::cos(az); y = std::sin(az); }
-            else { x = (u - S.cx) / S.fx; y = 0.0; }
-            l32.push_back(make_float2((float)x, (float)y));
-            l64.push_back(make_double2(x, y));
-        }
-        d.lut_row = (int64_t)l32.size();
-        for (int v = 0; v < S.height; ++v) {
-            double x, y;
-            if (S.model == PBA_SPHERICAL) { const double el = (v - S.cy) / S.fy; x = std::cos(el); y = std::sin(el); }
-            else { x = (v - S.cy) / S.fy; y = 0.0; }
-            l32.push_back(make_float2((float)x, (float)y));
-            l64.push_back(make_double2(x, y));
-        }
-    }
-    if ((s = upload(c, c->sensors_d, sd.data(), sd.size() * sizeof(SensorDev)))) return s;
-    if ((s = upload(c, c->lut32, l32.data(), l32.size() * sizeof(float2)))) return s;
-    if ((s = upload(c, c->lut64, l64.data(), l64.size() * sizeof(double2)))) return s;
-    if ((s = upload(c, c->kfs_d, kfs.data(), kfs.size() * sizeof(KfDev)))) return s;
-    if ((s = ensure(c, c->dep, off * sizeof(float)))) return s;
-    if (c->cfg.channels == 5) {
-        if ((s = ensure(c, c->att4, off * sizeof(float4)))) return s;
-    } else {
-        if ((s = ensure(c, c->att1, off * sizeof(float)))) return s;
-    }
+    const int prev_level = c->level;
+    const bool same_layout = c->N == n && (int)c->lv[0].kfs_h.size() == n &&
+                             std::equal(sensor_of.begin(), sensor_of.end(), c->lv[0].kfs_h.begin(),
+                                        [](int32_t a, const KfDev &f) { return a == f.sensor; });
+    // a new load drops any pyramid: level 0 becomes the only and active level
+    for (size_t l = 1; l < c->lv.size(); ++l) release_images(c->lv[l]);
+    c->lv.resize(1);
+    c->level = 0;
+    ImageSet &is = c->lv[0];
+    is.sensors = c->sensors;
+    if ((s = sensor_tables(c, is))) return s;
+    if ((s = image_layout(c, is, sensor_of))) return s;
+    const std::vector<KfDev> &kfs = is.kfs_h;
     // stage each keyframe on the device (copy if host) and pack
     DevBuf stage;
     for (int k = 0; k < n; ++k) {
@@ -570,22 +620,20 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
         const int blocks = std::min((npx + 255) / 256, 4096);
         const bool five = c->cfg.channels == 5;
         hipLaunchKernelGGL(pack_kernel, dim3(blocks), dim3(256), 0, c->stream, dI, dD, five ? dN : nullptr,
-                           P_<float>(c->dep) + kfs[k].off, five ? P_<float4>(c->att4) + kfs[k].off : nullptr,
-                           five ? nullptr : P_<float>(c->att1) + kfs[k].off, npx, S.min_depth, S.max_depth);
+                           P_<float>(c->L().dep) + kfs[k].off, five ? P_<float4>(c->L().att4) + kfs[k].off : nullptr,
+                           five ? nullptr : P_<float>(c->L().att1) + kfs[k].off, npx, S.min_depth, S.max_depth);
         if (!on_device) HIP_OK(hipStreamSynchronize(c->stream));   // stage is reused
     }
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(c->stream));
     release(stage);
     drop_graph(c);
-    bool same_layout = c->N == n && (int)c->kfs_h.size() == n;
-    for (int k = 0; same_layout && k < n; ++k) same_layout = c->kfs_h[k].sensor == kfs[k].sensor;
-    c->kfs_h = kfs;
-    c->sensors_dev_h = sd;
-    c->texels = off;
     c->system_valid = false;
     c->loss_ready = false;
-    if (same_layout) return PBA_OK;   // images replaced; poses and pairs kept
+    if (same_layout) {   // images replaced; poses and pairs kept (the plan follows level 0 again)
+        if (prev_level != 0 && c->P > 0 && (s = build_plan(c, c->src_h, c->tgt_h))) return s;
+        return PBA_OK;
+    }
     c->N = n;
     c->P = 0;
     c->poses_set = false;
@@ -646,6 +694,8 @@ pba_status pba_set_pairs(pba_ctx *c, int32_t p, const int32_t *src, const int32_
     if ((st = build_plan(c, s, t))) return st;
     if ((st = ensure_system(c))) return st;
     HIP_OK(hipStreamSynchronize(c->stream));
+    c->src_h = s;
+    c->tgt_h = t;
     c->P = p;
     c->system_valid = false;
     c->lam_carry = -1.0;
@@ -855,7 +905,7 @@ pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float
     if (!c->loss_ready) return fail(c, PBA_ESTATE, "pba_loss_backward needs a preceding pba_loss_forward");
     HIP_OK(hipSetDevice(c->cfg.device));
     const int N = c->N;
-    const int64_t tx = c->texels;
+    const int64_t tx = c->L().texels;
     const bool five = c->cfg.channels == 5;
     if ((s = ensure(c, c->g_int, (size_t)tx * 4))) return s;
     if ((s = ensure(c, c->g_dep, (size_t)tx * 4))) return s;
@@ -874,8 +924,8 @@ pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float
     }
     // recompute the evaluation at X0 boxplus delta in adjoint mode
     const int ngrp = (int)c->groups.size();
-    launch_pair_setup(P_<double>(c->loss_poses), P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->sensors_d),
-                      P_<KfDev>(c->kfs_d), P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ngrp * kXcd,
+    launch_pair_setup(P_<double>(c->loss_poses), P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->L().sensors_d),
+                      P_<KfDev>(c->L().kfs_d), P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ngrp * kXcd,
                       c->stream);
     EvalArgs a = make_args(c);
     a.g_int = P_<float>(c->g_int);
@@ -899,8 +949,8 @@ pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (grad_delta) HIP_OK(hipMemcpyAsync(grad_delta, c->g_pose.p, (size_t)N * 24, kind, c->stream));
     for (int k = 0; k < N; ++k) {
-        const size_t npx = (size_t)c->kfs_h[k].H * c->kfs_h[k].W;
-        const int64_t off = c->kfs_h[k].off;
+        const size_t npx = (size_t)c->L().kfs_h[k].H * c->L().kfs_h[k].W;
+        const int64_t off = c->L().kfs_h[k].off;
         if (grad_intensity && grad_intensity[k])
             HIP_OK(hipMemcpyAsync(grad_intensity[k], P_<float>(c->g_int) + off, npx * 4, kind, c->stream));
         if (grad_depth && grad_depth[k])
@@ -912,6 +962,139 @@ pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float
     return PBA_OK;
 }
 
+pba_status pba_build_pyramid(pba_ctx *c, int32_t n_levels)
+{
+    if (!c) return PBA_EINVAL;
+    if (c->N == 0) return fail(c, PBA_ESTATE, "no keyframes loaded");
+    if (n_levels < 1 || n_levels > 8) return fail(c, PBA_EINVAL, "n_levels %d out of range 1..8", n_levels);
+    for (const pba_sensor &S : c->sensors)
+        if ((S.height >> (n_levels - 1)) < 4 || (S.width >> (n_levels - 1)) < 4)
+            return fail(c, PBA_EINVAL, "level %d of a %d x %d sensor would be below 4 x 4", n_levels - 1, S.height,
+                        S.width);
+    HIP_OK(hipSetDevice(c->cfg.device));
+    for (size_t l = 1; l < c->lv.size(); ++l) release_images(c->lv[l]);
+    c->lv.resize(n_levels);
+    std::vector<int32_t> sensor_of(c->N);
+    for (int k = 0; k < c->N; ++k) sensor_of[k] = c->lv[0].kfs_h[k].sensor;
+    pba_status s;
+    for (int l = 1; l < n_levels; ++l) {
+        ImageSet &lo = c->lv[l - 1], &up = c->lv[l];
+        up.sensors = lo.sensors;
+        for (pba_sensor &S : up.sensors) {
+            S.height /= 2;
+            S.width /= 2;
+            S.fx /= 2.0;
+            S.fy /= 2.0;
+            S.cx = (S.cx - 0.5) / 2.0;
+            S.cy = (S.cy - 0.5) / 2.0;
+        }
+        if ((s = sensor_tables(c, up))) return s;
+        if ((s = image_layout(c, up, sensor_of))) return s;
+        const bool five = c->cfg.channels == 5;
+        for (int k = 0; k < c->N; ++k) {
+            const KfDev &a = lo.kfs_h[k], &b = up.kfs_h[k];
+            const double tau = lo.sensors[a.sensor].model == PBA_PINHOLE ? c->cfg.occlusion_tau_pinhole
+                                                                          : c->cfg.occlusion_tau_spherical;
+            launch_downsample(P_<float>(lo.dep) + a.off, five ? P_<float4>(lo.att4) + a.off : nullptr,
+                              five ? nullptr : P_<float>(lo.att1) + a.off, a.H, a.W, P_<float>(up.dep) + b.off,
+                              five ? P_<float4>(up.att4) + b.off : nullptr, five ? nullptr : P_<float>(up.att1) + b.off,
+                              b.H, b.W, tau, c->stream);
+        }
+        HIP_OK(hipGetLastError());
+    }
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (c->level >= n_levels) return pba_set_level(c, 0);
+    return PBA_OK;
+}
+
+pba_status pba_set_level(pba_ctx *c, int32_t level)
+{
+    if (!c) return PBA_EINVAL;
+    if (level < 0 || level >= (int)c->lv.size())
+        return fail(c, PBA_EINVAL, "level %d not built (%d levels)", level, (int)c->lv.size());
+    if (level == c->level) return PBA_OK;
+    HIP_OK(hipSetDevice(c->cfg.device));
+    drop_graph(c);
+    c->level = level;
+    c->system_valid = false;
+    c->loss_ready = false;
+    c->lam_carry = -1.0;
+    pba_status s;
+    if (c->P > 0 && (s = build_plan(c, c->src_h, c->tgt_h))) return s;
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return PBA_OK;
+}
+
+pba_status pba_optimize_pyramid(pba_ctx *c, const int32_t *iters, double rel_tol, int32_t use_lm, double lambda0,
+                                pba_iter_log *log, int32_t *level_of, int32_t *n_done)
+{
+    if (!c || !iters) return fail(c, PBA_EINVAL, "null argument");
+    if (!(rel_tol >= 0.0) || (use_lm && !(lambda0 > 0.0))) return fail(c, PBA_EINVAL, "bad rel_tol or lambda0");
+    pba_status s;
+    if ((s = check_ready(c))) return s;
+    const int nl = (int)c->lv.size();
+    for (int l = 0; l < nl; ++l)
+        if (iters[l] < 0) return fail(c, PBA_EINVAL, "iters[%d] < 0", l);
+    int done = 0;
+    for (int l = nl - 1; l >= 0; --l) {
+        if ((s = pba_set_level(c, l))) return s;
+        if (iters[l] == 0) continue;
+        // F at the level's start: the system at the current poses
+        if ((s = run_eval(c, P_<double>(c->poses), P_<double>(c->H), P_<double>(c->b), P_<double>(c->totals), false,
+                          c->stream)))
+            return s;
+        double F_prev;
+        HIP_OK(hipMemcpyAsync(&F_prev, c->totals.p, 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+        c->system_valid = true;
+        for (int it = 0; it < iters[l]; ++it) {
+            pba_iter_log row;
+            if ((s = pba_iterate(c, 1, use_lm, it == 0 ? (use_lm ? lambda0 : 0.0) : 0.0, &row))) return s;
+            if (log) log[done] = row;
+            if (level_of) level_of[done] = l;
+            ++done;
+            const bool small = row.accepted && F_prev > 0.0 && (F_prev - row.F) / F_prev < rel_tol;
+            if (row.accepted) F_prev = row.F;
+            if (small) break;
+        }
+    }
+    if (n_done) *n_done = done;
+    return pba_set_level(c, 0);
+}
+
+pba_status pba_get_level_image(pba_ctx *c, int32_t level, int32_t kf, float *intensity, float *depth, float *normals,
+                               int32_t *dims)
+{
+    if (!c) return PBA_EINVAL;
+    if (level < 0 || level >= (int)c->lv.size())
+        return fail(c, PBA_EINVAL, "level %d not built (%d levels)", level, (int)c->lv.size());
+    if (kf < 0 || kf >= c->N) return fail(c, PBA_EINVAL, "keyframe %d out of range", kf);
+    ImageSet &is = c->lv[level];
+    const KfDev &f = is.kfs_h[kf];
+    if (dims) { dims[0] = f.H; dims[1] = f.W; }
+    if (!intensity && !depth && !normals) return PBA_OK;
+    HIP_OK(hipSetDevice(c->cfg.device));
+    const size_t npx = (size_t)f.H * f.W;
+    DevBuf tmp;
+    pba_status s;
+    if ((s = ensure(c, tmp, npx * 5 * 4))) return s;
+    float *I = P_<float>(tmp), *D = I + npx, *N = D + npx;
+    const bool five = c->cfg.channels == 5;
+    launch_unpack(P_<float>(is.dep) + f.off, five ? P_<float4>(is.att4) + f.off : nullptr,
+                  five ? nullptr : P_<float>(is.att1) + f.off, (int)npx, I, D, five ? N : nullptr, c->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && intensity) e = hipMemcpyAsync(intensity, I, npx * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && depth) e = hipMemcpyAsync(depth, D, npx * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && normals) {
+        if (five) e = hipMemcpyAsync(normals, N, npx * 12, hipMemcpyDeviceToHost, c->stream);
+        else std::memset(normals, 0, npx * 12);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    release(tmp);
+    if (e != hipSuccess) return fail(c, PBA_EDEVICE, "pba_get_level_image: %s", hipGetErrorString(e));
+    return PBA_OK;
+}
+
 pba_status pba_debug_pair(pba_ctx *c, int32_t pair, uint8_t *status, float *uv, int32_t *cell, float *residuals)
 {
     if (!c) return PBA_EINVAL;
@@ -920,12 +1103,12 @@ pba_status pba_debug_pair(pba_ctx *c, int32_t pair, uint8_t *status, float *uv, 
     if (pair < 0 || pair >= c->P) return fail(c, PBA_EINVAL, "pair %d out of range", pair);
     HIP_OK(hipSetDevice(c->cfg.device));
     // pair transforms at the current poses
-    launch_pair_setup(P_<double>(c->poses), P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->sensors_d),
-                      P_<KfDev>(c->kfs_d), P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), 64, c->stream);
+    launch_pair_setup(P_<double>(c->poses), P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->L().sensors_d),
+                      P_<KfDev>(c->L().kfs_d), P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), 64, c->stream);
     int2 pr;
     HIP_OK(hipMemcpyAsync(&pr, P_<int2>(c->pairs_d) + pair, sizeof pr, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
-    const KfDev &ks = c->kfs_h[pr.x], &kt = c->kfs_h[pr.y];
+    const KfDev &ks = c->L().kfs_h[pr.x], &kt = c->L().kfs_h[pr.y];
     const int npx = ks.H * ks.W;
     if ((s = ensure(c, c->dbg_status, npx))) return s;
     if ((s = ensure(c, c->dbg_uv, (size_t)npx * 8))) return s;

@@ -53,56 +53,77 @@ __device__ __forceinline__ double bcast(double v, int lane)
 }
 
 // Factor the diagonal block at k0 and write L_kk (lower) to A and W = L_kk^-1 (lower, row-major
-// 64 x 64, zero above the diagonal) to Winv.  One wave; lane i keeps row i of L and of W in
-// registers and column entries are broadcast with readlane.  A ragged last block is padded with
-// the identity, whose factor and inverse are the identity.
+// 64 x 64, zero above the diagonal) to Winv.  One wave, 64 column steps each, written as loops
+// whose bodies address registers statically (the register window shifts by one column per
+// step), so the code stays small instead of being unrolled 64 x 64 times.
+// Factor (right-looking): lane i keeps the not yet eliminated part of row i, r[k] = a(i, j + k) at
+// step j; the step's column is published in LDS and read back as broadcasts.
+// Inverse: lane c keeps column c of W and runs the forward substitution L w = e_c, with the rows
+// of L read from LDS as broadcasts; w_0 .. w_{i-1} sit at the top of the window at step i.
+// A ragged last block is padded with the identity, whose factor and inverse are the identity.
 __global__ void __launch_bounds__(64) chol_diag_kernel(double *A, int n, int k0, double *Winv, int32_t *fail)
 {
+    __shared__ double col[2 * NB];
+    __shared__ double dinv[NB];
+    __shared__ double Lpad[NB + NB * NB];   // NB zeros, then L row-major
     if (*fail) return;
     const int nb = min(NB, n - k0);
     const int lane = threadIdx.x;
+    double *Ls = Lpad + NB;
+    col[NB + lane] = 0.0;
+    Lpad[lane] = 0.0;
     double r[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k)
         r[k] = (lane < nb && k < nb) ? A[(int64_t)(k0 + lane) * n + k0 + k] : (k == lane ? 1.0 : 0.0);
     bool bad = false;
-#pragma unroll
+#pragma nounroll
     for (int j = 0; j < NB; ++j) {
-        const double d = bcast(r[j], j);
+        col[lane] = r[0];
+        __syncthreads();
+        const double d = col[j];
         bad = bad || !(d > 0.0);
         const double sd = d > 0.0 ? sqrt(d) : 1.0;
         const double inv = 1.0 / sd;
-        r[j] = lane == j ? sd : (lane > j ? r[j] * inv : r[j]);
+        const double lij = lane == j ? sd : (lane > j ? r[0] * inv : 0.0);
+        Ls[lane * NB + j] = lij;
+        if (lane == j) dinv[j] = inv;
+        const double *cj = col + j;
 #pragma unroll
-        for (int k = j + 1; k < NB; ++k) {
-            const double lkj = bcast(r[j], k);
-            if (lane >= k) r[k] = fma(-r[j], lkj, r[k]);
+        for (int k = 1; k < NB; ++k) {
+            const double lkj = cj[k] * inv;   // L(j + k, j); zero padding beyond the block
+            r[k - 1] = lane >= j + k ? fma(-lij, lkj, r[k]) : r[k];
         }
+        r[NB - 1] = 0.0;
+        __syncthreads();
     }
-    // W = L^-1 row by row: row m is final once divided by L_mm, then removed from the rows below
+    // the factor, rows in lanes
+#pragma nounroll
+    for (int k = 0; k < nb; ++k)
+        if (lane < nb && k <= lane) A[(int64_t)(k0 + lane) * n + k0 + k] = Ls[lane * NB + k];
     double w[NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) w[c] = c == lane ? 1.0 : 0.0;
+    for (int m = 0; m < NB; ++m) w[m] = 0.0;
+#pragma nounroll
+    for (int i = 0; i < NB; ++i) {
+        // sum_{k < i} L(i, k) w_k with w_k at w[NB - i + k]: Lrow[m] = L(i, m + i - NB), zero for m < NB - i
+        const double *Lrow = Ls + i * NB + i - NB;
+        double s0 = i == lane ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-    for (int m = 0; m < NB; ++m) {
-        const double dm = bcast(r[m], m);
-        const double im = 1.0 / dm;
-        if (lane == m) {
-#pragma unroll
-            for (int c = 0; c <= m; ++c) w[c] *= im;
+        for (int m = 0; m < NB; m += 4) {
+            s0 = fma(-Lrow[m], w[m], s0);
+            s1 = fma(-Lrow[m + 1], w[m + 1], s1);
+            s2 = fma(-Lrow[m + 2], w[m + 2], s2);
+            s3 = fma(-Lrow[m + 3], w[m + 3], s3);
         }
+        const double wi = ((s0 + s1) + (s2 + s3)) * dinv[i];
 #pragma unroll
-        for (int c = 0; c <= m; ++c) {
-            const double wmc = bcast(w[c], m);
-            if (lane > m) w[c] = fma(-r[m], wmc, w[c]);
-        }
+        for (int m = 0; m < NB - 1; ++m) w[m] = w[m + 1];
+        w[NB - 1] = wi;
     }
     double *Wb = Winv + (int64_t)(k0 / NB) * NB * NB;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        Wb[lane * NB + k] = (lane < nb && k < nb && k <= lane) ? w[k] : 0.0;
-        if (lane < nb && k <= lane) A[(int64_t)(k0 + lane) * n + k0 + k] = r[k];
-    }
+    for (int i = 0; i < NB; ++i) Wb[i * NB + lane] = (i < nb && lane < nb && lane <= i) ? w[i] : 0.0;
     if (lane == 0 && __any(bad)) *fail = 1;
 }
 
@@ -199,66 +220,98 @@ void launch_cholesky(double *A, int n, double *Winv, int32_t *fail, hipStream_t 
     }
 }
 
-// L y = rhs, then L^T x = y, in place on x, with the inverted diagonal blocks W_kk.
-// One workgroup of 1024 threads (16 waves); rows of L are read with consecutive lanes on
-// consecutive columns.
-__global__ void __launch_bounds__(1024) chol_solve_kernel(const double *__restrict__ L, const double *__restrict__ Winv,
-                                                          double *__restrict__ x, int n, const int32_t *fail)
+// L y = rhs, then L^T x = y, as one launch per 64-row block and direction (right-looking, so each
+// launch spreads over many workgroups).  The right-hand side in x is consumed; y lives in the n
+// doubles of workspace that follow the inverted diagonal blocks in Winv; x receives the solution
+// (zero if the factorisation failed).
+
+// Forward block kb: y_k = W_kk r_k, then r_i -= L_ik y_k for the rows below.  Workgroup g owns
+// the 64 rows starting at k0 + nb + 64 g; every workgroup forms y_k itself (r_k is not written in
+// this launch), workgroup 0 stores it.
+__global__ void __launch_bounds__(256) trsv_fwd_kernel(const double *__restrict__ L, const double *__restrict__ Winv,
+                                                       double *__restrict__ r, double *__restrict__ y, int n, int kb,
+                                                       const int32_t *fail)
 {
-    __shared__ double sv[NB];
-    __shared__ double part[16][NB];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (*fail) {
-        for (int i = tid; i < n; i += blockDim.x) x[i] = 0.0;
-        return;
+    __shared__ double sy[NB];
+    if (*fail) return;
+    const int k0 = kb * NB, nb = min(NB, n - k0);
+    const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
+    const double *Wb = Winv + (int64_t)kb * NB * NB;
+    double s = 0.0;
+#pragma unroll
+    for (int c = part * 16; c < part * 16 + 16; ++c) s += c < nb ? Wb[row * NB + c] * r[k0 + c] : 0.0;
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (part == 0) sy[row] = s;
+    __syncthreads();
+    if (blockIdx.x == 0 && tid < nb) y[k0 + tid] = sy[tid];
+    const int i = k0 + nb + blockIdx.x * NB + row;
+    double u = 0.0;
+    if (i < n) {
+        const double *Lr = L + (int64_t)i * n + k0;
+#pragma unroll
+        for (int c = part * 16; c < part * 16 + 16; ++c) u += c < nb ? Lr[c] * sy[c] : 0.0;
     }
-    const int nblk = (n + NB - 1) / NB;
-    // forward: y_k = W_kk (r_k - sum_{j < k0} L[k0 + i][j] y_j)
-    for (int kb = 0; kb < nblk; ++kb) {
-        const int k0 = kb * NB, nb = min(NB, n - k0);
-        for (int i = wv; i < nb; i += 16) {
-            const double *Lr = L + (int64_t)(k0 + i) * n;
-            double s = 0.0;
-            for (int j = lane; j < k0; j += 64) s += Lr[j] * x[j];
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-            if (lane == 0) sv[i] = x[k0 + i] - s;
-        }
-        __syncthreads();
-        const double *Wb = Winv + (int64_t)kb * NB * NB;
-        for (int i = wv; i < nb; i += 16) {
-            double s = lane < nb ? Wb[i * NB + lane] * sv[lane] : 0.0;
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-            if (lane == 0) x[k0 + i] = s;
-        }
-        __syncthreads();
-    }
-    // backward: x_k = W_kk^T (y_k - sum_{j >= k0 + nb} L[j][k0 + c] x_j)
-    for (int kb = nblk - 1; kb >= 0; --kb) {
-        const int k0 = kb * NB, nb = min(NB, n - k0);
-        double s = 0.0;
-        if (lane < nb)
-            for (int j = k0 + nb + wv; j < n; j += 16) s += L[(int64_t)j * n + k0 + lane] * x[j];
-        part[wv][lane] = s;
-        __syncthreads();
-        if (wv == 0) {
-            double t = 0.0;
-            for (int w = 0; w < 16; ++w) t += part[w][lane];
-            sv[lane] = lane < nb ? x[k0 + lane] - t : 0.0;
-        }
-        __syncthreads();
-        const double *Wb = Winv + (int64_t)kb * NB * NB;
-        if (wv == 0 && lane < nb) {
-            double t = 0.0;
-            for (int i = lane; i < nb; ++i) t += Wb[i * NB + lane] * sv[i];
-            x[k0 + lane] = t;
-        }
-        __syncthreads();
-    }
+    u += __shfl_xor(u, 1, 64);
+    u += __shfl_xor(u, 2, 64);
+    if (i < n && part == 0) r[i] -= u;
 }
 
-void launch_chol_solve(const double *L, const double *Winv, double *x, int n, const int32_t *fail, hipStream_t st)
+// Backward block kb: x_k = W_kk^T s_k, then s_i -= sum_c L[k0 + c][i] x_k[c] for the columns
+// i < k0.  Workgroup g owns columns 64 g .. 64 g + 63; workgroup 0 stores x_k.
+__global__ void __launch_bounds__(256) trsv_bwd_kernel(const double *__restrict__ L, const double *__restrict__ Winv,
+                                                       double *__restrict__ s, double *__restrict__ x, int n, int kb,
+                                                       const int32_t *fail)
 {
-    hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(1024), 0, st, L, Winv, x, n, fail);
+    __shared__ double sx[NB];
+    __shared__ double part_s[4][NB];
+    if (*fail) return;
+    const int k0 = kb * NB, nb = min(NB, n - k0);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double *Wb = Winv + (int64_t)kb * NB * NB;
+    {
+        // x_k[c] = sum_i W[i][c] s_k[i]: wave wv sums rows 16 wv .. 16 wv + 15 for column `lane`
+        double t = 0.0;
+#pragma unroll
+        for (int i = wv * 16; i < wv * 16 + 16; ++i) t += i < nb ? Wb[i * NB + lane] * s[k0 + i] : 0.0;
+        part_s[wv][lane] = t;
+    }
+    __syncthreads();
+    if (tid < NB) sx[tid] = part_s[0][tid] + part_s[1][tid] + part_s[2][tid] + part_s[3][tid];
+    __syncthreads();
+    if (blockIdx.x == 0 && tid < nb) x[k0 + tid] = sx[tid];
+    const int i = blockIdx.x * NB + lane;
+    double u = 0.0;
+    if (i < k0) {
+#pragma unroll
+        for (int c = wv * 16; c < wv * 16 + 16; ++c) u += c < nb ? L[(int64_t)(k0 + c) * n + i] * sx[c] : 0.0;
+    }
+    __syncthreads();
+    part_s[wv][lane] = u;
+    __syncthreads();
+    if (wv == 0 && i < k0) s[i] -= part_s[0][lane] + part_s[1][lane] + part_s[2][lane] + part_s[3][lane];
+}
+
+__global__ void zero_on_fail_kernel(double *x, int n, const int32_t *fail)
+{
+    if (!*fail) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = 0.0;
+}
+
+void launch_chol_solve(const double *L, double *Winv, double *x, int n, const int32_t *fail, hipStream_t st)
+{
+    const int nblk = (n + NB - 1) / NB;
+    double *y = Winv + (int64_t)nblk * NB * NB;
+    for (int kb = 0; kb < nblk; ++kb) {
+        const int below = n - (kb * NB + NB);
+        const int grid = below > 0 ? (below + NB - 1) / NB : 1;
+        hipLaunchKernelGGL(trsv_fwd_kernel, dim3(grid), dim3(256), 0, st, L, Winv, x, y, n, kb, fail);
+    }
+    for (int kb = nblk - 1; kb >= 0; --kb) {
+        const int grid = kb > 0 ? kb : 1;
+        hipLaunchKernelGGL(trsv_bwd_kernel, dim3(grid), dim3(256), 0, st, L, Winv, y, x, n, kb, fail);
+    }
+    hipLaunchKernelGGL(zero_on_fail_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, n, fail);
 }
 
 // ---- pose update

@@ -4,7 +4,8 @@ torch.autograd.Function, against the FP64 oracle gradient and central finite dif
 Tolerances: pose gradient within 1e-4 of max|g| of the oracle's; image gradients in relative L2
 1e-3 with 99.9% of texels within 1e-3 of max|g| (FP32 path: a few pixels near cell boundaries
 take the other cell, and atomic sums round in varying order); central differences of the GPU loss
-in single texels within 1e-3 |g| + 1e-4 max|g|.
+(eps 1e-4) in every pose component of a one-plane scene within 2% of max|g|, and in single texels
+within 1e-3 |g| + 1e-4 max|g| (depth: 5e-3 |g| + 2e-3 max|g|, FP32 warp quantisation).
 """
 import sys
 
@@ -116,9 +117,15 @@ def test_loss_image_gradient_vs_fp32_finite_differences(fixture, request, pba):
     Huber kink); a depth texel can move a warp or flip an occlusion test, and a depth difference
     whose +-eps evaluations change the valid count is skipped (counted).  Pose components are not
     differenced here: at these sizes almost every +-eps pose step changes the valid set somewhere,
-    so the pose gradient is tied to the oracle's, whose own differences use realised steps and
-    frozen masks.  Bar: |FD - g| <= 1e-3 |g| + 1e-4 max|g| per texel (FP32 residuals, F summed in
-    FP64 in a fixed order, so F(+eps) - F(-eps) carries only the changed pixels' rounding)."""
+    so the pose components are differenced on the one-plane scene above.  Bar per texel:
+    |FD - g| <= 1e-3 |g| + 1e-4 max|g| (F is summed in FP64 in a fixed order, so F(+eps) - F(-eps)
+    carries only the changed pixels' rounding).  Depth texels get 5e-3 |g| + 2e-3 max|g|: a depth
+    step of 1e-4 m moves the source pixel's warped coordinate by only ~1e-3 px (pinhole) or
+    ~2e-4 px (LiDAR), while the FP32 coordinate is quantised to ulp(u') = 8e-6 px at u' ~ 100 and
+    6e-5 px at u' ~ 768, so the part of the difference quotient that goes through the warp
+    carries up to ~30% noise (measured: 1.6% of g at a LiDAR texel; the FP64 oracle's own
+    quotient at these texels matches its gradient to 1e-8).  The oracle comparison above is the
+    tight check of the depth gradient."""
     p = _prob5(request.getfixturevalue(fixture))
     rng = np.random.default_rng(11)
     delta = np.zeros((p.n, 6), np.float32)
@@ -153,9 +160,10 @@ def test_loss_image_gradient_vs_fp32_finite_differences(fixture, request, pba):
                     fd = (Fp - Fm) / h
                     g = float(grads[k].reshape(-1)[idx])
                     err = abs(fd - g)
-                    worst = max(worst, err / (1e-3 * abs(g) + 1e-4 * scale))
+                    bar = (5e-3 * abs(g) + 2e-3 * scale) if what == "depth" else (1e-3 * abs(g) + 1e-4 * scale)
+                    worst = max(worst, err / bar)
                     checked += 1
-                    assert err <= 1e-3 * abs(g) + 1e-4 * scale, (what, k, idx, fd, g)
+                    assert err <= bar, (what, k, idx, fd, g)
             _log(fixture, "%s FD eps=%g: checked %d texels, skipped %d (valid count changed), worst %.2f of bar"
                  % (what, eps, checked, skipped, worst))
             assert checked >= 0.75 * (checked + skipped) and checked > 0
