@@ -38,6 +38,7 @@ def run_path(pba, prob, precision, warmup, steps):
     import torch
     with pba.context_for_problem(prob, precision=precision) as ctx:
         torch.cuda.synchronize()
+        ev_init = ctx.evaluate(want_system=True)   # the system at the initial poses, for FP32 vs FP64
         if warmup:
             ctx.iterate(warmup, use_lm=True, lambda0=1e-4)
         ev = ctx.evaluate()                      # system at the current poses; counts per evaluation
@@ -53,8 +54,8 @@ def run_path(pba, prob, precision, warmup, steps):
             ev2 = ctx.evaluate()
         tm = ctx.timings(reset=True)
         poses = ctx.get_poses()
-    return dict(elapsed=elapsed, logs=logs, n_evaluated=ev["n_evaluated"], n_valid=ev["n_valid"],
-                n_refined=ev2["n_refined"], eval_ms=tm["eval_ms"] / n_eval_runs, n_items=tm["n_items"],
+    return dict(elapsed=elapsed, logs=logs, n_evaluated=ev["n_evaluated"], n_valid=ev["n_valid"], init=ev_init,
+                eval_ms=tm["eval_ms"] / n_eval_runs, n_items=tm["n_items"],
                 items_px=tm["items_px"], grid=tm["grid"], poses=poses, F=logs[-1]["F"])
 
 
@@ -179,7 +180,16 @@ def main():
         out["fp64_value"] = r64["n_evaluated"] * args.steps / r64["elapsed"]
         out["final_ate_rmse"]["f64"] = ate_rmse(r64["poses"], prob.gt_poses)
         out["final_ate_rmse"]["abs_diff"] = abs(out["final_ate_rmse"]["f64"] - out["final_ate_rmse"]["f32"])
-        log("FP64: %.2f ms/iter" % (1e3 * r64["elapsed"] / args.steps))
+        a, b = r32["init"], r64["init"]
+        out["fp32_vs_fp64"] = {
+            "at": "initial poses, then after the timed iterations",
+            "F_rel": abs(a["F"] - b["F"]) / abs(b["F"]),
+            "H_rel_max": float(np.abs(a["H"] - b["H"]).max() / np.abs(b["H"]).max()),
+            "b_rel_max": float(np.abs(a["b"] - b["b"]).max() / np.abs(b["b"]).max()),
+            "valid_diff": int(a["n_valid"]) - int(b["n_valid"]),
+            "final_pose_max_dt_m": float(np.abs(r32["poses"][:, 9:] - r64["poses"][:, 9:]).max()),
+        }
+        log("FP64: %.2f ms/iter; FP32 vs FP64: %s" % (1e3 * r64["elapsed"] / args.steps, out["fp32_vs_fp64"]))
     if not args.no_cpu:
         log("CPU oracle baseline (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(prob)

@@ -69,8 +69,7 @@ enum { PBA_F32 = 0, PBA_F64 = 1 };
 /* Length of one per-pair record written by pba_evaluate (pair_out):
  * [0,144)  H12, 12x12 row-major over [dx_s (6); dx_t (6)]
  * [144,156) b12
- * 156 F (sum of rho), 157 evaluated source pixels, 158 valid correspondences,
- * 159 pixels whose integer cell was decided in FP64 (FP32 path only). */
+ * 156 F (sum of rho), 157 evaluated source pixels, 158 valid correspondences, 159 reserved (0). */
 #define PBA_PAIR_OUT_LEN 160
 
 /* A sensor model (Sec. III) and its rigid offset on the platform (Supplementary). */
@@ -100,15 +99,15 @@ typedef struct {
     double occlusion_tau_pinhole, occlusion_tau_spherical;
     /* every stencil tap's depth must be within tau of the predicted depth (Sec. IV-C,
        occlusion suppression), chosen by the target sensor's model */
-    double refine_band;          /* FP32 path: a projected coordinate within this many pixels of an
-                                    integer is recomputed in FP64 before its cell is chosen; 0 = off */
 } pba_config;
 
 /* Fill *cfg with defaults: F32, 5 channels, grad_mode 0, anchor 0, graphs on, Omega 1,
- * Huber 0.1, tau 0.5 m (pinhole) / 1.0 m (spherical), refine band 2e-3 px. */
+ * Huber 0.1, tau 0.5 m (pinhole) / 1.0 m (spherical). */
 void pba_config_default(pba_config *cfg);
 
-/* Create a context on cfg->device.  *out receives the handle. */
+/* Create a context on cfg->device.  *out receives the handle.  PBA_EINVAL for an unknown
+ * precision, channel count or grad_mode, a negative anchor, negative or non-finite Omega,
+ * non-finite Huber threshold, or tau <= 0; PBA_EDEVICE for a device that does not exist. */
 pba_status pba_create(const pba_config *cfg, pba_ctx **out);
 pba_status pba_destroy(pba_ctx *ctx);
 
@@ -136,7 +135,6 @@ typedef struct {
     double F;                    /* sum over pairs and pixels of rho(chi^2) */
     int64_t n_evaluated;         /* (pair, source pixel with valid depth) evaluations */
     int64_t n_valid;             /* valid correspondences */
-    int64_t n_refined;           /* cells decided in FP64 (FP32 path) */
     double *H;                   /* nullable: 6N x 6N, raw (no gauge fix, no damping) */
     double *b;                   /* nullable: 6N */
     double *pair_out;            /* nullable: P x PBA_PAIR_OUT_LEN, in the platform frames */

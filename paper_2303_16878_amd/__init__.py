@@ -46,12 +46,12 @@ class pba_config(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("omega_intensity", ctypes.c_double),
                 ("omega_depth", ctypes.c_double), ("omega_normal", ctypes.c_double),
                 ("huber_delta", ctypes.c_double), ("occlusion_tau_pinhole", ctypes.c_double),
-                ("occlusion_tau_spherical", ctypes.c_double), ("refine_band", ctypes.c_double)]
+                ("occlusion_tau_spherical", ctypes.c_double)]
 
 
 class pba_eval_out(ctypes.Structure):
     _fields_ = [("F", ctypes.c_double), ("n_evaluated", ctypes.c_int64), ("n_valid", ctypes.c_int64),
-                ("n_refined", ctypes.c_int64), ("H", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("H", ctypes.c_void_p), ("b", ctypes.c_void_p),
                 ("pair_out", ctypes.c_void_p), ("on_device", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
@@ -146,7 +146,7 @@ class Context:
 
     def __init__(self, device=0, precision=PBA_F32, channels=5, grad_mode=0, anchor=0, stream=None,
                  omega_intensity=1.0, omega_depth=1.0, omega_normal=1.0, huber_delta=0.1,
-                 occlusion_tau_pinhole=0.5, occlusion_tau_spherical=1.0, refine_band=None, use_graph=True):
+                 occlusion_tau_pinhole=0.5, occlusion_tau_spherical=1.0, use_graph=True):
         self.lib = load_library()
         cfg = config_default()
         cfg.device, cfg.precision, cfg.channels, cfg.grad_mode, cfg.anchor = device, precision, channels, grad_mode, anchor
@@ -162,8 +162,6 @@ class Context:
         cfg.omega_intensity, cfg.omega_depth, cfg.omega_normal = omega_intensity, omega_depth, omega_normal
         cfg.huber_delta = huber_delta
         cfg.occlusion_tau_pinhole, cfg.occlusion_tau_spherical = occlusion_tau_pinhole, occlusion_tau_spherical
-        if refine_band is not None:
-            cfg.refine_band = refine_band
         self.cfg = cfg
         h = ctypes.c_void_p()
         self._check(self.lib.pba_create(ctypes.byref(cfg), ctypes.byref(h)), ctx=None)
@@ -264,7 +262,7 @@ class Context:
             out.pair_out = po.ctypes.data
         out.on_device = 0
         self._check(self.lib.pba_evaluate(self.h, ctypes.byref(out)))
-        r = dict(F=out.F, n_evaluated=out.n_evaluated, n_valid=out.n_valid, n_refined=out.n_refined)
+        r = dict(F=out.F, n_evaluated=out.n_evaluated, n_valid=out.n_valid)
         if want_system:
             r.update(H=H, b=b)
         if want_pairs:

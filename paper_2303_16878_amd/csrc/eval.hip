@@ -122,14 +122,9 @@ void launch_pair_setup(const double *poses, const int2 *pairs, int P, const Sens
 
 // ------------------------------------------------------------------ per-pixel evaluation
 
-template <typename T>
-__device__ __forceinline__ T my_sqrt(T x) { return sqrt(x); }
-template <>
-__device__ __forceinline__ float my_sqrt<float>(float x) { return sqrtf(x); }
-
 // 1/x and 1/sqrt(x): exact division in FP64; the hardware reciprocal and reciprocal square root
-// (about 1 ulp) in FP32, where they feed Jacobians, weights and projections whose own FP32
-// rounding is of the same order.
+// (about 1 ulp) in FP32, where they feed Jacobians and weights whose own FP32 rounding is of the
+// same order.
 template <typename T>
 __device__ __forceinline__ T fast_rcp(T x) { return T(1) / x; }
 template <>
@@ -139,38 +134,45 @@ __device__ __forceinline__ T fast_rsq(T x) { return T(1) / sqrt(x); }
 template <>
 __device__ __forceinline__ float fast_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// atan2 in FP32 for the spherical projection.  Octant reduction to t = min(|x|,|y|)/max(|x|,|y|)
-// in [0, 1] (reciprocal plus one correction step), atan(t) = t P(t^2) with a degree-8 polynomial
-// fitted by weighted least squares at Chebyshev nodes on [0, 1] (approximation error 5.8e-9, below
-// FP32 rounding of the result), then the octant is restored with pi/2 and pi carried as hi + lo
-// pairs so that no constant rounding offsets whole octants.  Measured against an FP64 atan2 over
-// 2e6 random arguments: unbiased, mean 0.57 ulp, max 3.4 ulp.
-__device__ __forceinline__ float atan2_f32(float y, float x)
+// 1/x in FP64 to an ulp or two: the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp_f64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// sqrt(x) for x > 0 in FP64 to about two ulps: x times the hardware reciprocal square root
+// refined by two Newton steps.
+__device__ __forceinline__ double sqrt_f64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return x * y;
+}
+
+// Coarse atan2 in FP32 (error below 6.1e-4 rad): octant reduction and a quadratic in t^2 fitted
+// to atan on [0, 1].  It only picks the nearest ray of a table, so a fraction of a pixel is enough.
+__device__ __forceinline__ float atan2_coarse(float y, float x)
 {
     const float ax = fabsf(x), ay = fabsf(y);
     const float mx = fmaxf(fmaxf(ax, ay), 1e-30f), mn = fminf(ax, ay);
-    const float r = __builtin_amdgcn_rcpf(mx);
-    float t = mn * r;
-    t = fmaf(fmaf(-t, mx, mn), r, t);
-    const float s = t * t;
-    float p = 0.0024567232467234135f;
-    p = fmaf(p, s, -0.014401355758309364f);
-    p = fmaf(p, s, 0.039781227707862854f);
-    p = fmaf(p, s, -0.07234858721494675f);
-    p = fmaf(p, s, 0.10498947650194168f);
-    p = fmaf(p, s, -0.14161230623722076f);
-    p = fmaf(p, s, 0.19985906779766083f);
-    p = fmaf(p, s, -0.33332598209381104f);
-    p = fmaf(p, s, 0.9999998807907104f);
-    float a = p * t;
-    if (ay > ax) a = (1.57079637050628662f - a) - 4.37113900018624284e-8f;
-    if (x < 0.f) a = (3.14159274101257324f - a) - 8.74227800037248568e-8f;
+    const float t = mn * __builtin_amdgcn_rcpf(mx), s = t * t;
+    float a = t * fmaf(fmaf(0.07933887839317322f, s, -0.28869009017944336f), s, 0.9953579306602478f);
+    if (ay > ax) a = 1.57079637f - a;
+    if (x < 0.f) a = 3.14159274f - a;
     return y < 0.f ? -a : a;
 }
-template <typename T>
-__device__ __forceinline__ T my_atan2(T y, T x) { return atan2(y, x); }
-template <>
-__device__ __forceinline__ float my_atan2<float>(float y, float x) { return atan2_f32(y, x); }
+
+// atan(t) for small |t| by its Taylor series to t^7 (remainder below t^9 / 9: 3e-13 rad at 0.05,
+// 1.1e-10 rad at 0.1).
+__device__ __forceinline__ double atan_small(double t)
+{
+    const double t2 = t * t;
+    return t * fma(t2, fma(t2, fma(t2, -1.0 / 7.0, 0.2), -1.0 / 3.0), 1.0);
+}
+
 
 // value and image Jacobian [d/dcol, d/drow] of one channel at the bilinear point.
 // a0..a3: row y0, cols x0-1..x0+2; b0..b3: row y0+1; c1,c2: row y0-1, cols x0, x0+1;
@@ -356,30 +358,31 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         const uint32_t magic = (uint32_t)uni((int)ss.magic_w);
         const int px1 = min(px0 + a.items_px, npx);
 
-        // pair constants in the evaluation precision (FP32: leading part plus correction)
-        T R[9], tr[3], cc[3], Rl[9], tl[3];
+        // pair transform in FP64 for the geometry of phase 1; in the evaluation precision for the
+        // normal cue of phase 2 (FP32: leading part plus correction, so that the rounding of R does
+        // not rotate every normal of the pair alike)
+        double Rd[9], td[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Rd[k] = pd.Rd[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) td[k] = pd.td[k];
+        T R[9], cc[3], Rl[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             R[k] = F32 ? (T)pd.R[k] : (T)pd.Rd[k];
             Rl[k] = F32 ? (T)pd.Rlo[k] : T(0);
         }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            tr[k] = F32 ? (T)pd.t[k] : (T)pd.td[k];
-            tl[k] = F32 ? (T)pd.tlo[k] : T(0);
-            cc[k] = (T)pd.c[k];
-        }
+        for (int k = 0; k < 3; ++k) cc[k] = (T)pd.c[k];
         if (!F32) {
             double cd[3];
             mtv3(st.Ro, st.to, cd);
             for (int k = 0; k < 3; ++k) cc[k] = (T)cd[k];
         }
-        const T fx = F32 ? (T)st.fx : (T)st.fxd, fy = F32 ? (T)st.fy : (T)st.fyd;
-        const T cx = F32 ? (T)st.cx : (T)st.cxd, cy = F32 ? (T)st.cy : (T)st.cyd;
-        const T dmin = F32 ? (T)st.dmin : (T)st.dmind;
+        const double st_fx = st.fxd, st_fy = st.fyd, st_cx = st.cxd, st_cy = st.cyd, st_dmin = st.dmind;
+        const T fx = (T)st_fx, fy = (T)st_fy;
         const T tau = F32 ? (T)st.tau : (T)st.taud;
         const T om_g = (T)a.omega_g, om_d = (T)a.omega_d, om_n = (T)a.omega_n, delta = (T)a.huber;
-        const float band = (float)a.refine_band;
         const L2 *lcol = lut + ss.lut_col, *lrow = lut + ss.lut_row;
         const float *sdep = a.dep + ks.off;
         const float4 *satt4 = a.att4 + ks.off;
@@ -392,7 +395,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         double acc[ACC_F + 1];
 #pragma unroll
         for (int k = 0; k <= ACC_F; ++k) acc[k] = 0.0;
-        int n_eval = 0, n_valid = 0, n_ref = 0;
+        int n_eval = 0, n_valid = 0;
         int head = 0, tail = 0;   // wave-uniform queue positions
 
         // phase 2: residuals, weights, Jacobian rows and accumulation of queue slot `slot`
@@ -457,8 +460,12 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             // Huber on sqrt(chi^2): w = d rho / d chi^2
             T w = T(1), rhov = chi2;
             if (delta > T(0)) {
-                const T isq = fast_rsq(chi2), sq = chi2 * isq;
-                if (sq > delta) { w = delta * isq; rhov = delta * (T(2) * sq - delta); }
+                // the reciprocal square root only where chi^2 is beyond delta^2 (never of a tiny value)
+                if (chi2 > delta * delta) {
+                    const T isq = fast_rsq(chi2), sq = chi2 * isq;
+                    w = delta * isq;
+                    rhov = delta * (T(2) * sq - delta);
+                }
             }
             acc[ACC_F] += (double)rhov;
             n_valid += 1;
@@ -567,97 +574,62 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 int row = (int)__umulhi((uint32_t)pix, magic);
                 int col = pix - row * Ws;
                 if (col < 0) { row -= 1; col += Ws; }   // the reciprocal can only round up
-                // unprojection q = d * ray(u) and transform into the target sensor frame
-                const L2 lc = lcol[col], lr = lrow[row];
-                const T d = (T)Ds;
-                T qx, qy, qz;
-                if (SM == MODEL_SPHERICAL) { qx = d * (lr.x * lc.x); qy = d * (lr.x * lc.y); qz = d * lr.y; }
-                else { qx = d * lc.x; qy = d * lr.x; qz = d; }
-                px = R[0] * qx + R[1] * qy + R[2] * qz + tr[0];
-                py = R[3] * qx + R[4] * qy + R[5] * qz + tr[1];
-                pz = R[6] * qx + R[7] * qy + R[8] * qz + tr[2];
-                if (F32) {
-                    px += Rl[0] * qx + Rl[1] * qy + Rl[2] * qz + tl[0];
-                    py += Rl[3] * qx + Rl[4] * qy + Rl[5] * qz + tl[1];
-                    pz += Rl[6] * qx + Rl[7] * qy + Rl[8] * qz + tl[2];
-                }
+                // Geometry in FP64 in both paths (on this chip FP64 vector arithmetic issues at the FP32
+                // rate): unprojection q = d * ray(u) from the FP64 ray table, p_bar = R q + t, the
+                // projected coordinates and the depth/range cue.  Cells, masks and the large-magnitude
+                // part of the depth residual then carry no FP32 rounding.
+                const double2 lcd = a.lut64[ss.lut_col + col], lrd = a.lut64[ss.lut_row + row];
+                const double dd = (double)Ds;
+                double q0, q1, q2;
+                if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
+                else { q0 = dd * lcd.x; q1 = dd * lrd.x; q2 = dd; }
+                const double X = fma(Rd[0], q0, fma(Rd[1], q1, fma(Rd[2], q2, td[0])));
+                const double Y = fma(Rd[3], q0, fma(Rd[4], q1, fma(Rd[5], q2, td[1])));
+                const double Z = fma(Rd[6], q0, fma(Rd[7], q1, fma(Rd[8], q2, td[2])));
+                px = (T)X; py = (T)Y; pz = (T)Z;
                 // projection (Sec. III) and predicted depth/range cue
-                T u, v, zeta_d;
-                bool ok;
+                double u, v, zeta;
+                bool ok, near = true;
                 if (TM == MODEL_PINHOLE) {
-                    ok = pz >= dmin;
-                    const T iz = fast_rcp(pz);
-                    u = fx * px * iz + cx;
-                    v = fy * py * iz + cy;
-                    zeta_d = pz;
+                    ok = Z >= st_dmin;
+                    const double iz = rcp_f64(Z);
+                    u = fma(st_fx * X, iz, st_cx);
+                    v = fma(st_fy * Y, iz, st_cy);
+                    zeta = Z;
                 } else {
-                    const T r2 = px * px + py * py, rho = F32 ? r2 * fast_rsq(r2) : my_sqrt(r2), n2 = r2 + pz * pz;
-                    ok = (r2 > T(0)) && (n2 >= dmin * dmin);
-                    u = fx * my_atan2(py, px) + cx;
-                    v = fy * my_atan2(pz, rho) + cy;
-                    zeta_d = my_sqrt(n2);
+                    const double r2 = fma(X, X, Y * Y), n2 = fma(Z, Z, r2);
+                    ok = (r2 > 0.0) && (n2 >= st_dmin * st_dmin);
+                    if (F32) {
+                        zeta = sqrt_f64(n2);
+                        const double rho = sqrt_f64(r2);
+                        // nearest column / row from a coarse FP32 estimate, then the exact angular offset
+                        // from that ray of the FP64 table: az - az_k = atan2(Y cos az_k - X sin az_k,
+                        // X cos az_k + Y sin az_k), a small angle, and likewise for the elevation
+                        const float ua = (float)st_fx * atan2_coarse((float)Y, (float)X) + (float)st_cx;
+                        const float va = (float)st_fy * atan2_coarse((float)Z, (float)rho) + (float)st_cy;
+                        // far outside the image the estimate decides alone (it is good to a fraction of a
+                        // pixel); inside, the nearest table ray is within 1 px, so the offset angle is small
+                        near = ua > -1.f && ua < (float)Wt && va > -1.f && va < (float)Ht;
+                        const int kc = min(max((int)rintf(ua), 0), Wt - 1), kr = min(max((int)rintf(va), 0), Ht - 1);
+                        const double2 cs = a.lut64[st.lut_col + kc], rs = a.lut64[st.lut_row + kr];
+                        const double tu = fma(Y, cs.x, -X * cs.y) * rcp_f64(fma(X, cs.x, Y * cs.y));
+                        const double tv = fma(Z, rs.x, -rho * rs.y) * rcp_f64(fma(rho, rs.x, Z * rs.y));
+                        u = fma(st_fx, atan_small(tu), (double)kc);
+                        v = fma(st_fy, atan_small(tv), (double)kr);
+                    } else {
+                        zeta = sqrt(n2);
+                        u = fma(st_fx, atan2(Y, X), st_cx);
+                        v = fma(st_fy, atan2(Z, sqrt(r2)), st_cy);
+                    }
                 }
+                const T zeta_d = (T)zeta;
                 if (ok) {
                     if (DBG) { a.dbg_status[pix] = 3; a.dbg_uv[pix] = make_float2((float)u, (float)v); }
-                    // choose the integer cell; near a cell boundary the FP32 path decides it in FP64
-                    bool refined = false;
-                    if (F32 && band > 0.f) {
-                        const float fu = (float)u - floorf((float)u), fv = (float)v - floorf((float)v);
-                        refined = fu < band || fu > 1.f - band || fv < band || fv > 1.f - band;
-                    }
-                    if (refined) {
-                        // Decide which side of the nearest integer each coordinate lies on exactly, in FP64:
-                        // u' >= k  <=>  the point is on the far side of the ray of column k (spherical: the
-                        // sign of Y cos az_k - X sin az_k, with (cos az_k, sin az_k) from the FP64 ray table;
-                        // pinhole: the sign of fx X - (k - cx) Z).  No transcendental is evaluated.
-                        const double2 lcd = a.lut64[ss.lut_col + col], lrd = a.lut64[ss.lut_row + row];
-                        const double dd = (double)Ds;
-                        double q0, q1, q2;
-                        if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
-                        else { q0 = dd * lcd.x; q1 = dd * lrd.x; q2 = dd; }
-                        const double *Rd = pd.Rd, *td = pd.td;
-                        const double X = Rd[0] * q0 + Rd[1] * q1 + Rd[2] * q2 + td[0];
-                        const double Y = Rd[3] * q0 + Rd[4] * q1 + Rd[5] * q2 + td[1];
-                        const double Z = Rd[6] * q0 + Rd[7] * q1 + Rd[8] * q2 + td[2];
-                        const float uf = (float)u, vf = (float)v;
-                        int xi = (int)floorf(uf), yi = (int)floorf(vf);
-                        const float ru = rintf(uf), rv = rintf(vf);
-                        if (fabsf(uf - ru) < band && ru >= 0.f && ru < (float)Wt) {
-                            const int k = (int)ru;
-                            bool ge;
-                            if (TM == MODEL_PINHOLE) {
-                                ge = st.fxd * X - ((double)k - st.cxd) * Z >= 0.0;
-                            } else {
-                                const double2 cs = a.lut64[st.lut_col + k];
-                                const double sd = Y * cs.x - X * cs.y;   // sign of az - az_k
-                                ge = st.fxd > 0.0 ? sd >= 0.0 : sd <= 0.0;
-                            }
-                            xi = ge ? k : k - 1;
-                        }
-                        if (fabsf(vf - rv) < band && rv >= 0.f && rv < (float)Ht) {
-                            const int k = (int)rv;
-                            bool ge;
-                            if (TM == MODEL_PINHOLE) {
-                                ge = st.fyd * Y - ((double)k - st.cyd) * Z >= 0.0;
-                            } else {
-                                const double2 cs = a.lut64[st.lut_row + k];
-                                const double sd = Z * cs.x - sqrt(X * X + Y * Y) * cs.y;   // sign of el - el_k
-                                ge = st.fyd > 0.0 ? sd >= 0.0 : sd <= 0.0;
-                            }
-                            yi = ge ? k : k - 1;
-                        }
-                        ++n_ref;
-                        ok = xi >= 1 && xi <= Wt - 3 && yi >= 1 && yi <= Ht - 3;
-                        if (ok) {
-                            x0 = xi; y0 = yi;
-                            al = u - (T)x0; be = v - (T)y0;
-                        }
-                    } else {
-                        ok = u >= T(1) && u < (T)(Wt - 2) && v >= T(1) && v < (T)(Ht - 2);
-                        if (ok) {
-                            x0 = (int)u; y0 = (int)v;
-                            al = u - (T)x0; be = v - (T)y0;
-                        }
+                    // the integer cell floor(u'), and the stencil inside the image
+                    ok = near && u >= 1.0 && u < (double)(Wt - 2) && v >= 1.0 && v < (double)(Ht - 2);
+                    if (ok) {
+                        x0 = (int)u; y0 = (int)v;
+                        al = (T)(u - (double)x0); be = (T)(v - (double)y0);
                     }
                     if (ok) {
                         if (DBG) { a.dbg_status[pix] = 4; a.dbg_cell[pix] = make_int2(x0, y0); }
@@ -675,11 +647,16 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         if (vis) {
                             const T w00 = (T(1) - al) * (T(1) - be), w01 = al * (T(1) - be);
                             const T w10 = (T(1) - al) * be, w11 = al * be;
-                            T Vd;
-                            sample_channel<T, GM>((T)tD[0], (T)tD[1], (T)tD[2], (T)tD[3], (T)tD[4], (T)tD[5],
-                                                  (T)tD[6], (T)tD[7], (T)tD[8], (T)tD[9], (T)tD[10], (T)tD[11],
-                                                  w00, w01, w10, w11, al, be, Vd, gxd, gyd);
-                            edv = zeta_d - Vd;
+                            // e_d = zeta - D(u') taken relative to the tap at (x0, y0): the taps lie within
+                            // tau of zeta, so their differences are exact and the large common part
+                            // cancels in FP64 before anything is rounded to the evaluation precision
+                            const float d0 = tD[1];
+                            T Vr;
+                            sample_channel<T, GM>((T)(tD[0] - d0), T(0), (T)(tD[2] - d0), (T)(tD[3] - d0),
+                                                  (T)(tD[4] - d0), (T)(tD[5] - d0), (T)(tD[6] - d0), (T)(tD[7] - d0),
+                                                  (T)(tD[8] - d0), (T)(tD[9] - d0), (T)(tD[10] - d0),
+                                                  (T)(tD[11] - d0), w00, w01, w10, w11, al, be, Vr, gxd, gyd);
+                            edv = (T)(zeta - (double)d0) - Vr;
                             valid = true;
                         }
                     }
@@ -711,8 +688,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         // workgroup reduction of the accumulators (fixed order: deterministic)
 #pragma unroll
         for (int k = 0; k < ACC_USED; ++k) {
-            double v = k <= ACC_F ? acc[k] : (k == ACC_VALID ? (double)n_valid : (k == ACC_EVAL ? (double)n_eval
-                                                                                                   : (double)n_ref));
+            double v = k <= ACC_F ? acc[k] : (k == ACC_VALID ? (double)n_valid : (double)n_eval);
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
             if (lane == 0) s_red[wave][k] = v;
@@ -927,7 +903,7 @@ __global__ void __launch_bounds__(64) reduce_pairs_kernel(const double *__restri
         o[156] = sums[ACC_F];
         o[157] = sums[ACC_EVAL];
         o[158] = sums[ACC_VALID];
-        o[159] = sums[ACC_REF];
+        o[159] = 0.0;
     }
 }
 
@@ -980,7 +956,7 @@ __global__ void __launch_bounds__(64) assemble_H_kernel(const double *__restrict
 }
 
 // b per keyframe (bk_ent = 2 * pair + side, side 0 = source, 1 = target) and the totals
-// F, evaluated, valid, refined summed over pairs in order (one workgroup).
+// F, evaluated, valid (and the reserved slot) summed over pairs in order (one workgroup).
 __global__ void __launch_bounds__(256) assemble_b_kernel(const double *__restrict__ pair_out, int P,
                                                          const int32_t *__restrict__ bk_ptr,
                                                          const int32_t *__restrict__ bk_ent, int N,

@@ -8,8 +8,8 @@ namespace pba {
 
 constexpr int kBlock = 256;      // threads per evaluation workgroup (4 wave64)
 constexpr int kAcc = 32;         // accumulator slots per work item
-// accumulator layout: 21 upper-triangular H terms, 6 b terms, F, valid, evaluated, refined
-enum { ACC_H = 0, ACC_B = 21, ACC_F = 27, ACC_VALID = 28, ACC_EVAL = 29, ACC_REF = 30, ACC_USED = 31 };
+// accumulator layout: 21 upper-triangular H terms, 6 b terms, F, valid, evaluated
+enum { ACC_H = 0, ACC_B = 21, ACC_F = 27, ACC_VALID = 28, ACC_EVAL = 29, ACC_USED = 30 };
 constexpr int kPairOut = 160;    // PBA_PAIR_OUT_LEN
 // packed depth of a pixel without a valid measurement: negative, so it fails any depth test
 // and every occlusion bound |D - zeta| <= tau
@@ -60,7 +60,7 @@ struct EvalArgs {
     int32_t pad;
     uint32_t *counter;           // kXcd queue counters of this launch
     void *partials;              // double[n_items][kAcc]
-    double omega_g, omega_d, omega_n, huber, refine_band;
+    double omega_g, omega_d, omega_n, huber;
     // loss adjoint outputs (adjoint launches only): arenas laid out like the images
     float *g_int, *g_dep, *g_nrm;
     double adj_scale;

@@ -361,7 +361,6 @@ EvalArgs make_args(pba_ctx *c)
     a.omega_d = c->cfg.omega_depth;
     a.omega_n = c->cfg.omega_normal;
     a.huber = c->cfg.huber_delta;
-    a.refine_band = c->cfg.precision == PBA_F32 ? c->cfg.refine_band : 0.0;
     return a;
 }
 
@@ -482,7 +481,6 @@ void pba_config_default(pba_config *cfg)
     cfg->huber_delta = 0.1;
     cfg->occlusion_tau_pinhole = 0.5;
     cfg->occlusion_tau_spherical = 1.0;
-    cfg->refine_band = 2e-3;
 }
 
 const char *pba_status_string(pba_status s)
@@ -509,7 +507,12 @@ pba_status pba_create(const pba_config *cfg, pba_ctx **out)
     if (cfg->channels != 2 && cfg->channels != 5) return PBA_EINVAL;
     if (cfg->grad_mode != 0 && cfg->grad_mode != 1) return PBA_EINVAL;
     if (cfg->anchor < 0) return PBA_EINVAL;
-    if (!(cfg->refine_band >= 0.0 && cfg->refine_band < 0.5)) return PBA_EINVAL;
+    const double w[6] = {cfg->omega_intensity, cfg->omega_depth, cfg->omega_normal, cfg->huber_delta,
+                         cfg->occlusion_tau_pinhole, cfg->occlusion_tau_spherical};
+    for (double x : w)
+        if (!std::isfinite(x)) return PBA_EINVAL;
+    if (cfg->omega_intensity < 0 || cfg->omega_depth < 0 || cfg->omega_normal < 0) return PBA_EINVAL;
+    if (!(cfg->occlusion_tau_pinhole > 0) || !(cfg->occlusion_tau_spherical > 0)) return PBA_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return PBA_EDEVICE;
     if (hipSetDevice(cfg->device) != hipSuccess) return PBA_EDEVICE;
@@ -723,7 +726,6 @@ pba_status pba_evaluate(pba_ctx *c, pba_eval_out *out)
     out->F = tot[0];
     out->n_evaluated = (int64_t)tot[1];
     out->n_valid = (int64_t)tot[2];
-    out->n_refined = (int64_t)tot[3];
     return PBA_OK;
 }
 

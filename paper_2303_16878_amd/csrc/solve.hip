@@ -52,79 +52,148 @@ __device__ __forceinline__ double bcast(double v, int lane)
     return __hiloint2double(hi, lo);
 }
 
-// Factor the diagonal block at k0 and write L_kk (lower) to A and W = L_kk^-1 (lower, row-major
-// 64 x 64, zero above the diagonal) to Winv.  One wave, 64 column steps each, written as loops
-// whose bodies address registers statically (the register window shifts by one column per
-// step), so the code stays small instead of being unrolled 64 x 64 times.
-// Factor (right-looking): lane i keeps the not yet eliminated part of row i, r[k] = a(i, j + k) at
-// step j; the step's column is published in LDS and read back as broadcasts.
-// Inverse: lane c keeps column c of W and runs the forward substitution L w = e_c, with the rows
-// of L read from LDS as broadcasts; w_0 .. w_{i-1} sit at the top of the window at step i.
-// A ragged last block is padded with the identity, whose factor and inverse are the identity.
-__global__ void __launch_bounds__(64) chol_diag_kernel(double *A, int n, int k0, double *Winv, int32_t *fail)
+// 1/sqrt(d) in FP64 to about an ulp: the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsqrt_f64(double d)
 {
-    __shared__ double col[2 * NB];
-    __shared__ double dinv[NB];
-    __shared__ double Lpad[NB + NB * NB];   // NB zeros, then L row-major
+    double y = __builtin_amdgcn_rsq(d);
+    y = y * fma(-0.5 * d * y, y, 1.5);
+    return y * fma(-0.5 * d * y, y, 1.5);
+}
+
+constexpr int SB = 16;   // sub-block of the diagonal factorisation
+
+// Factor the SB x SB SPD block at S (leading dimension ld, in LDS) in place (lower; zero above) and
+// write its inverse factor to Wd (leading dimension ld).  Lanes 0..SB-1 of one wave each keep one
+// row in registers; column entries are broadcast with readlane.  Returns true if a pivot was not
+// positive.
+__device__ bool factor_sub(double *S, double *Wd, int ld, int lane)
+{
+    double r[SB];
+#pragma unroll
+    for (int k = 0; k < SB; ++k) r[k] = lane < SB ? S[lane * ld + k] : 0.0;
+    bool bad = false;
+    double inv[SB];
+#pragma unroll
+    for (int j = 0; j < SB; ++j) {
+        const double d = bcast(r[j], j);
+        bad = bad || !(d > 0.0);
+        inv[j] = d > 0.0 ? rsqrt_f64(d) : 1.0;
+        const double sd = d > 0.0 ? d * inv[j] : 1.0;
+        r[j] = lane == j ? sd : (lane > j ? r[j] * inv[j] : r[j]);
+#pragma unroll
+        for (int k = j + 1; k < SB; ++k) {
+            const double lkj = bcast(r[j], k);
+            if (lane >= k) r[k] = fma(-r[j], lkj, r[k]);
+        }
+    }
+    // inverse row by row: row m is final once scaled by 1 / L_mm, then removed from the rows below
+    double w[SB];
+#pragma unroll
+    for (int c = 0; c < SB; ++c) w[c] = c == lane ? 1.0 : 0.0;
+#pragma unroll
+    for (int m = 0; m < SB; ++m) {
+        if (lane == m) {
+#pragma unroll
+            for (int c = 0; c <= m; ++c) w[c] *= inv[m];
+        }
+#pragma unroll
+        for (int c = 0; c <= m; ++c) {
+            const double wmc = bcast(w[c], m);
+            if (lane > m) w[c] = fma(-r[m], wmc, w[c]);
+        }
+    }
+    if (lane < SB) {
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+            S[lane * ld + k] = k <= lane ? r[k] : 0.0;
+            Wd[lane * ld + k] = k <= lane ? w[k] : 0.0;
+        }
+    }
+    return bad;
+}
+
+// Factor the diagonal block at k0 and write L_kk (lower) to A and W = L_kk^-1 (lower, row-major
+// 64 x 64, zero above the diagonal) to Winv.  One workgroup of 256 threads, the block in LDS,
+// right-looking over 16-wide sub-blocks: the 16 x 16 diagonal sub-block is factored and inverted by
+// one wave, the sub-panel below is multiplied by that inverse and the trailing lower triangle
+// updated by all threads.  The inverse is then assembled by block rows,
+// W_ij = -W_ii sum_{j <= k < i} L_ik W_kj.  A ragged last block is padded with the identity,
+// whose factor and inverse are the identity.
+__global__ void __launch_bounds__(256) chol_diag_kernel(double *A, int n, int k0, double *Winv, int32_t *fail)
+{
+    __shared__ double S[NB][NB + 1];
+    __shared__ double W[NB][NB + 1];
+    __shared__ double P[NB][SB + 1];
+    __shared__ double T[SB][NB + 1];
+    __shared__ int s_bad;
     if (*fail) return;
     const int nb = min(NB, n - k0);
-    const int lane = threadIdx.x;
-    double *Ls = Lpad + NB;
-    col[NB + lane] = 0.0;
-    Lpad[lane] = 0.0;
-    double r[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k)
-        r[k] = (lane < nb && k < nb) ? A[(int64_t)(k0 + lane) * n + k0 + k] : (k == lane ? 1.0 : 0.0);
-    bool bad = false;
-#pragma nounroll
-    for (int j = 0; j < NB; ++j) {
-        col[lane] = r[0];
-        __syncthreads();
-        const double d = col[j];
-        bad = bad || !(d > 0.0);
-        const double sd = d > 0.0 ? sqrt(d) : 1.0;
-        const double inv = 1.0 / sd;
-        const double lij = lane == j ? sd : (lane > j ? r[0] * inv : 0.0);
-        Ls[lane * NB + j] = lij;
-        if (lane == j) dinv[j] = inv;
-        const double *cj = col + j;
-#pragma unroll
-        for (int k = 1; k < NB; ++k) {
-            const double lkj = cj[k] * inv;   // L(j + k, j); zero padding beyond the block
-            r[k - 1] = lane >= j + k ? fma(-lij, lkj, r[k]) : r[k];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, k = e % NB;
+        S[i][k] = (i < nb && k < nb) ? A[(int64_t)(k0 + i) * n + k0 + k] : (i == k ? 1.0 : 0.0);
+        W[i][k] = 0.0;
+    }
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+#pragma unroll 1
+    for (int o = 0; o < NB; o += SB) {
+        if (wave == 0) {
+            const bool bad = factor_sub(&S[o][o], &W[o][o], NB + 1, lane);
+            if (lane == 0 && bad) s_bad = 1;
         }
-        r[NB - 1] = 0.0;
+        __syncthreads();
+        // sub-panel: L(i, o + c) = sum_k A(i, o + k) W_oo(c, k) for the rows below
+        const int rows = NB - o - SB;
+        for (int e = tid; e < rows * SB; e += blockDim.x) {
+            const int i = o + SB + e / SB, c = e % SB;
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < SB; ++k) acc = fma(S[i][o + k], W[o + c][o + k], acc);
+            P[i][c] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < rows * SB; e += blockDim.x) {
+            const int i = o + SB + e / SB, c = e % SB;
+            S[i][o + c] = P[i][c];
+        }
+        for (int e = tid; e < rows * rows; e += blockDim.x) {
+            const int i = o + SB + e / rows, j = o + SB + e % rows;
+            if (j <= i) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < SB; ++k) acc = fma(P[i][k], P[j][k], acc);
+                S[i][j] -= acc;
+            }
+        }
         __syncthreads();
     }
-    // the factor, rows in lanes
-#pragma nounroll
-    for (int k = 0; k < nb; ++k)
-        if (lane < nb && k <= lane) A[(int64_t)(k0 + lane) * n + k0 + k] = Ls[lane * NB + k];
-    double w[NB];
-#pragma unroll
-    for (int m = 0; m < NB; ++m) w[m] = 0.0;
-#pragma nounroll
-    for (int i = 0; i < NB; ++i) {
-        // sum_{k < i} L(i, k) w_k with w_k at w[NB - i + k]: Lrow[m] = L(i, m + i - NB), zero for m < NB - i
-        const double *Lrow = Ls + i * NB + i - NB;
-        double s0 = i == lane ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-        for (int m = 0; m < NB; m += 4) {
-            s0 = fma(-Lrow[m], w[m], s0);
-            s1 = fma(-Lrow[m + 1], w[m + 1], s1);
-            s2 = fma(-Lrow[m + 2], w[m + 2], s2);
-            s3 = fma(-Lrow[m + 3], w[m + 3], s3);
+    // off-diagonal blocks of the inverse, block row by block row
+#pragma unroll 1
+    for (int bi = 1; bi < NB / SB; ++bi) {
+        const int ri = bi * SB;
+        for (int e = tid; e < SB * ri; e += blockDim.x) {
+            const int r = e / ri, c = e % ri;      // T(r, c) = sum_{k = c_block .. ri - 1} L(ri + r, k) W(k, c)
+            double acc = 0.0;
+            for (int k = (c / SB) * SB; k < ri; ++k) acc = fma(S[ri + r][k], W[k][c], acc);
+            T[r][c] = acc;
         }
-        const double wi = ((s0 + s1) + (s2 + s3)) * dinv[i];
-#pragma unroll
-        for (int m = 0; m < NB - 1; ++m) w[m] = w[m + 1];
-        w[NB - 1] = wi;
+        __syncthreads();
+        for (int e = tid; e < SB * ri; e += blockDim.x) {
+            const int r = e / ri, c = e % ri;
+            double acc = 0.0;
+            for (int m = 0; m <= r; ++m) acc = fma(W[ri + r][ri + m], T[m][c], acc);
+            W[ri + r][c] = -acc;
+        }
+        __syncthreads();
     }
     double *Wb = Winv + (int64_t)(k0 / NB) * NB * NB;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) Wb[i * NB + lane] = (i < nb && lane < nb && lane <= i) ? w[i] : 0.0;
-    if (lane == 0 && __any(bad)) *fail = 1;
+    for (int e = tid; e < NB * NB; e += blockDim.x) {
+        const int i = e / NB, k = e % NB;
+        Wb[e] = (i < nb && k < nb && k <= i) ? W[i][k] : 0.0;
+        if (i < nb && k <= i) A[(int64_t)(k0 + i) * n + k0 + k] = S[i][k];
+    }
+    if (tid == 0 && s_bad) *fail = 1;
 }
 
 // Panel below the diagonal block: X = B W^T for 64 rows per workgroup (16 x 16 threads, 4 x 4 each).
@@ -210,7 +279,7 @@ void launch_cholesky(double *A, int n, double *Winv, int32_t *fail, hipStream_t 
 {
     hipLaunchKernelGGL(reset_flag_kernel, dim3(1), dim3(1), 0, st, fail);
     for (int k0 = 0; k0 < n; k0 += NB) {
-        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(64), 0, st, A, n, k0, Winv, fail);
+        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, A, n, k0, Winv, fail);
         const int rest = n - k0 - NB;
         if (rest > 0) {
             const int nbr = (rest + NB - 1) / NB;
@@ -374,7 +443,7 @@ void launch_boxplus(const double *X, const double *dx, double *Xout, int N, cons
     hipLaunchKernelGGL(boxplus_kernel, dim3(1), dim3(256), 0, st, X, dx, Xout, N, fail, lm);
 }
 
-// Accept/reject the candidate: totals_cand = {F, evaluated, valid, refined} at the candidate
+// Accept/reject the candidate: totals_cand = {F, evaluated, valid, 0} at the candidate
 // poses.  Gauss-Newton (use_lm = 0) accepts every solved step; LM accepts if F decreases.
 // On accept the candidate system, gradient and poses become current.  Writes one log row
 // {F, lambda, step_norm, valid, accepted}.

@@ -476,6 +476,44 @@ def lidar128(seed=4, **kw):
     return lidar_loop("lidar128", seed, **kw)
 
 
+def joint(seed=5, n_lidar=200, n_rgbd=400, H_l=128, W_l=1024, H_c=480, W_c=640, radius=20.0, length=2000.0,
+          n_struct=5000):
+    """Joint LiDAR + RGB-D rig on the 2 km driving loop: a spherical LiDAR (el -25..+8 deg) and a
+    forward-looking pinhole camera (fx = fy = 525 at 640x480, scaled with the size) mounted on one
+    platform with fixed seeded extrinsics (sensor -> platform offsets).  n_lidar LiDAR keyframes
+    and n_rgbd camera keyframes spaced along the loop; every ordered pair of keyframes within
+    `radius` metres is used, same-sensor and cross-sensor alike."""
+    rng = np.random.default_rng(seed)
+    pts, cum, rects = _driving_world(rng, n_struct, length)
+    # extrinsics: LiDAR 0.3 m above the platform origin; camera forward-looking with a small
+    # seeded misalignment, 0.2 m ahead
+    lid_off = np.concatenate([np.eye(3).reshape(-1), [0.0, 0.0, 0.3]])
+    Rc = np.array([[0.0, 0.0, 1.0], [-1.0, 0.0, 0.0], [0.0, -1.0, 0.0]])     # columns: right, down, forward
+    Rc = rot_axis_angle(rng.normal(size=3), math.radians(2.0)) @ Rc
+    cam_off = np.concatenate([Rc.reshape(-1), [0.2, rng.uniform(-0.1, 0.1), 0.1]])
+    sc = W_c / 640.0
+    lid = spherical_sensor(H_l, W_l, offset=lid_off)
+    cam = pinhole_sensor(H_c, W_c, 525.0 * sc, 525.0 * sc, (W_c - 1) / 2.0, (H_c - 1) / 2.0, min_depth=0.3,
+                         max_depth=40.0, offset=cam_off)
+    s_l = np.arange(n_lidar) * (length / max(n_lidar, 1))
+    s_c = (np.arange(n_rgbd) + 0.5) * (length / max(n_rgbd, 1))
+    p2, tan = _sample_curve(pts, cum, np.concatenate([s_l, s_c]))
+    gt = []
+    for k in range(len(p2)):
+        R = _look_frame_lidar([tan[k, 0], tan[k, 1], 0.0])
+        gt.append(np.concatenate([R.reshape(-1), [p2[k, 0], p2[k, 1], 1.5]]))
+    gt = np.array(gt)
+    kf_sensor = np.array([0] * n_lidar + [1] * n_rgbd, np.int32)
+    pos = gt[:, 9:]
+    d = np.linalg.norm(pos[:, None] - pos[None], axis=2)
+    n = len(gt)
+    pairs = np.array([(i, j) for i in range(n) for j in range(n) if i != j and d[i, j] < radius], np.int32)
+    init = _perturb(gt, np.random.default_rng(100 + seed), 0.05, 1.0)
+    params = dict(DEFAULT_PARAMS, channels=5, iterations=20, lm=True)
+    scene = dict(rects=rects, ground=1, ground_tex=_random_texture(rng), noise_i=0.01, noise_d=0.01, seed=seed)
+    return Problem("joint", [lid, cam], kf_sensor, gt, init, pairs, params, scene=scene)
+
+
 def plane_pair(model="pinhole", seed=7):
     """One large textured plane seen by three keyframes; keyframe 0 is the only source and keeps
     depth only in a central window (outside it the depth is 0, i.e. no measurement), keyframes 1 and 2 are targets whose whole view is the plane.  With small pose
@@ -528,7 +566,7 @@ def _mask_source(prob):
     return prob
 
 
-CONFIGS = {"rgbd_small": rgbd_small, "rgbd_room": rgbd_room, "lidar64": lidar64, "lidar128": lidar128, "plane_pair": plane_pair}
+CONFIGS = {"rgbd_small": rgbd_small, "rgbd_room": rgbd_room, "lidar64": lidar64, "lidar128": lidar128, "joint": joint, "plane_pair": plane_pair}
 
 
 def make(name, render_images=True, noise=True, kfs=None, **kw):

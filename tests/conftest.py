@@ -41,6 +41,25 @@ def lidar_mini_clean():
     return full.subset([0, 1, 2])
 
 
+JOINT_KFS = [0, 1, 2, 200, 201, 202, 203, 204]   # 3 LiDAR keyframes and 5 camera keyframes, 0-30 m
+
+
+@pytest.fixture(scope="session")
+def joint_mini():
+    """A 30 m stretch of the joint rig: 32x256 LiDAR and 60x80 camera keyframes with sensor
+    offsets; all four source/target model combinations occur among the 54 pairs."""
+    import synth
+    full = synth.make("joint", H_l=32, W_l=256, H_c=60, W_c=80, kfs=JOINT_KFS)
+    return full.subset(JOINT_KFS)
+
+
+@pytest.fixture(scope="session")
+def joint_mini_clean():
+    import synth
+    full = synth.make("joint", H_l=32, W_l=256, H_c=60, W_c=80, kfs=JOINT_KFS, noise=False)
+    return full.subset(JOINT_KFS)
+
+
 def rot_angle_deg(Ra, Rb):
     c = (np.trace(Ra.T @ Rb) - 1.0) / 2.0
     return float(np.degrees(np.arccos(np.clip(c, -1.0, 1.0))))

@@ -40,7 +40,7 @@ def test_struct_layout_matches_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", sizeof(pba_sensor), sizeof(pba_config), sizeof(pba_eval_out),
          sizeof(pba_iter_log), sizeof(pba_timings));
-  printf("%zu %zu %zu %zu\\n", offsetof(pba_config, stream), offsetof(pba_config, refine_band),
+  printf("%zu %zu %zu %zu\\n", offsetof(pba_config, stream), offsetof(pba_config, occlusion_tau_spherical),
          offsetof(pba_sensor, offset), offsetof(pba_eval_out, pair_out));
   printf("%d\\n", PBA_PAIR_OUT_LEN);
   return 0;
@@ -53,7 +53,7 @@ int main(void) {
     assert sizes == [ctypes.sizeof(pba.pba_sensor), ctypes.sizeof(pba.pba_config), ctypes.sizeof(pba.pba_eval_out),
                      ctypes.sizeof(pba.pba_iter_log), ctypes.sizeof(pba.pba_timings)]
     offs = [int(v) for v in lines[1].split()]
-    assert offs == [pba.pba_config.stream.offset, pba.pba_config.refine_band.offset, pba.pba_sensor.offset.offset,
+    assert offs == [pba.pba_config.stream.offset, pba.pba_config.occlusion_tau_spherical.offset, pba.pba_sensor.offset.offset,
                     pba.pba_eval_out.pair_out.offset]
     assert int(lines[2]) == pba.PBA_PAIR_OUT_LEN
 
@@ -74,7 +74,7 @@ def test_invalid_config_rejected_before_any_device_call():
     h = ctypes.c_void_p()
     assert lib.pba_create(ctypes.byref(cfg), ctypes.byref(h)) == pba.PBA_EINVAL
     cfg = pba.config_default()
-    cfg.refine_band = 0.7
+    cfg.occlusion_tau_spherical = -1.0
     assert lib.pba_create(ctypes.byref(cfg), ctypes.byref(h)) == pba.PBA_EINVAL
 
 

@@ -43,6 +43,8 @@ CASES = [
     ("lidar_mini", "F64", 5, 0),
     ("lidar_mini", "F32", 5, 1),
     ("lidar_mini", "F32", 2, 0),
+    ("joint_mini", "F32", 5, 0),     # two sensors with offsets, all four model combinations
+    ("joint_mini", "F64", 5, 0),
 ]
 
 
@@ -66,7 +68,7 @@ def test_pairs_match_oracle(fixture, prec, ch, gm, request, pba):
             fo = forced_oracle(prob, prob.init_poses, k, m["gpu"], params=params, grad_mode=gm)
             c = compare_pair_sums(ev["pairs"][k], fo, tol)
             assert c["ok"], (k, c)
-        _log("  band mismatches", tot_band, "refined", ev["n_refined"], "valid", ev["n_valid"])
+        _log("  band mismatches", tot_band, "valid", ev["n_valid"])
         # the assembled system against the oracle's own assembly (unforced)
         o = oracle.evaluate(prob, prob.init_poses, params, grad_mode=gm)
         assert ev["n_evaluated"] == o["n_eval"]
@@ -147,6 +149,21 @@ def test_levenberg_marquardt_matches_oracle(lidar_mini, pba):
         assert abs(lg["lam"] - lo["lam"]) <= 1e-12 * max(lo["lam"], 1e-300)
 
 
+def test_levenberg_marquardt_joint_rig_matches_oracle(joint_mini, pba):
+    """LiDAR + camera rig (sensor offsets, cross-sensor pairs, four model groups in one launch)."""
+    prob = joint_mini
+    X_or, log_or = oracle.optimize(prob, prob.init_poses, iters=5, lm=True, lam0=1e-4)
+    with pba.context_for_problem(prob, precision=pba.PBA_F64) as ctx:
+        logs = ctx.iterate(5, use_lm=True, lambda0=1e-4)
+        X = ctx.get_poses()
+    assert [l["accepted"] for l in logs] == [l["accepted"] for l in log_or]
+    dt, dr = _pose_err(X, X_or)
+    _log("joint LM pose diff vs oracle: %.3g m %.3g rad" % (dt, dr))
+    assert dt < 1e-6 and dr < 1e-6
+    for lg, lo in zip(logs, log_or):
+        assert abs(lg["F"] - lo["F"]) <= 1e-8 * lo["F"]
+
+
 # ---------------------------------------------------------------- edge cases
 
 def test_identity_pair_and_invalid_keyframe(rgbd_small, pba):
@@ -220,7 +237,7 @@ def test_full_size_sampled_pairs(name, sample, pba):
     _log("generated", name, prob.n, "keyframes", len(prob.pairs), "pairs")
     with pba.context_for_problem(prob) as ctx:
         ev = ctx.evaluate(want_pairs=True)
-        _log("  valid", ev["n_valid"], "of", ev["n_evaluated"], "refined", ev["n_refined"])
+        _log("  valid", ev["n_valid"], "of", ev["n_evaluated"])
         for k in sample:
             m = compare_pair_masks(ctx, prob, prob.init_poses, k)
             assert m["n_bad"] == 0, (k, m["n_mismatch"], m["bad_idx"])

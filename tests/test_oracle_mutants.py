@@ -3,7 +3,7 @@
 The pins in test_oracle_pins.py are only worth something if a plausible slip in
 the oracle trips them.  Each mutant below is one such slip (a sign, a factor,
 a transpose, the printed source-normal Jacobian, a dropped half in the central
-difference, the wrong depth cue, two slips in the loss adjoint); the checks are
+difference, the wrong depth cue, two slips in the loss adjoint, two in the sensor offsets); the checks are
 condensed versions of the pins: FD gradient, ground-truth residuals, the
 linear-ramp identity and FD of the image gradients.
 """
@@ -36,6 +36,9 @@ MUTANTS = {
                            "g -= k[ch] * (ac[0] * dp[0] + ac[1] * dp[1] + ac[2] * dp[2]);"),
     "adjoint_normal_transpose": ("k[2] * RR[j] + k[3] * RR[3+j] + k[4] * RR[6+j];",
                                  "k[2] * RR[3*j] + k[3] * RR[3*j+1] + k[4] * RR[3*j+2];"),
+    "source_offset_sign": ("for (int k = 0; k < 3; ++k) pu[k] += ss->to[k];",
+                           "for (int k = 0; k < 3; ++k) pu[k] -= ss->to[k];"),
+    "target_offset_untransposed": ("matvec3(RotT, ym, pbar);", "matvec3(st->Ro, ym, pbar);"),
 }
 
 
@@ -47,8 +50,8 @@ def _fd_ok(p, prm):
     return np.abs(g - fd).max() < 2e-5 * np.abs(fd).max()
 
 
-def _gt_ok(p, prm):
-    r = oracle.eval_pair(p, p.gt_poses, 1, 0, prm, pixels=True)
+def _gt_ok(p, prm, s=1, t=0):
+    r = oracle.eval_pair(p, p.gt_poses, s, t, prm, pixels=True)
     v = r["status"] == 0
     if v.sum() < 0.3 * r["n_eval"]:
         return False
@@ -99,15 +102,32 @@ def problems():
     rgc = synth.make("rgbd_small", noise=False)
     li = synth.make("lidar128", kfs=[0, 1], H=32, W=512).subset([0, 1])
     lic = synth.make("lidar128", kfs=[0, 1], H=32, W=512, noise=False).subset([0, 1])
-    return rg, rgc, li, lic
+    kfs = [0, 1, 200, 201]   # two LiDAR and two camera keyframes of the joint rig
+    jc = synth.make("joint", H_l=32, W_l=256, H_c=60, W_c=80, kfs=kfs, noise=False).subset(kfs)
+    return rg, rgc, li, lic, jc
+
+
+def _joint_gt_ok(jc):
+    # camera -> LiDAR and LiDAR -> camera through both sensor offsets (looser valid fraction: the
+    # camera sees part of the LiDAR panorama only)
+    for s, t in ((2, 1), (1, 2)):
+        r = oracle.eval_pair(jc, jc.gt_poses, s, t, jc.params, pixels=True)
+        v = r["status"] == 0
+        if v.sum() < 100:
+            return False
+        med = np.median(np.abs(r["res"][v]), 0)
+        if not (med[1] < 2e-3 and np.all(med[2:] < 1e-5)):
+            return False
+    return True
 
 
 def _checks(problems):
-    rg, rgc, li, lic = problems
+    rg, rgc, li, lic, jc = problems
     p5 = dict(rg.params, channels=5)
     l5 = dict(li.params, channels=5)
     return {"fd_rgbd": _fd_ok(rg, p5), "fd_lidar": _fd_ok(li, l5), "gt_rgbd": _gt_ok(rgc, p5),
-            "gt_lidar": _gt_ok(lic, l5), "ramp": _ramp_ok(rg, p5), "adjoint": _adj_ok(rg, p5)}
+            "gt_lidar": _gt_ok(lic, l5), "ramp": _ramp_ok(rg, p5), "adjoint": _adj_ok(rg, p5),
+            "gt_joint": _joint_gt_ok(jc)}
 
 
 def test_unmutated_oracle_passes_condensed_checks(problems):

@@ -146,6 +146,44 @@ def _huber_rho(chi2, delta):
     return np.where(e <= delta, chi2, 2 * delta * e - delta * delta)
 
 
+# pairs of the joint rig (keyframes 0-2 LiDAR, 3-7 camera): camera -> LiDAR, LiDAR -> camera,
+# camera -> camera, each through both sensor offsets
+JOINT_PAIRS = [(4, 1), (1, 4), (4, 3)]
+
+
+@pytest.mark.parametrize("s,t", JOINT_PAIRS)
+def test_joint_rig_ground_truth_residuals(joint_mini_clean, s, t):
+    """Noise-free rig at ground truth: points of one sensor, moved through its offset, both
+    platform poses and the other sensor's offset, land on the other sensor's depth/range and
+    normals; at the perturbed poses the depth/range residuals are >10x larger.  Pins the offset
+    composition of the warp (Supplementary: multi-sensor point transform)."""
+    p = joint_mini_clean
+    prm = _params(p, **CH5)
+    gt = oracle.eval_pair(p, p.gt_poses, s, t, prm, pixels=True)
+    bad = oracle.eval_pair(p, p.init_poses, s, t, prm, pixels=True)
+    assert gt["n_valid"] > 100
+    eg = np.abs(gt["res"][gt["status"] == 0])
+    eb = np.abs(bad["res"][bad["status"] == 0])
+    med_g, med_b = np.median(eg, 0), np.median(eb, 0)
+    assert med_g[1] < 2e-3, med_g
+    assert np.all(med_g[2:] < 1e-5), med_g
+    assert med_g[1] * 10 < med_b[1]
+
+
+@pytest.mark.parametrize("s,t", JOINT_PAIRS)
+def test_joint_rig_gradient_matches_finite_differences(joint_mini, s, t):
+    """2b = dF/dx by central differences for both platform poses of a pair whose sensors carry
+    offsets (pins the offset terms of the supplementary point Jacobians)."""
+    p = joint_mini
+    X = p.init_poses
+    r = oracle.eval_pair(p, X, s, t, p.params, grad_mode=1)
+    assert r["n_valid"] > 50
+    g_fd, flips = fd_grad_F(p, X, s, t, p.params)
+    assert flips == 0
+    g = 2 * r["b12"]
+    assert np.abs(g - g_fd).max() < 2e-5 * np.abs(g_fd).max()
+
+
 @pytest.mark.parametrize("fixture", ["rgbd_small", "lidar_mini"])
 def test_hessian_matches_per_pixel_finite_differences(fixture, request):
     """H = sum w J^T Omega J rebuilt from per-pixel central differences of the residual vector
