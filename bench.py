@@ -33,6 +33,22 @@ def bytes_per_px_pair(channels):
     return 2 * 4 * channels
 
 
+def measured_traffic(root):
+    """HBM bytes per evaluation launch from the committed PMC summary, or None when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(root, "profiles", "eval_kernel_lidar128_traffic.md")
+    src = os.path.join(root, "paper_2303_16878_amd", "csrc", "eval.hip")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if fields.get("eval_source_sha256", "").strip() != sha:
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run_path(pba, prob, precision, warmup, steps):
     import numpy as np
     import torch
@@ -172,6 +188,11 @@ def main():
         "final_ate_rmse": {"f32": ate_rmse(r32["poses"], prob.gt_poses),
                            "init": ate_rmse(prob.init_poses, prob.gt_poses)},
     }
+    tb = measured_traffic(os.path.dirname(os.path.abspath(__file__))) if args.workload == "lidar128" else None
+    if tb is not None:   # HBM bytes per launch (PMC, scaled by a 1 GiB copy) over the same launch time
+        out["roofline"]["traffic"] = tb / eval_s / 1e9
+        out["roofline"]["traffic_bytes_per_launch"] = tb
+        out["roofline"]["algorithmic_bytes_per_launch"] = bytes_per_px_pair(ch) * r32["n_evaluated"]
     if not args.no_fp64:
         log("FP64 path: warmup %d, timed %d iterations" % (args.warmup, args.steps))
         r64 = run_path(pba, prob, pba.PBA_F64, args.warmup, args.steps)
