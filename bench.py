@@ -49,11 +49,12 @@ def measured_traffic(root):
         return None
 
 
-def run_path(pba, prob, precision, warmup, steps):
+def run_path(pba, prob, precision, warmup, steps, autotune=True):
     import numpy as np
     import torch
     with pba.context_for_problem(prob, precision=precision) as ctx:
         torch.cuda.synchronize()
+        tune = ctx.autotune() if autotune else []
         ev_init = ctx.evaluate(want_system=True)   # the system at the initial poses, for FP32 vs FP64
         if warmup:
             ctx.iterate(warmup, use_lm=True, lambda0=1e-4)
@@ -70,7 +71,7 @@ def run_path(pba, prob, precision, warmup, steps):
             ev2 = ctx.evaluate()
         tm = ctx.timings(reset=True)
         poses = ctx.get_poses()
-    return dict(elapsed=elapsed, logs=logs, n_evaluated=ev["n_evaluated"], n_valid=ev["n_valid"], init=ev_init,
+    return dict(elapsed=elapsed, logs=logs, n_evaluated=ev["n_evaluated"], n_valid=ev["n_valid"], init=ev_init, tune=tune,
                 eval_ms=tm["eval_ms"] / n_eval_runs, n_items=tm["n_items"],
                 items_px=tm["items_px"], grid=tm["grid"], poses=poses, F=logs[-1]["F"])
 
@@ -107,6 +108,7 @@ def main():
     ap.add_argument("--workload", default="lidar128", choices=["lidar128", "lidar64", "rgbd_room", "rgbd_small"])
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default item size and grid")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate byte counters")
     args = ap.parse_args()
@@ -140,7 +142,7 @@ def main():
     sen = prob.sensors[0]
 
     log("FP32 path: warmup %d, timed %d iterations" % (args.warmup, args.steps))
-    r32 = run_path(pba, prob, pba.PBA_F32, args.warmup, args.steps)
+    r32 = run_path(pba, prob, pba.PBA_F32, args.warmup, args.steps, not args.no_autotune)
     ms_step = 1e3 * r32["elapsed"] / args.steps
     value = r32["n_evaluated"] * args.steps / r32["elapsed"]
     eval_s = r32["eval_ms"] / 1e3
@@ -171,6 +173,8 @@ def main():
             "work_items": r32["n_items"],
             "items_px": r32["items_px"],
             "grid": r32["grid"],
+            "autotune": "item size and grid chosen by pba_autotune over %d points" % len(r32["tune"])
+            if r32["tune"] else "off",
         },
         "roofline": {
             "bound": "hbm",
@@ -195,7 +199,7 @@ def main():
         out["roofline"]["algorithmic_bytes_per_launch"] = bytes_per_px_pair(ch) * r32["n_evaluated"]
     if not args.no_fp64:
         log("FP64 path: warmup %d, timed %d iterations" % (args.warmup, args.steps))
-        r64 = run_path(pba, prob, pba.PBA_F64, args.warmup, args.steps)
+        r64 = run_path(pba, prob, pba.PBA_F64, args.warmup, args.steps, not args.no_autotune)
         out["s_per_iter"]["f64"] = r64["elapsed"] / args.steps
         out["eval_px_pairs_per_s"]["f64"] = r64["n_evaluated"] / (r64["eval_ms"] / 1e3)
         out["fp64_value"] = r64["n_evaluated"] * args.steps / r64["elapsed"]

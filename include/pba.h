@@ -220,6 +220,20 @@ pba_status pba_optimize_pyramid(pba_ctx *ctx, const int32_t *iters, double rel_t
 pba_status pba_get_level_image(pba_ctx *ctx, int32_t level, int32_t kf, float *intensity, float *depth,
                                float *normals, int32_t *dims);
 
+typedef struct {
+    int32_t items_px;            /* source pixels per work item */
+    int32_t grid;                /* workgroups of the persistent evaluation launch */
+    double eval_ms;              /* evaluation kernel time(s) of one evaluation at this point */
+} pba_tune_point;
+
+/* Autotuner of the persistent evaluation launch (work-item size and grid): times one evaluation
+ * at the current poses and level for every item size in {4096, 8192, 16384, 32768} and grid in
+ * {2, 4, 8} x (compute units) workgroups, keeps the fastest for this context (until keyframes or
+ * pairs change the plan again) and reports the measured points (points nullable, up to
+ * max_points; *n_points nullable).  Results of evaluations do not depend on the choice except in
+ * the summation order of the per-pair sums. */
+pba_status pba_autotune(pba_ctx *ctx, pba_tune_point *points, int32_t max_points, int32_t *n_points);
+
 /* Per-pixel view of one pair for inspection (host outputs, each nullable, source-image sized):
  * status (0 valid, 1 no depth, 2 not projectable, 3 outside, 4 invalid or occluded tap),
  * uv (2 floats: projected column, row), cell (2 ints: integer cell x0, y0) and residuals

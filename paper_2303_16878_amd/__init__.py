@@ -28,7 +28,7 @@ ABI_FUNCTIONS = (
     "pba_config_default", "pba_create", "pba_destroy", "pba_add_sensor", "pba_load_keyframes",
     "pba_set_poses", "pba_get_poses", "pba_set_pairs", "pba_evaluate", "pba_solve_step",
     "pba_apply_step", "pba_iterate", "pba_loss_forward", "pba_loss_backward", "pba_build_pyramid",
-    "pba_set_level", "pba_optimize_pyramid", "pba_get_level_image", "pba_debug_pair",
+    "pba_set_level", "pba_optimize_pyramid", "pba_get_level_image", "pba_autotune", "pba_debug_pair",
     "pba_get_timings", "pba_status_string", "pba_last_error",
 )
 
@@ -58,6 +58,10 @@ class pba_eval_out(ctypes.Structure):
 class pba_iter_log(ctypes.Structure):
     _fields_ = [("F", ctypes.c_double), ("lambda_", ctypes.c_double), ("step_norm", ctypes.c_double),
                 ("n_valid", ctypes.c_int64), ("accepted", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class pba_tune_point(ctypes.Structure):
+    _fields_ = [("items_px", ctypes.c_int32), ("grid", ctypes.c_int32), ("eval_ms", ctypes.c_double)]
 
 
 class pba_timings(ctypes.Structure):
@@ -98,6 +102,7 @@ def load_library(path: str = LIB_PATH):
         "pba_set_level": (i32, [vp, i32]),
         "pba_optimize_pyramid": (i32, [vp, vp, f64, i32, f64, vp, vp, vp]),
         "pba_get_level_image": (i32, [vp, i32, i32, vp, vp, vp, vp]),
+        "pba_autotune": (i32, [vp, vp, i32, vp]),
         "pba_debug_pair": (i32, [vp, i32, vp, vp, vp, vp]),
         "pba_get_timings": (i32, [vp, ctypes.POINTER(pba_timings), i32]),
         "pba_status_string": (ctypes.c_char_p, [i32]),
@@ -287,6 +292,14 @@ class Context:
                                          ctypes.cast(logs, ctypes.c_void_p)))
         return [dict(F=l.F, lam=l.lambda_, step=l.step_norm, n_valid=l.n_valid, accepted=bool(l.accepted))
                 for l in logs[:n_iters]]
+
+    def autotune(self):
+        """Time the evaluation launch over item sizes and grids, keep the fastest; returns the
+        measured points [(items_px, grid, eval_ms)]."""
+        pts = (pba_tune_point * 64)()
+        n = ctypes.c_int32()
+        self._check(self.lib.pba_autotune(self.h, ctypes.cast(pts, ctypes.c_void_p), 64, ctypes.byref(n)))
+        return [(pts[i].items_px, pts[i].grid, pts[i].eval_ms) for i in range(n.value)]
 
     def build_pyramid(self, n_levels):
         """Levels 1 .. n_levels - 1 as 2x2 reductions of the loaded images (level 0)."""

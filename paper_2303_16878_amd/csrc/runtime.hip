@@ -964,6 +964,45 @@ pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float
     return PBA_OK;
 }
 
+pba_status pba_autotune(pba_ctx *c, pba_tune_point *points, int32_t max_points, int32_t *n_points)
+{
+    if (!c) return PBA_EINVAL;
+    if (max_points < 0) return fail(c, PBA_EINVAL, "negative max_points");
+    pba_status s;
+    if ((s = check_ready(c))) return s;
+    HIP_OK(hipSetDevice(c->cfg.device));
+    const int sizes[4] = {4096, 8192, 16384, 32768};
+    const int mult[3] = {2, 4, 8};
+    int best_px = c->items_px, best_grid = c->grid, n = 0;
+    double best = 1e300;
+    for (int si = 0; si < 4; ++si) {
+        c->items_px = sizes[si];
+        if ((s = build_plan(c, c->src_h, c->tgt_h))) return s;
+        for (int gi = 0; gi < 3; ++gi) {
+            c->grid = c->num_cu * mult[gi];
+            double ms = 0.0;
+            for (int rep = 0; rep < 2; ++rep) {   // the first run warms caches and code
+                const double before = c->eval_ms;
+                if ((s = run_eval(c, P_<double>(c->poses), P_<double>(c->H_cand), P_<double>(c->b_cand),
+                                  P_<double>(c->totals) + 4, true, c->stream)))
+                    return s;
+                if ((s = accumulate_eval_time(c))) return s;
+                ms = c->eval_ms - before;
+            }
+            if (points && n < max_points) points[n] = pba_tune_point{sizes[si], c->grid, ms};
+            ++n;
+            if (ms < best) { best = ms; best_px = sizes[si]; best_grid = c->grid; }
+        }
+    }
+    c->items_px = best_px;
+    c->grid = best_grid;
+    if ((s = build_plan(c, c->src_h, c->tgt_h))) return s;
+    drop_graph(c);
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (n_points) *n_points = std::min(n, max_points);
+    return PBA_OK;
+}
+
 pba_status pba_build_pyramid(pba_ctx *c, int32_t n_levels)
 {
     if (!c) return PBA_EINVAL;

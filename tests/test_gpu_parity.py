@@ -281,3 +281,20 @@ def test_graph_replays_match_eager_iterations(lidar_mini, pba):
             assert lg == le, it
         eg, ee = cg.evaluate(want_system=True), ce.evaluate(want_system=True)
         assert np.array_equal(eg["H"], ee["H"])
+
+
+def test_autotune_keeps_results(lidar_mini, pba):
+    """The autotuner only changes the work decomposition: the evaluation after it equals the one
+    before up to the summation order of the item partials."""
+    with pba.context_for_problem(lidar_mini) as ctx:
+        a = ctx.evaluate(want_system=True)
+        pts = ctx.autotune()
+        assert len(pts) == 12 and all(ms > 0 for _, _, ms in pts)
+        t = ctx.timings()
+        assert (t["items_px"], t["grid"]) in [(p, g) for p, g, _ in pts]
+        b = ctx.evaluate(want_system=True)
+        assert a["n_valid"] == b["n_valid"] and a["n_evaluated"] == b["n_evaluated"]
+        assert abs(a["F"] - b["F"]) <= 1e-12 * abs(a["F"])
+        assert np.abs(a["H"] - b["H"]).max() <= 1e-12 * np.abs(a["H"]).max()
+        logs = ctx.iterate(2, use_lm=True)
+        assert all(np.isfinite(l["F"]) for l in logs)
