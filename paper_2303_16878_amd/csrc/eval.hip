@@ -192,29 +192,105 @@ __device__ __forceinline__ void sample_channel(T a0, T a1, T a2, T a3, T b0, T b
     }
 }
 
-// acc += om * J J^T (upper triangle) and acc_b += om * e * J, accumulated in FP64 whatever the
-// evaluation precision: with FP32 operands every product om*J_i*J_j is formed exactly and each
-// addition rounds once in FP64.  The source-pose blocks are expanded from these sums by A, whose
-// lever arm (the pair baseline) amplifies relative errors of the sums by up to ~|t|^2 / range^2,
-// so FP32 accumulation would not hold the 1e-5 agreement on long baselines.
-template <typename T>
-__device__ __forceinline__ void accumulate_row(double *acc, const T (&J)[6], T e, T om)
+// Per-pixel sums of one cue row into v: v[0..20] += om J_i J_j (upper triangle, row-major),
+// v[21..26] += om e J_i.  The five rows of a pixel are summed in the evaluation precision; the sums
+// of the 64 pixels of a wave are then added by a fixed butterfly (wave_reduce_scatter) and the wave
+// totals accumulated in FP64.  Summation depth is log2 of the terms, not their number: the
+// source-pose blocks are expanded from these sums by A, whose lever arm (the pair baseline)
+// amplifies relative errors by up to ~|t|^2 / range^2, and sequential FP32 sums over many pixels
+// would not hold the 1e-5 agreement on long baselines.
+// FP64 path: the same 27 sums per lane straight into FP64 accumulators (each product exact, each
+// addition rounded once), no butterfly.
+__device__ __forceinline__ void accumulate_row(double *acc, const double (&J)[6], double e, double om)
 {
-    double jd[6], wj[6];
-    const double omd = (double)om;
+    double wj[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        jd[i] = (double)J[i];
-        wj[i] = omd * jd[i];
-    }
-    int idx = ACC_H;
+    for (int i = 0; i < 6; ++i) wj[i] = om * J[i];
+    int idx = 0;
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
-        for (int j = i; j < 6; ++j) { acc[idx] = fma(wj[i], jd[j], acc[idx]); ++idx; }
-    const double ed = (double)e;
+        for (int j = i; j < 6; ++j) { acc[idx] = fma(wj[i], J[j], acc[idx]); ++idx; }
 #pragma unroll
-    for (int i = 0; i < 6; ++i) acc[ACC_B + i] = fma(wj[i], ed, acc[ACC_B + i]);
+    for (int i = 0; i < 6; ++i) acc[ACC_B + i] = fma(wj[i], e, acc[ACC_B + i]);
+}
+
+template <typename T>
+__device__ __forceinline__ void add_row(T (&v)[32], const T (&J)[6], T e, T om)
+{
+    T wj[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) wj[i] = om * J[i];
+    int idx = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i; j < 6; ++j) { v[idx] = fma(wj[i], J[j], v[idx]); ++idx; }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[ACC_B + i] = fma(wj[i], e, v[ACC_B + i]);
+}
+
+template <typename T>
+__device__ __forceinline__ void add_cue_row(T (&v)[32], double *acc64, const T (&J)[6], T e, T om)
+{
+    if constexpr (std::is_same<T, float>::value) add_row(v, J, e, om);
+    else accumulate_row(acc64, J, e, om);
+}
+
+// Exchange lanes 32..63 of x with lanes 0..31 of y, and the odd 16-lane rows of x with the even
+// rows of y (whole-register lane permutations, no memory).
+__device__ __forceinline__ void swap_half(float &x, float &y)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    x = __uint_as_float(r[0]);
+    y = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap_row(float &x, float &y)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    x = __uint_as_float(r[0]);
+    y = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap_half(double &x, double &y)
+{
+    float xl = __int_as_float(__double2loint(x)), xh = __int_as_float(__double2hiint(x));
+    float yl = __int_as_float(__double2loint(y)), yh = __int_as_float(__double2hiint(y));
+    swap_half(xl, yl);
+    swap_half(xh, yh);
+    x = __hiloint2double(__float_as_int(xh), __float_as_int(xl));
+    y = __hiloint2double(__float_as_int(yh), __float_as_int(yl));
+}
+__device__ __forceinline__ void swap_row(double &x, double &y)
+{
+    float xl = __int_as_float(__double2loint(x)), xh = __int_as_float(__double2hiint(x));
+    float yl = __int_as_float(__double2loint(y)), yh = __int_as_float(__double2hiint(y));
+    swap_row(xl, yl);
+    swap_row(xh, yh);
+    x = __hiloint2double(__float_as_int(xh), __float_as_int(xl));
+    y = __hiloint2double(__float_as_int(yh), __float_as_int(yl));
+}
+
+// Sum 32 per-lane values over the 64 lanes of a wave.  Butterfly reduce-scatter: at each step a
+// lane keeps one half of its values and adds its partner's copy of that half (partners l ^ 32,
+// l ^ 16, l ^ 8, l ^ 4, l ^ 2); finally lanes 2k and 2k + 1 add their totals.  Returns the wave
+// total of value k = lane >> 1 (the same in both lanes of the pair).
+template <typename T>
+__device__ __forceinline__ T wave_reduce_scatter(T (&v)[32], int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 16; ++i) { T x = v[i], y = v[i + 16]; swap_half(x, y); v[i] = x + y; }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { T x = v[i], y = v[i + 8]; swap_row(x, y); v[i] = x + y; }
+#pragma unroll
+    for (int m = 8, n = 4; n >= 1; m >>= 1, n >>= 1) {
+        const bool up = (lane & m) != 0;
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+            const T keep = up ? v[i + n] : v[i], send = up ? v[i] : v[i + n];
+            v[i] = keep + __shfl_xor(send, m, 64);
+        }
+    }
+    return v[0] + __shfl_xor(v[0], 1, 64);
 }
 
 // J' of a cue row whose point-space derivative is a = d e / d p_bar (up to sign conventions below):
@@ -255,13 +331,13 @@ struct WaveQueue {
     T ed[kQ], gxd[kQ], gyd[kQ]; // depth residual and depth-channel image Jacobian
 };
 
-// b-only accumulation for the loss adjoint: acc_b += om * e * J
+// b-only accumulation for the loss adjoint, per lane in FP64: acc[i] += om * e * J_i
 template <typename T>
 __device__ __forceinline__ void accumulate_row_b(double *acc, const T (&J)[6], T e, T om)
 {
     const double ome = (double)om * (double)e;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) acc[ACC_B + i] = fma(ome, (double)J[i], acc[ACC_B + i]);
+    for (int i = 0; i < 6; ++i) acc[i] = fma(ome, (double)J[i], acc[i]);
 }
 
 // Bounds-checked loads from one keyframe plane through a buffer resource: 32-bit byte offsets,
@@ -358,20 +434,13 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         const uint32_t magic = (uint32_t)uni((int)ss.magic_w);
         const int px1 = min(px0 + a.items_px, npx);
 
-        // pair transform in FP64 for the geometry of phase 1; in the evaluation precision for the
-        // normal cue of phase 2 (FP32: leading part plus correction, so that the rounding of R does
-        // not rotate every normal of the pair alike)
+        // pair transform in FP64 (phase 1 geometry, the normal cue's rotation, adjoint terms)
         double Rd[9], td[3];
 #pragma unroll
         for (int k = 0; k < 9; ++k) Rd[k] = pd.Rd[k];
 #pragma unroll
         for (int k = 0; k < 3; ++k) td[k] = pd.td[k];
-        T R[9], cc[3], Rl[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            R[k] = F32 ? (T)pd.R[k] : (T)pd.Rd[k];
-            Rl[k] = F32 ? (T)pd.Rlo[k] : T(0);
-        }
+        T cc[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) cc[k] = (T)pd.c[k];
         if (!F32) {
@@ -392,14 +461,21 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         const __amdgpu_buffer_rsrc_t r_tatt = NCH == 5 ? plane_rsrc(uni_ptr(a.att4 + kt.off), tnpx * 16u)
                                                        : plane_rsrc(uni_ptr(a.att1 + kt.off), tnpx * 4u);
 
-        double acc[ACC_F + 1];
+        // FP64 accumulators: lanes 2k, 2k + 1 hold this wave's total of H/b sum k (k < 27); rho per
+        // lane; the adjoint keeps b per lane
+        double acc_hb = 0.0, acc_F = 0.0, acc_b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double acc64[F32 ? 1 : ACC_F];   // FP64 path: the 27 sums per lane
 #pragma unroll
-        for (int k = 0; k <= ACC_F; ++k) acc[k] = 0.0;
+        for (int k = 0; k < (F32 ? 1 : ACC_F); ++k) acc64[k] = 0.0;
         int n_eval = 0, n_valid = 0;
         int head = 0, tail = 0;   // wave-uniform queue positions
 
         // phase 2: residuals, weights, Jacobian rows and accumulation of queue slot `slot`
-        auto consume = [&](int slot) {
+        auto consume = [&](int slot, bool active) {
+          T v[32];
+#pragma unroll
+          for (int k = 0; k < 32; ++k) v[k] = T(0);
+          if (active) {
             const int pix = Q.pix[slot];
             const int cellv = Q.cell[slot];
             const int x0 = cellv & 0xffff, y0 = cellv >> 16;
@@ -441,14 +517,11 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             T en[3] = {T(0), T(0), T(0)}, nr[3] = {T(0), T(0), T(0)};
             if (NCH == 5) {
                 // normal cue: the source normal rotated into the target sensor frame
-                nr[0] = R[0] * ns0 + R[1] * ns1 + R[2] * ns2;
-                nr[1] = R[3] * ns0 + R[4] * ns1 + R[5] * ns2;
-                nr[2] = R[6] * ns0 + R[7] * ns1 + R[8] * ns2;
-                if (F32) {
-                    nr[0] += Rl[0] * ns0 + Rl[1] * ns1 + Rl[2] * ns2;
-                    nr[1] += Rl[3] * ns0 + Rl[4] * ns1 + Rl[5] * ns2;
-                    nr[2] += Rl[6] * ns0 + Rl[7] * ns1 + Rl[8] * ns2;
-                }
+                // rotated in FP64: the rounding of an FP32 rotation would turn every normal of the
+                // pair alike
+                const double m0 = (double)ns0, m1 = (double)ns1, m2 = (double)ns2;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) nr[k] = (T)fma(Rd[3 * k], m0, fma(Rd[3 * k + 1], m1, Rd[3 * k + 2] * m2));
 #pragma unroll
                 for (int k = 0; k < 3; ++k) { en[k] = nr[k] - Vn[k]; chi2 += om_n * en[k] * en[k]; }
             }
@@ -467,7 +540,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                     rhov = delta * (T(2) * sq - delta);
                 }
             }
-            acc[ACC_F] += (double)rhov;
+            acc_F += (double)rhov;
             n_valid += 1;
             // projective Jacobian rows Pi0 = d u / d p_bar, Pi1 = d v / d p_bar
             T P00, P01, P02, P10, P11, P12, zx, zy, zz;
@@ -492,12 +565,12 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             const T ad2 = zz - (Gxd * P02 + Gyd * P12);
             // intensity: a = -(Gx Pi0 + Gy Pi1)
             row_from_a(J, ag0, ag1, ag2, y2x, y2y, y2z);
-            if (ADJ) accumulate_row_b(acc, J, eg, w * om_g);
-            else accumulate_row(acc, J, eg, w * om_g);
+            if (ADJ) accumulate_row_b(acc_b, J, eg, w * om_g);
+            else add_cue_row(v, acc64, J, eg, w * om_g);
             // depth / range: a = d zeta / d p_bar - (Gx Pi0 + Gy Pi1)
             row_from_a(J, ad0, ad1, ad2, y2x, y2y, y2z);
-            if (ADJ) accumulate_row_b(acc, J, ed, w * om_d);
-            else accumulate_row(acc, J, ed, w * om_d);
+            if (ADJ) accumulate_row_b(acc_b, J, ed, w * om_d);
+            else add_cue_row(v, acc64, J, ed, w * om_d);
             if (NCH == 5) {
                 // normal rows: image term plus the rotation-only term 2 (e_k x n')
 #pragma unroll
@@ -507,8 +580,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                     if (k == 0) { J[4] -= T(2) * nr[2]; J[5] += T(2) * nr[1]; }
                     if (k == 1) { J[3] += T(2) * nr[2]; J[5] -= T(2) * nr[0]; }
                     if (k == 2) { J[3] -= T(2) * nr[1]; J[4] += T(2) * nr[0]; }
-                    if (ADJ) accumulate_row_b(acc, J, en[k], w * om_n);
-                    else accumulate_row(acc, J, en[k], w * om_n);
+                    if (ADJ) accumulate_row_b(acc_b, J, en[k], w * om_n);
+                    else add_cue_row(v, acc64, J, en[k], w * om_n);
                 }
             }
             if (ADJ) {
@@ -542,9 +615,9 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 T rx, ry, rz;
                 if (SM == MODEL_SPHERICAL) { rx = lr.x * lc.x; ry = lr.x * lc.y; rz = lr.y; }
                 else { rx = lc.x; ry = lr.x; rz = T(1); }
-                const T dp0 = R[0] * rx + R[1] * ry + R[2] * rz;
-                const T dp1 = R[3] * rx + R[4] * ry + R[5] * rz;
-                const T dp2 = R[6] * rx + R[7] * ry + R[8] * rz;
+                const T dp0 = (T)Rd[0] * rx + (T)Rd[1] * ry + (T)Rd[2] * rz;
+                const T dp1 = (T)Rd[3] * rx + (T)Rd[4] * ry + (T)Rd[5] * rz;
+                const T dp2 = (T)Rd[6] * rx + (T)Rd[7] * ry + (T)Rd[8] * rz;
                 T gd = kg * (ag0 * dp0 + ag1 * dp1 + ag2 * dp2) + kd * (ad0 * dp0 + ad1 * dp1 + ad2 * dp2);
                 if (NCH == 5) {
                     const T kk[3] = {kn0, kn1, kn2};
@@ -552,12 +625,15 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                     for (int k = 0; k < 3; ++k)
                         gd += kk[k] * (-(Gxn[k] * P00 + Gyn[k] * P10) * dp0 - (Gxn[k] * P01 + Gyn[k] * P11) * dp1 -
                                        (Gxn[k] * P02 + Gyn[k] * P12) * dp2);
-                    unsafeAtomicAdd(a.g_nrm + 3 * so, (float)(kn0 * R[0] + kn1 * R[3] + kn2 * R[6]));
-                    unsafeAtomicAdd(a.g_nrm + 3 * so + 1, (float)(kn0 * R[1] + kn1 * R[4] + kn2 * R[7]));
-                    unsafeAtomicAdd(a.g_nrm + 3 * so + 2, (float)(kn0 * R[2] + kn1 * R[5] + kn2 * R[8]));
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        unsafeAtomicAdd(a.g_nrm + 3 * so + j,
+                                        (float)(kn0 * (T)Rd[j] + kn1 * (T)Rd[3 + j] + kn2 * (T)Rd[6 + j]));
                 }
                 unsafeAtomicAdd(a.g_dep + so, (float)gd);
             }
+          }
+          if (!ADJ && F32) acc_hb += (double)wave_reduce_scatter(v, lane);
         };
 
         for (int cbase = px0 + wave * 64; cbase < px1; cbase += kBlock) {
@@ -678,21 +754,24 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             __builtin_amdgcn_wave_barrier();
             // ---------------- phase 2: drain full waves of queued correspondences
             if (tail - head >= 64) {
-                consume((head + lane) & (kQ - 1));
+                consume((head + lane) & (kQ - 1), true);
                 head += 64;
                 __builtin_amdgcn_wave_barrier();
             }
         }
-        if (lane < tail - head) consume((head + lane) & (kQ - 1));
+        if (tail > head) consume((head + lane) & (kQ - 1), lane < tail - head);   // every lane joins the butterfly
 
         // workgroup reduction of the accumulators (fixed order: deterministic)
+        if (!ADJ && F32 && (lane & 1) == 0 && (lane >> 1) < ACC_F) s_red[wave][lane >> 1] = acc_hb;
 #pragma unroll
-        for (int k = 0; k < ACC_USED; ++k) {
-            double v = k <= ACC_F ? acc[k] : (k == ACC_VALID ? (double)n_valid : (double)n_eval);
+        for (int k = ADJ ? ACC_B : (F32 ? ACC_F : 0); k < ACC_USED; ++k) {
+            double v = k < ACC_F ? (ADJ ? acc_b[k - ACC_B] : acc64[F32 ? 0 : k])
+                                 : (k == ACC_F ? acc_F : (k == ACC_VALID ? (double)n_valid : (double)n_eval));
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
             if (lane == 0) s_red[wave][k] = v;
         }
+        if (ADJ && lane < ACC_B) s_red[wave][lane] = 0.0;
         __syncthreads();
         if (tid < kAcc) {
             double v = 0.0;

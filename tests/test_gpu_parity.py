@@ -285,7 +285,8 @@ def test_graph_replays_match_eager_iterations(lidar_mini, pba):
 
 def test_autotune_keeps_results(lidar_mini, pba):
     """The autotuner only changes the work decomposition: the evaluation after it equals the one
-    before up to the summation order of the item partials."""
+    before up to summation order (which pixels share a wave's FP32 tree sum, and the order of the
+    FP64 item partials): 1e-6 of max|H|, far inside the 1e-5 parity tolerance."""
     with pba.context_for_problem(lidar_mini) as ctx:
         a = ctx.evaluate(want_system=True)
         pts = ctx.autotune()
@@ -295,6 +296,6 @@ def test_autotune_keeps_results(lidar_mini, pba):
         b = ctx.evaluate(want_system=True)
         assert a["n_valid"] == b["n_valid"] and a["n_evaluated"] == b["n_evaluated"]
         assert abs(a["F"] - b["F"]) <= 1e-12 * abs(a["F"])
-        assert np.abs(a["H"] - b["H"]).max() <= 1e-12 * np.abs(a["H"]).max()
+        assert np.abs(a["H"] - b["H"]).max() <= 1e-6 * np.abs(a["H"]).max()
         logs = ctx.iterate(2, use_lm=True)
         assert all(np.isfinite(l["F"]) for l in logs)
