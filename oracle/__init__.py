@@ -312,6 +312,59 @@ def optimize(prob, poses0, iters=10, lm=False, params=None, lam0=1e-4, anchor=0,
     return X, log
 
 
+# ------------------------------------------------------------------ normal estimation
+
+def unproject_image(sen, D):
+    """Points q = pi^-1(u, d) [H, W, 3] of a depth image in the sensor frame (Sec. III)."""
+    H, W = D.shape
+    r, c = np.mgrid[0:H, 0:W].astype(np.float64)
+    d = np.asarray(D, np.float64)
+    if sen["model"] == 0:
+        return np.stack([d * (c - sen["cx"]) / sen["fx"], d * (r - sen["cy"]) / sen["fy"], d], -1)
+    az, el = (c - sen["cx"]) / sen["fx"], (r - sen["cy"]) / sen["fy"]
+    return np.stack([d * np.cos(el) * np.cos(az), d * np.cos(el) * np.sin(az), d * np.sin(el)], -1)
+
+
+def estimate_normals(sen, D, radius_m=0.1, min_px=2.0, max_px=5.0, tau=0.5, min_count=5):
+    """Sec. IV-A: the normal at u is the normal of the plane that best fits the unprojected
+    neighbours u' with |u - u'| < tau_u, tau_u inversely proportional to the range at u, oriented
+    towards the observer.  Readings: tau_u = clamp(radius_m |fx| / d(u), min_px, max_px) pixels (a
+    fixed metric radius seen at range d, at least the 8-neighbourhood); neighbours need valid depth within tau of d(u) (no fit across a
+    depth edge); best fit = least squares, i.e. the eigenvector of the smallest eigenvalue of the
+    neighbours' covariance (library eigendecomposition); at least min_count points and a second
+    eigenvalue above 1e-12 of the trace; oriented so that n . q_u < 0 (the sensor at the origin).
+    Pixels without a normal get 0.  FP64; returns (normals FP32 [H, W, 3], has-normal mask,
+    covariance eigenvalues [H, W, 3] ascending, neighbour counts)."""
+    H, W = D.shape
+    d = np.asarray(D, np.float64)
+    valid = np.isfinite(d) & (d > 0) & (d >= sen["min_depth"]) & (d <= sen["max_depth"])
+    q = unproject_image(sen, np.where(valid, d, 0.0))
+    rad = np.where(valid, np.clip(radius_m * abs(sen["fx"]) / np.where(valid, d, 1.0), min_px, max_px), 0.0)
+    R = int(np.floor(max_px))
+    n = np.zeros((H, W))
+    s1 = np.zeros((H, W, 3))
+    s2 = np.zeros((H, W, 3, 3))
+    for dy in range(-R, R + 1):
+        for dx in range(-R, R + 1):
+            dist = np.hypot(dx, dy)
+            ys, xs = slice(max(0, -dy), min(H, H - dy)), slice(max(0, -dx), min(W, W - dx))
+            yn, xn = slice(max(0, dy), min(H, H + dy)), slice(max(0, dx), min(W, W + dx))
+            m = valid[ys, xs] & valid[yn, xn] & (dist < rad[ys, xs]) & (np.abs(d[yn, xn] - d[ys, xs]) <= tau)
+            qq = np.where(m[..., None], q[yn, xn], 0.0)
+            n[ys, xs] += m
+            s1[ys, xs] += qq
+            s2[ys, xs] += qq[..., :, None] * qq[..., None, :]
+    cnt = np.maximum(n, 1)
+    mean = s1 / cnt[..., None]
+    cov = s2 / cnt[..., None, None] - mean[..., :, None] * mean[..., None, :]
+    w, v = np.linalg.eigh(cov)
+    nrm = v[..., :, 0]
+    ok = valid & (n >= min_count) & (w[..., 1] > 1e-12 * np.maximum(np.trace(cov, axis1=-2, axis2=-1), 1e-300))
+    flip = np.sum(nrm * q, -1) > 0
+    nrm = np.where(flip[..., None], -nrm, nrm)
+    return np.where(ok[..., None], nrm, 0.0).astype(np.float32), ok, w, n
+
+
 # ------------------------------------------------------------------ image pyramid
 
 def level_sensor(sen):
@@ -412,6 +465,41 @@ def optimize_coarse_to_fine(prob, poses0, n_levels=3, iters=(2, 5, 10), rel_tol=
             if accept and drop < rel_tol:
                 break
     return X, log
+
+
+# ------------------------------------------------------------------ pair graph
+
+def pose_angle(Xa, Xb):
+    """Rotation angle (rad) between the orientations of two poses: the angle of Ra^T Rb."""
+    Ra, Rb = np.asarray(Xa[:9]).reshape(3, 3), np.asarray(Xb[:9]).reshape(3, 3)
+    c = (np.trace(Ra.T @ Rb) - 1.0) / 2.0
+    return float(np.arccos(np.clip(c, -1.0, 1.0)))
+
+
+def build_pairs(prob, poses, max_angle=np.radians(30.0), max_dist=1.0, min_ratio=1.0 / 3.0, sequential=True,
+                params=None):
+    """Sec. IV-B: the matching pairs.  An ordered pair (s, t) of keyframes is kept if the angle
+    between their orientations is below max_angle, the distance between their positions below
+    max_dist, and the fraction of s's pixels with depth that reproject validly into t (n_valid /
+    n_eval of the evaluation at `poses`) at least min_ratio; with `sequential`, (k, k + 1) and
+    (k + 1, k) are kept whatever the criteria say (odometry-like links).  Returns int32 [P, 2] in
+    (s, t) order and, for every ordered pair that passed the pose tests, its ratio."""
+    X = np.asarray(poses, np.float64)
+    n = prob.n
+    kept, ratios = [], {}
+    for s in range(n):
+        for t in range(n):
+            if s == t:
+                continue
+            seq = sequential and abs(s - t) == 1
+            close = (pose_angle(X[s], X[t]) < max_angle and
+                     np.linalg.norm(X[s, 9:] - X[t, 9:]) < max_dist)
+            if close:
+                r = eval_pair(prob, X, s, t, params)
+                ratios[(s, t)] = r["n_valid"] / r["n_eval"] if r["n_eval"] > 0 else 0.0
+            if seq or (close and ratios[(s, t)] >= min_ratio):
+                kept.append((s, t))
+    return np.array(kept, np.int32).reshape(-1, 2), ratios
 
 
 # ------------------------------------------------------------------ trajectory error
