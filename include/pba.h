@@ -220,6 +220,27 @@ pba_status pba_optimize_pyramid(pba_ctx *ctx, const int32_t *iters, double rel_t
 pba_status pba_get_level_image(pba_ctx *ctx, int32_t level, int32_t kf, float *intensity, float *depth,
                                float *normals, int32_t *dims);
 
+/* Normals from depth (Sec. IV-A), replacing the loaded normal images of every keyframe: the
+ * normal at u is the normal of the least-squares plane through the unprojected neighbours u' with
+ * |u - u'| < tau_u pixels, tau_u = clamp(radius_m |fx| / d(u), min_px, max_px) (a fixed metric
+ * radius seen at range d, so inversely proportional to it); neighbours need valid depth within the
+ * sensor model's occlusion tau of d(u); at least min_count of them and a non-degenerate spread;
+ * oriented towards the sensor; pixels without a normal get 0.  Needs 5 channels.  Drops any
+ * pyramid (rebuild it afterwards) and the system held for the current poses. */
+pba_status pba_estimate_normals(pba_ctx *ctx, double radius_m, double min_px, double max_px, int32_t min_count);
+
+/* Matching pairs from the current poses (Sec. IV-B): an ordered pair (s, t) is kept if the angle
+ * between the orientations of X_s and X_t (the rotation angle of R_s^T R_t) is below max_angle
+ * (radians), the distance between their positions below max_dist, and the fraction of s's
+ * pixels with valid depth that reproject validly into t (valid correspondences / evaluated
+ * pixels of an evaluation at the current poses and level) at least min_ratio; with sequential
+ * != 0, (k, k+1) and (k+1, k) are kept regardless (odometry-like links).  The kept pairs replace
+ * the context's pairs (in (s, t) lexicographic order) and are copied to src_out / tgt_out
+ * (nullable, up to cap entries); *n_out (nullable) receives their number.  PBA_ESTATE without
+ * keyframes or poses; PBA_EINVAL for a negative threshold. */
+pba_status pba_build_pairs(pba_ctx *ctx, double max_angle, double max_dist, double min_ratio, int32_t sequential,
+                           int32_t cap, int32_t *src_out, int32_t *tgt_out, int32_t *n_out);
+
 typedef struct {
     int32_t items_px;            /* source pixels per work item */
     int32_t grid;                /* workgroups of the persistent evaluation launch */
@@ -249,6 +270,10 @@ typedef struct {
     int64_t n_items;             /* work items of the evaluation queue */
     int32_t items_px;            /* source pixels per work item */
     int32_t grid;                /* workgroups of the persistent evaluation launch */
+    double iter_eval_ms;         /* summed duration of the evaluations inside pba_iterate (device
+                                    wall-clock stamps before and after the evaluation launches of
+                                    each iteration, also under graph replay) */
+    int64_t iter_evals;
 } pba_timings;
 
 /* Kernel timing counters; reset = 1 clears them after reading. */

@@ -28,7 +28,7 @@ ABI_FUNCTIONS = (
     "pba_config_default", "pba_create", "pba_destroy", "pba_add_sensor", "pba_load_keyframes",
     "pba_set_poses", "pba_get_poses", "pba_set_pairs", "pba_evaluate", "pba_solve_step",
     "pba_apply_step", "pba_iterate", "pba_loss_forward", "pba_loss_backward", "pba_build_pyramid",
-    "pba_set_level", "pba_optimize_pyramid", "pba_get_level_image", "pba_autotune", "pba_debug_pair",
+    "pba_set_level", "pba_optimize_pyramid", "pba_get_level_image", "pba_autotune", "pba_build_pairs", "pba_estimate_normals", "pba_debug_pair",
     "pba_get_timings", "pba_status_string", "pba_last_error",
 )
 
@@ -67,7 +67,7 @@ class pba_tune_point(ctypes.Structure):
 class pba_timings(ctypes.Structure):
     _fields_ = [("eval_ms", ctypes.c_double), ("eval_launches", ctypes.c_int64), ("iterate_ms", ctypes.c_double),
                 ("iterations", ctypes.c_int64), ("n_items", ctypes.c_int64), ("items_px", ctypes.c_int32),
-                ("grid", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("iter_eval_ms", ctypes.c_double), ("iter_evals", ctypes.c_int64)]
 
 
 _lib = None
@@ -103,6 +103,8 @@ def load_library(path: str = LIB_PATH):
         "pba_optimize_pyramid": (i32, [vp, vp, f64, i32, f64, vp, vp, vp]),
         "pba_get_level_image": (i32, [vp, i32, i32, vp, vp, vp, vp]),
         "pba_autotune": (i32, [vp, vp, i32, vp]),
+        "pba_build_pairs": (i32, [vp, f64, f64, f64, i32, i32, vp, vp, vp]),
+        "pba_estimate_normals": (i32, [vp, f64, f64, f64, i32]),
         "pba_debug_pair": (i32, [vp, i32, vp, vp, vp, vp]),
         "pba_get_timings": (i32, [vp, ctypes.POINTER(pba_timings), i32]),
         "pba_status_string": (ctypes.c_char_p, [i32]),
@@ -293,6 +295,24 @@ class Context:
         return [dict(F=l.F, lam=l.lambda_, step=l.step_norm, n_valid=l.n_valid, accepted=bool(l.accepted))
                 for l in logs[:n_iters]]
 
+    def estimate_normals(self, radius_m=0.1, min_px=2.0, max_px=5.0, min_count=5):
+        """Replace the keyframes' normal images with plane fits to the depth (Sec. IV-A)."""
+        self._check(self.lib.pba_estimate_normals(self.h, float(radius_m), float(min_px), float(max_px),
+                                                  int(min_count)))
+
+    def build_pairs(self, max_angle=np.radians(30.0), max_dist=1.0, min_ratio=1.0 / 3.0, sequential=True):
+        """Matching pairs from the current poses (angle, distance, valid-reprojection ratio,
+        sequential links); they replace the context's pairs.  Returns int32 [P, 2]."""
+        n = ctypes.c_int32()
+        cap = max(1, self.n * (self.n - 1))
+        src = np.zeros(cap, np.int32)
+        tgt = np.zeros(cap, np.int32)
+        self._check(self.lib.pba_build_pairs(self.h, float(max_angle), float(max_dist), float(min_ratio),
+                                             int(bool(sequential)), cap, src.ctypes.data, tgt.ctypes.data,
+                                             ctypes.byref(n)))
+        self.p = n.value
+        return np.stack([src[:n.value], tgt[:n.value]], 1)
+
     def autotune(self):
         """Time the evaluation launch over item sizes and grids, keep the fastest; returns the
         measured points [(items_px, grid, eval_ms)]."""
@@ -394,7 +414,8 @@ class Context:
         t = pba_timings()
         self._check(self.lib.pba_get_timings(self.h, ctypes.byref(t), int(bool(reset))))
         return dict(eval_ms=t.eval_ms, eval_launches=t.eval_launches, iterate_ms=t.iterate_ms,
-                    iterations=t.iterations, n_items=t.n_items, items_px=t.items_px, grid=t.grid)
+                    iterations=t.iterations, n_items=t.n_items, items_px=t.items_px, grid=t.grid,
+                    iter_eval_ms=t.iter_eval_ms, iter_evals=t.iter_evals)
 
 
 def context_for_problem(prob, precision=PBA_F32, channels=None, grad_mode=0, device=0, poses=None, images=None,

@@ -272,8 +272,9 @@ __device__ __forceinline__ void swap_row(double &x, double &y)
 
 // Sum 32 per-lane values over the 64 lanes of a wave.  Butterfly reduce-scatter: at each step a
 // lane keeps one half of its values and adds its partner's copy of that half (partners l ^ 32,
-// l ^ 16, l ^ 8, l ^ 4, l ^ 2); finally lanes 2k and 2k + 1 add their totals.  Returns the wave
-// total of value k = lane >> 1 (the same in both lanes of the pair).
+// l ^ 16, l ^ 8, l ^ 7, l ^ 2; each partner differs from the lane in the bit that chooses the
+// half, and the five masks span all 64 lanes); finally lanes 2k and 2k + 1 add their totals.
+// Returns the wave total of value k = lane >> 1 (the same in both lanes of the pair).
 template <typename T>
 __device__ __forceinline__ T wave_reduce_scatter(T (&v)[32], int lane)
 {
@@ -284,13 +285,53 @@ __device__ __forceinline__ T wave_reduce_scatter(T (&v)[32], int lane)
 #pragma unroll
     for (int m = 8, n = 4; n >= 1; m >>= 1, n >>= 1) {
         const bool up = (lane & m) != 0;
+        const int pm = m == 4 ? 7 : m;
 #pragma unroll
         for (int i = 0; i < n; ++i) {
             const T keep = up ? v[i + n] : v[i], send = up ? v[i] : v[i + n];
-            v[i] = keep + __shfl_xor(send, m, 64);
+            v[i] = keep + __shfl_xor(send, pm, 64);
         }
     }
     return v[0] + __shfl_xor(v[0], 1, 64);
+}
+
+// Lane permutations inside 16-lane rows (DPP): xor 8 = rotate the row by 8, xor 7 = mirror each
+// half-row, xor 2 and xor 1 = quad permutations [2,3,0,1] and [1,0,3,2].
+constexpr int kDppXor8 = 0x128, kDppXor7 = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+// (m & a) | (~m & b) for an all-ones / all-zeros lane mask m (one bit-field insert)
+__device__ __forceinline__ float bsel(uint32_t m, float a, float b)
+{
+    return __uint_as_float((m & __float_as_uint(a)) | (~m & __float_as_uint(b)));
+}
+// Lane mask of bit `b` of the lane index, opaque to the compiler: a visible boolean would be
+// turned back into per-value selects (and, over several steps, into chains of compares).
+template <int B>
+__device__ __forceinline__ uint32_t lane_bit_mask(int lane)
+{
+    uint32_t r;
+    asm volatile("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(lane), "i"(B));
+    return r;
+}
+
+template <>
+__device__ __forceinline__ float wave_reduce_scatter<float>(float (&v)[32], int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 16; ++i) { float x = v[i], y = v[i + 16]; swap_half(x, y); v[i] = x + y; }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { float x = v[i], y = v[i + 8]; swap_row(x, y); v[i] = x + y; }
+    const uint32_t m3 = lane_bit_mask<3>(lane), m2 = lane_bit_mask<2>(lane), m1 = lane_bit_mask<1>(lane);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = bsel(m3, v[i + 4], v[i]) + dpp<kDppXor8>(bsel(m3, v[i], v[i + 4]));
+#pragma unroll
+    for (int i = 0; i < 2; ++i) v[i] = bsel(m2, v[i + 2], v[i]) + dpp<kDppXor7>(bsel(m2, v[i], v[i + 2]));
+    v[0] = bsel(m1, v[1], v[0]) + dpp<kDppXor2>(bsel(m1, v[0], v[1]));
+    return v[0] + dpp<kDppXor1>(v[0]);
 }
 
 // J' of a cue row whose point-space derivative is a = d e / d p_bar (up to sign conventions below):
@@ -346,6 +387,14 @@ __device__ __forceinline__ void accumulate_row_b(double *acc, const T (&J)[6], T
 // fourth word for raw 32-bit element access on this target family (out-of-range loads return 0).
 constexpr int kRawBufferWord3 = 0x00020000;
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Per-pair constants (pose product, sensor intrinsics, thresholds) are the same in every lane:
+// readfirstlane pins them to scalar registers, which frees about 30 vector registers and lets the
+// spherical FP32 kernel run four waves per SIMD instead of three.
+__device__ __forceinline__ float uni_f(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ double uni_d(double v)
+{
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)), __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
 template <typename P>
 __device__ __forceinline__ const P *uni_ptr(const P *p)
 {
@@ -437,20 +486,20 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         // pair transform in FP64 (phase 1 geometry, the normal cue's rotation, adjoint terms)
         double Rd[9], td[3];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) Rd[k] = pd.Rd[k];
+        for (int k = 0; k < 9; ++k) Rd[k] = uni_d(pd.Rd[k]);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) td[k] = pd.td[k];
+        for (int k = 0; k < 3; ++k) td[k] = uni_d(pd.td[k]);
         T cc[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) cc[k] = (T)pd.c[k];
+        for (int k = 0; k < 3; ++k) cc[k] = (T)uni_f(pd.c[k]);
         if (!F32) {
             double cd[3];
             mtv3(st.Ro, st.to, cd);
             for (int k = 0; k < 3; ++k) cc[k] = (T)cd[k];
         }
-        const double st_fx = st.fxd, st_fy = st.fyd, st_cx = st.cxd, st_cy = st.cyd, st_dmin = st.dmind;
+        const double st_fx = uni_d(st.fxd), st_fy = uni_d(st.fyd), st_cx = uni_d(st.cxd), st_cy = uni_d(st.cyd), st_dmin = uni_d(st.dmind);
         const T fx = (T)st_fx, fy = (T)st_fy;
-        const T tau = F32 ? (T)st.tau : (T)st.taud;
+        const T tau = F32 ? (T)uni_f(st.tau) : (T)uni_d(st.taud);
         const T om_g = (T)a.omega_g, om_d = (T)a.omega_d, om_n = (T)a.omega_n, delta = (T)a.huber;
         const L2 *lcol = lut + ss.lut_col, *lrow = lut + ss.lut_row;
         const float *sdep = a.dep + ks.off;

@@ -101,10 +101,14 @@ void launch_downsample(const float *dep, const float4 *att4, const float *att1, 
                        float4 *att4_2, float *att1_2, int H2, int W2, double tau, hipStream_t st);
 void launch_unpack(const float *dep, const float4 *att4, const float *att1, int npx, float *I, float *D, float *N,
                    hipStream_t st);
+void launch_normals(const float *dep, float4 *att4, int H, int W, const double2 *lcol, const double2 *lrow,
+                    int spherical, double scale, double min_px, double max_px, double tau, int min_count,
+                    hipStream_t st);
 // Winv: the inverted diagonal blocks followed by n doubles of workspace.
 void launch_chol_solve(const double *L, double *Winv, double *x, int n, const int32_t *fail, hipStream_t st);
 void launch_boxplus(const double *X, const double *dx, double *Xout, int N, const int32_t *fail,
                     LmState *lm, hipStream_t st);
+void launch_stamp(const LmState *lm, double *logbuf, int log_cap, int which, hipStream_t st);
 void launch_lm_decide(LmState *lm, const double *totals_cand, int64_t nH, double *H_cur, const double *H_cand,
                       double *b_cur, const double *b_cand, double *X_cur, const double *X_cand, int N,
                       double *totals_cur, double *logbuf, int log_cap, hipStream_t st);

@@ -79,7 +79,9 @@ struct pba_ctx {
 
     // timing
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    double eval_ms = 0.0, iterate_ms = 0.0;
+    double eval_ms = 0.0, iterate_ms = 0.0, iter_eval_ms = 0.0;
+    int64_t iter_evals = 0;
+    double wall_khz = 0.0;   // device wall-clock rate
     int64_t eval_launches = 0, iterations = 0;
     int grid = 0;
 };
@@ -366,15 +368,18 @@ EvalArgs make_args(pba_ctx *c)
 
 // Evaluate at `poses` into (H, b, totals).  Launch order on the context stream:
 // pair setup (also clears the queue counters) -> persistent evaluation per model group
-// -> ordered per-pair reduction/expansion -> assembly.
+// -> ordered per-pair reduction/expansion -> assembly.  `timed` brackets the evaluation launches
+// with the context's HIP events; `stamped` with wall-clock stamps into the LM log row (for
+// launches inside a captured iteration, where the events would only keep the last replay).
 pba_status run_eval(pba_ctx *c, const double *poses, double *H, double *b, double *totals, bool timed,
-                    hipStream_t st)
+                    hipStream_t st, bool stamped = false)
 {
     const int ngrp = (int)c->groups.size();
     launch_pair_setup(poses, P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->L().sensors_d), P_<KfDev>(c->L().kfs_d),
                       P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ngrp * kXcd, st);
     EvalArgs a = make_args(c);
     if (timed) HIP_OK(hipEventRecord(c->ev0, st));
+    if (stamped) launch_stamp(P_<LmState>(c->lm), P_<double>(c->logbuf), c->log_cap, 0, st);
     for (int g = 0; g < ngrp; ++g) {
         const auto &G = c->groups[g];
         a.counter = P_<uint32_t>(c->counters) + g * kXcd;
@@ -383,6 +388,7 @@ pba_status run_eval(pba_ctx *c, const double *poses, double *H, double *b, doubl
                     st);
     }
     if (timed) HIP_OK(hipEventRecord(c->ev1, st));
+    if (stamped) launch_stamp(P_<LmState>(c->lm), P_<double>(c->logbuf), c->log_cap, 1, st);
     HIP_OK(hipGetLastError());
     launch_reduce_pairs(c->partials.p, c->cfg.precision, P_<int32_t>(c->pitems), P_<int32_t>(c->ibeg),
                         P_<int32_t>(c->icnt), P_<PairDev>(c->pair_dev), P_<double>(c->pair_out), c->P, st);
@@ -415,7 +421,7 @@ pba_status enqueue_iteration(pba_ctx *c, hipStream_t st)
     launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->N, P_<int32_t>(c->fail),
                    P_<LmState>(c->lm), st);
     pba_status s = run_eval(c, P_<double>(c->poses_cand), P_<double>(c->H_cand), P_<double>(c->b_cand), totals + 4,
-                            false, st);
+                            false, st, true);
     if (s) return s;
     launch_lm_decide(P_<LmState>(c->lm), totals + 4, (int64_t)n * n, P_<double>(c->H), P_<double>(c->H_cand),
                      P_<double>(c->b), P_<double>(c->b_cand), P_<double>(c->poses), P_<double>(c->poses_cand), c->N,
@@ -524,6 +530,9 @@ pba_status pba_create(const pba_config *cfg, pba_ctx **out)
     if (hipGetDeviceProperties(&prop, cfg->device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cu = prop.multiProcessorCount;
     c->grid = c->num_cu * 4;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, cfg->device) == hipSuccess && khz > 0)
+        c->wall_khz = khz;
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         delete c;
         return PBA_EDEVICE;
@@ -858,6 +867,13 @@ pba_status pba_iterate(pba_ctx *c, int32_t n_iters, int32_t use_lm, double lambd
             log[it].pad = 0;
         }
         if (r[5] != 0.0) any_fail = true;
+        uint64_t t0, t1;
+        std::memcpy(&t0, &r[6], 8);
+        std::memcpy(&t1, &r[7], 8);
+        if (c->wall_khz > 0.0 && t1 >= t0) {
+            c->iter_eval_ms += (double)(t1 - t0) / c->wall_khz;
+            c->iter_evals += 1;
+        }
     }
     if (use_lm) c->lam_carry = lg[8 * (size_t)(n_iters - 1) + 1];
     if (any_fail && !use_lm) return fail(c, PBA_ENOTPD, "Gauss-Newton system not positive definite");
@@ -961,6 +977,104 @@ pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float
             HIP_OK(hipMemcpyAsync(grad_normals[k], P_<float>(c->g_nrm) + 3 * off, npx * 12, kind, c->stream));
     }
     HIP_OK(hipStreamSynchronize(c->stream));
+    return PBA_OK;
+}
+
+pba_status pba_estimate_normals(pba_ctx *c, double radius_m, double min_px, double max_px, int32_t min_count)
+{
+    if (!c) return PBA_EINVAL;
+    if (c->N == 0) return fail(c, PBA_ESTATE, "no keyframes loaded");
+    if (c->cfg.channels != 5) return fail(c, PBA_ESTATE, "normal estimation needs 5 channels");
+    if (!(radius_m > 0.0) || !(min_px >= 0.0) || !(max_px >= min_px) || max_px > 16.0 || min_count < 1)
+        return fail(c, PBA_EINVAL, "bad normal-estimation parameters");
+    HIP_OK(hipSetDevice(c->cfg.device));
+    pba_status s;
+    if (c->level != 0 || c->lv.size() > 1) {
+        for (size_t l = 1; l < c->lv.size(); ++l) release_images(c->lv[l]);
+        c->lv.resize(1);
+        if (c->level != 0) {
+            c->level = 0;
+            if (c->P > 0 && (s = build_plan(c, c->src_h, c->tgt_h))) return s;
+        }
+    }
+    ImageSet &is = c->lv[0];
+    for (int k = 0; k < c->N; ++k) {
+        const KfDev &f = is.kfs_h[k];
+        const pba_sensor &S = is.sensors[f.sensor];
+        const SensorDev &sd = is.sensors_dev_h[f.sensor];
+        const double tau = S.model == PBA_PINHOLE ? c->cfg.occlusion_tau_pinhole : c->cfg.occlusion_tau_spherical;
+        launch_normals(P_<float>(is.dep) + f.off, P_<float4>(is.att4) + f.off, f.H, f.W,
+                       P_<double2>(is.lut64) + sd.lut_col, P_<double2>(is.lut64) + sd.lut_row,
+                       S.model == PBA_SPHERICAL, radius_m * std::fabs(S.fx), min_px, max_px, tau, min_count,
+                       c->stream);
+    }
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    c->system_valid = false;
+    c->loss_ready = false;
+    return PBA_OK;
+}
+
+pba_status pba_build_pairs(pba_ctx *c, double max_angle, double max_dist, double min_ratio, int32_t sequential,
+                           int32_t cap, int32_t *src_out, int32_t *tgt_out, int32_t *n_out)
+{
+    if (!c) return PBA_EINVAL;
+    if (!(max_angle >= 0.0) || !(max_dist >= 0.0) || !(min_ratio >= 0.0) || cap < 0)
+        return fail(c, PBA_EINVAL, "negative threshold or capacity");
+    if (c->N == 0) return fail(c, PBA_ESTATE, "no keyframes loaded");
+    if (!c->poses_set) return fail(c, PBA_ESTATE, "poses not set");
+    HIP_OK(hipSetDevice(c->cfg.device));
+    const int N = c->N;
+    std::vector<double> X((size_t)N * 12);
+    HIP_OK(hipMemcpyAsync(X.data(), c->poses.p, X.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    // pose tests on the host; the candidates (and sequential links) are then evaluated together
+    std::vector<int32_t> cs, ct;
+    std::vector<char> close, seq;
+    for (int s = 0; s < N; ++s)
+        for (int t = 0; t < N; ++t) {
+            if (s == t) continue;
+            const double *a = &X[12 * (size_t)s], *b = &X[12 * (size_t)t];
+            double tr = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int k = 0; k < 3; ++k) tr += a[3 * k + i] * b[3 * k + i];   // trace(Ra^T Rb)
+            const double ang = std::acos(std::min(1.0, std::max(-1.0, (tr - 1.0) / 2.0)));
+            const double dx = a[9] - b[9], dy = a[10] - b[10], dz = a[11] - b[11];
+            const bool cl = ang < max_angle && std::sqrt(dx * dx + dy * dy + dz * dz) < max_dist;
+            const bool sq = sequential && (s - t == 1 || t - s == 1);
+            if (!cl && !sq) continue;
+            cs.push_back(s);
+            ct.push_back(t);
+            close.push_back(cl);
+            seq.push_back(sq);
+        }
+    pba_status st;
+    std::vector<int32_t> ks, kt;
+    if (!cs.empty()) {
+        if ((st = pba_set_pairs(c, (int32_t)cs.size(), cs.data(), ct.data()))) return st;
+        if ((st = run_eval(c, P_<double>(c->poses), P_<double>(c->H_cand), P_<double>(c->b_cand),
+                           P_<double>(c->totals) + 4, false, c->stream)))
+            return st;
+        std::vector<double> po((size_t)c->P * kPairOut);
+        HIP_OK(hipMemcpyAsync(po.data(), c->pair_out.p, po.size() * 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(hipStreamSynchronize(c->stream));
+        for (size_t k = 0; k < cs.size(); ++k) {
+            const double n_eval = po[k * kPairOut + 157], n_valid = po[k * kPairOut + 158];
+            const bool ratio_ok = n_eval > 0.0 && n_valid >= min_ratio * n_eval;
+            if (seq[k] || (close[k] && ratio_ok)) {
+                ks.push_back(cs[k]);
+                kt.push_back(ct[k]);
+            }
+        }
+    }
+    if ((st = pba_set_pairs(c, (int32_t)ks.size(), ks.data(), kt.data()))) return st;
+    const int n = (int)ks.size();
+    for (int k = 0; k < std::min(n, cap); ++k) {
+        if (src_out) src_out[k] = ks[k];
+        if (tgt_out) tgt_out[k] = kt[k];
+    }
+    if (n_out) *n_out = n;
     return PBA_OK;
 }
 
@@ -1186,9 +1300,11 @@ pba_status pba_get_timings(pba_ctx *c, pba_timings *out, int32_t reset)
     out->n_items = c->n_items;
     out->items_px = c->items_px;
     out->grid = c->grid;
+    out->iter_eval_ms = c->iter_eval_ms;
+    out->iter_evals = c->iter_evals;
     if (reset) {
-        c->eval_ms = c->iterate_ms = 0.0;
-        c->eval_launches = c->iterations = 0;
+        c->eval_ms = c->iterate_ms = c->iter_eval_ms = 0.0;
+        c->eval_launches = c->iterations = c->iter_evals = 0;
     }
     return PBA_OK;
 }

@@ -511,6 +511,21 @@ __global__ void copy_kernel(double *__restrict__ dst, const double *__restrict__
         dst[i] = src[i];
 }
 
+// Device wall-clock stamp (constant-rate counter) into slot 6 + which of the current iteration's
+// log row: the evaluation inside a captured iteration is bracketed by two of these, so every
+// replay of the graph leaves its own evaluation duration.
+__global__ void stamp_kernel(const LmState *lm, double *logbuf, int log_cap, int which)
+{
+    if (threadIdx.x != 0) return;
+    uint64_t *row = reinterpret_cast<uint64_t *>(logbuf + 8 * (int64_t)min(lm->iter, log_cap - 1));
+    row[6 + which] = (uint64_t)wall_clock64();
+}
+
+void launch_stamp(const LmState *lm, double *logbuf, int log_cap, int which, hipStream_t st)
+{
+    hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, st, lm, logbuf, log_cap, which);
+}
+
 void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st)
 {
     if (n <= 0) return;

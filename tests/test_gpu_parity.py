@@ -283,6 +283,19 @@ def test_graph_replays_match_eager_iterations(lidar_mini, pba):
         assert np.array_equal(eg["H"], ee["H"])
 
 
+def test_iteration_eval_stamps(lidar_mini, pba):
+    """The wall-clock stamps around the evaluation inside each iteration (graph replays included)
+    give one positive duration per iteration, shorter than the whole iteration."""
+    for use_graph in (True, False):
+        with pba.context_for_problem(lidar_mini, use_graph=use_graph) as ctx:
+            ctx.evaluate()
+            ctx.timings(reset=True)
+            ctx.iterate(3, use_lm=True)
+            t = ctx.timings(reset=True)
+            assert t["iter_evals"] == 3 and t["iterations"] == 3, t
+            assert 0.0 < t["iter_eval_ms"] < t["iterate_ms"], t
+
+
 def test_autotune_keeps_results(lidar_mini, pba):
     """The autotuner only changes the work decomposition: the evaluation after it equals the one
     before up to summation order (which pixels share a wave's FP32 tree sum, and the order of the
@@ -299,3 +312,24 @@ def test_autotune_keeps_results(lidar_mini, pba):
         assert np.abs(a["H"] - b["H"]).max() <= 1e-6 * np.abs(a["H"]).max()
         logs = ctx.iterate(2, use_lm=True)
         assert all(np.isfinite(l["F"]) for l in logs)
+
+
+def test_build_pairs_matches_oracle(pba):
+    """Sec. IV-B pair graph on a 12-keyframe stretch of the 640x480 room trajectory (at 160x120):
+    the FP64 path's counts equal the oracle's, so the kept pair sets are identical; the FP32 path
+    may differ only for pairs whose valid ratio is within 1e-3 of the threshold."""
+    kfs = list(range(12))
+    p = synth.make("rgbd_room", kfs=kfs, H=120, W=160).subset(kfs)
+    want, ratios = oracle.build_pairs(p, p.init_poses, max_dist=1.0)
+    for precision in (pba.PBA_F64, pba.PBA_F32):
+        with pba.context_for_problem(p, precision=precision) as ctx:
+            got = ctx.build_pairs(max_dist=1.0)
+            ev = ctx.evaluate()
+        g, w = set(map(tuple, got.tolist())), set(map(tuple, want.tolist()))
+        _log("build_pairs: %d kept (oracle %d) of %d candidates" % (len(g), len(w), len(ratios)))
+        if precision == pba.PBA_F64:
+            assert g == w
+        else:
+            for pr in g ^ w:
+                assert abs(ratios[pr] - 1.0 / 3.0) < 1e-3, (pr, ratios[pr])
+        assert ev["n_evaluated"] > 0
