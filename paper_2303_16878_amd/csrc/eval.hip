@@ -134,20 +134,20 @@ __device__ __forceinline__ T fast_rsq(T x) { return T(1) / sqrt(x); }
 template <>
 __device__ __forceinline__ float fast_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// 1/x in FP64 to an ulp or two: the hardware estimate refined by two Newton steps.
+// 1/x in FP64: the hardware estimate (relative error below 2^-24, measured on this target) refined
+// by one Newton step, which squares the error: below 3e-15.  The geometry needs far less (a
+// projected coordinate of 2000 px then carries ~1e-11 px).
 __device__ __forceinline__ double rcp_f64(double x)
 {
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
+    const double r = __builtin_amdgcn_rcp(x);
     return fma(r, fma(-x, r, 1.0), r);
 }
 
-// sqrt(x) for x > 0 in FP64 to about two ulps: x times the hardware reciprocal square root
-// refined by two Newton steps.
+// sqrt(x) for x > 0 in FP64: x times the hardware reciprocal square root (below 2^-24) refined by
+// one Newton step: relative error below 5e-15 (3e-13 m at 80 m range).
 __device__ __forceinline__ double sqrt_f64(double x)
 {
     double y = __builtin_amdgcn_rsq(x);
-    y = y * fma(-0.5 * x * y, y, 1.5);
     y = y * fma(-0.5 * x * y, y, 1.5);
     return x * y;
 }
@@ -165,12 +165,13 @@ __device__ __forceinline__ float atan2_coarse(float y, float x)
     return y < 0.f ? -a : a;
 }
 
-// atan(t) for small |t| by its Taylor series to t^7 (remainder below t^9 / 9: 3e-13 rad at 0.05,
-// 1.1e-10 rad at 0.1).
+// atan(t) for small |t| by its Taylor series to t^5 (remainder below t^7 / 7: 2.4e-19 rad at 3e-3,
+// about the largest offset from the nearest ray of a 2048 x 128 spherical image; 1.1e-10 rad at
+// 0.05, the offset of a 64-column image).
 __device__ __forceinline__ double atan_small(double t)
 {
     const double t2 = t * t;
-    return t * fma(t2, fma(t2, fma(t2, -1.0 / 7.0, 0.2), -1.0 / 3.0), 1.0);
+    return t * fma(t2, fma(t2, 0.2, -1.0 / 3.0), 1.0);
 }
 
 
@@ -178,10 +179,9 @@ __device__ __forceinline__ double atan_small(double t)
 // a0..a3: row y0, cols x0-1..x0+2; b0..b3: row y0+1; c1,c2: row y0-1, cols x0, x0+1;
 // d1,d2: row y0+2, cols x0, x0+1.
 template <typename T, int GM>
-__device__ __forceinline__ void sample_channel(T a0, T a1, T a2, T a3, T b0, T b1, T b2, T b3, T c1, T c2, T d1,
-                                               T d2, T w00, T w01, T w10, T w11, T al, T be, T &V, T &Gx, T &Gy)
+__device__ __forceinline__ void sample_grad(T a0, T a1, T a2, T a3, T b0, T b1, T b2, T b3, T c1, T c2, T d1, T d2,
+                                            T w00, T w01, T w10, T w11, T al, T be, T &Gx, T &Gy)
 {
-    V = w00 * a1 + w01 * a2 + w10 * b1 + w11 * b2;
     if (GM == 0) {
         // central differences 1/2 (I[x+1] - I[x-1]) at each tap, blended with the bilinear weights
         Gx = T(0.5) * (w00 * (a2 - a0) + w01 * (a3 - a1) + w10 * (b2 - b0) + w11 * (b3 - b1));
@@ -190,6 +190,13 @@ __device__ __forceinline__ void sample_channel(T a0, T a1, T a2, T a3, T b0, T b
         Gx = (T(1) - be) * (a2 - a1) + be * (b2 - b1);
         Gy = (T(1) - al) * (b1 - a1) + al * (b2 - a2);
     }
+}
+template <typename T, int GM>
+__device__ __forceinline__ void sample_channel(T a0, T a1, T a2, T a3, T b0, T b1, T b2, T b3, T c1, T c2, T d1,
+                                               T d2, T w00, T w01, T w10, T w11, T al, T be, T &V, T &Gx, T &Gy)
+{
+    V = w00 * a1 + w01 * a2 + w10 * b1 + w11 * b2;
+    sample_grad<T, GM>(a0, a1, a2, a3, b0, b1, b2, b3, c1, c2, d1, d2, w00, w01, w10, w11, al, be, Gx, Gy);
 }
 
 // Per-pixel sums of one cue row into v: v[0..20] += om J_i J_j (upper triangle, row-major),
@@ -395,6 +402,15 @@ __device__ __forceinline__ double uni_d(double v)
 {
     return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)), __builtin_amdgcn_readfirstlane(__double2loint(v)));
 }
+// A register whose contents do not matter (an empty asm statement defines it): for values that
+// are only read on paths that set them, without instructions that clear them on the others.
+template <typename V>
+__device__ __forceinline__ V any_value()
+{
+    V x;
+    asm volatile("" : "=v"(x));
+    return x;
+}
 template <typename P>
 __device__ __forceinline__ const P *uni_ptr(const P *p)
 {
@@ -501,7 +517,11 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         const T fx = (T)st_fx, fy = (T)st_fy;
         const T tau = F32 ? (T)uni_f(st.tau) : (T)uni_d(st.taud);
         const T om_g = (T)a.omega_g, om_d = (T)a.omega_d, om_n = (T)a.omega_n, delta = (T)a.huber;
-        const L2 *lcol = lut + ss.lut_col, *lrow = lut + ss.lut_row;
+        // ray-table offsets of the source (unprojection) and target (projection) sensors in scalar
+        // registers: read once per item, not from the sensor record in every chunk
+        const int s_lcol = uni(ss.lut_col), s_lrow = uni(ss.lut_row);
+        const int t_lcol = uni(st.lut_col), t_lrow = uni(st.lut_row);
+        const L2 *lcol = lut + s_lcol, *lrow = lut + s_lrow;
         const float *sdep = a.dep + ks.off;
         const float4 *satt4 = a.att4 + ks.off;
         const float *satt1 = a.att1 + ks.off;
@@ -689,8 +709,10 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             // ---------------- phase 1: projection, cell, validity and occlusion, depth channel
             const int pix = cbase + lane;
             bool valid = false;
-            int x0 = 0, y0 = 0;
-            T al = T(0), be = T(0), px = T(0), py = T(0), pz = T(0), edv = T(0), gxd = T(0), gyd = T(0);
+            // queued only where valid: elsewhere any value will do (no instructions to clear them)
+            int x0 = any_value<int>(), y0 = any_value<int>();
+            T al = any_value<T>(), be = any_value<T>(), px = any_value<T>(), py = any_value<T>();
+            T pz = any_value<T>(), edv = any_value<T>(), gxd = any_value<T>(), gyd = any_value<T>();
             const float Ds = pix < px1 ? sdep[pix] : 0.f;
             if (DBG && pix < px1) a.dbg_status[pix] = 1;
             if (Ds > 0.f) {
@@ -703,7 +725,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 // rate): unprojection q = d * ray(u) from the FP64 ray table, p_bar = R q + t, the
                 // projected coordinates and the depth/range cue.  Cells, masks and the large-magnitude
                 // part of the depth residual then carry no FP32 rounding.
-                const double2 lcd = a.lut64[ss.lut_col + col], lrd = a.lut64[ss.lut_row + row];
+                const double2 lcd = a.lut64[s_lcol + col], lrd = a.lut64[s_lrow + row];
                 const double dd = (double)Ds;
                 double q0, q1, q2;
                 if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
@@ -736,7 +758,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         // pixel); inside, the nearest table ray is within 1 px, so the offset angle is small
                         near = ua > -1.f && ua < (float)Wt && va > -1.f && va < (float)Ht;
                         const int kc = min(max((int)rintf(ua), 0), Wt - 1), kr = min(max((int)rintf(va), 0), Ht - 1);
-                        const double2 cs = a.lut64[st.lut_col + kc], rs = a.lut64[st.lut_row + kr];
+                        const double2 cs = a.lut64[t_lcol + kc], rs = a.lut64[t_lrow + kr];
                         const double tu = fma(Y, cs.x, -X * cs.y) * rcp_f64(fma(X, cs.x, Y * cs.y));
                         const double tv = fma(Z, rs.x, -rho * rs.y) * rcp_f64(fma(rho, rs.x, Z * rs.y));
                         u = fma(st_fx, atan_small(tu), (double)kc);
@@ -765,22 +787,22 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                                                ((y0 - 1) * Wt + (x0 - 1)) * 4, Wt * 4);
                         // invalid target depths hold a large negative sentinel, so one bound on the
                         // largest |D - zeta| also rejects them
-                        T dev = T(0);
+                        float dmin = tD[0], dmax = tD[0];
 #pragma unroll
-                        for (int k = 0; k < 12; ++k) dev = fmax(dev, fabs((T)tD[k] - zeta_d));
-                        const bool vis = dev <= tau;
+                        for (int k = 1; k < 12; ++k) { dmin = fminf(dmin, tD[k]); dmax = fmaxf(dmax, tD[k]); }
+                        const bool vis = fmax((T)dmax - zeta_d, zeta_d - (T)dmin) <= tau;
                         if (vis) {
                             const T w00 = (T(1) - al) * (T(1) - be), w01 = al * (T(1) - be);
                             const T w10 = (T(1) - al) * be, w11 = al * be;
                             // e_d = zeta - D(u') taken relative to the tap at (x0, y0): the taps lie within
                             // tau of zeta, so their differences are exact and the large common part
-                            // cancels in FP64 before anything is rounded to the evaluation precision
+                            // cancels in FP64 before anything is rounded to the evaluation precision; the
+                            // image Jacobian only takes differences of taps
                             const float d0 = tD[1];
-                            T Vr;
-                            sample_channel<T, GM>((T)(tD[0] - d0), T(0), (T)(tD[2] - d0), (T)(tD[3] - d0),
-                                                  (T)(tD[4] - d0), (T)(tD[5] - d0), (T)(tD[6] - d0), (T)(tD[7] - d0),
-                                                  (T)(tD[8] - d0), (T)(tD[9] - d0), (T)(tD[10] - d0),
-                                                  (T)(tD[11] - d0), w00, w01, w10, w11, al, be, Vr, gxd, gyd);
+                            const T Vr = w01 * (T)(tD[2] - d0) + w10 * (T)(tD[5] - d0) + w11 * (T)(tD[6] - d0);
+                            sample_grad<T, GM>((T)tD[0], (T)tD[1], (T)tD[2], (T)tD[3], (T)tD[4], (T)tD[5], (T)tD[6],
+                                               (T)tD[7], (T)tD[8], (T)tD[9], (T)tD[10], (T)tD[11], w00, w01, w10, w11,
+                                               al, be, gxd, gyd);
                             edv = (T)(zeta - (double)d0) - Vr;
                             valid = true;
                         }
