@@ -45,11 +45,11 @@ void launch_damp_copy(const double *H, const double *b, double *A, double *rhs, 
 // form the panel below as X = B W^T with W = L_kk^-1 (tiled product), then update the
 // trailing lower triangle.  The inverted diagonal blocks are kept for the solves.
 
-__device__ __forceinline__ double bcast(double v, int lane)
+// The value of v in lane l (wave-uniform l), to every lane.
+__device__ __forceinline__ double bcast_lane(double v, int l)
 {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
 // 1/sqrt(d) in FP64 to about an ulp: the hardware estimate refined by two Newton steps.
@@ -60,140 +60,95 @@ __device__ __forceinline__ double rsqrt_f64(double d)
     return y * fma(-0.5 * d * y, y, 1.5);
 }
 
-constexpr int SB = 16;   // sub-block of the diagonal factorisation
-
-// Factor the SB x SB SPD block at S (leading dimension ld, in LDS) in place (lower; zero above) and
-// write its inverse factor to Wd (leading dimension ld).  Lanes 0..SB-1 of one wave each keep one
-// row in registers; column entries are broadcast with readlane.  Returns true if a pivot was not
-// positive.
-__device__ bool factor_sub(double *S, double *Wd, int ld, int lane)
-{
-    double r[SB];
-#pragma unroll
-    for (int k = 0; k < SB; ++k) r[k] = lane < SB ? S[lane * ld + k] : 0.0;
-    bool bad = false;
-    double inv[SB];
-#pragma unroll
-    for (int j = 0; j < SB; ++j) {
-        const double d = bcast(r[j], j);
-        bad = bad || !(d > 0.0);
-        inv[j] = d > 0.0 ? rsqrt_f64(d) : 1.0;
-        const double sd = d > 0.0 ? d * inv[j] : 1.0;
-        r[j] = lane == j ? sd : (lane > j ? r[j] * inv[j] : r[j]);
-#pragma unroll
-        for (int k = j + 1; k < SB; ++k) {
-            const double lkj = bcast(r[j], k);
-            if (lane >= k) r[k] = fma(-r[j], lkj, r[k]);
-        }
-    }
-    // inverse row by row: row m is final once scaled by 1 / L_mm, then removed from the rows below
-    double w[SB];
-#pragma unroll
-    for (int c = 0; c < SB; ++c) w[c] = c == lane ? 1.0 : 0.0;
-#pragma unroll
-    for (int m = 0; m < SB; ++m) {
-        if (lane == m) {
-#pragma unroll
-            for (int c = 0; c <= m; ++c) w[c] *= inv[m];
-        }
-#pragma unroll
-        for (int c = 0; c <= m; ++c) {
-            const double wmc = bcast(w[c], m);
-            if (lane > m) w[c] = fma(-r[m], wmc, w[c]);
-        }
-    }
-    if (lane < SB) {
-#pragma unroll
-        for (int k = 0; k < SB; ++k) {
-            S[lane * ld + k] = k <= lane ? r[k] : 0.0;
-            Wd[lane * ld + k] = k <= lane ? w[k] : 0.0;
-        }
-    }
-    return bad;
-}
-
 // Factor the diagonal block at k0 and write L_kk (lower) to A and W = L_kk^-1 (lower, row-major
-// 64 x 64, zero above the diagonal) to Winv.  One workgroup of 256 threads, the block in LDS,
-// right-looking over 16-wide sub-blocks: the 16 x 16 diagonal sub-block is factored and inverted by
-// one wave, the sub-panel below is multiplied by that inverse and the trailing lower triangle
-// updated by all threads.  The inverse is then assembled by block rows,
-// W_ij = -W_ii sum_{j <= k < i} L_ik W_kj.  A ragged last block is padded with the identity,
-// whose factor and inverse are the identity.
+// 64 x 64, zero above the diagonal) to Winv.  One workgroup of 256 threads; a ragged last block is
+// padded with the identity, whose factor and inverse are the identity.
+//
+// Right-looking over single pivots, factor and inverse together, in registers: lane i of wave w
+// holds row i, columns 16 w .. 16 w + 15, of the working copy S and of V, the working rows of the
+// inverse (V = I initially).  At pivot k, with p = S(k, k), c_i = S(i, k) for i > k and 0
+// otherwise, and r_j = V(k, j) (zero for j > k, r_k = 1: V stays lower triangular), every element
+// takes both
+//   S(i, j) -= c_i c_j / p,      V(i, j) -= c_i r_j / p
+// (c_j = 0 leaves S left of the pivot alone, r_j = 0 leaves V right of it alone), because
+// L(i, k) = c_i / sqrt(p) and row k of the inverse is V(k, :) / sqrt(p).  Column k of S is final
+// from then on, so S ends up holding L column-scaled by sqrt(p_j), and V holds W row-scaled by
+// sqrt(p_i).
+//
+// Pivots go four at a time per barrier: the wave owning columns k .. k + 3 factors that 64 x 4
+// panel on copies (cross-lane values by readlane) and publishes the four columns c as they stand
+// at their pivots, with their pivots; then every wave applies the four rank-one steps in order.
+// Row k + m of V, needed as r by the m-th step, is read from lane k + m of the same wave, which
+// has already applied the steps before it.  No step branches on the lane or the wave.
 __global__ void __launch_bounds__(256) chol_diag_kernel(double *A, int n, int k0, double *Winv, int32_t *fail)
 {
-    __shared__ double S[NB][NB + 1];
-    __shared__ double W[NB][NB + 1];
-    __shared__ double P[NB][SB + 1];
-    __shared__ double T[SB][NB + 1];
-    __shared__ int s_bad;
+    __shared__ double cb[2][4][NB];   // the four columns c of a pivot group
+    __shared__ double pb[2][4];       // their pivots
+    __shared__ double piv[NB];
     if (*fail) return;
     const int nb = min(NB, n - k0);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, k = e % NB;
-        S[i][k] = (i < nb && k < nb) ? A[(int64_t)(k0 + i) * n + k0 + k] : (i == k ? 1.0 : 0.0);
-        W[i][k] = 0.0;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c0 = 16 * w;
+    double a[16], v[16];
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+        const int j = c0 + jj;
+        a[jj] = (lane < nb && j < nb) ? A[(int64_t)(k0 + lane) * n + k0 + j] : (lane == j ? 1.0 : 0.0);
+        v[jj] = lane == j ? 1.0 : 0.0;
     }
-    if (tid == 0) s_bad = 0;
-    __syncthreads();
+    bool bad = false;
 #pragma unroll 1
-    for (int o = 0; o < NB; o += SB) {
-        if (wave == 0) {
-            const bool bad = factor_sub(&S[o][o], &W[o][o], NB + 1, lane);
-            if (lane == 0 && bad) s_bad = 1;
-        }
-        __syncthreads();
-        // sub-panel: L(i, o + c) = sum_k A(i, o + k) W_oo(c, k) for the rows below
-        const int rows = NB - o - SB;
-        for (int e = tid; e < rows * SB; e += blockDim.x) {
-            const int i = o + SB + e / SB, c = e % SB;
-            double acc = 0.0;
+    for (int wo = 0; wo < 4; ++wo) {
 #pragma unroll
-            for (int k = 0; k < SB; ++k) acc = fma(S[i][o + k], W[o + c][o + k], acc);
-            P[i][c] = acc;
-        }
-        __syncthreads();
-        for (int e = tid; e < rows * SB; e += blockDim.x) {
-            const int i = o + SB + e / SB, c = e % SB;
-            S[i][o + c] = P[i][c];
-        }
-        for (int e = tid; e < rows * rows; e += blockDim.x) {
-            const int i = o + SB + e / rows, j = o + SB + e % rows;
-            if (j <= i) {
-                double acc = 0.0;
+        for (int tb = 0; tb < 4; ++tb) {
+            const int kb = 4 * tb, k = 16 * wo + kb, b = tb & 1;
+            if (w == wo) {
+                // the 64 x 4 panel at its pivots, on copies
+                double t[4] = {a[kb], a[kb + 1], a[kb + 2], a[kb + 3]};
 #pragma unroll
-                for (int k = 0; k < SB; ++k) acc = fma(P[i][k], P[j][k], acc);
-                S[i][j] -= acc;
+                for (int m = 0; m < 4; ++m) {
+                    const double p = bcast_lane(t[m], k + m);
+                    double q = __builtin_amdgcn_rcp(p);
+                    q = fma(q, fma(-p, q, 1.0), q);
+                    q = fma(q, fma(-p, q, 1.0), q);
+                    const double c = lane > k + m ? t[m] : 0.0;
+                    cb[b][m][lane] = c;
+                    if (lane == 0) pb[b][m] = p;
+#pragma unroll
+                    for (int m2 = m + 1; m2 < 4; ++m2) t[m2] = fma(-c * q, bcast_lane(t[m], k + m2), t[m2]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const double p = pb[b][m];
+                const bool ok = p > 0.0;
+                bad = bad || !ok;
+                double q = __builtin_amdgcn_rcp(p);
+                q = fma(q, fma(-p, q, 1.0), q);
+                q = fma(q, fma(-p, q, 1.0), q);
+                if (threadIdx.x == 0) piv[k + m] = ok ? p : 1.0;
+                const double cr = ok ? -cb[b][m][lane] * q : 0.0;
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj) {
+                    a[jj] = fma(cr, cb[b][m][c0 + jj], a[jj]);
+                    v[jj] = fma(cr, bcast_lane(v[jj], k + m), v[jj]);
+                }
             }
         }
-        __syncthreads();
     }
-    // off-diagonal blocks of the inverse, block row by block row
-#pragma unroll 1
-    for (int bi = 1; bi < NB / SB; ++bi) {
-        const int ri = bi * SB;
-        for (int e = tid; e < SB * ri; e += blockDim.x) {
-            const int r = e / ri, c = e % ri;      // T(r, c) = sum_{k = c_block .. ri - 1} L(ri + r, k) W(k, c)
-            double acc = 0.0;
-            for (int k = (c / SB) * SB; k < ri; ++k) acc = fma(S[ri + r][k], W[k][c], acc);
-            T[r][c] = acc;
-        }
-        __syncthreads();
-        for (int e = tid; e < SB * ri; e += blockDim.x) {
-            const int r = e / ri, c = e % ri;
-            double acc = 0.0;
-            for (int m = 0; m <= r; ++m) acc = fma(W[ri + r][ri + m], T[m][c], acc);
-            W[ri + r][c] = -acc;
-        }
-        __syncthreads();
-    }
+    __syncthreads();
     double *Wb = Winv + (int64_t)(k0 / NB) * NB * NB;
-    for (int e = tid; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, k = e % NB;
-        Wb[e] = (i < nb && k < nb && k <= i) ? W[i][k] : 0.0;
-        if (i < nb && k <= i) A[(int64_t)(k0 + i) * n + k0 + k] = S[i][k];
+    const double si = rsqrt_f64(piv[lane]);
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+        const int j = c0 + jj;
+        const bool low = j <= lane, in = lane < nb && j < nb;
+        Wb[lane * NB + j] = (low && in) ? v[jj] * si : 0.0;
+        if (low && in) A[(int64_t)(k0 + lane) * n + k0 + j] = a[jj] * rsqrt_f64(piv[j]);
     }
-    if (tid == 0 && s_bad) *fail = 1;
+    if (threadIdx.x == 0 && bad) *fail = 1;
 }
 
 // Panel below the diagonal block: X = B W^T for 64 rows per workgroup (16 x 16 threads, 4 x 4 each).
