@@ -206,21 +206,29 @@ def eval_pairs(prob, poses, params=None, pairs=None, grad_mode=0):
                 n_eval=np.array([o.n_eval for o in outs]), n_valid=np.array([o.n_valid for o in outs]))
 
 
-def assemble(pair_res, pairs, n):
-    """Sum per-pair 12x12 blocks into the 6N x 6N system in pair order."""
+def assemble(pair_res, pairs, n, pose_of=None):
+    """Sum per-pair 12x12 blocks into the 6n x 6n system in pair order.  With pose_of (keyframe ->
+    pose variable, for keyframes that share a rig pose), the source and target blocks go to their
+    keyframes' variables: the chain rule for X_kf = X_var under a common right perturbation, so a
+    pair inside one variable adds all four of its 6x6 blocks to that variable's diagonal block."""
     H = np.zeros((6 * n, 6 * n))
     b = np.zeros(6 * n)
     for p, (s, t) in enumerate(np.asarray(pairs)):
-        idx = np.r_[6 * s:6 * s + 6, 6 * t:6 * t + 6]
-        H[np.ix_(idx, idx)] += pair_res["H12"][p]
-        b[idx] += pair_res["b12"][p]
+        v = (int(s), int(t)) if pose_of is None else (int(pose_of[s]), int(pose_of[t]))
+        for a in range(2):
+            b[6 * v[a]:6 * v[a] + 6] += pair_res["b12"][p][6 * a:6 * a + 6]
+            for c in range(2):
+                H[6 * v[a]:6 * v[a] + 6, 6 * v[c]:6 * v[c] + 6] += pair_res["H12"][p][6 * a:6 * a + 6, 6 * c:6 * c + 6]
     return H, b
 
 
 def evaluate(prob, poses, params=None, pairs=None, grad_mode=0):
+    """The system at `poses`: one pose per keyframe, or per pose variable when prob.pose_of is set."""
     pairs = prob.pairs if pairs is None else pairs
-    pr = eval_pairs(prob, poses, params, pairs, grad_mode)
-    H, b = assemble(pr, pairs, prob.n)
+    pose_of = getattr(prob, "pose_of", None)
+    kfp = np.asarray(poses, np.float64) if pose_of is None else np.asarray(poses, np.float64)[np.asarray(pose_of)]
+    pr = eval_pairs(prob, kfp, params, pairs, grad_mode)
+    H, b = assemble(pr, pairs, prob.n if pose_of is None else int(np.max(pose_of)) + 1, pose_of)
     return dict(H=H, b=b, F=float(pr["F"].sum()), n_eval=int(pr["n_eval"].sum()),
                 n_valid=int(pr["n_valid"].sum()), pairs=pr)
 
@@ -551,18 +559,22 @@ def quat_right_jacobian(dq):
 def loss_and_grad(prob, poses0, delta, params=None, pairs=None):
     """F(X0 boxplus delta) = sum of rho over pairs and valid pixels, and its exact gradients.
 
-    delta: [N, 6] per pose [dt, dq].  Returns dict(F, g_delta [N,6], gI, gD, gN per keyframe).
+    delta: [N, 6] per pose [dt, dq] (per pose variable when prob.pose_of is set).  Returns
+    dict(F, g_delta [N,6], gI, gD, gN per keyframe).
     The derivative of F is taken with the slope of the bilinear interpolant (the sampled images
     are what F depends on); masks and integer cells are those of the evaluation at X."""
     lib = _load()
     params = prob.params if params is None else params
     pairs = prob.pairs if pairs is None else np.asarray(pairs, np.int32)
-    delta = np.asarray(delta, np.float64).reshape(prob.n, 6)
-    X = boxplus(poses0, delta.reshape(-1))
+    pose_of = getattr(prob, "pose_of", None)
+    nv = prob.n if pose_of is None else int(np.max(pose_of)) + 1
+    var = np.arange(prob.n) if pose_of is None else np.asarray(pose_of)
+    delta = np.asarray(delta, np.float64).reshape(nv, 6)
+    X = boxplus(poses0, delta.reshape(-1))[var]
     gI = [np.zeros(prob.depth[k].shape) for k in range(prob.n)]
     gD = [np.zeros(prob.depth[k].shape) for k in range(prob.n)]
     gN = [np.zeros(prob.depth[k].shape + (3,)) for k in range(prob.n)]
-    b = np.zeros(6 * prob.n)
+    b = np.zeros(6 * nv)
     F = 0.0
     for (s, t) in pairs:
         s, t = int(s), int(t)
@@ -582,11 +594,11 @@ def loss_and_grad(prob, poses0, delta, params=None, pairs=None):
             raise RuntimeError("orc_eval_pair_grad failed (%d)" % rc)
         F += out.F
         bb = np.array(out.b)
-        b[6 * s:6 * s + 6] += bb[:6]
-        b[6 * t:6 * t + 6] += bb[6:]
+        b[6 * var[s]:6 * var[s] + 6] += bb[:6]
+        b[6 * var[t]:6 * var[t] + 6] += bb[6:]
     # dF/d(right perturbation at X) = 2 b; chain rule through X0 boxplus delta
-    g = np.zeros((prob.n, 6))
-    for k in range(prob.n):
+    g = np.zeros((nv, 6))
+    for k in range(nv):
         q = delta[k, 3:]
         g[k, :3] = quat_rot(q) @ (2.0 * b[6 * k:6 * k + 3])
         g[k, 3:] = quat_right_jacobian(q).T @ (2.0 * b[6 * k + 3:6 * k + 6])

@@ -163,10 +163,22 @@ class Problem:
     depth: list = field(default_factory=list)
     normals: list = field(default_factory=list)     # float32 [H,W,3]
     scene: dict = field(default_factory=dict)
+    # keyframe -> pose variable (several sensors of one rig frame share a pose); None: one pose
+    # per keyframe.  With it, gt_poses / init_poses hold one pose per variable.
+    pose_of: np.ndarray = None
 
     @property
     def n(self):
         return len(self.kf_sensor)
+
+    @property
+    def n_poses(self):
+        return self.n if self.pose_of is None else int(np.max(self.pose_of)) + 1
+
+    def kf_poses(self, X):
+        """Per-keyframe poses from per-variable poses."""
+        X = np.asarray(X, np.float64)
+        return X if self.pose_of is None else X[np.asarray(self.pose_of)]
 
     def subset(self, kfs):
         """Problem restricted to keyframes `kfs` (re-indexed), keeping pairs among them."""
@@ -174,6 +186,7 @@ class Problem:
         remap = {k: i for i, k in enumerate(kfs)}
         pairs = np.array([(remap[s], remap[t]) for s, t in self.pairs if s in remap and t in remap],
                          np.int32).reshape(-1, 2)
+        assert self.pose_of is None, "subset of a problem with shared poses"
         sub = Problem(self.name + "_sub", self.sensors, self.kf_sensor[kfs].copy(), self.gt_poses[kfs].copy(),
                       self.init_poses[kfs].copy(), pairs, dict(self.params), scene=self.scene)
         if self.intensity:
@@ -200,7 +213,7 @@ def render(prob: Problem, kfs=None, noise=True, poses=None):
         prob.depth = [None] * N
         prob.normals = [None] * N
     kfs = list(range(N)) if kfs is None else list(kfs)
-    poses = prob.gt_poses if poses is None else poses
+    poses = prob.kf_poses(prob.gt_poses if poses is None else poses)
     sc = prob.scene
     rects = np.ascontiguousarray(sc["rects"])
     gtex = np.ascontiguousarray(sc["ground_tex"], dtype=np.float64)
@@ -514,6 +527,28 @@ def joint(seed=5, n_lidar=200, n_rgbd=400, H_l=128, W_l=1024, H_c=480, W_c=640, 
     return Problem("joint", [lid, cam], kf_sensor, gt, init, pairs, params, scene=scene)
 
 
+def rig_pair(seed=5, H_l=64, W_l=512, H_c=240, W_c=320, station=300.0, perturb_t=0.1, perturb_deg=3.0,
+             perturb_seed=0):
+    """One frame of the joint LiDAR + RGB-D rig (the joint loop's world and extrinsics) and a copy
+    of it: keyframes [LiDAR, camera] of frame 0 and the same images again as frame 1, each frame
+    one pose variable (pose_of = [0, 0, 1, 1]).  Frame 0 is held at the true pose; frame 1 starts
+    from it moved by perturb_t metres and perturb_deg degrees in seeded directions, so aligning the
+    frame to itself should return the identity.  Pairs: LiDAR 0 <-> 2, camera 1 <-> 3."""
+    base = joint(seed=seed, n_lidar=1, n_rgbd=1, H_l=H_l, W_l=W_l, H_c=H_c, W_c=W_c)
+    # the platform at `station` metres along the loop
+    rng = np.random.default_rng(seed)
+    pts, cum, _ = _driving_world(rng, 5000, 2000.0)
+    p2, tan = _sample_curve(pts, cum, np.array([station]))
+    X = np.concatenate([_look_frame_lidar([tan[0, 0], tan[0, 1], 0.0]).reshape(-1), [p2[0, 0], p2[0, 1], 1.5]])
+    gt = np.array([X, X])
+    init = _perturb(gt, np.random.default_rng(1000 + perturb_seed), perturb_t, perturb_deg, anchor=0)
+    prob = Problem("rig_pair", base.sensors, np.array([0, 1, 0, 1], np.int32), gt, init,
+                   np.array([(0, 2), (2, 0), (1, 3), (3, 1)], np.int32), dict(base.params, iterations=30),
+                   scene=base.scene, pose_of=np.array([0, 0, 1, 1], np.int32))
+    prob._copy_images = {2: 0, 3: 1}
+    return prob
+
+
 def plane_pair(model="pinhole", seed=7):
     """One large textured plane seen by three keyframes; keyframe 0 is the only source and keeps
     depth only in a central window (outside it the depth is 0, i.e. no measurement), keyframes 1 and 2 are targets whose whole view is the plane.  With small pose
@@ -566,12 +601,16 @@ def _mask_source(prob):
     return prob
 
 
-CONFIGS = {"rgbd_small": rgbd_small, "rgbd_room": rgbd_room, "lidar64": lidar64, "lidar128": lidar128, "joint": joint, "plane_pair": plane_pair}
+CONFIGS = {"rgbd_small": rgbd_small, "rgbd_room": rgbd_room, "lidar64": lidar64, "lidar128": lidar128, "joint": joint,
+           "plane_pair": plane_pair, "rig_pair": rig_pair}
 
 
 def make(name, render_images=True, noise=True, kfs=None, **kw):
     prob = CONFIGS[name](**kw)
     if render_images:
-        render(prob, kfs=kfs, noise=noise)
+        copies = getattr(prob, "_copy_images", {})
+        render(prob, kfs=[k for k in (range(prob.n) if kfs is None else kfs) if k not in copies], noise=noise)
+        for k, src in copies.items():
+            prob.intensity[k], prob.depth[k], prob.normals[k] = prob.intensity[src], prob.depth[src], prob.normals[src]
         _mask_source(prob)
     return prob
