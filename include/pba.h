@@ -123,10 +123,20 @@ pba_status pba_load_keyframes(pba_ctx *ctx, int32_t n, const int32_t *sensor_id,
                               const float *const *intensity, const float *const *depth,
                               const float *const *normals, int32_t on_device);
 
-/* Poses of all n keyframes (n must equal the number loaded).  Rejects non-finite values and
- * rotations with max |R^T R - I| > 1e-6. */
+/* Poses of all n keyframes (n must equal the number loaded), or of the n pose variables after
+ * pba_set_pose_groups.  Rejects non-finite values and rotations with max |R^T R - I| > 1e-6. */
 pba_status pba_set_poses(pba_ctx *ctx, int32_t n, const double *poses, int32_t on_device);
 pba_status pba_get_poses(pba_ctx *ctx, double *poses, int32_t on_device);
+
+/* Keyframes that share one pose variable (the sensors of one rig frame, each with its own offset:
+ * the coupled LiDAR + RGB-D formulation of the fusion experiments).  pose_of[k] in [0, n_poses)
+ * for each of the N loaded keyframes, every variable used by at least one keyframe; pose_of = NULL
+ * restores one pose per keyframe.  Afterwards poses, steps and pose gradients have n_poses
+ * entries: pba_set_poses must be called again, and the anchor is a pose variable.  A pair inside
+ * one variable contributes all four of its 6 x 6 blocks to that variable (its Jacobians cancel).
+ * Loading a different keyframe set resets the grouping.  Errors: PBA_EINVAL for a bad map,
+ * PBA_ESTATE before keyframes are loaded. */
+pba_status pba_set_pose_groups(pba_ctx *ctx, const int32_t *pose_of, int32_t n_poses);
 
 /* Ordered pairs (src[k] -> tgt[k]); ids in [0, n).  Replaces any previous set. */
 pba_status pba_set_pairs(pba_ctx *ctx, int32_t p, const int32_t *src, const int32_t *tgt);
@@ -146,7 +156,8 @@ typedef struct {
 pba_status pba_evaluate(pba_ctx *ctx, pba_eval_out *out);
 
 /* Solve (H + lambda diag H) dx = -b at the current poses (anchor fixed), FP64 Cholesky.
- * dx (6N, nullable) receives the step; it is also kept for pba_apply_step. */
+ * dx (6N, N poses or pose variables, nullable) receives the step; it is also kept for
+ * pba_apply_step. */
 pba_status pba_solve_step(pba_ctx *ctx, double lambda, double *dx, int32_t on_device);
 
 /* X_k <- X_k exp(dx_k) for every pose; dx NULL applies the last solved step. */
@@ -172,7 +183,7 @@ pba_status pba_iterate(pba_ctx *ctx, int32_t n_iters, int32_t use_lm, double lam
 
 /* Photometric loss F(X0 boxplus delta) = sum over pairs and valid pixels of rho(chi^2)
  * (Sec. IV-C, Eq. (total-error-multicue)), with X0 the current poses and delta [N][6] float32
- * per pose [dt, dq] (X0 exp(delta), Supplementary).  Evaluates at X0 boxplus delta and keeps
+ * per pose (or pose variable) [dt, dq] (X0 exp(delta), Supplementary).  Evaluates at X0 boxplus delta and keeps
  * delta for pba_loss_backward.  *F_out (host) receives F, *n_valid_out (host, nullable) the number
  * of valid correspondences.  The poses X0 are not changed. */
 pba_status pba_loss_forward(pba_ctx *ctx, const float *delta, int32_t on_device, double *F_out,

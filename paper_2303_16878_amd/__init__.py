@@ -26,7 +26,7 @@ PBA_PAIR_OUT_LEN = 160
 # names declared in include/pba.h
 ABI_FUNCTIONS = (
     "pba_config_default", "pba_create", "pba_destroy", "pba_add_sensor", "pba_load_keyframes",
-    "pba_set_poses", "pba_get_poses", "pba_set_pairs", "pba_evaluate", "pba_solve_step",
+    "pba_set_poses", "pba_get_poses", "pba_set_pose_groups", "pba_set_pairs", "pba_evaluate", "pba_solve_step",
     "pba_apply_step", "pba_iterate", "pba_loss_forward", "pba_loss_backward", "pba_build_pyramid",
     "pba_set_level", "pba_optimize_pyramid", "pba_get_level_image", "pba_autotune", "pba_build_pairs", "pba_estimate_normals", "pba_debug_pair",
     "pba_get_timings", "pba_status_string", "pba_last_error",
@@ -81,6 +81,13 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError("libpba.so is not built (%s): run __graft_entry__.build() or "
                            "python -m paper_2303_16878_amd.build" % path)
+    # torch ships its own copy of the HIP runtime library; the process must use one runtime for
+    # the tensors it hands over and for this library, so torch (if present) is loaded first and
+    # its runtime then also serves libpba
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     sig = {
@@ -92,6 +99,7 @@ def load_library(path: str = LIB_PATH):
         "pba_set_poses": (i32, [vp, i32, vp, i32]),
         "pba_get_poses": (i32, [vp, vp, i32]),
         "pba_set_pairs": (i32, [vp, i32, vp, vp]),
+        "pba_set_pose_groups": (i32, [vp, vp, i32]),
         "pba_evaluate": (i32, [vp, ctypes.POINTER(pba_eval_out)]),
         "pba_solve_step": (i32, [vp, f64, vp, i32]),
         "pba_apply_step": (i32, [vp, vp, i32]),
@@ -174,6 +182,7 @@ class Context:
         self._check(self.lib.pba_create(ctypes.byref(cfg), ctypes.byref(h)), ctx=None)
         self.h = h
         self.n = 0
+        self.n_poses = 0
         self.p = 0
         self.sensor_sizes = []
         self.kf_sensor = None
@@ -237,18 +246,33 @@ class Context:
             ctypes.cast(ptrs["D"], ctypes.c_void_p),
             ctypes.cast(ptrs["N"], ctypes.c_void_p) if ptrs["N"] is not None else None, int(on_dev or 0)))
         self.n = n
+        self.n_poses = n
         self.kf_sensor = sid.copy()
 
     def set_poses(self, poses):
         p, dev, ka = _ptr(poses, np.float64)
-        self._check(self.lib.pba_set_poses(self.h, self.n, p, dev))
+        self._check(self.lib.pba_set_poses(self.h, self.n_poses, p, dev))
 
     def get_poses(self, out=None):
         if out is None:
-            out = np.empty((self.n, 12), np.float64)
+            out = np.empty((self.n_poses, 12), np.float64)
         p, dev, ka = _ptr(out, np.float64)
         self._check(self.lib.pba_get_poses(self.h, p, dev))
         return out
+
+    def set_pose_groups(self, pose_of=None):
+        """Keyframes sharing pose variables (pose_of[k] = variable of keyframe k); None restores one
+        pose per keyframe.  Poses must be set again afterwards (one per variable)."""
+        if pose_of is None:
+            self._check(self.lib.pba_set_pose_groups(self.h, None, 0))
+            self.n_poses = self.n
+            return
+        g = np.ascontiguousarray(pose_of, np.int32).reshape(-1)
+        if len(g) != self.n:
+            raise ValueError("pose_of needs one entry per keyframe")
+        npv = int(g.max()) + 1 if len(g) else 0
+        self._check(self.lib.pba_set_pose_groups(self.h, g.ctypes.data, npv))
+        self.n_poses = npv
 
     def set_pairs(self, pairs):
         pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
@@ -261,8 +285,8 @@ class Context:
         out = pba_eval_out()
         H = b = po = None
         if want_system:
-            H = np.empty((6 * self.n, 6 * self.n), np.float64)
-            b = np.empty(6 * self.n, np.float64)
+            H = np.empty((6 * self.n_poses, 6 * self.n_poses), np.float64)
+            b = np.empty(6 * self.n_poses, np.float64)
             out.H, out.b = H.ctypes.data, b.ctypes.data
         if want_pairs:
             po = np.empty((self.p, PBA_PAIR_OUT_LEN), np.float64)
@@ -277,7 +301,7 @@ class Context:
         return r
 
     def solve_step(self, lam=0.0):
-        dx = np.empty(6 * self.n, np.float64)
+        dx = np.empty(6 * self.n_poses, np.float64)
         self._check(self.lib.pba_solve_step(self.h, float(lam), dx.ctypes.data, 0))
         return dx
 
@@ -437,6 +461,8 @@ def context_for_problem(prob, precision=PBA_F32, channels=None, grad_mode=0, dev
                        s["max_depth"], s["offset"])
     I, D, N = images if images is not None else (prob.intensity, prob.depth, prob.normals)
     ctx.load_keyframes(prob.kf_sensor, I, D, N if ch == 5 else None)
+    if getattr(prob, "pose_of", None) is not None:
+        ctx.set_pose_groups(prob.pose_of)
     ctx.set_poses(prob.init_poses if poses is None else poses)
     ctx.set_pairs(prob.pairs)
     return ctx
@@ -478,7 +504,7 @@ def _photometric_loss_function():
         def backward(ctx, grad_out):
             pctx = ctx.pctx
             n = pctx.n
-            g_delta = torch.empty((n, 6), dtype=torch.float32, device=ctx.device)
+            g_delta = torch.empty((pctx.n_poses, 6), dtype=torch.float32, device=ctx.device)
             outs = [torch.empty(sh, dtype=torch.float32, device=ctx.device) for sh in ctx.shapes]
             lists = None
             if ctx.n_images:

@@ -63,8 +63,8 @@ __global__ void pair_setup_kernel(const double *__restrict__ poses, const int2 *
     const int s = pairs[p].x, t = pairs[p].y;
     const SensorDev &ss = sensors[kfs[s].sensor];
     const SensorDev &st = sensors[kfs[t].sensor];
-    const double *Rs = poses + 12 * (int64_t)s, *ts = Rs + 9;
-    const double *Rt = poses + 12 * (int64_t)t, *tt = Rt + 9;
+    const double *Rs = poses + 12 * (int64_t)kfs[s].pose, *ts = Rs + 9;
+    const double *Rt = poses + 12 * (int64_t)kfs[t].pose, *tt = Rt + 9;
     // platform-level relative pose X_t^-1 X_s
     double Rp[9], tp[3], d3[3];
     mtm3(Rt, Rs, Rp);

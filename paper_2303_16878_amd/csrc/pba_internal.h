@@ -27,7 +27,8 @@ struct SensorDev {
 };
 
 struct KfDev {
-    int32_t sensor, H, W, pad;
+    int32_t sensor, H, W;
+    int32_t pose;                // pose variable (keyframes of one rig frame share one)
     int64_t off;                 // texel offset of this keyframe in the image arenas
 };
 

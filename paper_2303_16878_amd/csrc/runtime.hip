@@ -50,6 +50,8 @@ struct pba_ctx {
     ImageSet &L() { return lv[level]; }
     std::vector<int32_t> src_h, tgt_h; // the pairs as set
     int N = 0, P = 0;
+    int NP = 0;                       // pose variables (N unless keyframes share rig poses)
+    std::vector<int32_t> pose_of;     // keyframe -> pose variable; empty: one per keyframe
     bool poses_set = false;
     bool system_valid = false;   // H, b, totals[0..3] hold the system at the current poses
     double lam_carry = -1.0;     // LM damping left by the previous pba_iterate call
@@ -153,7 +155,8 @@ bool pose_ok(const double *x)
     return true;
 }
 
-int n_sys(const pba_ctx *c) { return 6 * c->N; }
+int n_sys(const pba_ctx *c) { return 6 * c->NP; }
+int pose_var(const pba_ctx *c, int kf) { return c->pose_of.empty() ? kf : c->pose_of[kf]; }
 
 // texel preparation: sanitise depth (invalid -> 0; the depth test is made in FP64, as the
 // sensor's limits are given) and split into the depth plane and the attribute plane
@@ -235,6 +238,7 @@ pba_status image_layout(pba_ctx *c, ImageSet &is, const std::vector<int32_t> &se
         f.sensor = sensor_of[k];
         f.H = is.sensors[f.sensor].height;
         f.W = is.sensors[f.sensor].width;
+        f.pose = pose_var(c, (int)k);
         f.off = off;
         off += (int64_t)f.H * f.W;
     }
@@ -310,9 +314,10 @@ pba_status build_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::ve
 
     // assembly plan: contributions of each nonzero 6x6 block, in pair order
     std::map<std::pair<int, int>, std::vector<int32_t>> blocks;
-    std::vector<std::vector<int32_t>> bk(c->N);
+    // keyed by pose variable: a pair inside one rig frame adds all four blocks to its diagonal
+    std::vector<std::vector<int32_t>> bk(c->NP);
     for (int p = 0; p < P; ++p) {
-        const int a = src[p], t = tgt[p];
+        const int a = pose_var(c, src[p]), t = pose_var(c, tgt[p]);
         blocks[{a, a}].push_back(4 * p + 0);
         blocks[{a, t}].push_back(4 * p + 1);
         blocks[{t, a}].push_back(4 * p + 2);
@@ -331,7 +336,7 @@ pba_status build_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::ve
     }
     c->nblk = (int)rc.size();
     std::vector<int32_t> bptr(1, 0), bent;
-    for (int k = 0; k < c->N; ++k) {
+    for (int k = 0; k < c->NP; ++k) {
         bent.insert(bent.end(), bk[k].begin(), bk[k].end());
         bptr.push_back((int32_t)bent.size());
     }
@@ -393,7 +398,7 @@ pba_status run_eval(pba_ctx *c, const double *poses, double *H, double *b, doubl
     launch_reduce_pairs(c->partials.p, c->cfg.precision, P_<int32_t>(c->pitems), P_<int32_t>(c->ibeg),
                         P_<int32_t>(c->icnt), P_<PairDev>(c->pair_dev), P_<double>(c->pair_out), c->P, st);
     launch_assemble(P_<double>(c->pair_out), c->P, P_<int2>(c->blk_rc), P_<int32_t>(c->blk_ptr),
-                    P_<int32_t>(c->blk_ent), c->nblk, P_<int32_t>(c->bk_ptr), P_<int32_t>(c->bk_ent), c->N, H, b,
+                    P_<int32_t>(c->blk_ent), c->nblk, P_<int32_t>(c->bk_ptr), P_<int32_t>(c->bk_ent), c->NP, H, b,
                     totals, st);
     HIP_OK(hipGetLastError());
     return PBA_OK;
@@ -412,19 +417,19 @@ void drop_graph(pba_ctx *c)
 // evaluation at the candidate, device-side accept/reject.  Identical launches every iteration.
 pba_status enqueue_iteration(pba_ctx *c, hipStream_t st)
 {
-    const int n = 6 * c->N;
+    const int n = n_sys(c);
     double *totals = P_<double>(c->totals);   // [0..3] current, [4..7] candidate
     launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
                      P_<LmState>(c->lm), -1.0, st);
     launch_cholesky(P_<double>(c->A), n, P_<double>(c->Winv), P_<int32_t>(c->fail), st);
     launch_chol_solve(P_<double>(c->A), P_<double>(c->Winv), P_<double>(c->dx), n, P_<int32_t>(c->fail), st);
-    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->N, P_<int32_t>(c->fail),
+    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->NP, P_<int32_t>(c->fail),
                    P_<LmState>(c->lm), st);
     pba_status s = run_eval(c, P_<double>(c->poses_cand), P_<double>(c->H_cand), P_<double>(c->b_cand), totals + 4,
                             false, st, true);
     if (s) return s;
     launch_lm_decide(P_<LmState>(c->lm), totals + 4, (int64_t)n * n, P_<double>(c->H), P_<double>(c->H_cand),
-                     P_<double>(c->b), P_<double>(c->b_cand), P_<double>(c->poses), P_<double>(c->poses_cand), c->N,
+                     P_<double>(c->b), P_<double>(c->b_cand), P_<double>(c->poses), P_<double>(c->poses_cand), c->NP,
                      totals, P_<double>(c->logbuf), c->log_cap, st);
     HIP_OK(hipGetLastError());
     return PBA_OK;
@@ -611,6 +616,7 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
     ImageSet &is = c->lv[0];
     is.sensors = c->sensors;
     if ((s = sensor_tables(c, is))) return s;
+    if (!same_layout) c->pose_of.clear();   // a new keyframe set starts with one pose per keyframe
     if ((s = image_layout(c, is, sensor_of))) return s;
     const std::vector<KfDev> &kfs = is.kfs_h;
     // stage each keyframe on the device (copy if host) and pack
@@ -647,6 +653,7 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
         return PBA_OK;
     }
     c->N = n;
+    c->NP = n;
     c->P = 0;
     c->poses_set = false;
     if ((s = ensure(c, c->poses, (size_t)n * 12 * 8))) return s;
@@ -658,7 +665,7 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
 pba_status pba_set_poses(pba_ctx *c, int32_t n, const double *poses, int32_t on_device)
 {
     if (!c || !poses) return fail(c, PBA_EINVAL, "null argument");
-    if (n != c->N || n == 0) return fail(c, PBA_EINVAL, "expected %d poses, got %d", c->N, n);
+    if (n != c->NP || n == 0) return fail(c, PBA_EINVAL, "expected %d poses, got %d", c->NP, n);
     std::vector<double> h((size_t)n * 12);
     HIP_OK(hipSetDevice(c->cfg.device));
     if (on_device) {
@@ -683,8 +690,48 @@ pba_status pba_get_poses(pba_ctx *c, double *poses, int32_t on_device)
     if (!c || !poses) return fail(c, PBA_EINVAL, "null argument");
     if (!c->poses_set) return fail(c, PBA_ESTATE, "poses not set");
     HIP_OK(hipSetDevice(c->cfg.device));
-    HIP_OK(hipMemcpyAsync(poses, c->poses.p, (size_t)c->N * 96, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+    HIP_OK(hipMemcpyAsync(poses, c->poses.p, (size_t)c->NP * 96, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                           c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return PBA_OK;
+}
+
+pba_status pba_set_pose_groups(pba_ctx *c, const int32_t *pose_of, int32_t n_poses)
+{
+    if (!c) return PBA_EINVAL;
+    if (c->N == 0) return fail(c, PBA_ESTATE, "no keyframes loaded");
+    std::vector<int32_t> g;
+    int np = c->N;
+    if (pose_of) {
+        if (n_poses < 1 || n_poses > c->N) return fail(c, PBA_EINVAL, "n_poses %d not in 1..%d", n_poses, c->N);
+        g.assign(pose_of, pose_of + c->N);
+        std::vector<char> used(n_poses, 0);
+        for (int k = 0; k < c->N; ++k) {
+            if (g[k] < 0 || g[k] >= n_poses) return fail(c, PBA_EINVAL, "keyframe %d: pose variable %d out of range", k, g[k]);
+            used[g[k]] = 1;
+        }
+        for (int v = 0; v < n_poses; ++v)
+            if (!used[v]) return fail(c, PBA_EINVAL, "pose variable %d has no keyframe", v);
+        np = n_poses;
+    }
+    if (c->cfg.anchor >= np) return fail(c, PBA_EINVAL, "anchor %d >= number of pose variables %d", c->cfg.anchor, np);
+    HIP_OK(hipSetDevice(c->cfg.device));
+    c->pose_of = g;
+    c->NP = np;
+    pba_status s;
+    for (ImageSet &is : c->lv) {
+        for (int k = 0; k < c->N; ++k) is.kfs_h[k].pose = pose_var(c, k);
+        if ((s = upload(c, is.kfs_d, is.kfs_h.data(), is.kfs_h.size() * sizeof(KfDev)))) return s;
+    }
+    drop_graph(c);
+    c->poses_set = false;
+    c->system_valid = false;
+    c->loss_ready = false;
+    c->lam_carry = -1.0;
+    if (c->P > 0) {
+        if ((s = build_plan(c, c->src_h, c->tgt_h))) return s;
+        if ((s = ensure_system(c))) return s;
+    }
     HIP_OK(hipStreamSynchronize(c->stream));
     return PBA_OK;
 }
@@ -785,9 +832,9 @@ pba_status pba_apply_step(pba_ctx *c, const double *dx, int32_t on_device)
             if (!std::isfinite(v)) return fail(c, PBA_EINVAL, "non-finite step");
         if ((s = upload(c, c->dx, h.data(), (size_t)n * 8))) return s;
     }
-    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->N, nullptr, nullptr,
+    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->NP, nullptr, nullptr,
                    c->stream);
-    launch_copy(P_<double>(c->poses), P_<double>(c->poses_cand), (int64_t)c->N * 12, c->stream);
+    launch_copy(P_<double>(c->poses), P_<double>(c->poses_cand), (int64_t)c->NP * 12, c->stream);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(c->stream));
     c->system_valid = false;
@@ -886,7 +933,7 @@ pba_status pba_loss_forward(pba_ctx *c, const float *delta, int32_t on_device, d
     pba_status s;
     if ((s = check_ready(c))) return s;
     HIP_OK(hipSetDevice(c->cfg.device));
-    const int N = c->N;
+    const int N = c->NP;   // pose variables
     if ((s = ensure(c, c->loss_delta, (size_t)N * 6 * 4))) return s;
     if ((s = ensure(c, c->loss_poses, (size_t)N * 12 * 8))) return s;
     if (on_device) {
@@ -922,7 +969,7 @@ pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float
     if ((s = check_ready(c))) return s;
     if (!c->loss_ready) return fail(c, PBA_ESTATE, "pba_loss_backward needs a preceding pba_loss_forward");
     HIP_OK(hipSetDevice(c->cfg.device));
-    const int N = c->N;
+    const int N = c->NP;   // pose variables
     const int64_t tx = c->L().texels;
     const bool five = c->cfg.channels == 5;
     if ((s = ensure(c, c->g_int, (size_t)tx * 4))) return s;
@@ -1026,9 +1073,12 @@ pba_status pba_build_pairs(pba_ctx *c, double max_angle, double max_dist, double
     if (!c->poses_set) return fail(c, PBA_ESTATE, "poses not set");
     HIP_OK(hipSetDevice(c->cfg.device));
     const int N = c->N;
-    std::vector<double> X((size_t)N * 12);
-    HIP_OK(hipMemcpyAsync(X.data(), c->poses.p, X.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> Xv((size_t)c->NP * 12), X((size_t)N * 12);
+    HIP_OK(hipMemcpyAsync(Xv.data(), c->poses.p, Xv.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < N; ++k)   // keyframe (platform) poses
+        std::copy(Xv.begin() + 12 * (size_t)pose_var(c, k), Xv.begin() + 12 * (size_t)pose_var(c, k) + 12,
+                  X.begin() + 12 * (size_t)k);
     // pose tests on the host; the candidates (and sequential links) are then evaluated together
     std::vector<int32_t> cs, ct;
     std::vector<char> close, seq;
