@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <vector>
 
 namespace pba {
 
@@ -97,7 +98,15 @@ struct LmState {
 };
 void launch_damp_copy(const double *H, const double *b, double *A, double *rhs, int n, int anchor,
                       const LmState *lm, double lam_override, hipStream_t st);
-void launch_cholesky(double *A, int n, double *Winv, int32_t *fail, hipStream_t st);
+// Tiles of the Cholesky factor that can be nonzero (host-built from the pair graph with the
+// factorisation's symbolic fill): for block column k, rcnt[k] tile rows i > k at rows + rbeg[k]
+// (device, ascending); for block row k, ccnt[k] tile columns j < k at cols + cbeg[k] (device).
+// The panel, trailing update and triangular solves touch only these tiles.
+struct CholPlan {
+    const int32_t *rows = nullptr, *cols = nullptr;
+    std::vector<int> rbeg, rcnt, cbeg, ccnt;
+};
+void launch_cholesky(double *A, int n, double *Winv, const CholPlan &plan, int32_t *fail, hipStream_t st);
 void launch_downsample(const float *dep, const float4 *att4, const float *att1, int H, int W, float *dep2,
                        float4 *att4_2, float *att1_2, int H2, int W2, double tau, hipStream_t st);
 void launch_unpack(const float *dep, const float4 *att4, const float *att1, int npx, float *I, float *D, float *N,
@@ -106,7 +115,8 @@ void launch_normals(const float *dep, float4 *att4, int H, int W, const double2 
                     int spherical, double scale, double min_px, double max_px, double tau, int min_count,
                     hipStream_t st);
 // Winv: the inverted diagonal blocks followed by n doubles of workspace.
-void launch_chol_solve(const double *L, double *Winv, double *x, int n, const int32_t *fail, hipStream_t st);
+void launch_chol_solve(const double *L, double *Winv, double *x, int n, const CholPlan &plan, const int32_t *fail,
+                       hipStream_t st);
 void launch_boxplus(const double *X, const double *dx, double *Xout, int N, const int32_t *fail,
                     LmState *lm, hipStream_t st);
 void launch_stamp(const LmState *lm, double *logbuf, int log_cap, int which, hipStream_t st);

@@ -67,6 +67,8 @@ struct pba_ctx {
     // device buffers
     DevBuf poses, poses_cand, pairs_d, pair_dev, item_pair, item_px0, pitems, ibeg, icnt, counters, partials, pair_out;
     DevBuf blk_rc, blk_ptr, blk_ent, bk_ptr, bk_ent;
+    DevBuf chol_rows, chol_cols;
+    CholPlan chol;   // tiles of the Cholesky factor that can be nonzero
     DevBuf H, b, H_cand, b_cand, totals, A, Winv, dx, lm, fail, logbuf;
     DevBuf dbg_status, dbg_uv, dbg_cell, dbg_res;
     DevBuf loss_delta, loss_poses, g_int, g_dep, g_nrm, g_pose;
@@ -250,6 +252,67 @@ pba_status image_layout(pba_ctx *c, ImageSet &is, const std::vector<int32_t> &se
     return ensure(c, is.att1, off * sizeof(float));
 }
 
+// Tiles (64 x 64) of the Cholesky factor of the 6 NP x 6 NP system that can be nonzero: those
+// holding part of a pose variable's own 6 x 6 block or of a pair's coupling block, and those the
+// factorisation fills (tile (i, j), i >= j, once tiles (i, k) and (j, k) are nonzero for some
+// k < j).  The damped, gauge-fixed matrix has no nonzero outside this pattern, so the panel,
+// trailing update and triangular solves may skip every other tile.
+void drop_graph(pba_ctx *c);
+
+// (A captured iteration holds the list pointers and launch counts, so it is dropped.)
+pba_status build_chol_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt)
+{
+    drop_graph(c);
+    const int nt = (n_sys(c) + 63) / 64;
+    std::vector<char> occ((size_t)nt * nt, 0);   // lower triangle: occ[i * nt + j], i >= j
+    auto mark = [&](int a, int b) {
+        const int ta[2] = {6 * a / 64, (6 * a + 5) / 64}, tb[2] = {6 * b / 64, (6 * b + 5) / 64};
+        for (int x : ta)
+            for (int y : tb) occ[(size_t)std::max(x, y) * nt + std::min(x, y)] = 1;
+    };
+    for (int v = 0; v < c->NP; ++v) mark(v, v);
+    for (size_t p = 0; p < src.size(); ++p) mark(pose_var(c, src[p]), pose_var(c, tgt[p]));
+    for (int k = 0; k < nt; ++k) occ[(size_t)k * nt + k] = 1;
+    std::vector<int32_t> rows, cols;
+    CholPlan &pl = c->chol;
+    pl.rbeg.assign(nt, 0);
+    pl.rcnt.assign(nt, 0);
+    pl.cbeg.assign(nt, 0);
+    pl.ccnt.assign(nt, 0);
+    for (int k = 0; k < nt; ++k) {
+        pl.rbeg[k] = (int)rows.size();
+        for (int i = k + 1; i < nt; ++i)
+            if (occ[(size_t)i * nt + k]) rows.push_back(i);
+        pl.rcnt[k] = (int)rows.size() - pl.rbeg[k];
+        // symbolic fill of this column's update
+        for (int a = pl.rbeg[k]; a < (int)rows.size(); ++a)
+            for (int b = pl.rbeg[k]; b <= a; ++b) occ[(size_t)rows[a] * nt + rows[b]] = 1;
+    }
+    for (int k = 0; k < nt; ++k) {
+        pl.cbeg[k] = (int)cols.size();
+        for (int j = 0; j < k; ++j)
+            if (occ[(size_t)k * nt + j]) cols.push_back(j);
+        pl.ccnt[k] = (int)cols.size() - pl.cbeg[k];
+    }
+    rows.push_back(0);   // keep the device arrays non-empty
+    cols.push_back(0);
+    pba_status s;
+    if ((s = upload(c, c->chol_rows, rows.data(), rows.size() * 4))) return s;
+    if ((s = upload(c, c->chol_cols, cols.data(), cols.size() * 4))) return s;
+    pl.rows = P_<int32_t>(c->chol_rows);
+    pl.cols = P_<int32_t>(c->chol_cols);
+    return PBA_OK;
+}
+
+// The plan is dropped whenever the keyframes, the pose variables or the pairs change; rebuilt here
+// from the pairs as set (none before any are set).
+pba_status ensure_chol_plan(pba_ctx *c)
+{
+    if (c->chol.rows && (int)c->chol.rcnt.size() == (n_sys(c) + 63) / 64) return PBA_OK;
+    const std::vector<int32_t> none;
+    return c->P > 0 ? build_chol_plan(c, c->src_h, c->tgt_h) : build_chol_plan(c, none, none);
+}
+
 pba_status build_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt)
 {
     const int P = (int)src.size();
@@ -346,7 +409,7 @@ pba_status build_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::ve
     if ((s = upload(c, c->bk_ptr, bptr.data(), bptr.size() * 4))) return s;
     if ((s = upload(c, c->bk_ent, bent.data(), bent.size() * 4))) return s;
     if ((s = ensure(c, c->counters, 64 * 4))) return s;
-    return PBA_OK;
+    return build_chol_plan(c, src, tgt);
 }
 
 EvalArgs make_args(pba_ctx *c)
@@ -421,8 +484,8 @@ pba_status enqueue_iteration(pba_ctx *c, hipStream_t st)
     double *totals = P_<double>(c->totals);   // [0..3] current, [4..7] candidate
     launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
                      P_<LmState>(c->lm), -1.0, st);
-    launch_cholesky(P_<double>(c->A), n, P_<double>(c->Winv), P_<int32_t>(c->fail), st);
-    launch_chol_solve(P_<double>(c->A), P_<double>(c->Winv), P_<double>(c->dx), n, P_<int32_t>(c->fail), st);
+    launch_cholesky(P_<double>(c->A), n, P_<double>(c->Winv), c->chol, P_<int32_t>(c->fail), st);
+    launch_chol_solve(P_<double>(c->A), P_<double>(c->Winv), P_<double>(c->dx), n, c->chol, P_<int32_t>(c->fail), st);
     launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->NP, P_<int32_t>(c->fail),
                    P_<LmState>(c->lm), st);
     pba_status s = run_eval(c, P_<double>(c->poses_cand), P_<double>(c->H_cand), P_<double>(c->b_cand), totals + 4,
@@ -556,7 +619,8 @@ pba_status pba_destroy(pba_ctx *c)
                       &c->counters, &c->partials, &c->pair_out, &c->blk_rc, &c->blk_ptr, &c->blk_ent, &c->bk_ptr,
                       &c->bk_ent, &c->H, &c->b, &c->H_cand, &c->b_cand, &c->totals, &c->A, &c->Winv, &c->dx, &c->lm,
                       &c->fail, &c->logbuf, &c->dbg_status, &c->dbg_uv, &c->dbg_cell, &c->dbg_res,
-                      &c->loss_delta, &c->loss_poses, &c->g_int, &c->g_dep, &c->g_nrm, &c->g_pose};
+                      &c->loss_delta, &c->loss_poses, &c->g_int, &c->g_dep, &c->g_nrm, &c->g_pose,
+                      &c->chol_rows, &c->chol_cols};
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) release(*b);
@@ -655,6 +719,7 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
     c->N = n;
     c->NP = n;
     c->P = 0;
+    c->chol.rows = nullptr;
     c->poses_set = false;
     if ((s = ensure(c, c->poses, (size_t)n * 12 * 8))) return s;
     if ((s = ensure(c, c->poses_cand, (size_t)n * 12 * 8))) return s;
@@ -718,6 +783,7 @@ pba_status pba_set_pose_groups(pba_ctx *c, const int32_t *pose_of, int32_t n_pos
     HIP_OK(hipSetDevice(c->cfg.device));
     c->pose_of = g;
     c->NP = np;
+    c->chol.rows = nullptr;
     pba_status s;
     for (ImageSet &is : c->lv) {
         for (int k = 0; k < c->N; ++k) is.kfs_h[k].pose = pose_var(c, k);
@@ -792,6 +858,7 @@ pba_status pba_solve_step(pba_ctx *c, double lambda, double *dx, int32_t on_devi
     pba_status s;
     if ((s = check_ready(c))) return s;
     HIP_OK(hipSetDevice(c->cfg.device));
+    if ((s = ensure_chol_plan(c))) return s;
     const int n = n_sys(c);
     if (!c->system_valid) {
         if ((s = run_eval(c, P_<double>(c->poses), P_<double>(c->H), P_<double>(c->b), P_<double>(c->totals),
@@ -801,8 +868,9 @@ pba_status pba_solve_step(pba_ctx *c, double lambda, double *dx, int32_t on_devi
     }
     launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
                      P_<LmState>(c->lm), lambda, c->stream);
-    launch_cholesky(P_<double>(c->A), n, P_<double>(c->Winv), P_<int32_t>(c->fail), c->stream);
-    launch_chol_solve(P_<double>(c->A), P_<double>(c->Winv), P_<double>(c->dx), n, P_<int32_t>(c->fail), c->stream);
+    launch_cholesky(P_<double>(c->A), n, P_<double>(c->Winv), c->chol, P_<int32_t>(c->fail), c->stream);
+    launch_chol_solve(P_<double>(c->A), P_<double>(c->Winv), P_<double>(c->dx), n, c->chol, P_<int32_t>(c->fail),
+                      c->stream);
     HIP_OK(hipGetLastError());
     int32_t f = 0;
     HIP_OK(hipMemcpyAsync(&f, c->fail.p, 4, hipMemcpyDeviceToHost, c->stream));
@@ -851,6 +919,7 @@ pba_status pba_iterate(pba_ctx *c, int32_t n_iters, int32_t use_lm, double lambd
     if ((s = check_ready(c))) return s;
     if (n_iters == 0) return PBA_OK;
     HIP_OK(hipSetDevice(c->cfg.device));
+    if ((s = ensure_chol_plan(c))) return s;
     if (n_iters > c->log_cap) {
         const int cap = std::max(n_iters, 64);
         release(c->logbuf);

@@ -6,6 +6,8 @@
 
 #include "pba_internal.h"
 
+#include <algorithm>
+
 namespace pba {
 
 constexpr int NB = 64;   // Cholesky block size
@@ -153,13 +155,13 @@ __global__ void __launch_bounds__(256) chol_diag_kernel(double *A, int n, int k0
 
 // Panel below the diagonal block: X = B W^T for 64 rows per workgroup (16 x 16 threads, 4 x 4 each).
 __global__ void __launch_bounds__(256) chol_trsm_kernel(double *A, int n, int k0, const double *Winv,
-                                                        const int32_t *fail)
+                                                        const int32_t *__restrict__ tiles, const int32_t *fail)
 {
     __shared__ double Bs[NB][NB + 1];
     __shared__ double Ws[NB][NB + 1];
     if (*fail) return;
     const int nb = min(NB, n - k0);
-    const int r0 = k0 + nb + blockIdx.x * NB;
+    const int r0 = tiles[blockIdx.x] * NB;   // a tile row below the diagonal block
     const int rows = min(NB, n - r0);
     const int tid = threadIdx.x;
     const double *Wb = Winv + (int64_t)(k0 / NB) * NB * NB;
@@ -188,20 +190,20 @@ __global__ void __launch_bounds__(256) chol_trsm_kernel(double *A, int n, int k0
 }
 
 // Trailing update A_ij -= L_i L_j^T for block pairs i >= j below the panel.
-__global__ void __launch_bounds__(256) chol_update_kernel(double *A, int n, int k0, const int32_t *fail)
+__global__ void __launch_bounds__(256) chol_update_kernel(double *A, int n, int k0, const int32_t *__restrict__ tiles,
+                                                          const int32_t *fail)
 {
     __shared__ double Li[NB][NB + 1];
     __shared__ double Lj[NB][NB + 1];
     if (*fail) return;
     const int nb = min(NB, n - k0);
-    const int t0 = k0 + nb;
-    // blockIdx.x -> (bi, bj) with bi >= bj over the trailing blocks
+    // blockIdx.x -> (bi, bj) with bi >= bj over the panel's tile rows
     const int idx = blockIdx.x;
     int bi = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
     while ((bi + 1) * (bi + 2) / 2 <= idx) ++bi;
     while (bi * (bi + 1) / 2 > idx) --bi;
     const int bj = idx - bi * (bi + 1) / 2;
-    const int ri = t0 + bi * NB, rj = t0 + bj * NB;
+    const int ri = tiles[bi] * NB, rj = tiles[bj] * NB;
     const int ni = min(NB, n - ri), nj = min(NB, n - rj);
     const int tid = threadIdx.x;
     for (int e = tid; e < NB * NB; e += blockDim.x) {
@@ -230,16 +232,18 @@ __global__ void __launch_bounds__(256) chol_update_kernel(double *A, int n, int 
 
 __global__ void reset_flag_kernel(int32_t *f) { *f = 0; }
 
-void launch_cholesky(double *A, int n, double *Winv, int32_t *fail, hipStream_t st)
+void launch_cholesky(double *A, int n, double *Winv, const CholPlan &plan, int32_t *fail, hipStream_t st)
 {
     hipLaunchKernelGGL(reset_flag_kernel, dim3(1), dim3(1), 0, st, fail);
-    for (int k0 = 0; k0 < n; k0 += NB) {
+    const int nblk = (n + NB - 1) / NB;
+    for (int kb = 0; kb < nblk; ++kb) {
+        const int k0 = kb * NB;
         hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, A, n, k0, Winv, fail);
-        const int rest = n - k0 - NB;
-        if (rest > 0) {
-            const int nbr = (rest + NB - 1) / NB;
-            hipLaunchKernelGGL(chol_trsm_kernel, dim3(nbr), dim3(256), 0, st, A, n, k0, Winv, fail);
-            hipLaunchKernelGGL(chol_update_kernel, dim3(nbr * (nbr + 1) / 2), dim3(256), 0, st, A, n, k0, fail);
+        const int m = plan.rcnt[kb];
+        if (m > 0) {
+            const int32_t *tiles = plan.rows + plan.rbeg[kb];
+            hipLaunchKernelGGL(chol_trsm_kernel, dim3(m), dim3(256), 0, st, A, n, k0, Winv, tiles, fail);
+            hipLaunchKernelGGL(chol_update_kernel, dim3(m * (m + 1) / 2), dim3(256), 0, st, A, n, k0, tiles, fail);
         }
     }
 }
@@ -250,10 +254,11 @@ void launch_cholesky(double *A, int n, double *Winv, int32_t *fail, hipStream_t 
 // (zero if the factorisation failed).
 
 // Forward block kb: y_k = W_kk r_k, then r_i -= L_ik y_k for the rows below.  Workgroup g owns
-// the 64 rows starting at k0 + nb + 64 g; every workgroup forms y_k itself (r_k is not written in
-// this launch), workgroup 0 stores it.
+// the 64 rows of the g-th tile row in the block column's list; every workgroup forms y_k itself
+// (r_k is not written in this launch), workgroup 0 stores it.
 __global__ void __launch_bounds__(256) trsv_fwd_kernel(const double *__restrict__ L, const double *__restrict__ Winv,
                                                        double *__restrict__ r, double *__restrict__ y, int n, int kb,
+                                                       const int32_t *__restrict__ tiles, int ntiles,
                                                        const int32_t *fail)
 {
     __shared__ double sy[NB];
@@ -269,7 +274,8 @@ __global__ void __launch_bounds__(256) trsv_fwd_kernel(const double *__restrict_
     if (part == 0) sy[row] = s;
     __syncthreads();
     if (blockIdx.x == 0 && tid < nb) y[k0 + tid] = sy[tid];
-    const int i = k0 + nb + blockIdx.x * NB + row;
+    // the tile row this workgroup updates (none when block kb couples to no row below it)
+    const int i = (ntiles > 0 ? tiles[blockIdx.x] * NB : n) + row;
     double u = 0.0;
     if (i < n) {
         const double *Lr = L + (int64_t)i * n + k0;
@@ -282,9 +288,11 @@ __global__ void __launch_bounds__(256) trsv_fwd_kernel(const double *__restrict_
 }
 
 // Backward block kb: x_k = W_kk^T s_k, then s_i -= sum_c L[k0 + c][i] x_k[c] for the columns
-// i < k0.  Workgroup g owns columns 64 g .. 64 g + 63; workgroup 0 stores x_k.
+// i < k0.  Workgroup g owns the 64 columns of the g-th tile in the block row's list; workgroup 0
+// stores x_k.
 __global__ void __launch_bounds__(256) trsv_bwd_kernel(const double *__restrict__ L, const double *__restrict__ Winv,
                                                        double *__restrict__ s, double *__restrict__ x, int n, int kb,
+                                                       const int32_t *__restrict__ tiles, int ntiles,
                                                        const int32_t *fail)
 {
     __shared__ double sx[NB];
@@ -304,7 +312,8 @@ __global__ void __launch_bounds__(256) trsv_bwd_kernel(const double *__restrict_
     if (tid < NB) sx[tid] = part_s[0][tid] + part_s[1][tid] + part_s[2][tid] + part_s[3][tid];
     __syncthreads();
     if (blockIdx.x == 0 && tid < nb) x[k0 + tid] = sx[tid];
-    const int i = blockIdx.x * NB + lane;
+    // the tile column this workgroup updates (none when block row kb couples to no column left of it)
+    const int i = (ntiles > 0 ? tiles[blockIdx.x] * NB : k0) + lane;
     double u = 0.0;
     if (i < k0) {
 #pragma unroll
@@ -322,18 +331,20 @@ __global__ void zero_on_fail_kernel(double *x, int n, const int32_t *fail)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = 0.0;
 }
 
-void launch_chol_solve(const double *L, double *Winv, double *x, int n, const int32_t *fail, hipStream_t st)
+void launch_chol_solve(const double *L, double *Winv, double *x, int n, const CholPlan &plan, const int32_t *fail,
+                       hipStream_t st)
 {
     const int nblk = (n + NB - 1) / NB;
     double *y = Winv + (int64_t)nblk * NB * NB;
     for (int kb = 0; kb < nblk; ++kb) {
-        const int below = n - (kb * NB + NB);
-        const int grid = below > 0 ? (below + NB - 1) / NB : 1;
-        hipLaunchKernelGGL(trsv_fwd_kernel, dim3(grid), dim3(256), 0, st, L, Winv, x, y, n, kb, fail);
+        const int m = plan.rcnt[kb];
+        hipLaunchKernelGGL(trsv_fwd_kernel, dim3(std::max(m, 1)), dim3(256), 0, st, L, Winv, x, y, n, kb,
+                           plan.rows + plan.rbeg[kb], m, fail);
     }
     for (int kb = nblk - 1; kb >= 0; --kb) {
-        const int grid = kb > 0 ? kb : 1;
-        hipLaunchKernelGGL(trsv_bwd_kernel, dim3(grid), dim3(256), 0, st, L, Winv, y, x, n, kb, fail);
+        const int m = plan.ccnt[kb];
+        hipLaunchKernelGGL(trsv_bwd_kernel, dim3(std::max(m, 1)), dim3(256), 0, st, L, Winv, y, x, n, kb,
+                           plan.cols + plan.cbeg[kb], m, fail);
     }
     hipLaunchKernelGGL(zero_on_fail_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, n, fail);
 }
