@@ -1105,25 +1105,31 @@ __global__ void __launch_bounds__(64) assemble_H_kernel(const double *__restrict
     H[(int64_t)(6 * rc.x + i) * n + 6 * rc.y + j] = s;
 }
 
-// b per keyframe (bk_ent = 2 * pair + side, side 0 = source, 1 = target) and the totals
-// F, evaluated, valid (and the reserved slot) summed over pairs in order (one workgroup).
+// b per pose variable (bk_ent = 2 * pair + side, side 0 = source, 1 = target), one thread per
+// entry of b in the workgroups before the last, and the totals F, evaluated, valid (and the
+// reserved slot) summed over pairs in the last workgroup; every sum runs in a fixed order.
 __global__ void __launch_bounds__(256) assemble_b_kernel(const double *__restrict__ pair_out, int P,
                                                          const int32_t *__restrict__ bk_ptr,
                                                          const int32_t *__restrict__ bk_ent, int N,
                                                          double *__restrict__ b, double *__restrict__ totals)
 {
     const int tid = threadIdx.x;
-    for (int r = tid; r < 6 * N; r += blockDim.x) {
+    if (blockIdx.x + 1 < gridDim.x) {
+        const int r = blockIdx.x * blockDim.x + tid;
+        if (r >= 6 * N) return;
         const int k = r / 6, j = r % 6;
         double s = 0.0;
+#pragma unroll 4
         for (int e = bk_ptr[k]; e < bk_ptr[k + 1]; ++e) {
             const int ent = bk_ent[e];
             s += pair_out[(int64_t)(ent >> 1) * kPairOut + 144 + 6 * (ent & 1) + j];
         }
         b[r] = s;
+        return;
     }
     __shared__ double red[4][256];
     double acc[4] = {0, 0, 0, 0};
+#pragma unroll 4
     for (int p = tid; p < P; p += blockDim.x)
         for (int k = 0; k < 4; ++k) acc[k] += pair_out[(int64_t)p * kPairOut + 156 + k];
     for (int k = 0; k < 4; ++k) red[k][tid] = acc[k];
@@ -1144,7 +1150,8 @@ void launch_assemble(const double *pair_out, int P, const int2 *blk_rc, const in
     launch_fill(H, (int64_t)n * n, 0.0, st);
     if (nblk > 0)
         hipLaunchKernelGGL(assemble_H_kernel, dim3(nblk), dim3(64), 0, st, pair_out, blk_rc, blk_ptr, blk_ent, n, H);
-    hipLaunchKernelGGL(assemble_b_kernel, dim3(1), dim3(256), 0, st, pair_out, P, bk_ptr, bk_ent, N, b, totals);
+    hipLaunchKernelGGL(assemble_b_kernel, dim3((6 * N + 255) / 256 + 1), dim3(256), 0, st, pair_out, P, bk_ptr, bk_ent,
+                       N, b, totals);
 }
 
 void launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);

@@ -101,12 +101,20 @@ void launch_damp_copy(const double *H, const double *b, double *A, double *rhs, 
 // Tiles of the Cholesky factor that can be nonzero (host-built from the pair graph with the
 // factorisation's symbolic fill): for block column k, rcnt[k] tile rows i > k at rows + rbeg[k]
 // (device, ascending); for block row k, ccnt[k] tile columns j < k at cols + cbeg[k] (device).
+// meta holds rbeg, rcnt, cbeg, ccnt on the device (nblk ints each, in that order), then for each
+// block column its first kCholPre tile rows and for each block row its first kCholPre tile
+// columns (-1 where there are fewer).
 // The panel, trailing update and triangular solves touch only these tiles.
+constexpr int kCholPre = 4;
 struct CholPlan {
-    const int32_t *rows = nullptr, *cols = nullptr;
+    const int32_t *rows = nullptr, *cols = nullptr, *meta = nullptr;
     std::vector<int> rbeg, rcnt, cbeg, ccnt;
 };
-void launch_cholesky(double *A, int n, double *Winv, const CholPlan &plan, int32_t *fail, hipStream_t st);
+// A (n x n, lower triangle used) is overwritten; the factor's panel tiles go to L and, transposed,
+// to LT (n x n each), the inverted diagonal blocks W and their transposes to Winv (2 nblk blocks of
+// 64 x 64: all W, then all W^T).
+void launch_cholesky(double *A, double *L, double *LT, int n, double *Winv, const CholPlan &plan, int32_t *fail,
+                     hipStream_t st);
 void launch_downsample(const float *dep, const float4 *att4, const float *att1, int H, int W, float *dep2,
                        float4 *att4_2, float *att1_2, int H2, int W2, double tau, hipStream_t st);
 void launch_unpack(const float *dep, const float4 *att4, const float *att1, int npx, float *I, float *D, float *N,
@@ -114,9 +122,9 @@ void launch_unpack(const float *dep, const float4 *att4, const float *att1, int 
 void launch_normals(const float *dep, float4 *att4, int H, int W, const double2 *lcol, const double2 *lrow,
                     int spherical, double scale, double min_px, double max_px, double tau, int min_count,
                     hipStream_t st);
-// Winv: the inverted diagonal blocks followed by n doubles of workspace.
-void launch_chol_solve(const double *L, double *Winv, double *x, int n, const CholPlan &plan, const int32_t *fail,
-                       hipStream_t st);
+// Solves L L^T x = x in place with the factor as launch_cholesky leaves it.
+void launch_chol_solve(const double *L, const double *LT, double *Winv, double *x, int n, const CholPlan &plan,
+                       const int32_t *fail, hipStream_t st);
 void launch_boxplus(const double *X, const double *dx, double *Xout, int N, const int32_t *fail,
                     LmState *lm, hipStream_t st);
 void launch_stamp(const LmState *lm, double *logbuf, int log_cap, int which, hipStream_t st);

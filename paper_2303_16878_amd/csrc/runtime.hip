@@ -67,7 +67,7 @@ struct pba_ctx {
     // device buffers
     DevBuf poses, poses_cand, pairs_d, pair_dev, item_pair, item_px0, pitems, ibeg, icnt, counters, partials, pair_out;
     DevBuf blk_rc, blk_ptr, blk_ent, bk_ptr, bk_ent;
-    DevBuf chol_rows, chol_cols;
+    DevBuf chol_rows, chol_cols, chol_meta;
     CholPlan chol;   // tiles of the Cholesky factor that can be nonzero
     DevBuf H, b, H_cand, b_cand, totals, A, Winv, dx, lm, fail, logbuf;
     DevBuf dbg_status, dbg_uv, dbg_cell, dbg_res;
@@ -299,8 +299,18 @@ pba_status build_chol_plan(pba_ctx *c, const std::vector<int32_t> &src, const st
     pba_status s;
     if ((s = upload(c, c->chol_rows, rows.data(), rows.size() * 4))) return s;
     if ((s = upload(c, c->chol_cols, cols.data(), cols.size() * 4))) return s;
+    std::vector<int32_t> meta;
+    for (const std::vector<int> *v : {&pl.rbeg, &pl.rcnt, &pl.cbeg, &pl.ccnt}) meta.insert(meta.end(), v->begin(), v->end());
+    // the first kCholPre tile rows of each block column, then the first tile columns of each block
+    // row, -1 padded
+    for (int k = 0; k < nt; ++k)
+        for (int e = 0; e < kCholPre; ++e) meta.push_back(e < pl.rcnt[k] ? rows[pl.rbeg[k] + e] : -1);
+    for (int k = 0; k < nt; ++k)
+        for (int e = 0; e < kCholPre; ++e) meta.push_back(e < pl.ccnt[k] ? cols[pl.cbeg[k] + e] : -1);
+    if ((s = upload(c, c->chol_meta, meta.data(), meta.size() * 4))) return s;
     pl.rows = P_<int32_t>(c->chol_rows);
     pl.cols = P_<int32_t>(c->chol_cols);
+    pl.meta = P_<int32_t>(c->chol_meta);
     return PBA_OK;
 }
 
@@ -484,8 +494,9 @@ pba_status enqueue_iteration(pba_ctx *c, hipStream_t st)
     double *totals = P_<double>(c->totals);   // [0..3] current, [4..7] candidate
     launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
                      P_<LmState>(c->lm), -1.0, st);
-    launch_cholesky(P_<double>(c->A), n, P_<double>(c->Winv), c->chol, P_<int32_t>(c->fail), st);
-    launch_chol_solve(P_<double>(c->A), P_<double>(c->Winv), P_<double>(c->dx), n, c->chol, P_<int32_t>(c->fail), st);
+    double *Lf = P_<double>(c->A) + (size_t)n * n, *LTf = Lf + (size_t)n * n;
+    launch_cholesky(P_<double>(c->A), Lf, LTf, n, P_<double>(c->Winv), c->chol, P_<int32_t>(c->fail), st);
+    launch_chol_solve(Lf, LTf, P_<double>(c->Winv), P_<double>(c->dx), n, c->chol, P_<int32_t>(c->fail), st);
     launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->NP, P_<int32_t>(c->fail),
                    P_<LmState>(c->lm), st);
     pba_status s = run_eval(c, P_<double>(c->poses_cand), P_<double>(c->H_cand), P_<double>(c->b_cand), totals + 4,
@@ -523,11 +534,11 @@ pba_status ensure_system(pba_ctx *c)
     if ((s = ensure(c, c->H, n * n * 8))) return s;
     if ((s = ensure(c, c->b, n * 8))) return s;
     if ((s = ensure(c, c->totals, 8 * 8))) return s;
-    if ((s = ensure(c, c->A, n * n * 8))) return s;
+    if ((s = ensure(c, c->A, 3 * n * n * 8))) return s;   // working matrix, the factor's panels, their transposes
     if ((s = ensure(c, c->H_cand, n * n * 8))) return s;
     if ((s = ensure(c, c->b_cand, n * 8))) return s;
-    // inverted diagonal blocks, then n doubles of triangular-solve workspace
-    if ((s = ensure(c, c->Winv, ((n + 63) / 64) * 64 * 64 * 8 + (size_t)n * 8))) return s;
+    // inverted diagonal blocks, 64 x 64 each, zero-padded, then their transposes
+    if ((s = ensure(c, c->Winv, 2 * ((n + 63) / 64) * 64 * 64 * 8))) return s;
     if ((s = ensure(c, c->dx, n * 8))) return s;
     if ((s = ensure(c, c->lm, sizeof(LmState)))) return s;
     if ((s = ensure(c, c->fail, 16))) return s;
@@ -620,7 +631,7 @@ pba_status pba_destroy(pba_ctx *c)
                       &c->bk_ent, &c->H, &c->b, &c->H_cand, &c->b_cand, &c->totals, &c->A, &c->Winv, &c->dx, &c->lm,
                       &c->fail, &c->logbuf, &c->dbg_status, &c->dbg_uv, &c->dbg_cell, &c->dbg_res,
                       &c->loss_delta, &c->loss_poses, &c->g_int, &c->g_dep, &c->g_nrm, &c->g_pose,
-                      &c->chol_rows, &c->chol_cols};
+                      &c->chol_rows, &c->chol_cols, &c->chol_meta};
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) release(*b);
@@ -868,8 +879,9 @@ pba_status pba_solve_step(pba_ctx *c, double lambda, double *dx, int32_t on_devi
     }
     launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
                      P_<LmState>(c->lm), lambda, c->stream);
-    launch_cholesky(P_<double>(c->A), n, P_<double>(c->Winv), c->chol, P_<int32_t>(c->fail), c->stream);
-    launch_chol_solve(P_<double>(c->A), P_<double>(c->Winv), P_<double>(c->dx), n, c->chol, P_<int32_t>(c->fail),
+    double *Lf = P_<double>(c->A) + (size_t)n * n, *LTf = Lf + (size_t)n * n;
+    launch_cholesky(P_<double>(c->A), Lf, LTf, n, P_<double>(c->Winv), c->chol, P_<int32_t>(c->fail), c->stream);
+    launch_chol_solve(Lf, LTf, P_<double>(c->Winv), P_<double>(c->dx), n, c->chol, P_<int32_t>(c->fail),
                       c->stream);
     HIP_OK(hipGetLastError());
     int32_t f = 0;

@@ -7,6 +7,7 @@
 #include "pba_internal.h"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace pba {
 
@@ -43,9 +44,11 @@ void launch_damp_copy(const double *H, const double *b, double *A, double *rhs, 
 }
 
 // ---- blocked right-looking Cholesky, lower triangle, A row-major n x n.
-// Per 64-wide block column: factor the diagonal block and invert its factor (one wave),
-// form the panel below as X = B W^T with W = L_kk^-1 (tiled product), then update the
-// trailing lower triangle.  The inverted diagonal blocks are kept for the solves.
+// Per 64-wide block column: factor the diagonal block and invert its factor (one workgroup),
+// then, in one launch, form the panel below as X = B W^T with W = L_kk^-1 and update the
+// trailing lower triangle with it.  The panel tiles of the factor go to a second n x n matrix
+// (A itself keeps the input panel, which the same launch reads); the inverted diagonal blocks
+// are kept for the solves.
 
 // The value of v in lane l (wave-uniform l), to every lane.
 __device__ __forceinline__ double bcast_lane(double v, int l)
@@ -62,8 +65,8 @@ __device__ __forceinline__ double rsqrt_f64(double d)
     return y * fma(-0.5 * d * y, y, 1.5);
 }
 
-// Factor the diagonal block at k0 and write L_kk (lower) to A and W = L_kk^-1 (lower, row-major
-// 64 x 64, zero above the diagonal) to Winv.  One workgroup of 256 threads; a ragged last block is
+// Factor the diagonal block at k0 and write L_kk (lower) to A, W = L_kk^-1 (lower, row-major
+// 64 x 64, zero above the diagonal) and W^T to Winv (blocks k0 / 64 and nblk + k0 / 64).  One workgroup of 256 threads; a ragged last block is
 // padded with the identity, whose factor and inverse are the identity.
 //
 // Right-looking over single pivots, factor and inverse together, in registers: lane i of wave w
@@ -81,7 +84,8 @@ __device__ __forceinline__ double rsqrt_f64(double d)
 // panel on copies (cross-lane values by readlane) and publishes the four columns c as they stand
 // at their pivots, with their pivots; then every wave applies the four rank-one steps in order.
 // Row k + m of V, needed as r by the m-th step, is read from lane k + m of the same wave, which
-// has already applied the steps before it.  No step branches on the lane or the wave.
+// has already applied the steps before it.  No step branches on the lane or the wave (skipping
+// the column ranges a step cannot change, wave by wave, measured slower).
 __global__ void __launch_bounds__(256) chol_diag_kernel(double *A, int n, int k0, double *Winv, int32_t *fail)
 {
     __shared__ double cb[2][4][NB];   // the four columns c of a pivot group
@@ -141,98 +145,135 @@ __global__ void __launch_bounds__(256) chol_diag_kernel(double *A, int n, int k0
         }
     }
     __syncthreads();
+    // W to block k0 / 64 of Winv, W^T to block nblk + k0 / 64
     double *Wb = Winv + (int64_t)(k0 / NB) * NB * NB;
+    double *Wtb = Winv + (int64_t)((n + NB - 1) / NB + k0 / NB) * NB * NB;
     const double si = rsqrt_f64(piv[lane]);
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
         const int j = c0 + jj;
         const bool low = j <= lane, in = lane < nb && j < nb;
-        Wb[lane * NB + j] = (low && in) ? v[jj] * si : 0.0;
+        const double wv = (low && in) ? v[jj] * si : 0.0;
+        Wb[lane * NB + j] = wv;
+        Wtb[j * NB + lane] = wv;
         if (low && in) A[(int64_t)(k0 + lane) * n + k0 + j] = a[jj] * rsqrt_f64(piv[j]);
     }
     if (threadIdx.x == 0 && bad) *fail = 1;
 }
 
-// Panel below the diagonal block: X = B W^T for 64 rows per workgroup (16 x 16 threads, 4 x 4 each).
-__global__ void __launch_bounds__(256) chol_trsm_kernel(double *A, int n, int k0, const double *Winv,
-                                                        const int32_t *__restrict__ tiles, const int32_t *fail)
+// C += P Q^T over k = 0..63 for tiles in LDS (rows padded to 65 doubles), 16 x 16 threads,
+// RA x RB outputs each: rows ty + 16 a of P, rows tx + 16 b of Q.  With the odd row pitch the 16
+// rows a wave reads from Q fall in distinct banks (rows 4 tx + b would collide four ways).
+template <int RA, int RB>
+__device__ __forceinline__ void tile_nt(const double (*P)[NB + 1], const double (*Q)[NB + 1], int tx, int ty,
+                                        double (&c)[RA][RB])
 {
-    __shared__ double Bs[NB][NB + 1];
-    __shared__ double Ws[NB][NB + 1];
-    if (*fail) return;
-    const int nb = min(NB, n - k0);
-    const int r0 = tiles[blockIdx.x] * NB;   // a tile row below the diagonal block
-    const int rows = min(NB, n - r0);
-    const int tid = threadIdx.x;
-    const double *Wb = Winv + (int64_t)(k0 / NB) * NB * NB;
-    for (int e = tid; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, k = e % NB;
-        Bs[i][k] = (i < rows && k < nb) ? A[(int64_t)(r0 + i) * n + k0 + k] : 0.0;
-        Ws[i][k] = Wb[e];
+#pragma unroll 16
+    for (int k = 0; k < NB; ++k) {
+        double p[RA], q[RB];
+#pragma unroll
+        for (int a = 0; a < RA; ++a) p[a] = P[ty + 16 * a][k];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) q[b] = Q[tx + 16 * b][k];
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+#pragma unroll
+            for (int b = 0; b < RB; ++b) c[a][b] = fma(p[a], q[b], c[a][b]);
     }
-    __syncthreads();
-    const int tx = tid & 15, ty = tid >> 4;
-    double c[4][4];
-    for (int a = 0; a < 4; ++a)
-        for (int q = 0; q < 4; ++q) c[a][q] = 0.0;
-    for (int k = 0; k < nb; ++k) {
-        double b[4], w[4];
-        for (int a = 0; a < 4; ++a) b[a] = Bs[ty * 4 + a][k];
-        for (int q = 0; q < 4; ++q) w[q] = Ws[tx * 4 + q][k];
-        for (int a = 0; a < 4; ++a)
-            for (int q = 0; q < 4; ++q) c[a][q] += b[a] * w[q];
-    }
-    for (int a = 0; a < 4; ++a)
-        for (int q = 0; q < 4; ++q) {
-            const int i = ty * 4 + a, j = tx * 4 + q;
-            if (i < rows && j < nb) A[(int64_t)(r0 + i) * n + k0 + j] = c[a][q];
-        }
 }
 
-// Trailing update A_ij -= L_i L_j^T for block pairs i >= j below the panel.
-__global__ void __launch_bounds__(256) chol_update_kernel(double *A, int n, int k0, const int32_t *__restrict__ tiles,
-                                                          const int32_t *fail)
+// Rows r0 .. r0 + R - 1 (those below `rows`), columns c0 .. c0 + nc - 1 of the row-major matrix M
+// (row pitch ld, even; c0 and nc even) into a zero-padded R x 64 LDS tile, by a 256-thread
+// workgroup.  All of a thread's 16-byte loads are issued before the first is used.
+template <int R>
+__device__ __forceinline__ void load_tile(double (*T)[NB + 1], const double *M, int64_t ld, int rows, int r0,
+                                          int c0, int nc)
 {
-    __shared__ double Li[NB][NB + 1];
-    __shared__ double Lj[NB][NB + 1];
+    constexpr int kIt = R * NB / 2 / 256;
+    double2 v[kIt];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int e = it * 256 + (int)threadIdx.x, i = e >> 5, k = (e & 31) * 2;
+        v[it] = (r0 + i < rows && k < nc) ? *reinterpret_cast<const double2 *>(M + (r0 + i) * ld + c0 + k)
+                                          : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+        const int e = it * 256 + (int)threadIdx.x, i = e >> 5, k = (e & 31) * 2;
+        T[i][k] = v[it].x;
+        T[i][k + 1] = v[it].y;
+    }
+}
+
+// Panel and trailing update of block column k0 in one launch, four workgroups per pair (bi, bj),
+// bi >= bj, of the column's tile rows (ascending list `tiles`).  Workgroup (pair, qi, qj) takes
+// rows 32 qi .. 32 qi + 31 of tile row bi and rows 32 qj .. 32 qj + 31 of tile row bj: it forms
+// those rows of the panel, X = B W^T, from the input panel B in A, then applies A_ij -= X_i X_j^T
+// to its 32 x 32 quarter of tile (bi, bj).  On the diagonal pairs the quarter above the diagonal
+// has nothing to do, and the workgroups with qj = 0 write their rows of X_i to L and L^T.  Panel rows are
+// recomputed by the workgroups that need them, so no workgroup waits for another.
+__global__ void __launch_bounds__(256) chol_panel_update_kernel(double *A, double *L, double *LT, int n, int k0,
+                                                                const double *__restrict__ Winv,
+                                                                const int32_t *__restrict__ tiles,
+                                                                const int32_t *fail)
+{
+    constexpr int H = NB / 2;
+    __shared__ double Ws[NB][NB + 1];
+    __shared__ double Xi[H][NB + 1];
+    __shared__ double Xj[H][NB + 1];
     if (*fail) return;
     const int nb = min(NB, n - k0);
-    // blockIdx.x -> (bi, bj) with bi >= bj over the panel's tile rows
-    const int idx = blockIdx.x;
+    const int idx = blockIdx.x >> 2, qi = (blockIdx.x >> 1) & 1, qj = blockIdx.x & 1;
     int bi = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
     while ((bi + 1) * (bi + 2) / 2 <= idx) ++bi;
     while (bi * (bi + 1) / 2 > idx) --bi;
     const int bj = idx - bi * (bi + 1) / 2;
-    const int ri = tiles[bi] * NB, rj = tiles[bj] * NB;
-    const int ni = min(NB, n - ri), nj = min(NB, n - rj);
-    const int tid = threadIdx.x;
-    for (int e = tid; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, k = e % NB;
-        Li[i][k] = (i < ni && k < nb) ? A[(int64_t)(ri + i) * n + k0 + k] : 0.0;
-        Lj[i][k] = (i < nj && k < nb) ? A[(int64_t)(rj + i) * n + k0 + k] : 0.0;
-    }
+    const bool diag = bi == bj;
+    const int ri = tiles[bi] * NB + H * qi, rj = tiles[bj] * NB + H * qj;
+    const int ni = min(H, n - ri), nj = min(H, n - rj);
+    if ((diag && qj > qi) || ni <= 0 || nj <= 0) return;   // uniform over the workgroup
+    const bool same = diag && qi == qj;                      // X_j rows are X_i's
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    load_tile<NB>(Ws, Winv + (int64_t)(k0 / NB) * NB * NB, NB, NB, 0, 0, NB);
+    load_tile<H>(Xi, A, n, n, ri, k0, nb);
+    if (!same) load_tile<H>(Xj, A, n, n, rj, k0, nb);
     __syncthreads();
-    const int tx = tid & 15, ty = tid >> 4;
-    double c[4][4];
-    for (int a = 0; a < 4; ++a)
-        for (int q = 0; q < 4; ++q) c[a][q] = 0.0;
-    for (int k = 0; k < nb; ++k) {
-        double li[4], lj[4];
-        for (int a = 0; a < 4; ++a) li[a] = Li[ty * 4 + a][k];
-        for (int q = 0; q < 4; ++q) lj[q] = Lj[tx * 4 + q][k];
-        for (int a = 0; a < 4; ++a)
-            for (int q = 0; q < 4; ++q) c[a][q] += li[a] * lj[q];
-    }
-    for (int a = 0; a < 4; ++a)
+    // X = B W^T in place: the results stay in registers until every thread has read B
+    double ci[2][4] = {}, cj[2][4] = {};
+    tile_nt(Xi, Ws, tx, ty, ci);
+    if (!same) tile_nt(Xj, Ws, tx, ty, cj);
+    __syncthreads();
+    const bool write_l = diag && qj == 0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int i = ty * 4 + a, j = tx * 4 + q;
-            if (i < ni && j < nj && (bi != bj || j <= i)) A[(int64_t)(ri + i) * n + rj + j] -= c[a][q];
+            const int i = ty + 16 * a, j = tx + 16 * q;
+            Xi[i][j] = ci[a][q];
+            if (!same) Xj[i][j] = cj[a][q];
+            if (write_l && i < ni && j < nb) L[(int64_t)(ri + i) * n + k0 + j] = ci[a][q];
+        }
+    __syncthreads();
+    if (write_l)   // the same rows into L^T, read back column-wise so the stores run along its rows
+        for (int e = tid; e < H * NB; e += 256) {
+            const int i = e % H, j = e / H;
+            if (i < ni && j < nb) LT[(int64_t)(k0 + j) * n + ri + i] = Xi[i][j];
+        }
+    double c[2][2] = {};
+    tile_nt(Xi, same ? Xi : Xj, tx, ty, c);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int i = ty + 16 * a, j = tx + 16 * q;
+            if (i < ni && j < nj && (!diag || H * qj + j <= H * qi + i)) A[(int64_t)(ri + i) * n + rj + j] -= c[a][q];
         }
 }
 
 __global__ void reset_flag_kernel(int32_t *f) { *f = 0; }
 
-void launch_cholesky(double *A, int n, double *Winv, const CholPlan &plan, int32_t *fail, hipStream_t st)
+void launch_cholesky(double *A, double *L, double *LT, int n, double *Winv, const CholPlan &plan, int32_t *fail,
+                     hipStream_t st)
 {
     hipLaunchKernelGGL(reset_flag_kernel, dim3(1), dim3(1), 0, st, fail);
     const int nblk = (n + NB - 1) / NB;
@@ -240,89 +281,170 @@ void launch_cholesky(double *A, int n, double *Winv, const CholPlan &plan, int32
         const int k0 = kb * NB;
         hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, A, n, k0, Winv, fail);
         const int m = plan.rcnt[kb];
-        if (m > 0) {
-            const int32_t *tiles = plan.rows + plan.rbeg[kb];
-            hipLaunchKernelGGL(chol_trsm_kernel, dim3(m), dim3(256), 0, st, A, n, k0, Winv, tiles, fail);
-            hipLaunchKernelGGL(chol_update_kernel, dim3(m * (m + 1) / 2), dim3(256), 0, st, A, n, k0, tiles, fail);
+        if (m > 0)
+            hipLaunchKernelGGL(chol_panel_update_kernel, dim3(4 * (m * (m + 1) / 2)), dim3(256), 0, st, A, L, LT, n, k0, Winv,
+                               plan.rows + plan.rbeg[kb], fail);
+    }
+}
+
+// L y = rhs, then L^T x = y, both in one launch of one 1024-thread workgroup that walks the
+// block columns forward and then backward: the factor couples each block to a few tiles, so a
+// block step is a few thousand FMAs and a launch per step would cost more than the step.  The
+// vector being solved for sits in LDS when it fits (kTrsvLds doubles), else in x itself; it holds
+// the right-hand side, then y block by block, then the solution.  The two sweeps are the same
+// loop: block k takes u_k = M_k v_k in place of v_k, then v_i -= F_ik u_k for the tiles i listed
+// for k, with M = W_kk, F = L (tile rows below k) forward and M = W_kk^T, F = L^T (tile columns
+// left of k, read as rows of L^T) backward, so every product runs along rows: 16 lanes per row,
+// 4 columns each, summed within the lanes' row by DPP.  The next step's M_k and first kTrsvPre
+// tiles (listed per block, -1 padded, after the plan's counts) are fetched into registers while
+// the current step runs: they do not depend on the vector, so only LDS traffic and barriers
+// remain on the chain of steps.  A barrier also makes global writes before it visible to the
+// whole workgroup.
+constexpr int kTrsvLds = 16384;
+constexpr int kTrsvPre = kCholPre;
+
+// Workgroup barrier that orders LDS accesses only: global loads issued before it stay in flight
+// (__syncthreads() also waits for those).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Lane permutations without LDS round trips.  DPP row_ror:n rotates each 16-lane row by n.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kRowRor8 = 0x128, kRowRor4 = 0x124, kRowRor2 = 0x122, kRowRor1 = 0x121;
+
+// Sum over each 16-lane row, in every lane of the row (rotations by 8, 4, 2, 1).  Rows of a wave
+// may be active or inactive as a whole.
+__device__ __forceinline__ double row_sum(double u)
+{
+    u += dpp_f64<kRowRor8>(u);
+    u += dpp_f64<kRowRor4>(u);
+    u += dpp_f64<kRowRor2>(u);
+    return u + dpp_f64<kRowRor1>(u);
+}
+
+// Two doubles at p (16-byte aligned) if ok, else the two at `safe`, without a branch, so every
+// call issues exactly one load and the compiler can count the loads still in flight (a select
+// to zero would be placed right after the load and wait for it).  The callers skip a value that
+// was not ok, or multiply it by an exact zero, and `safe` holds finite values.
+__device__ __forceinline__ void load2_or_safe(const double *p, bool ok, double &a, double &b, const double *safe)
+{
+    const double2 v = *reinterpret_cast<const double2 *>(ok ? p : safe);
+    a = v.x;
+    b = v.y;
+}
+
+template <bool kInLds>
+__global__ void __launch_bounds__(1024) trsv_band_kernel(const double *__restrict__ L,
+                                                         const double *__restrict__ LT,
+                                                         const double *__restrict__ Winv, double *x, int n,
+                                                         const int32_t *__restrict__ rows,
+                                                         const int32_t *__restrict__ cols,
+                                                         const int32_t *__restrict__ meta, const int32_t *fail)
+{
+    __shared__ double vs[kInLds ? kTrsvLds : 1];
+    __shared__ double vk[NB];
+    if (*fail) return;
+    double *v = kInLds ? vs : x;
+    // with the vector in LDS the barriers need not wait for the prefetches
+    auto sync = [] {
+        if constexpr (kInLds) lds_barrier();
+        else __syncthreads();
+    };
+    const int t = threadIdx.x, nblk = (n + NB - 1) / NB;
+    const int32_t *rbeg = meta, *rcnt = meta + nblk, *cbeg = meta + 2 * nblk, *ccnt = meta + 3 * nblk;
+    const int32_t *rpre = meta + 4 * nblk, *cpre = rpre + kTrsvPre * nblk;   // first tiles, -1 padded
+    if (kInLds) {
+        for (int e = t; e < n; e += blockDim.x) vs[e] = x[e];
+        sync();
+    }
+    const int row = t >> 4, c4 = (t & 15) * 4;   // thread = (row of the product, 4 columns)
+    auto sweep = [&](const double *M, const double *F, const int32_t *pre, const int32_t *beg, const int32_t *cnt,
+                     const int32_t *list, bool forward) {
+        double wa[4], la[kTrsvPre][4], wb[4], lb[kTrsvPre][4];
+        auto fetch = [&](int kb, double (&wn)[4], double (&ln)[kTrsvPre][4]) {
+            const int k0 = kb * NB, nb = min(NB, n - k0);
+            const double2 *Mr = reinterpret_cast<const double2 *>(M + ((int64_t)kb * NB + row) * NB + c4);
+            const double2 m01 = Mr[0], m23 = Mr[1];   // the block is zero-padded
+            wn[0] = m01.x;
+            wn[1] = m01.y;
+            wn[2] = m23.x;
+            wn[3] = m23.y;
+#pragma unroll
+            for (int e = 0; e < kTrsvPre; ++e) {
+                const int tile = pre[kTrsvPre * kb + e];
+                const int i = tile >= 0 ? tile * NB + row : n;
+#pragma unroll
+                for (int h = 0; h < 2; ++h)   // columns c4 + 2 h, c4 + 2 h + 1 (nb is even)
+                    load2_or_safe(F + (int64_t)i * n + k0 + c4 + 2 * h, i < n && c4 + 2 * h < nb, ln[e][2 * h],
+                                  ln[e][2 * h + 1], M);
+            }
+        };
+        auto step = [&](int kb, const double (&w)[4], const double (&l)[kTrsvPre][4]) {
+            const int k0 = kb * NB, nb = min(NB, n - k0);
+            double u = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) u = fma(w[q], c4 + q < nb ? v[k0 + c4 + q] : 0.0, u);
+            u = row_sum(u);   // zero for rows beyond the block (M is zero-padded)
+            if ((t & 15) == 0) vk[row] = u;
+            sync();
+            if ((t & 15) == 0 && row < nb) v[k0 + row] = u;
+            double vq[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) vq[q] = vk[c4 + q];
+#pragma unroll
+            for (int e = 0; e < kTrsvPre; ++e) {
+                const int tile = pre[kTrsvPre * kb + e];
+                const int i = tile >= 0 ? tile * NB + row : n;
+                if (i < n) {   // uniform over the row's 16 lanes
+                    double z = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) z = fma(l[e][q], vq[q], z);
+                    z = row_sum(z);
+                    if ((t & 15) == 0) v[i] -= z;
+                }
+            }
+            for (int e = kTrsvPre; e < cnt[kb]; ++e) {
+                const int i = list[beg[kb] + e] * NB + row;
+                if (i >= n) continue;
+                double z = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (c4 + q < nb) z = fma(F[(int64_t)i * n + k0 + c4 + q], vq[q], z);
+                z = row_sum(z);
+                if ((t & 15) == 0) v[i] -= z;
+            }
+            sync();
+        };
+        // Two steps per pass with the register sets swapped (static indexing keeps them in registers;
+        // a copy out of the prefetch set would wait for its loads).  The fetches are unconditional
+        // (past the end they repeat the last block), so that the loads in flight are the same on
+        // every path and the waits for them can be counted.
+        const int first = forward ? 0 : nblk - 1, dir = forward ? 1 : -1;
+        auto clampb = [&](int kb) { return min(max(kb, 0), nblk - 1); };
+        fetch(first, wa, la);
+        for (int s = 0; s < nblk; s += 2) {
+            const int kb = first + dir * s;
+            fetch(clampb(kb + dir), wb, lb);
+            step(kb, wa, la);
+            if (s + 1 >= nblk) break;
+            fetch(clampb(kb + 2 * dir), wa, la);
+            step(kb + dir, wb, lb);
         }
-    }
-}
-
-// L y = rhs, then L^T x = y, as one launch per 64-row block and direction (right-looking, so each
-// launch spreads over many workgroups).  The right-hand side in x is consumed; y lives in the n
-// doubles of workspace that follow the inverted diagonal blocks in Winv; x receives the solution
-// (zero if the factorisation failed).
-
-// Forward block kb: y_k = W_kk r_k, then r_i -= L_ik y_k for the rows below.  Workgroup g owns
-// the 64 rows of the g-th tile row in the block column's list; every workgroup forms y_k itself
-// (r_k is not written in this launch), workgroup 0 stores it.
-__global__ void __launch_bounds__(256) trsv_fwd_kernel(const double *__restrict__ L, const double *__restrict__ Winv,
-                                                       double *__restrict__ r, double *__restrict__ y, int n, int kb,
-                                                       const int32_t *__restrict__ tiles, int ntiles,
-                                                       const int32_t *fail)
-{
-    __shared__ double sy[NB];
-    if (*fail) return;
-    const int k0 = kb * NB, nb = min(NB, n - k0);
-    const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
-    const double *Wb = Winv + (int64_t)kb * NB * NB;
-    double s = 0.0;
-#pragma unroll
-    for (int c = part * 16; c < part * 16 + 16; ++c) s += c < nb ? Wb[row * NB + c] * r[k0 + c] : 0.0;
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    if (part == 0) sy[row] = s;
-    __syncthreads();
-    if (blockIdx.x == 0 && tid < nb) y[k0 + tid] = sy[tid];
-    // the tile row this workgroup updates (none when block kb couples to no row below it)
-    const int i = (ntiles > 0 ? tiles[blockIdx.x] * NB : n) + row;
-    double u = 0.0;
-    if (i < n) {
-        const double *Lr = L + (int64_t)i * n + k0;
-#pragma unroll
-        for (int c = part * 16; c < part * 16 + 16; ++c) u += c < nb ? Lr[c] * sy[c] : 0.0;
-    }
-    u += __shfl_xor(u, 1, 64);
-    u += __shfl_xor(u, 2, 64);
-    if (i < n && part == 0) r[i] -= u;
-}
-
-// Backward block kb: x_k = W_kk^T s_k, then s_i -= sum_c L[k0 + c][i] x_k[c] for the columns
-// i < k0.  Workgroup g owns the 64 columns of the g-th tile in the block row's list; workgroup 0
-// stores x_k.
-__global__ void __launch_bounds__(256) trsv_bwd_kernel(const double *__restrict__ L, const double *__restrict__ Winv,
-                                                       double *__restrict__ s, double *__restrict__ x, int n, int kb,
-                                                       const int32_t *__restrict__ tiles, int ntiles,
-                                                       const int32_t *fail)
-{
-    __shared__ double sx[NB];
-    __shared__ double part_s[4][NB];
-    if (*fail) return;
-    const int k0 = kb * NB, nb = min(NB, n - k0);
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const double *Wb = Winv + (int64_t)kb * NB * NB;
-    {
-        // x_k[c] = sum_i W[i][c] s_k[i]: wave wv sums rows 16 wv .. 16 wv + 15 for column `lane`
-        double t = 0.0;
-#pragma unroll
-        for (int i = wv * 16; i < wv * 16 + 16; ++i) t += i < nb ? Wb[i * NB + lane] * s[k0 + i] : 0.0;
-        part_s[wv][lane] = t;
-    }
-    __syncthreads();
-    if (tid < NB) sx[tid] = part_s[0][tid] + part_s[1][tid] + part_s[2][tid] + part_s[3][tid];
-    __syncthreads();
-    if (blockIdx.x == 0 && tid < nb) x[k0 + tid] = sx[tid];
-    // the tile column this workgroup updates (none when block row kb couples to no column left of it)
-    const int i = (ntiles > 0 ? tiles[blockIdx.x] * NB : k0) + lane;
-    double u = 0.0;
-    if (i < k0) {
-#pragma unroll
-        for (int c = wv * 16; c < wv * 16 + 16; ++c) u += c < nb ? L[(int64_t)(k0 + c) * n + i] * sx[c] : 0.0;
-    }
-    __syncthreads();
-    part_s[wv][lane] = u;
-    __syncthreads();
-    if (wv == 0 && i < k0) s[i] -= part_s[0][lane] + part_s[1][lane] + part_s[2][lane] + part_s[3][lane];
+    };
+    sweep(Winv, L, rpre, rbeg, rcnt, rows, true);
+    sweep(Winv + (int64_t)nblk * NB * NB, LT, cpre, cbeg, ccnt, cols, false);
+    if (kInLds)
+        for (int e = t; e < n; e += blockDim.x) x[e] = vs[e];
 }
 
 __global__ void zero_on_fail_kernel(double *x, int n, const int32_t *fail)
@@ -331,21 +453,19 @@ __global__ void zero_on_fail_kernel(double *x, int n, const int32_t *fail)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = 0.0;
 }
 
-void launch_chol_solve(const double *L, double *Winv, double *x, int n, const CholPlan &plan, const int32_t *fail,
-                       hipStream_t st)
+void launch_chol_solve(const double *L, const double *LT, double *Winv, double *x, int n, const CholPlan &plan,
+                       const int32_t *fail, hipStream_t st)
 {
-    const int nblk = (n + NB - 1) / NB;
-    double *y = Winv + (int64_t)nblk * NB * NB;
-    for (int kb = 0; kb < nblk; ++kb) {
-        const int m = plan.rcnt[kb];
-        hipLaunchKernelGGL(trsv_fwd_kernel, dim3(std::max(m, 1)), dim3(256), 0, st, L, Winv, x, y, n, kb,
-                           plan.rows + plan.rbeg[kb], m, fail);
-    }
-    for (int kb = nblk - 1; kb >= 0; --kb) {
-        const int m = plan.ccnt[kb];
-        hipLaunchKernelGGL(trsv_bwd_kernel, dim3(std::max(m, 1)), dim3(256), 0, st, L, Winv, y, x, n, kb,
-                           plan.cols + plan.cbeg[kb], m, fail);
-    }
+    // PBA_TRSV_LDS_MAX (doubles, at most kTrsvLds) lowers the size up to which the vector is kept
+    // in LDS; 0 selects the global-memory variant for every size.
+    int lds_max = kTrsvLds;
+    if (const char *e = std::getenv("PBA_TRSV_LDS_MAX")) lds_max = std::min(kTrsvLds, std::max(0, std::atoi(e)));
+    if (n <= lds_max)
+        hipLaunchKernelGGL(trsv_band_kernel<true>, dim3(1), dim3(1024), 0, st, L, LT, Winv, x, n, plan.rows,
+                           plan.cols, plan.meta, fail);
+    else
+        hipLaunchKernelGGL(trsv_band_kernel<false>, dim3(1), dim3(1024), 0, st, L, LT, Winv, x, n, plan.rows,
+                           plan.cols, plan.meta, fail);
     hipLaunchKernelGGL(zero_on_fail_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, n, fail);
 }
 

@@ -268,6 +268,36 @@ def test_multiblock_solve_and_lm(pba):
     assert dt < 1e-6 and dr < 1e-6
 
 
+@pytest.mark.parametrize("lds_max", [None, "0"])
+def test_scattered_pattern_solve(pba, lds_max, monkeypatch):
+    """Keyframes mapped to pose variables by a random permutation: the chain of pairs then couples
+    each 64-wide block to most others and the factorisation fills in, so block columns carry more
+    tiles than the triangular solve prefetches.  The solve matches a dense solve of the same
+    system, with the vector of the triangular solves in LDS and (PBA_TRSV_LDS_MAX=0) in global
+    memory."""
+    if lds_max is not None:
+        monkeypatch.setenv("PBA_TRSV_LDS_MAX", lds_max)
+    n_kf = 72
+    prob = synth.make("lidar128", kfs=range(n_kf), H=16, W=256).subset(range(n_kf))
+    perm = np.random.default_rng(7).permutation(n_kf).astype(np.int32)
+    X_var = np.empty_like(prob.init_poses)
+    X_var[perm] = prob.init_poses
+    with pba.context_for_problem(prob, precision=pba.PBA_F64) as ctx:
+        ctx.set_pose_groups(perm)
+        ctx.set_poses(X_var)
+        ev = ctx.evaluate(want_system=True)
+        H = ev["H"]
+        nt = (H.shape[0] + 63) // 64
+        coupled = [sum(np.abs(H[64 * i:64 * i + 64, 64 * k:64 * k + 64]).max() > 0 for i in range(k + 1, nt))
+                   for k in range(nt)]
+        assert max(coupled) > 4, coupled
+        for lam in (0.0, 1e-4):
+            dx = ctx.solve_step(lam)
+            ref, ok = oracle.solve_step(H, ev["b"], lam, anchor=0)
+            assert ok
+            assert np.abs(dx - ref).max() <= 1e-8 * np.abs(ref).max(), lam
+
+
 def test_graph_replays_match_eager_iterations(lidar_mini, pba):
     """Each replay of the captured iteration graph gives bitwise the same poses and log as the
     same kernels launched one by one; the host reads results between replays."""
