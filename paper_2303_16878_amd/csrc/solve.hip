@@ -65,38 +65,44 @@ __device__ __forceinline__ double rsqrt_f64(double d)
     return y * fma(-0.5 * d * y, y, 1.5);
 }
 
-// Factor the diagonal block at k0 and write L_kk (lower) to A, W = L_kk^-1 (lower, row-major
-// 64 x 64, zero above the diagonal) and W^T to Winv (blocks k0 / 64 and nblk + k0 / 64).  One workgroup of 256 threads; a ragged last block is
-// padded with the identity, whose factor and inverse are the identity.
+// Factor the diagonal block at k0 and write W = L_kk^-1 (lower, row-major 64 x 64, zero above the
+// diagonal) and W^T to Winv (blocks k0 / 64 and nblk + k0 / 64); the factor itself is not needed
+// (the panel and the solves use W).  One workgroup of 256 threads; a ragged last block is padded
+// with the identity, whose factor and inverse are the identity.
 //
 // Right-looking over single pivots, factor and inverse together, in registers: lane i of wave w
-// holds row i, columns 16 w .. 16 w + 15, of the working copy S and of V, the working rows of the
-// inverse (V = I initially).  At pivot k, with p = S(k, k), c_i = S(i, k) for i > k and 0
-// otherwise, and r_j = V(k, j) (zero for j > k, r_k = 1: V stays lower triangular), every element
-// takes both
+// holds S(i, 16 w + jj), row i of the working copy S, and lane j of wave w holds V(16 w + jj, j),
+// column j of the working rows of the inverse (V = I initially), jj = 0..15.  At pivot k, with
+// p = S(k, k), c_i = S(i, k) for i > k and 0 otherwise, and r_j = V(k, j) (zero for j > k, r_k = 1:
+// V stays lower triangular), every element takes both
 //   S(i, j) -= c_i c_j / p,      V(i, j) -= c_i r_j / p
 // (c_j = 0 leaves S left of the pivot alone, r_j = 0 leaves V right of it alone), because
 // L(i, k) = c_i / sqrt(p) and row k of the inverse is V(k, :) / sqrt(p).  Column k of S is final
-// from then on, so S ends up holding L column-scaled by sqrt(p_j), and V holds W row-scaled by
-// sqrt(p_i).
+// from then on, and V ends up holding W row-scaled by sqrt(p_i).  Both updates of a wave use the
+// same 16 values c_(16 w + jj), read from LDS as broadcasts, and one value per lane (c_i for S,
+// r_j for V).
 //
-// Pivots go four at a time per barrier: the wave owning columns k .. k + 3 factors that 64 x 4
-// panel on copies (cross-lane values by readlane) and publishes the four columns c as they stand
-// at their pivots, with their pivots; then every wave applies the four rank-one steps in order.
-// Row k + m of V, needed as r by the m-th step, is read from lane k + m of the same wave, which
-// has already applied the steps before it.  No step branches on the lane or the wave (skipping
-// the column ranges a step cannot change, wave by wave, measured slower).
-__global__ void __launch_bounds__(256) chol_diag_kernel(double *A, int n, int k0, double *Winv, int32_t *fail)
+// Pivots go four at a time per barrier: the wave owning columns k .. k + 3 of S (and rows
+// k .. k + 3 of V) factors that 64 x 4 panel on copies (cross-lane values by readlane), carries
+// the four rows of V along, and publishes the four columns c and rows r as they stand at their
+// pivots, with the pivots and their reciprocals; then every wave applies the four rank-one steps
+// in order.  No step branches on the lane or the wave.  (Broadcasting the 16 values by readlane
+// instead of LDS, skipping the column ranges a step cannot change, or eight pivots per barrier
+// all measured slower; keeping V with lane = row, which needs 32 readlanes per pivot, cost 30%.)
+__global__ void __launch_bounds__(256) chol_diag_kernel(const double *A, int n, int k0, double *Winv, int32_t *fail)
 {
-    __shared__ double cb[2][4][NB];   // the four columns c of a pivot group
-    __shared__ double pb[2][4];       // their pivots
+    __shared__ double cb[2][4][NB];   // the four columns c of a pivot group (double-buffered)
+    __shared__ double rb[2][4][NB];   // the four rows r of V at their pivots
+    __shared__ double pb[2][4];       // the pivots
+    __shared__ double qb[2][4];       // their reciprocals
     __shared__ double piv[NB];
+    __shared__ double Ts[NB][NB + 1];   // W, transposed on the way out
     if (*fail) return;
     const int nb = min(NB, n - k0);
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c0 = 16 * w;
-    double a[16], v[16];
+    double a[16], v[16];   // S(lane, c0 + jj), V(c0 + jj, lane)
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
         const int j = c0 + jj;
@@ -110,8 +116,12 @@ __global__ void __launch_bounds__(256) chol_diag_kernel(double *A, int n, int k0
         for (int tb = 0; tb < 4; ++tb) {
             const int kb = 4 * tb, k = 16 * wo + kb, b = tb & 1;
             if (w == wo) {
-                // the 64 x 4 panel at its pivots, on copies
-                double t[4] = {a[kb], a[kb + 1], a[kb + 2], a[kb + 3]};
+                double t[4], r[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    t[m] = a[kb + m];
+                    r[m] = v[kb + m];
+                }
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const double p = bcast_lane(t[m], k + m);
@@ -120,9 +130,17 @@ __global__ void __launch_bounds__(256) chol_diag_kernel(double *A, int n, int k0
                     q = fma(q, fma(-p, q, 1.0), q);
                     const double c = lane > k + m ? t[m] : 0.0;
                     cb[b][m][lane] = c;
-                    if (lane == 0) pb[b][m] = p;
+                    rb[b][m][lane] = r[m];
+                    if (lane == 0) {
+                        pb[b][m] = p;
+                        qb[b][m] = q;
+                    }
 #pragma unroll
-                    for (int m2 = m + 1; m2 < 4; ++m2) t[m2] = fma(-c * q, bcast_lane(t[m], k + m2), t[m2]);
+                    for (int m2 = m + 1; m2 < 4; ++m2) {
+                        const double cm2 = bcast_lane(t[m], k + m2);
+                        t[m2] = fma(-c * q, cm2, t[m2]);
+                        r[m2] = fma(-cm2 * q, r[m], r[m2]);
+                    }
                 }
             }
             __syncthreads();
@@ -131,33 +149,33 @@ __global__ void __launch_bounds__(256) chol_diag_kernel(double *A, int n, int k0
                 const double p = pb[b][m];
                 const bool ok = p > 0.0;
                 bad = bad || !ok;
-                double q = __builtin_amdgcn_rcp(p);
-                q = fma(q, fma(-p, q, 1.0), q);
-                q = fma(q, fma(-p, q, 1.0), q);
                 if (threadIdx.x == 0) piv[k + m] = ok ? p : 1.0;
-                const double cr = ok ? -cb[b][m][lane] * q : 0.0;
+                const double qq = ok ? qb[b][m] : 0.0;
+                const double cr = -cb[b][m][lane] * qq, rr = -rb[b][m][lane] * qq;
 #pragma unroll
                 for (int jj = 0; jj < 16; ++jj) {
-                    a[jj] = fma(cr, cb[b][m][c0 + jj], a[jj]);
-                    v[jj] = fma(cr, bcast_lane(v[jj], k + m), v[jj]);
+                    const double cj = cb[b][m][c0 + jj];
+                    a[jj] = fma(cr, cj, a[jj]);
+                    v[jj] = fma(rr, cj, v[jj]);
                 }
             }
         }
     }
     __syncthreads();
-    // W to block k0 / 64 of Winv, W^T to block nblk + k0 / 64
     double *Wb = Winv + (int64_t)(k0 / NB) * NB * NB;
     double *Wtb = Winv + (int64_t)((n + NB - 1) / NB + k0 / NB) * NB * NB;
-    const double si = rsqrt_f64(piv[lane]);
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
-        const int j = c0 + jj;
-        const bool low = j <= lane, in = lane < nb && j < nb;
-        const double wv = (low && in) ? v[jj] * si : 0.0;
-        Wb[lane * NB + j] = wv;
-        Wtb[j * NB + lane] = wv;
-        if (low && in) A[(int64_t)(k0 + lane) * n + k0 + j] = a[jj] * rsqrt_f64(piv[j]);
+        const int i = c0 + jj;
+        const double sp = rsqrt_f64(piv[i]);
+        const bool low = lane <= i, in = i < nb && lane < nb;
+        const double wv = (low && in) ? v[jj] * sp : 0.0;
+        Wb[i * NB + lane] = wv;
+        Ts[lane][i] = wv;
     }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) Wtb[(c0 + jj) * NB + lane] = Ts[c0 + jj][lane];
     if (threadIdx.x == 0 && bad) *fail = 1;
 }
 
