@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(256) chol_diag_kernel(const double *A, int n, 
     __shared__ double qb[2][4];       // their reciprocals
     __shared__ double piv[NB];
     __shared__ double Ts[NB][NB + 1];   // W, transposed on the way out
-    if (*fail) return;
+    if (k0 > 0 && *fail) return;   // the first block starts the factorisation and clears the flag
     const int nb = min(NB, n - k0);
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(256) chol_diag_kernel(const double *A, int n, 
     __syncthreads();
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) Wtb[(c0 + jj) * NB + lane] = Ts[c0 + jj][lane];
-    if (threadIdx.x == 0 && bad) *fail = 1;
+    if (threadIdx.x == 0 && (bad || k0 == 0)) *fail = bad ? 1 : 0;
 }
 
 // C += P Q^T over k = 0..63 for tiles in LDS (rows padded to 65 doubles), 16 x 16 threads,
@@ -288,12 +288,9 @@ __global__ void __launch_bounds__(256) chol_panel_update_kernel(double *A, doubl
         }
 }
 
-__global__ void reset_flag_kernel(int32_t *f) { *f = 0; }
-
 void launch_cholesky(double *A, double *L, double *LT, int n, double *Winv, const CholPlan &plan, int32_t *fail,
                      hipStream_t st)
 {
-    hipLaunchKernelGGL(reset_flag_kernel, dim3(1), dim3(1), 0, st, fail);
     const int nblk = (n + NB - 1) / NB;
     for (int kb = 0; kb < nblk; ++kb) {
         const int k0 = kb * NB;
@@ -309,7 +306,8 @@ void launch_cholesky(double *A, double *L, double *LT, int n, double *Winv, cons
 // block columns forward and then backward: the factor couples each block to a few tiles, so a
 // block step is a few thousand FMAs and a launch per step would cost more than the step.  The
 // vector being solved for sits in LDS when it fits (kTrsvLds doubles), else in x itself; it holds
-// the right-hand side, then y block by block, then the solution.  The two sweeps are the same
+// the right-hand side, then y block by block, then the solution (x is zeroed instead if the
+// factorisation failed).  The two sweeps are the same
 // loop: block k takes u_k = M_k v_k in place of v_k, then v_i -= F_ik u_k for the tiles i listed
 // for k, with M = W_kk, F = L (tile rows below k) forward and M = W_kk^T, F = L^T (tile columns
 // left of k, read as rows of L^T) backward, so every product runs along rows: 16 lanes per row,
@@ -371,7 +369,10 @@ __global__ void __launch_bounds__(1024) trsv_band_kernel(const double *__restric
 {
     __shared__ double vs[kInLds ? kTrsvLds : 1];
     __shared__ double vk[NB];
-    if (*fail) return;
+    if (*fail) {   // no factor: the step is zero
+        for (int e = threadIdx.x; e < n; e += blockDim.x) x[e] = 0.0;
+        return;
+    }
     double *v = kInLds ? vs : x;
     // with the vector in LDS the barriers need not wait for the prefetches
     auto sync = [] {
@@ -465,12 +466,6 @@ __global__ void __launch_bounds__(1024) trsv_band_kernel(const double *__restric
         for (int e = t; e < n; e += blockDim.x) x[e] = vs[e];
 }
 
-__global__ void zero_on_fail_kernel(double *x, int n, const int32_t *fail)
-{
-    if (!*fail) return;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = 0.0;
-}
-
 void launch_chol_solve(const double *L, const double *LT, double *Winv, double *x, int n, const CholPlan &plan,
                        const int32_t *fail, hipStream_t st)
 {
@@ -484,7 +479,6 @@ void launch_chol_solve(const double *L, const double *LT, double *Winv, double *
     else
         hipLaunchKernelGGL(trsv_band_kernel<false>, dim3(1), dim3(1024), 0, st, L, LT, Winv, x, n, plan.rows,
                            plan.cols, plan.meta, fail);
-    hipLaunchKernelGGL(zero_on_fail_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, n, fail);
 }
 
 // ---- pose update

@@ -298,6 +298,31 @@ def test_scattered_pattern_solve(pba, lds_max, monkeypatch):
             assert np.abs(dx - ref).max() <= 1e-8 * np.abs(ref).max(), lam
 
 
+def test_not_positive_definite_then_recovers(lidar_mini, pba):
+    """A keyframe left out of every pair has an all-zero 6x6 block, so the damped system is singular:
+    solve_step reports PBA_ENOTPD and the step it writes is zero.  With the pairs restored, the next
+    solve matches the dense solve again (the failure flag does not stick)."""
+    prob = lidar_mini
+    pairs = np.asarray(prob.pairs, np.int32)
+    lone = prob.n - 1   # not the gauge anchor (keyframe 0)
+    keep = pairs[(pairs[:, 0] != lone) & (pairs[:, 1] != lone)]
+    assert 0 < len(keep) < len(pairs)
+    with pba.context_for_problem(prob, precision=pba.PBA_F64) as ctx:
+        ctx.set_pairs(keep)
+        dx = np.full(6 * ctx.n_poses, np.nan)
+        st = ctx.lib.pba_solve_step(ctx.h, 1e-3, dx.ctypes.data, 0)
+        assert st == pba.PBA_ENOTPD
+        assert np.all(dx == 0.0)
+        with pytest.raises(pba.PbaError):
+            ctx.solve_step(1e-3)
+        ctx.set_pairs(pairs)
+        ev = ctx.evaluate(want_system=True)
+        dx = ctx.solve_step(1e-3)
+        ref, ok = oracle.solve_step(ev["H"], ev["b"], 1e-3, anchor=0)
+        assert ok
+        assert np.abs(dx - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
 def test_graph_replays_match_eager_iterations(lidar_mini, pba):
     """Each replay of the captured iteration graph gives bitwise the same poses and log as the
     same kernels launched one by one; the host reads results between replays."""
