@@ -15,7 +15,10 @@ What it computes (paper section in brackets):
     solved by a Cholesky factorisation (library primitive);
   * the pose update X <- X exp(dx) with exp(dx) = [R(dq), dt], R(dq) the
     rotation of the unit quaternion with imaginary part dq [Supplementary];
-  * ATE RMSE after Horn's closed-form SE(3) alignment [Sec. V].
+  * ATE RMSE after Horn's closed-form SE(3) alignment [Sec. V];
+  * optionally, occlusion suppression by a z-buffer of the pair's own warped source points in
+    addition to the depth-consistency gate [Sec. IV-C: occluded portions are suppressed; the
+    mechanism is a reading].
 
 Every function here is pinned by tests/test_oracle_pins.py against facts that
 do not come from the oracle itself (finite differences, closed forms,
@@ -35,7 +38,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 # per-pixel status codes written by orc_eval_pair
-ST_VALID, ST_NODEPTH, ST_NOPROJ, ST_OUTSIDE, ST_BADTAP, ST_OCCLUDED, ST_SKIPPED = range(7)
+ST_VALID, ST_NODEPTH, ST_NOPROJ, ST_OUTSIDE, ST_BADTAP, ST_OCCLUDED, ST_SKIPPED, ST_ZOCCLUDED = range(8)
 
 
 class OrcSensor(ctypes.Structure):
@@ -47,7 +50,8 @@ class OrcSensor(ctypes.Structure):
 
 class OrcParams(ctypes.Structure):
     _fields_ = [("channels", ctypes.c_int32), ("grad_mode", ctypes.c_int32),
-                ("omega", ctypes.c_double * 3), ("huber", ctypes.c_double), ("occ_tau", ctypes.c_double)]
+                ("omega", ctypes.c_double * 3), ("huber", ctypes.c_double), ("occ_tau", ctypes.c_double),
+                ("zbuffer", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class OrcPairOut(ctypes.Structure):
@@ -96,6 +100,8 @@ def _load():
                                       ctypes.POINTER(OrcPairOut), vp, vp, vp, vp]
         lib.orc_eval_pair_grad.restype = ctypes.c_int
         lib.orc_eval_pair_grad.argtypes = lib.orc_eval_pair.argtypes + [ctypes.POINTER(OrcImageGrad)]
+        lib.orc_zbuffer.restype = None
+        lib.orc_zbuffer.argtypes = [ctypes.POINTER(OrcSensor), vp, ctypes.POINTER(OrcSensor), vp, vp, vp]
         lib.orc_eval_pairs.restype = ctypes.c_int
         lib.orc_eval_pairs.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, ctypes.POINTER(OrcParams),
                                        ctypes.POINTER(OrcParams), vp]
@@ -127,6 +133,7 @@ def params_struct(params: dict, model: int, grad_mode: int = 0) -> OrcParams:
     p.omega[2] = params["omega_normal"]
     p.huber = params["huber_delta"]
     p.occ_tau = params["occ_tau_pinhole"] if model == 0 else params["occ_tau_spherical"]
+    p.zbuffer = int(params.get("occlusion_zbuffer", 0))
     return p
 
 
@@ -173,6 +180,20 @@ def eval_pair(prob, poses, s, t, params=None, force_valid=None, force_cell=None,
     if pixels:
         r.update(status=status, uv=uv, res=res, margin=margin)
     return r
+
+
+def zbuffer(prob, poses, s, t):
+    """The source z-buffer of the ordered pair (s -> t) used by the z-buffer occlusion variant:
+    [Ht, Wt] float32, per target cell the smallest predicted depth (FP32) of the pair's source
+    points whose integer cell lies in the evaluated region, +inf elsewhere (orc_zbuffer)."""
+    lib = _load()
+    ss, st = prob.sensors[prob.kf_sensor[s]], prob.sensors[prob.kf_sensor[t]]
+    Ds = _c(prob.depth[s], np.float32)
+    Xs, Xt = _c(poses[s], np.float64), _c(poses[t], np.float64)
+    Z = np.empty((st["H"], st["W"]), np.float32)
+    lib.orc_zbuffer(ctypes.byref(sensor_struct(ss)), Ds.ctypes.data, ctypes.byref(sensor_struct(st)),
+                    Xs.ctypes.data, Xt.ctypes.data, Z.ctypes.data)
+    return Z
 
 
 def eval_pairs(prob, poses, params=None, pairs=None, grad_mode=0):

@@ -26,6 +26,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 typedef struct {
@@ -40,6 +41,8 @@ typedef struct {
     double omega[3];            /* information of intensity, depth, normal */
     double huber;               /* <= 0: plain squares */
     double occ_tau;             /* occlusion gate on |e_depth| for this pair's target */
+    int32_t zbuffer;            /* 1: also the source z-buffer test (occlusion by the pair's own points) */
+    int32_t pad;
 } OrcParams;
 
 typedef struct {
@@ -52,7 +55,7 @@ typedef struct {
 
 /* per-pixel status codes */
 enum { ST_VALID = 0, ST_NODEPTH = 1, ST_NOPROJ = 2, ST_OUTSIDE = 3, ST_BADTAP = 4, ST_OCCLUDED = 5,
-       ST_SKIPPED = 6 };
+       ST_SKIPPED = 6, ST_ZOCCLUDED = 7 };
 
 /* ---------------------------------------------------------------- 3x3 helpers (row-major) */
 static void matmul3(const double *A, const double *B, double *C) {
@@ -115,6 +118,52 @@ static int project(const OrcSensor *s, const double *p, double *uv) {
     return 1;
 }
 
+static inline double px(const float *img, int W, int r, int c) { return (double)img[(int64_t)r * W + c]; }
+
+/* p_bar of source pixel (c, r) at depth d in the target sensor frame:
+ * p_u = R_os pi_s^-1(u, d) + t_os, y = R_j^T (R_i p_u + t_i - t_j), p_bar = R_ot^T (y - t_ot). */
+static void warp_pixel(const OrcSensor *ss, const OrcSensor *st, const double *Xs, const double *Xt, int c, int r,
+                       double d, double *pu, double *y, double *pbar)
+{
+    const double *Ri = Xs, *ti = Xs + 9, *Rj = Xt, *tj = Xt + 9;
+    double q[3], w3[3], ym[3], RjT[9], RotT[9];
+    unproject(ss, (double)c, (double)r, d, q);
+    matvec3(ss->Ro, q, pu);
+    for (int k = 0; k < 3; ++k) pu[k] += ss->to[k];
+    matvec3(Ri, pu, w3);
+    for (int k = 0; k < 3; ++k) w3[k] += ti[k] - tj[k];
+    transpose3(Rj, RjT);
+    matvec3(RjT, w3, y);
+    for (int k = 0; k < 3; ++k) ym[k] = y[k] - st->to[k];
+    transpose3(st->Ro, RotT);
+    matvec3(RotT, ym, pbar);
+}
+
+/* Source z-buffer of one pair (the z-buffer occlusion variant): for every target cell, the
+ * smallest predicted depth zeta^d (p_bar_z for a pinhole target, |p_bar| for a spherical one),
+ * rounded to FP32, over the pair's source points with valid depth that project with their
+ * integer cell floor(u') inside the evaluated region [1, W-3] x [1, H-3]; +inf where none lands.
+ * Z has Ht * Wt floats. */
+void orc_zbuffer(const OrcSensor *ss, const float *Ds, const OrcSensor *st, const double *Xs, const double *Xt,
+                 float *Z)
+{
+    const int Ht = st->H, Wt = st->W;
+    for (int64_t k = 0; k < (int64_t)Ht * Wt; ++k) Z[k] = INFINITY;
+    for (int r = 0; r < ss->H; ++r) for (int c = 0; c < ss->W; ++c) {
+        const double d = px(Ds, ss->W, r, c);
+        if (!depth_ok(d, ss)) continue;
+        double pu[3], y[3], pbar[3], uv[2];
+        warp_pixel(ss, st, Xs, Xt, c, r, d, pu, y, pbar);
+        if (!project(st, pbar, uv)) continue;
+        const double fx0 = floor(uv[0]), fy0 = floor(uv[1]);
+        if (!(fx0 >= 1.0 && fx0 <= Wt - 3.0 && fy0 >= 1.0 && fy0 <= Ht - 3.0)) continue;
+        const double zeta = st->model == 0 ? pbar[2] : sqrt(pbar[0]*pbar[0] + pbar[1]*pbar[1] + pbar[2]*pbar[2]);
+        const int64_t cell = (int64_t)fy0 * Wt + (int64_t)fx0;
+        const float zf = (float)zeta;
+        if (zf < Z[cell]) Z[cell] = zf;
+    }
+}
+
 /* projective Jacobian d pi / d p (2x3, row-major), Supplementary */
 static void proj_jacobian(const OrcSensor *s, const double *p, double *P) {
     if (s->model == 0) {
@@ -147,7 +196,6 @@ static double huber_rho(double chi2, double delta, double *w) {
     return 2.0 * delta * e - delta * delta;
 }
 
-static inline double px(const float *img, int W, int r, int c) { return (double)img[(int64_t)r * W + c]; }
 
 /*
  * Evaluate one ordered pair.  Images are row-major [H][W] (normals [H][W][3]).
@@ -198,6 +246,12 @@ int orc_eval_pair_grad(const OrcSensor *ss, const float *Is, const float *Ds, co
     const int Hs = ss->H, Ws = ss->W, Ht = st->H, Wt = st->W;
     memset(out, 0, sizeof *out);
 
+    float *Z = NULL;   /* the pair's source z-buffer (z-buffer occlusion variant) */
+    if (prm->zbuffer && !force_valid) {
+        Z = (float *)malloc(sizeof(float) * (size_t)Ht * Wt);
+        if (!Z) return -4;
+        orc_zbuffer(ss, Ds, st, Xs, Xt, Z);
+    }
     const double *Ri = Xs, *ti = Xs + 9, *Rj = Xt, *tj = Xt + 9;
     double RjT[9], RjTRi[9], RotT[9], M_RotRjRi[9];
     transpose3(Rj, RjT);
@@ -315,6 +369,12 @@ int orc_eval_pair_grad(const OrcSensor *ss, const float *Is, const float *Ds, co
                 }
                 if (margin_out) margin_out[pix] = margin;
                 if (!vis) { status = ST_OCCLUDED; goto done; }
+                /* z-buffer variant: no more than occ_tau behind the nearest of the pair's own
+                 * points landing in the same cell (both depths as FP32, compared in FP64) */
+                if (Z && (double)(float)zeta[1] - (double)Z[(int64_t)y0 * Wt + x0] > prm->occ_tau) {
+                    status = ST_ZOCCLUDED;
+                    goto done;
+                }
             }
             if (res_out) for (int ch = 0; ch < C; ++ch) res_out[5*pix+ch] = e[ch];
 
@@ -432,6 +492,7 @@ int orc_eval_pair_grad(const OrcSensor *ss, const float *Is, const float *Ds, co
 done:
         if (status_out) status_out[pix] = status;
     }
+    free(Z);
     return 0;
 }
 
