@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default item size and grid")
+    ap.add_argument("--zbuffer", action="store_true",
+                    help="the z-buffer occlusion variant (an extra projection-only pass per evaluation)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate byte counters")
     args = ap.parse_args()
@@ -142,6 +144,8 @@ def main():
     prob = synth.make(args.workload)
     log("generated %s: %d keyframes, %d pairs in %.1f s" % (args.workload, prob.n, len(prob.pairs),
                                                              time.perf_counter() - t0))
+    if args.zbuffer:
+        prob.params["occlusion_zbuffer"] = 1
     ch = prob.params["channels"]
     sen = prob.sensors[0]
 
@@ -180,6 +184,7 @@ def main():
             "grid": r32["grid"],
             "autotune": "item size and grid chosen by pba_autotune over %d points" % len(r32["tune"])
             if r32["tune"] else "off",
+            "occlusion": "depth gate + z-buffer of the pair's source points" if args.zbuffer else "depth gate",
         },
         "roofline": {
             "bound": "hbm",

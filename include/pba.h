@@ -99,10 +99,17 @@ typedef struct {
     double occlusion_tau_pinhole, occlusion_tau_spherical;
     /* every stencil tap's depth must be within tau of the predicted depth (Sec. IV-C,
        occlusion suppression), chosen by the target sensor's model */
+    int32_t occlusion_zbuffer;   /* 1: also drop a point lying more than tau behind the nearest of
+                                    the pair's own warped source points whose integer cell floor(u')
+                                    is the same (a z-buffer of the pair's source points, depths as
+                                    FP32; Sec. IV-C occlusion suppression, z-buffer reading).  Costs
+                                    one projection-only pass over every pair per evaluation and
+                                    4 bytes per target pixel per pair of device memory; 0: off */
+    int32_t reserved;            /* must be 0 */
 } pba_config;
 
 /* Fill *cfg with defaults: F32, 5 channels, grad_mode 0, anchor 0, graphs on, Omega 1,
- * Huber 0.1, tau 0.5 m (pinhole) / 1.0 m (spherical). */
+ * Huber 0.1, tau 0.5 m (pinhole) / 1.0 m (spherical), no z-buffer. */
 void pba_config_default(pba_config *cfg);
 
 /* Create a context on cfg->device.  *out receives the handle.  PBA_EINVAL for an unknown

@@ -272,18 +272,10 @@ int orc_eval_pair_grad(const OrcSensor *ss, const float *Is, const float *Ds, co
         out->n_eval++;
         if (force_valid && !force_valid[pix]) { if (status_out) status_out[pix] = ST_SKIPPED; continue; }
 
-        /* p_u = R_o pi^-1(u, d) + t_o (source offset) */
-        double q[3], pu[3];
-        unproject(ss, (double)c, (double)r, d, q);
-        matvec3(ss->Ro, q, pu);
-        for (int k = 0; k < 3; ++k) pu[k] += ss->to[k];
-        /* y = R_j^T (R_i p_u + t_i - t_j) ; p_bar = R_o^T (y - t_o) (target offset) */
-        double w3[3], y[3], pbar[3], ym[3];
-        matvec3(Ri, pu, w3);
-        for (int k = 0; k < 3; ++k) w3[k] += ti[k] - tj[k];
-        matvec3(RjT, w3, y);
-        for (int k = 0; k < 3; ++k) ym[k] = y[k] - st->to[k];
-        matvec3(RotT, ym, pbar);
+        /* p_u = R_o pi^-1(u, d) + t_o (source offset); y = R_j^T (R_i p_u + t_i - t_j);
+         * p_bar = R_o^T (y - t_o) (target offset) */
+        double pu[3], y[3], pbar[3];
+        warp_pixel(ss, st, Xs, Xt, c, r, d, pu, y, pbar);
 
         double uv[2];
         int x0, y0;

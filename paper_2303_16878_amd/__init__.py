@@ -46,7 +46,8 @@ class pba_config(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("omega_intensity", ctypes.c_double),
                 ("omega_depth", ctypes.c_double), ("omega_normal", ctypes.c_double),
                 ("huber_delta", ctypes.c_double), ("occlusion_tau_pinhole", ctypes.c_double),
-                ("occlusion_tau_spherical", ctypes.c_double)]
+                ("occlusion_tau_spherical", ctypes.c_double), ("occlusion_zbuffer", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class pba_eval_out(ctypes.Structure):
@@ -161,7 +162,7 @@ class Context:
 
     def __init__(self, device=0, precision=PBA_F32, channels=5, grad_mode=0, anchor=0, stream=None,
                  omega_intensity=1.0, omega_depth=1.0, omega_normal=1.0, huber_delta=0.1,
-                 occlusion_tau_pinhole=0.5, occlusion_tau_spherical=1.0, use_graph=True):
+                 occlusion_tau_pinhole=0.5, occlusion_tau_spherical=1.0, use_graph=True, occlusion_zbuffer=False):
         self.lib = load_library()
         cfg = config_default()
         cfg.device, cfg.precision, cfg.channels, cfg.grad_mode, cfg.anchor = device, precision, channels, grad_mode, anchor
@@ -177,6 +178,7 @@ class Context:
         cfg.omega_intensity, cfg.omega_depth, cfg.omega_normal = omega_intensity, omega_depth, omega_normal
         cfg.huber_delta = huber_delta
         cfg.occlusion_tau_pinhole, cfg.occlusion_tau_spherical = occlusion_tau_pinhole, occlusion_tau_spherical
+        cfg.occlusion_zbuffer = int(bool(occlusion_zbuffer))
         self.cfg = cfg
         h = ctypes.c_void_p()
         self._check(self.lib.pba_create(ctypes.byref(cfg), ctypes.byref(h)), ctx=None)
@@ -455,7 +457,7 @@ def context_for_problem(prob, precision=PBA_F32, channels=None, grad_mode=0, dev
                   omega_intensity=prm["omega_intensity"], omega_depth=prm["omega_depth"],
                   omega_normal=prm["omega_normal"], huber_delta=prm["huber_delta"],
                   occlusion_tau_pinhole=prm["occ_tau_pinhole"], occlusion_tau_spherical=prm["occ_tau_spherical"],
-                  **kw)
+                  **dict(dict(occlusion_zbuffer=bool(prm.get("occlusion_zbuffer", 0))), **kw))
     for s in prob.sensors:
         ctx.add_sensor(s["model"], s["H"], s["W"], s["fx"], s["fy"], s["cx"], s["cy"], s["min_depth"],
                        s["max_depth"], s["offset"])

@@ -452,7 +452,9 @@ __device__ __forceinline__ void load_stencil(V (&t)[12], L ld, int voff, int row
 
 // ADJ: the loss adjoint -- only b (gradient) is accumulated, and dF/d(image) is scattered into
 // the gradient arenas with hardware float atomics.
-template <typename T, int NCH, int SM, int TM, int GM, bool DBG, bool ADJ = false>
+// ZB: the z-buffer occlusion variant (a separate instantiation, so the plain evaluation carries
+// none of its code).
+template <typename T, int NCH, int SM, int TM, int GM, bool DBG, bool ADJ = false, bool ZB = false>
 __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base, int n_items)
 {
     __shared__ int s_item;
@@ -525,6 +527,9 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         const float *sdep = a.dep + ks.off;
         const float4 *satt4 = a.att4 + ks.off;
         const float *satt1 = a.att1 + ks.off;
+        // z-buffer occlusion variant: this pair's source z-buffer (FP32 depth bits per target cell)
+        uint32_t *const zb = ZB ? a.zbuf + a.zoff[pair] : nullptr;
+        const double taud = ZB ? uni_d(st.taud) : 0.0;
         const uint32_t tnpx = (uint32_t)Ht * (uint32_t)Wt;
         const __amdgpu_buffer_rsrc_t r_tdep = plane_rsrc(uni_ptr(a.dep + kt.off), tnpx * 4u);
         const __amdgpu_buffer_rsrc_t r_tatt = NCH == 5 ? plane_rsrc(uni_ptr(a.att4 + kt.off), tnpx * 16u)
@@ -778,6 +783,12 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         x0 = (int)u; y0 = (int)v;
                         al = (T)(u - (double)x0); be = (T)(v - (double)y0);
                     }
+                    if (ZB && ok && a.zpass) {
+                        // z-buffer pass: keep the nearest predicted depth per target cell (depths are
+                        // positive, so their FP32 bit patterns order like the values); nothing queued
+                        atomicMin(zb + y0 * Wt + x0, __float_as_uint((float)zeta));
+                        ok = false;
+                    }
                     if (ok) {
                         if (DBG) { a.dbg_status[pix] = 4; a.dbg_cell[pix] = make_int2(x0, y0); }
                         // the 12-tap depth stencil: validity and occlusion suppression -- every tap
@@ -790,7 +801,11 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         float dmin = tD[0], dmax = tD[0];
 #pragma unroll
                         for (int k = 1; k < 12; ++k) { dmin = fminf(dmin, tD[k]); dmax = fmaxf(dmax, tD[k]); }
-                        const bool vis = fmax((T)dmax - zeta_d, zeta_d - (T)dmin) <= tau;
+                        bool vis = fmax((T)dmax - zeta_d, zeta_d - (T)dmin) <= tau;
+                        // z-buffer variant: also no more than tau behind the nearest of the pair's own
+                        // points in this cell (both depths as FP32, compared in FP64)
+                        if (ZB && vis)
+                            vis = (double)(float)zeta - (double)__uint_as_float(zb[y0 * Wt + x0]) <= taud;
                         if (vis) {
                             const T w00 = (T(1) - al) * (T(1) - be), w01 = al * (T(1) - be);
                             const T w10 = (T(1) - al) * be, w11 = al * be;
@@ -859,8 +874,12 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
 template <int NCH, int SM, int TM>
 static void launch_adj_t(const EvalArgs &a, int item_base, int n_items, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((eval_kernel<float, NCH, SM, TM, 1, false, true>), dim3(grid), dim3(kBlock), 0, st, a,
-                       item_base, n_items);
+    if (a.zbuf)
+        hipLaunchKernelGGL((eval_kernel<float, NCH, SM, TM, 1, false, true, true>), dim3(grid), dim3(kBlock), 0, st, a,
+                           item_base, n_items);
+    else
+        hipLaunchKernelGGL((eval_kernel<float, NCH, SM, TM, 1, false, true>), dim3(grid), dim3(kBlock), 0, st, a,
+                           item_base, n_items);
 }
 
 void launch_eval_adjoint(const EvalArgs &a, int channels, int sm, int tm, int item_base, int n_items, int grid,
@@ -933,8 +952,12 @@ void launch_delta_to_dx(const float *delta, double *dx, int N, hipStream_t st)
 template <typename T, int NCH, int SM, int TM, int GM, bool DBG>
 static void launch_eval_t(const EvalArgs &a, int item_base, int n_items, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((eval_kernel<T, NCH, SM, TM, GM, DBG>), dim3(grid), dim3(kBlock), 0, st, a, item_base,
-                       n_items);
+    if (a.zbuf)
+        hipLaunchKernelGGL((eval_kernel<T, NCH, SM, TM, GM, DBG, false, true>), dim3(grid), dim3(kBlock), 0, st, a,
+                           item_base, n_items);
+    else
+        hipLaunchKernelGGL((eval_kernel<T, NCH, SM, TM, GM, DBG>), dim3(grid), dim3(kBlock), 0, st, a, item_base,
+                           n_items);
 }
 
 template <typename T, int NCH, int GM, bool DBG>

@@ -66,6 +66,12 @@ struct EvalArgs {
     // loss adjoint outputs (adjoint launches only): arenas laid out like the images
     float *g_int, *g_dep, *g_nrm;
     double adj_scale;
+    // z-buffer occlusion variant (nullptr: off): per pair, Ht * Wt FP32 depth bits at zbuf + zoff[pair];
+    // zpass = 1 fills it (atomic minimum per cell) instead of evaluating
+    uint32_t *zbuf;
+    const int64_t *zoff;
+    int32_t zpass;
+    int32_t pad_z;
     // per-pixel inspection outputs (debug launches only)
     uint8_t *dbg_status;
     float2 *dbg_uv;

@@ -69,6 +69,8 @@ struct pba_ctx {
     DevBuf blk_rc, blk_ptr, blk_ent, bk_ptr, bk_ent;
     DevBuf chol_rows, chol_cols, chol_meta;
     CholPlan chol;   // tiles of the Cholesky factor that can be nonzero
+    DevBuf zbuf, zoff;   // z-buffer occlusion variant: per pair, one FP32 depth per target pixel
+    int64_t zcells = 0;
     DevBuf H, b, H_cand, b_cand, totals, A, Winv, dx, lm, fail, logbuf;
     DevBuf dbg_status, dbg_uv, dbg_cell, dbg_res;
     DevBuf loss_delta, loss_poses, g_int, g_dep, g_nrm, g_pose;
@@ -419,6 +421,17 @@ pba_status build_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::ve
     if ((s = upload(c, c->bk_ptr, bptr.data(), bptr.size() * 4))) return s;
     if ((s = upload(c, c->bk_ent, bent.data(), bent.size() * 4))) return s;
     if ((s = ensure(c, c->counters, 64 * 4))) return s;
+    if (c->cfg.occlusion_zbuffer) {   // one z-buffer per pair, sized for its target at this level
+        std::vector<int64_t> zo(std::max(P, 1), 0);
+        int64_t tot = 0;
+        for (int p = 0; p < P; ++p) {
+            zo[p] = tot;
+            tot += (int64_t)c->L().kfs_h[tgt[p]].H * c->L().kfs_h[tgt[p]].W;
+        }
+        if ((s = upload(c, c->zoff, zo.data(), zo.size() * 8))) return s;
+        if ((s = ensure(c, c->zbuf, (size_t)(tot + 2) * 4))) return s;   // whole doubles for the fill
+        c->zcells = tot;
+    }
     return build_chol_plan(c, src, tgt);
 }
 
@@ -441,7 +454,34 @@ EvalArgs make_args(pba_ctx *c)
     a.omega_d = c->cfg.omega_depth;
     a.omega_n = c->cfg.omega_normal;
     a.huber = c->cfg.huber_delta;
+    if (c->cfg.occlusion_zbuffer) {
+        a.zbuf = P_<uint32_t>(c->zbuf);
+        a.zoff = P_<int64_t>(c->zoff);
+    }
     return a;
+}
+
+// z-buffer occlusion variant: every pair's z-buffer at the poses the last pair setup used (+inf, then
+// the nearest predicted depth per target cell by a projection-only pass of the evaluation kernel),
+// then the pair setup again, which clears the queue counters for the evaluation proper.
+void zbuffer_pass(pba_ctx *c, const double *poses, hipStream_t st)
+{
+    if (!c->cfg.occlusion_zbuffer || c->P == 0) return;
+    const uint64_t inf2 = 0x7F8000007F800000ull;   // two FP32 +inf (a finite double)
+    double fill;
+    std::memcpy(&fill, &inf2, 8);
+    launch_fill(P_<double>(c->zbuf), (c->zcells + 1) / 2, fill, st);
+    EvalArgs a = make_args(c);
+    a.zpass = 1;
+    const int ngrp = (int)c->groups.size();
+    for (int g = 0; g < ngrp; ++g) {
+        const auto &G = c->groups[g];
+        a.counter = P_<uint32_t>(c->counters) + g * kXcd;
+        launch_eval(a, c->cfg.precision, c->cfg.channels, c->cfg.grad_mode, G.sm, G.tm, false, G.base, G.count,
+                    std::max(1, std::min(G.count, c->grid)), st);
+    }
+    launch_pair_setup(poses, P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->L().sensors_d), P_<KfDev>(c->L().kfs_d),
+                      P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ngrp * kXcd, st);
 }
 
 // Evaluate at `poses` into (H, b, totals).  Launch order on the context stream:
@@ -455,6 +495,7 @@ pba_status run_eval(pba_ctx *c, const double *poses, double *H, double *b, doubl
     const int ngrp = (int)c->groups.size();
     launch_pair_setup(poses, P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->L().sensors_d), P_<KfDev>(c->L().kfs_d),
                       P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ngrp * kXcd, st);
+    zbuffer_pass(c, poses, st);
     EvalArgs a = make_args(c);
     if (timed) HIP_OK(hipEventRecord(c->ev0, st));
     if (stamped) launch_stamp(P_<LmState>(c->lm), P_<double>(c->logbuf), c->log_cap, 0, st);
@@ -598,6 +639,7 @@ pba_status pba_create(const pba_config *cfg, pba_ctx **out)
         if (!std::isfinite(x)) return PBA_EINVAL;
     if (cfg->omega_intensity < 0 || cfg->omega_depth < 0 || cfg->omega_normal < 0) return PBA_EINVAL;
     if (!(cfg->occlusion_tau_pinhole > 0) || !(cfg->occlusion_tau_spherical > 0)) return PBA_EINVAL;
+    if ((cfg->occlusion_zbuffer != 0 && cfg->occlusion_zbuffer != 1) || cfg->reserved != 0) return PBA_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return PBA_EDEVICE;
     if (hipSetDevice(cfg->device) != hipSuccess) return PBA_EDEVICE;
@@ -631,7 +673,7 @@ pba_status pba_destroy(pba_ctx *c)
                       &c->bk_ent, &c->H, &c->b, &c->H_cand, &c->b_cand, &c->totals, &c->A, &c->Winv, &c->dx, &c->lm,
                       &c->fail, &c->logbuf, &c->dbg_status, &c->dbg_uv, &c->dbg_cell, &c->dbg_res,
                       &c->loss_delta, &c->loss_poses, &c->g_int, &c->g_dep, &c->g_nrm, &c->g_pose,
-                      &c->chol_rows, &c->chol_cols, &c->chol_meta};
+                      &c->chol_rows, &c->chol_cols, &c->chol_meta, &c->zbuf, &c->zoff};
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) release(*b);
@@ -1073,6 +1115,7 @@ pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float
     launch_pair_setup(P_<double>(c->loss_poses), P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->L().sensors_d),
                       P_<KfDev>(c->L().kfs_d), P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ngrp * kXcd,
                       c->stream);
+    zbuffer_pass(c, P_<double>(c->loss_poses), c->stream);
     EvalArgs a = make_args(c);
     a.g_int = P_<float>(c->g_int);
     a.g_dep = P_<float>(c->g_dep);
@@ -1391,6 +1434,7 @@ pba_status pba_debug_pair(pba_ctx *c, int32_t pair, uint8_t *status, float *uv, 
     // pair transforms at the current poses
     launch_pair_setup(P_<double>(c->poses), P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->L().sensors_d),
                       P_<KfDev>(c->L().kfs_d), P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), 64, c->stream);
+    zbuffer_pass(c, P_<double>(c->poses), c->stream);
     int2 pr;
     HIP_OK(hipMemcpyAsync(&pr, P_<int2>(c->pairs_d) + pair, sizeof pr, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));

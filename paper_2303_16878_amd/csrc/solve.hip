@@ -318,6 +318,7 @@ void launch_cholesky(double *A, double *L, double *LT, int n, double *Winv, cons
 // whole workgroup.
 constexpr int kTrsvLds = 16384;
 constexpr int kTrsvPre = kCholPre;
+constexpr int kTrsvLpr = 16;   // lanes per row of the products (per solve at n = 1800: 4 -> 393 us, 8 -> 240, 16 -> 192)
 
 // Workgroup barrier that orders LDS accesses only: global loads issued before it stay in flight
 // (__syncthreads() also waits for those).
@@ -336,16 +337,24 @@ __device__ __forceinline__ double dpp_f64(double x)
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
-constexpr int kRowRor8 = 0x128, kRowRor4 = 0x124, kRowRor2 = 0x122, kRowRor1 = 0x121;
+constexpr int kRowRor8 = 0x128, kRowRor4 = 0x124;
 
-// Sum over each 16-lane row, in every lane of the row (rotations by 8, 4, 2, 1).  Rows of a wave
-// may be active or inactive as a whole.
-__device__ __forceinline__ double row_sum(double u)
+constexpr int kHalfMirror = 0x141, kQuadXor2 = 0x4E, kQuadXor1 = 0xB1;
+
+// Sum over each aligned group of G lanes (16: rotations of the 16-lane row by 8, 4, 2, 1; 8: the
+// half-row mirror, which pairs lane i with 7 - i, then quad permutes xor 2 and xor 1; 4: the quad
+// permutes), in every lane of the group.  Groups may be active or inactive as a whole.
+template <int G>
+__device__ __forceinline__ double group_sum(double u)
 {
-    u += dpp_f64<kRowRor8>(u);
-    u += dpp_f64<kRowRor4>(u);
-    u += dpp_f64<kRowRor2>(u);
-    return u + dpp_f64<kRowRor1>(u);
+    if constexpr (G == 16) {
+        u += dpp_f64<kRowRor8>(u);
+        u += dpp_f64<kRowRor4>(u);
+    } else if constexpr (G == 8) {
+        u += dpp_f64<kHalfMirror>(u);
+    }
+    u += dpp_f64<kQuadXor2>(u);
+    return u + dpp_f64<kQuadXor1>(u);
 }
 
 // Two doubles at p (16-byte aligned) if ok, else the two at `safe`, without a branch, so every
@@ -359,8 +368,8 @@ __device__ __forceinline__ void load2_or_safe(const double *p, bool ok, double &
     b = v.y;
 }
 
-template <bool kInLds>
-__global__ void __launch_bounds__(1024) trsv_band_kernel(const double *__restrict__ L,
+template <bool kInLds, int LPR>
+__global__ void __launch_bounds__(64 * LPR) trsv_band_kernel(const double *__restrict__ L,
                                                          const double *__restrict__ LT,
                                                          const double *__restrict__ Winv, double *x, int n,
                                                          const int32_t *__restrict__ rows,
@@ -386,50 +395,53 @@ __global__ void __launch_bounds__(1024) trsv_band_kernel(const double *__restric
         for (int e = t; e < n; e += blockDim.x) vs[e] = x[e];
         sync();
     }
-    const int row = t >> 4, c4 = (t & 15) * 4;   // thread = (row of the product, 4 columns)
+    constexpr int CPL = NB / LPR;   // columns per lane
+    const int row = t / LPR, c4 = (t % LPR) * CPL;   // thread = (row of the product, CPL columns)
     auto sweep = [&](const double *M, const double *F, const int32_t *pre, const int32_t *beg, const int32_t *cnt,
                      const int32_t *list, bool forward) {
-        double wa[4], la[kTrsvPre][4], wb[4], lb[kTrsvPre][4];
-        auto fetch = [&](int kb, double (&wn)[4], double (&ln)[kTrsvPre][4]) {
+        double wa[CPL], la[kTrsvPre][CPL], wb[CPL], lb[kTrsvPre][CPL];
+        auto fetch = [&](int kb, double (&wn)[CPL], double (&ln)[kTrsvPre][CPL]) {
             const int k0 = kb * NB, nb = min(NB, n - k0);
             const double2 *Mr = reinterpret_cast<const double2 *>(M + ((int64_t)kb * NB + row) * NB + c4);
-            const double2 m01 = Mr[0], m23 = Mr[1];   // the block is zero-padded
-            wn[0] = m01.x;
-            wn[1] = m01.y;
-            wn[2] = m23.x;
-            wn[3] = m23.y;
+#pragma unroll
+            for (int h = 0; h < CPL / 2; ++h) {   // the block is zero-padded
+                const double2 m = Mr[h];
+                wn[2 * h] = m.x;
+                wn[2 * h + 1] = m.y;
+            }
 #pragma unroll
             for (int e = 0; e < kTrsvPre; ++e) {
                 const int tile = pre[kTrsvPre * kb + e];
                 const int i = tile >= 0 ? tile * NB + row : n;
 #pragma unroll
-                for (int h = 0; h < 2; ++h)   // columns c4 + 2 h, c4 + 2 h + 1 (nb is even)
+                for (int h = 0; h < CPL / 2; ++h)   // columns c4 + 2 h, c4 + 2 h + 1 (nb is even)
                     load2_or_safe(F + (int64_t)i * n + k0 + c4 + 2 * h, i < n && c4 + 2 * h < nb, ln[e][2 * h],
                                   ln[e][2 * h + 1], M);
             }
         };
-        auto step = [&](int kb, const double (&w)[4], const double (&l)[kTrsvPre][4]) {
+        auto step = [&](int kb, const double (&w)[CPL], const double (&l)[kTrsvPre][CPL]) {
             const int k0 = kb * NB, nb = min(NB, n - k0);
             double u = 0.0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) u = fma(w[q], c4 + q < nb ? v[k0 + c4 + q] : 0.0, u);
-            u = row_sum(u);   // zero for rows beyond the block (M is zero-padded)
-            if ((t & 15) == 0) vk[row] = u;
+            for (int q = 0; q < CPL; ++q) u = fma(w[q], c4 + q < nb ? v[k0 + c4 + q] : 0.0, u);
+            u = group_sum<LPR>(u);   // zero for rows beyond the block (M is zero-padded)
+            const bool lead = t % LPR == 0;
+            if (lead) vk[row] = u;
             sync();
-            if ((t & 15) == 0 && row < nb) v[k0 + row] = u;
-            double vq[4];
+            if (lead && row < nb) v[k0 + row] = u;
+            double vq[CPL];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) vq[q] = vk[c4 + q];
+            for (int q = 0; q < CPL; ++q) vq[q] = vk[c4 + q];
 #pragma unroll
             for (int e = 0; e < kTrsvPre; ++e) {
                 const int tile = pre[kTrsvPre * kb + e];
                 const int i = tile >= 0 ? tile * NB + row : n;
-                if (i < n) {   // uniform over the row's 16 lanes
+                if (i < n) {   // uniform over the row's lanes
                     double z = 0.0;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) z = fma(l[e][q], vq[q], z);
-                    z = row_sum(z);
-                    if ((t & 15) == 0) v[i] -= z;
+                    for (int q = 0; q < CPL; ++q) z = fma(l[e][q], vq[q], z);
+                    z = group_sum<LPR>(z);
+                    if (lead) v[i] -= z;
                 }
             }
             for (int e = kTrsvPre; e < cnt[kb]; ++e) {
@@ -437,10 +449,10 @@ __global__ void __launch_bounds__(1024) trsv_band_kernel(const double *__restric
                 if (i >= n) continue;
                 double z = 0.0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < CPL; ++q)
                     if (c4 + q < nb) z = fma(F[(int64_t)i * n + k0 + c4 + q], vq[q], z);
-                z = row_sum(z);
-                if ((t & 15) == 0) v[i] -= z;
+                z = group_sum<LPR>(z);
+                if (lead) v[i] -= z;
             }
             sync();
         };
@@ -470,15 +482,26 @@ void launch_chol_solve(const double *L, const double *LT, double *Winv, double *
                        const int32_t *fail, hipStream_t st)
 {
     // PBA_TRSV_LDS_MAX (doubles, at most kTrsvLds) lowers the size up to which the vector is kept
-    // in LDS; 0 selects the global-memory variant for every size.
-    int lds_max = kTrsvLds;
+    // in LDS; 0 selects the global-memory variant for every size.  PBA_TRSV_LPR (4, 8 or 16) sets
+    // the lanes per row of the products.
+    int lds_max = kTrsvLds, lpr = kTrsvLpr;
     if (const char *e = std::getenv("PBA_TRSV_LDS_MAX")) lds_max = std::min(kTrsvLds, std::max(0, std::atoi(e)));
-    if (n <= lds_max)
-        hipLaunchKernelGGL(trsv_band_kernel<true>, dim3(1), dim3(1024), 0, st, L, LT, Winv, x, n, plan.rows,
-                           plan.cols, plan.meta, fail);
-    else
-        hipLaunchKernelGGL(trsv_band_kernel<false>, dim3(1), dim3(1024), 0, st, L, LT, Winv, x, n, plan.rows,
-                           plan.cols, plan.meta, fail);
+    if (const char *e = std::getenv("PBA_TRSV_LPR")) lpr = std::atoi(e);
+    const bool in_lds = n <= lds_max;
+#define PBA_TRSV_LAUNCH(LDS, G)                                                                                 \
+    hipLaunchKernelGGL((trsv_band_kernel<LDS, G>), dim3(1), dim3(64 * G), 0, st, L, LT, Winv, x, n, plan.rows, \
+                       plan.cols, plan.meta, fail)
+    if (lpr == 4) {
+        if (in_lds) PBA_TRSV_LAUNCH(true, 4);
+        else PBA_TRSV_LAUNCH(false, 4);
+    } else if (lpr == 16) {
+        if (in_lds) PBA_TRSV_LAUNCH(true, 16);
+        else PBA_TRSV_LAUNCH(false, 16);
+    } else {
+        if (in_lds) PBA_TRSV_LAUNCH(true, 8);
+        else PBA_TRSV_LAUNCH(false, 8);
+    }
+#undef PBA_TRSV_LAUNCH
 }
 
 // ---- pose update

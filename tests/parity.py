@@ -12,7 +12,7 @@ import numpy as np
 
 import oracle
 
-GPU_STATUS_FROM_ORACLE = np.array([0, 1, 2, 3, 4, 4, 6], np.uint8)
+GPU_STATUS_FROM_ORACLE = np.array([0, 1, 2, 3, 4, 4, 6, 4], np.uint8)
 
 
 def compare_pair_masks(ctx, prob, poses, k, band=1e-4, gate=1e-5, params=None, grad_mode=0):
@@ -29,6 +29,20 @@ def compare_pair_masks(ctx, prob, poses, k, band=1e-4, gate=1e-5, params=None, g
     dist = np.where(np.isfinite(dist), dist, np.inf)
     near_int = dist < band
     near_gate = np.abs(np.nan_to_num(o["margin"], nan=np.inf)) < gate
+    if (params or prob.params).get("occlusion_zbuffer", 0):
+        # z-buffer variant: a point within the band of a cell boundary may enter either cell's
+        # z-buffer, so the decisions of the points in the cells it can reach are ties as well
+        Wt = prob.sensors[prob.kf_sensor[t]]["W"]
+        fin = np.isfinite(uv).all(-1)
+        bu = uv[near_int & fin]
+        tied = set()
+        for du in (-band, band):
+            for dv in (-band, band):
+                cx, cy = np.floor(bu[:, 0] + du).astype(np.int64), np.floor(bu[:, 1] + dv).astype(np.int64)
+                tied.update((cy * Wt + cx).tolist())
+        own = np.full(uv.shape[:2], -1, np.int64)
+        own[fin] = (np.floor(uv[fin][:, 1]).astype(np.int64) * Wt + np.floor(uv[fin][:, 0]).astype(np.int64))
+        near_gate = near_gate | np.isin(own, np.fromiter(tied, np.int64, len(tied)))
     bad = mism & ~near_int & ~near_gate
     code_mismatch = (GPU_STATUS_FROM_ORACLE[o["status"]] != g["status"]) & ~mism & ~near_int & ~near_gate
     return dict(gpu=g, orc=o, n_mismatch=int(mism.sum()), n_band=int((mism & near_int).sum()),

@@ -269,14 +269,16 @@ def test_multiblock_solve_and_lm(pba):
 
 
 @pytest.mark.parametrize("lds_max", [None, "0"])
-def test_scattered_pattern_solve(pba, lds_max, monkeypatch):
+@pytest.mark.parametrize("lpr", ["4", "8", "16"])
+def test_scattered_pattern_solve(pba, lds_max, lpr, monkeypatch):
     """Keyframes mapped to pose variables by a random permutation: the chain of pairs then couples
     each 64-wide block to most others and the factorisation fills in, so block columns carry more
     tiles than the triangular solve prefetches.  The solve matches a dense solve of the same
     system, with the vector of the triangular solves in LDS and (PBA_TRSV_LDS_MAX=0) in global
-    memory."""
+    memory, for each supported number of lanes per row of their products (PBA_TRSV_LPR)."""
     if lds_max is not None:
         monkeypatch.setenv("PBA_TRSV_LDS_MAX", lds_max)
+    monkeypatch.setenv("PBA_TRSV_LPR", lpr)
     n_kf = 72
     prob = synth.make("lidar128", kfs=range(n_kf), H=16, W=256).subset(range(n_kf))
     perm = np.random.default_rng(7).permutation(n_kf).astype(np.int32)
