@@ -186,7 +186,7 @@ template <int RA, int RB>
 __device__ __forceinline__ void tile_nt(const double (*P)[NB + 1], const double (*Q)[NB + 1], int tx, int ty,
                                         double (&c)[RA][RB])
 {
-#pragma unroll 16
+#pragma unroll 32
     for (int k = 0; k < NB; ++k) {
         double p[RA], q[RB];
 #pragma unroll
