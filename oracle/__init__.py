@@ -99,7 +99,7 @@ def _load():
                                       vp, vp, vp, ctypes.POINTER(OrcParams), vp, vp,
                                       ctypes.POINTER(OrcPairOut), vp, vp, vp, vp]
         lib.orc_eval_pair_grad.restype = ctypes.c_int
-        lib.orc_eval_pair_grad.argtypes = lib.orc_eval_pair.argtypes + [ctypes.POINTER(OrcImageGrad)]
+        lib.orc_eval_pair_grad.argtypes = lib.orc_eval_pair.argtypes + [vp, ctypes.POINTER(OrcImageGrad)]
         lib.orc_zbuffer.restype = None
         lib.orc_zbuffer.argtypes = [ctypes.POINTER(OrcSensor), vp, ctypes.POINTER(OrcSensor), vp, vp, vp]
         lib.orc_eval_pairs.restype = ctypes.c_int
@@ -147,7 +147,8 @@ def eval_pair(prob, poses, s, t, params=None, force_valid=None, force_cell=None,
               grad_mode=0):
     """One ordered pair (s -> t).
 
-    Returns dict(H12, b12, babs12, F, n_eval, n_valid[, status, uv, res, margin])."""
+    Returns dict(H12, b12, babs12, F, n_eval, n_valid[, status, uv, res, margin, G]); G is the
+    per-pixel image Jacobian [H, W, 5, 2] (d/dcol, d/drow of each channel at u'; NaN where not valid)."""
     lib = _load()
     params = prob.params if params is None else params
     ss, st = prob.sensors[prob.kf_sensor[s]], prob.sensors[prob.kf_sensor[t]]
@@ -161,24 +162,26 @@ def eval_pair(prob, poses, s, t, params=None, force_valid=None, force_cell=None,
     uv = np.empty((Hs, Ws, 2), np.float64) if pixels else None
     res = np.empty((Hs, Ws, 5), np.float64) if pixels else None
     margin = np.empty((Hs, Ws), np.float64) if pixels else None
+    gimg = np.empty((Hs, Ws, 5, 2), np.float64) if pixels else None
     fv = _c(force_valid, np.uint8) if force_valid is not None else None
     fc = _c(force_cell, np.int32) if force_cell is not None else None
-    rc = lib.orc_eval_pair(ctypes.byref(sensor_struct(ss)), Is.ctypes.data, Ds.ctypes.data, Ns.ctypes.data,
-                           ctypes.byref(sensor_struct(st)), It.ctypes.data, Dt.ctypes.data, Nt.ctypes.data,
-                           Xs.ctypes.data, Xt.ctypes.data, ctypes.byref(prm),
-                           fv.ctypes.data if fv is not None else None,
-                           fc.ctypes.data if fc is not None else None,
-                           ctypes.byref(out),
-                           status.ctypes.data if pixels else None,
-                           uv.ctypes.data if pixels else None,
-                           res.ctypes.data if pixels else None,
-                           margin.ctypes.data if pixels else None)
+    rc = lib.orc_eval_pair_grad(ctypes.byref(sensor_struct(ss)), Is.ctypes.data, Ds.ctypes.data, Ns.ctypes.data,
+                                ctypes.byref(sensor_struct(st)), It.ctypes.data, Dt.ctypes.data, Nt.ctypes.data,
+                                Xs.ctypes.data, Xt.ctypes.data, ctypes.byref(prm),
+                                fv.ctypes.data if fv is not None else None,
+                                fc.ctypes.data if fc is not None else None,
+                                ctypes.byref(out),
+                                status.ctypes.data if pixels else None,
+                                uv.ctypes.data if pixels else None,
+                                res.ctypes.data if pixels else None,
+                                margin.ctypes.data if pixels else None,
+                                gimg.ctypes.data if pixels else None, None)
     if rc != 0:
         raise RuntimeError("orc_eval_pair failed (%d)" % rc)
     r = dict(H12=np.array(out.H).reshape(12, 12), b12=np.array(out.b), babs12=np.array(out.babs), F=out.F,
              n_eval=out.n_eval, n_valid=out.n_valid)
     if pixels:
-        r.update(status=status, uv=uv, res=res, margin=margin)
+        r.update(status=status, uv=uv, res=res, margin=margin, G=gimg)
     return r
 
 
@@ -610,7 +613,7 @@ def loss_and_grad(prob, poses0, delta, params=None, pairs=None):
                                     imgs[2].ctypes.data, ctypes.byref(sensor_struct(st)), imgs[3].ctypes.data,
                                     imgs[4].ctypes.data, imgs[5].ctypes.data, Xs.ctypes.data, Xt.ctypes.data,
                                     ctypes.byref(params_struct(params, st["model"], 1)), None, None,
-                                    ctypes.byref(out), None, None, None, None, ctypes.byref(ig))
+                                    ctypes.byref(out), None, None, None, None, None, ctypes.byref(ig))
         if rc != 0:
             raise RuntimeError("orc_eval_pair_grad failed (%d)" % rc)
         F += out.F

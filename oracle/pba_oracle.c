@@ -206,7 +206,8 @@ static double huber_rho(double chi2, double delta, double *w) {
  * correspondences).
  * Optional per-pixel outputs: status (uint8), uv (2 doubles), res (5 doubles) and
  * margin (1 double: min over the stencil taps of occ_tau - |depth_tap - zeta^d|,
- * written for pixels that reach the occlusion test).
+ * written for pixels that reach the occlusion test) and imgjac (10 doubles: the image
+ * Jacobian g_c = [dI/dcol, dI/drow] of each channel at u', written for valid pixels).
  */
 /* Gradients of F with respect to the images (loss adjoint), accumulated when non-NULL:
  * source and target intensity [H][W], depth [H][W], normals [H][W][3].  The masks, the
@@ -222,7 +223,7 @@ int orc_eval_pair_grad(const OrcSensor *ss, const float *Is, const float *Ds, co
                        const double *Xs, const double *Xt, const OrcParams *prm,
                        const uint8_t *force_valid, const int32_t *force_cell,
                        OrcPairOut *out, uint8_t *status_out, double *uv_out, double *res_out,
-                       double *margin_out, const OrcImageGrad *ig);
+                       double *margin_out, double *imgjac_out, const OrcImageGrad *ig);
 
 int orc_eval_pair(const OrcSensor *ss, const float *Is, const float *Ds, const float *Ns,
                   const OrcSensor *st, const float *It, const float *Dt, const float *Nt,
@@ -232,7 +233,7 @@ int orc_eval_pair(const OrcSensor *ss, const float *Is, const float *Ds, const f
                   double *margin_out)
 {
     return orc_eval_pair_grad(ss, Is, Ds, Ns, st, It, Dt, Nt, Xs, Xt, prm, force_valid, force_cell, out,
-                              status_out, uv_out, res_out, margin_out, NULL);
+                              status_out, uv_out, res_out, margin_out, NULL, NULL);
 }
 
 int orc_eval_pair_grad(const OrcSensor *ss, const float *Is, const float *Ds, const float *Ns,
@@ -240,7 +241,7 @@ int orc_eval_pair_grad(const OrcSensor *ss, const float *Is, const float *Ds, co
                        const double *Xs, const double *Xt, const OrcParams *prm,
                        const uint8_t *force_valid, const int32_t *force_cell,
                        OrcPairOut *out, uint8_t *status_out, double *uv_out, double *res_out,
-                       double *margin_out, const OrcImageGrad *ig)
+                       double *margin_out, double *imgjac_out, const OrcImageGrad *ig)
 {
     const int C = prm->channels;
     const int Hs = ss->H, Ws = ss->W, Ht = st->H, Wt = st->W;
@@ -266,6 +267,7 @@ int orc_eval_pair_grad(const OrcSensor *ss, const float *Is, const float *Ds, co
         if (uv_out) { uv_out[2*pix] = NAN; uv_out[2*pix+1] = NAN; }
         if (res_out) for (int k = 0; k < 5; ++k) res_out[5*pix+k] = NAN;
         if (margin_out) margin_out[pix] = NAN;
+        if (imgjac_out) for (int k = 0; k < 10; ++k) imgjac_out[10*pix+k] = NAN;
 
         const double d = px(Ds, Ws, r, c);
         if (!depth_ok(d, ss)) continue;
@@ -369,6 +371,10 @@ int orc_eval_pair_grad(const OrcSensor *ss, const float *Is, const float *Ds, co
                 }
             }
             if (res_out) for (int ch = 0; ch < C; ++ch) res_out[5*pix+ch] = e[ch];
+            if (imgjac_out) for (int ch = 0; ch < C; ++ch) {
+                imgjac_out[10*pix+2*ch] = G[ch][0];
+                imgjac_out[10*pix+2*ch+1] = G[ch][1];
+            }
 
             double chi2 = prm->omega[0] * e[0] * e[0] + prm->omega[1] * e[1] * e[1];
             for (int ch = 2; ch < C; ++ch) chi2 += prm->omega[2] * e[ch] * e[ch];

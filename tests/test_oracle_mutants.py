@@ -5,7 +5,12 @@ the oracle trips them.  Each mutant below is one such slip (a sign, a factor,
 a transpose, the printed source-normal Jacobian, a dropped half in the central
 difference, the wrong depth cue, two slips in the loss adjoint, two in the sensor offsets); the checks are
 condensed versions of the pins: FD gradient, ground-truth residuals, the
-linear-ramp identity and FD of the image gradients.
+linear-ramp identity, FD of the image gradients, the closed-form image Jacobian on
+quadratic textures, the exact valid set of the border rule and the brute-force pair
+evaluation on tiny images.  The last three mutants (a central difference from the wrong
+rows, two blend weights exchanged, the border one column too permissive) pass the FD,
+ground-truth, ramp and adjoint checks; the quadratic-texture and valid-set pins and the
+brute force catch them (the first two mutants: quadratic and brute force; the third: all three).
 """
 import os
 import subprocess
@@ -15,7 +20,9 @@ import pytest
 
 import oracle
 import synth
+from test_oracle_bruteforce import compare_with_oracle, tiny_rig
 from test_oracle_pins import fd_grad_F
+from test_oracle_stencil import expected_valid, quadratic_G_error, valid_set
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "pba_oracle.c")
 
@@ -39,6 +46,14 @@ MUTANTS = {
     "source_offset_sign": ("for (int k = 0; k < 3; ++k) pu[k] += ss->to[k];",
                            "for (int k = 0; k < 3; ++k) pu[k] -= ss->to[k];"),
     "target_offset_untransposed": ("matvec3(RotT, ym, pbar);", "matvec3(st->Ro, ym, pbar);"),
+    # the image-Jacobian stencil: a central difference read from the wrong rows, the bilinear
+    # weights of two taps exchanged, the border rule one column too permissive
+    "gr10_wrong_row": ("double gr10 = 0.5 * (T(y0+2, x0) - T(y0, x0));",
+                       "double gr10 = 0.5 * (T(y0+1, x0) - T(y0-1, x0));"),
+    "blend_weights_swapped": ("G[ch][0] = (1-bb) * ((1-a) * gc00 + a * gc01) + bb * ((1-a) * gc10 + a * gc11);",
+                              "G[ch][0] = (1-bb) * ((1-a) * gc00 + a * gc10) + bb * ((1-a) * gc01 + a * gc11);"),
+    "stencil_bound_off_by_one": ("fx0 <= Wt - 3.0 && fy0 >= 1.0 && fy0 <= Ht - 3.0)) { status",
+                                 "fx0 <= Wt - 2.0 && fy0 >= 1.0 && fy0 <= Ht - 3.0)) { status"),
 }
 
 
@@ -96,6 +111,33 @@ def _adj_ok(p, prm):
     return True
 
 
+def _quadratic_ok(rg, li):
+    for p in (rg, li):
+        for gm in (0, 1):
+            err, n, verr, _ = quadratic_G_error(p, 1, 0, gm)
+            if not (n > 2000 and err < 1e-12 and verr < 1e-12):
+                return False
+    return True
+
+
+def _valid_set_ok():
+    for kx, ky in ((2.5, 0.5), (-2.5, -0.5)):
+        r, H, W = valid_set(kx, ky)
+        if not np.array_equal(r["status"] == oracle.ST_VALID, expected_valid(kx, ky, H, W)):
+            return False
+    return True
+
+
+def _brute_ok(rig):
+    try:
+        for s, t in ((0, 1), (2, 3), (0, 2), (2, 0)):
+            for X in (rig.gt_poses, rig.init_poses):
+                compare_with_oracle(rig, X, s, t, rig.params, 0)
+    except AssertionError:
+        return False
+    return True
+
+
 @pytest.fixture(scope="module")
 def problems():
     rg = synth.make("rgbd_small")
@@ -104,7 +146,7 @@ def problems():
     lic = synth.make("lidar128", kfs=[0, 1], H=32, W=512, noise=False).subset([0, 1])
     kfs = [0, 1, 200, 201]   # two LiDAR and two camera keyframes of the joint rig
     jc = synth.make("joint", H_l=32, W_l=256, H_c=60, W_c=80, kfs=kfs, noise=False).subset(kfs)
-    return rg, rgc, li, lic, jc
+    return rg, rgc, li, lic, jc, tiny_rig()
 
 
 def _joint_gt_ok(jc):
@@ -122,12 +164,13 @@ def _joint_gt_ok(jc):
 
 
 def _checks(problems):
-    rg, rgc, li, lic, jc = problems
+    rg, rgc, li, lic, jc, rig = problems
     p5 = dict(rg.params, channels=5)
     l5 = dict(li.params, channels=5)
     return {"fd_rgbd": _fd_ok(rg, p5), "fd_lidar": _fd_ok(li, l5), "gt_rgbd": _gt_ok(rgc, p5),
             "gt_lidar": _gt_ok(lic, l5), "ramp": _ramp_ok(rg, p5), "adjoint": _adj_ok(rg, p5),
-            "gt_joint": _joint_gt_ok(jc)}
+            "gt_joint": _joint_gt_ok(jc), "quadratic": _quadratic_ok(rg, li), "valid_set": _valid_set_ok(),
+            "brute": _brute_ok(rig)}
 
 
 def test_unmutated_oracle_passes_condensed_checks(problems):
@@ -151,3 +194,10 @@ def test_planted_mistake_is_caught(name, problems, tmp_path):
     finally:
         oracle.use_library(os.path.join(os.path.dirname(SRC), "liboracle.so"))
     assert not all(res.values()), (name, res)
+    if name in DESIGNED:
+        assert not res[DESIGNED[name]], (name, res)
+
+
+# the pin each stencil mutant was designed against (it must be among those that fail)
+DESIGNED = {"gr10_wrong_row": "quadratic", "blend_weights_swapped": "quadratic",
+            "stencil_bound_off_by_one": "valid_set"}
