@@ -106,6 +106,14 @@ typedef struct {
                                     one projection-only pass over every pair per evaluation and
                                     4 bytes per target pixel per pair of device memory; 0: off */
     int32_t reserved;            /* must be 0 */
+    /* Device memory of the context (images, plans, systems, work buffers) comes from these
+     * callbacks when both are set (e.g. a framework's caching allocator), else from hipMalloc.
+     * dev_alloc(bytes, alloc_user) returns device memory of cfg->device usable on cfg->stream, or
+     * NULL (the call then fails with PBA_ENOMEM); dev_free(ptr, bytes, alloc_user) returns it.
+     * Both must stay callable until pba_destroy returns; setting only one is PBA_EINVAL. */
+    void *(*dev_alloc)(size_t bytes, void *alloc_user);
+    void (*dev_free)(void *ptr, size_t bytes, void *alloc_user);
+    void *alloc_user;
 } pba_config;
 
 /* Fill *cfg with defaults: F32, 5 channels, grad_mode 0, anchor 0, graphs on, Omega 1,
@@ -176,7 +184,8 @@ typedef struct {
     double step_norm;            /* |dx| of the step tried */
     int64_t n_valid;
     int32_t accepted;            /* 1 if the step was taken */
-    int32_t pad;
+    float ms;                    /* device time of the iteration (solve, update, evaluation,
+                                    decision) from wall-clock stamps; -1 if unavailable */
 } pba_iter_log;
 
 /* Run n_iters Gauss-Newton (use_lm = 0: every solved step taken) or Levenberg-Marquardt

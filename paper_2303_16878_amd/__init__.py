@@ -47,7 +47,8 @@ class pba_config(ctypes.Structure):
                 ("omega_depth", ctypes.c_double), ("omega_normal", ctypes.c_double),
                 ("huber_delta", ctypes.c_double), ("occlusion_tau_pinhole", ctypes.c_double),
                 ("occlusion_tau_spherical", ctypes.c_double), ("occlusion_zbuffer", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("dev_alloc", ctypes.c_void_p), ("dev_free", ctypes.c_void_p),
+                ("alloc_user", ctypes.c_void_p)]
 
 
 class pba_eval_out(ctypes.Structure):
@@ -58,7 +59,7 @@ class pba_eval_out(ctypes.Structure):
 
 class pba_iter_log(ctypes.Structure):
     _fields_ = [("F", ctypes.c_double), ("lambda_", ctypes.c_double), ("step_norm", ctypes.c_double),
-                ("n_valid", ctypes.c_int64), ("accepted", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("n_valid", ctypes.c_int64), ("accepted", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 class pba_tune_point(ctypes.Structure):
@@ -72,6 +73,54 @@ class pba_timings(ctypes.Structure):
 
 
 _lib = None
+
+# device allocator callbacks of pba_config (dev_alloc, dev_free)
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """Routes the library's device allocations through torch's caching allocator (on the
+    context's device and stream).  Holds the ctypes callbacks alive for the context's life."""
+
+    def __init__(self, device, stream):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.stream = stream          # torch.cuda.Stream the library works on
+        self.live = {}
+
+        def _alloc(nbytes, user):
+            try:
+                ptr = int(torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device, stream=self.stream))
+            except Exception:
+                return None
+            self.live[ptr] = int(nbytes)
+            return ptr
+
+        def _free(ptr, nbytes, user):
+            if ptr and self.live.pop(int(ptr), None) is not None:
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+        self.alloc_cb = _ALLOC_T(_alloc)
+        self.free_cb = _FREE_T(_free)
+
+    def install(self, cfg):
+        cfg.dev_alloc = ctypes.cast(self.alloc_cb, ctypes.c_void_p)
+        cfg.dev_free = ctypes.cast(self.free_cb, ctypes.c_void_p)
+        cfg.alloc_user = None
+
+
+_open_contexts = None
+
+
+def _close_open_contexts():
+    # contexts whose memory belongs to torch's allocator are destroyed before torch shuts down
+    for ctx in list(_open_contexts or ()):
+        try:
+            ctx.close()
+        except Exception:
+            pass
 
 
 def load_library(path: str = LIB_PATH):
@@ -162,19 +211,31 @@ class Context:
 
     def __init__(self, device=0, precision=PBA_F32, channels=5, grad_mode=0, anchor=0, stream=None,
                  omega_intensity=1.0, omega_depth=1.0, omega_normal=1.0, huber_delta=0.1,
-                 occlusion_tau_pinhole=0.5, occlusion_tau_spherical=1.0, use_graph=True, occlusion_zbuffer=False):
+                 occlusion_tau_pinhole=0.5, occlusion_tau_spherical=1.0, use_graph=True, occlusion_zbuffer=False,
+                 allocator="torch"):
+        """allocator: "torch" -- device memory from torch's caching allocator (when torch sees a GPU
+        and no raw stream handle is given), "hip" -- the library's own hipMalloc."""
         self.lib = load_library()
+        self.h = None
+        self.allocator = None
         cfg = config_default()
         cfg.device, cfg.precision, cfg.channels, cfg.grad_mode, cfg.anchor = device, precision, channels, grad_mode, anchor
         cfg.use_graph = int(bool(use_graph))
+        tstream = None
         if stream is None:
             try:
                 import torch
                 if torch.cuda.is_available():
-                    stream = torch.cuda.current_stream(device).cuda_stream
+                    tstream = torch.cuda.current_stream(device)
+                    stream = tstream.cuda_stream
             except ImportError:
                 stream = None
         cfg.stream = stream
+        if allocator == "torch" and tstream is not None:
+            self.allocator = TorchAllocator(device, tstream)
+            self.allocator.install(cfg)
+        elif allocator not in ("torch", "hip"):
+            raise ValueError("allocator must be 'torch' or 'hip'")
         cfg.omega_intensity, cfg.omega_depth, cfg.omega_normal = omega_intensity, omega_depth, omega_normal
         cfg.huber_delta = huber_delta
         cfg.occlusion_tau_pinhole, cfg.occlusion_tau_spherical = occlusion_tau_pinhole, occlusion_tau_spherical
@@ -183,6 +244,13 @@ class Context:
         h = ctypes.c_void_p()
         self._check(self.lib.pba_create(ctypes.byref(cfg), ctypes.byref(h)), ctx=None)
         self.h = h
+        global _open_contexts
+        if _open_contexts is None:
+            import atexit
+            import weakref
+            _open_contexts = weakref.WeakSet()
+            atexit.register(_close_open_contexts)
+        _open_contexts.add(self)
         self.n = 0
         self.n_poses = 0
         self.p = 0
@@ -318,7 +386,7 @@ class Context:
         logs = (pba_iter_log * max(1, n_iters))()
         self._check(self.lib.pba_iterate(self.h, int(n_iters), int(bool(use_lm)), float(lambda0),
                                          ctypes.cast(logs, ctypes.c_void_p)))
-        return [dict(F=l.F, lam=l.lambda_, step=l.step_norm, n_valid=l.n_valid, accepted=bool(l.accepted))
+        return [dict(F=l.F, lam=l.lambda_, step=l.step_norm, n_valid=l.n_valid, accepted=bool(l.accepted), ms=l.ms)
                 for l in logs[:n_iters]]
 
     def estimate_normals(self, radius_m=0.1, min_px=2.0, max_px=5.0, min_count=5):

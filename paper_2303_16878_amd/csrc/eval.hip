@@ -80,15 +80,9 @@ __global__ void pair_setup_kernel(const double *__restrict__ poses, const int2 *
     double c[3];
     mtv3(st.Ro, st.to, c);
     PairDev &o = out[p];
-    for (int k = 0; k < 9; ++k) {
-        o.Rd[k] = R[k];
-        o.R[k] = (float)R[k];
-        o.Rlo[k] = (float)(R[k] - (double)o.R[k]);
-    }
+    for (int k = 0; k < 9; ++k) o.Rd[k] = R[k];
     for (int k = 0; k < 3; ++k) {
         o.td[k] = tv[k];
-        o.t[k] = (float)tv[k];
-        o.tlo[k] = (float)(tv[k] - (double)o.t[k]);
         o.c[k] = (float)c[k];
     }
     // D = R_ot^T ; A = [[-Rp, 2 skewp(tp) Rp], [0, -Rp]] ; E = blockdiag(D, D) A

@@ -12,6 +12,9 @@ constexpr int kAcc = 32;         // accumulator slots per work item
 // accumulator layout: 21 upper-triangular H terms, 6 b terms, F, valid, evaluated
 enum { ACC_H = 0, ACC_B = 21, ACC_F = 27, ACC_VALID = 28, ACC_EVAL = 29, ACC_USED = 30 };
 constexpr int kPairOut = 160;    // PBA_PAIR_OUT_LEN
+// one row of the LM log per iteration: F, lambda, step norm, valid, accepted, solve failed, then
+// device wall-clock stamps: evaluation begin / end, iteration begin / end
+constexpr int kLogRow = 10;
 // packed depth of a pixel without a valid measurement: negative, so it fails any depth test
 // and every occlusion bound |D - zeta| <= tau
 constexpr float kNoDepth = -1e30f;
@@ -34,12 +37,10 @@ struct KfDev {
 };
 
 // Per-pair transform from the source sensor frame to the target sensor frame,
-// p_bar = R q + t for q = pi_s^-1(u, d), and c = R_ot^T t_ot so that the target
-// platform point expressed in the target sensor axes is y'' = p_bar + c.
+// p_bar = Rd q + td for q = pi_s^-1(u, d) (FP64 in both paths), and c = R_ot^T t_ot so that the
+// target platform point expressed in the target sensor axes is y'' = p_bar + c.
 struct alignas(16) PairDev {
-    float R[9], t[3], c[3], pad;
-    float Rlo[9], tlo[3];        // FP32 path: R = R + Rlo, t = t + tlo to ~48 bits, so that the
-                                 // rounding of the pair transform does not shift every point alike
+    float c[3], pad;
     double Rd[9], td[3];
     double D[9];                 // R_ot^T: target-sensor axes of the platform perturbation
     double E[36];                // D A: source-pose rows follow as J_s = J' E (6x6 row-major)
@@ -50,7 +51,7 @@ struct EvalArgs {
     const SensorDev *sensors;
     const KfDev *kfs;
     const PairDev *pairs;
-    const float *dep;            // depth plane (invalid pixels hold 0)
+    const float *dep;            // depth plane (pixels without a valid depth hold kNoDepth)
     const float4 *att4;          // 5 channels: {intensity, nx, ny, nz}
     const float *att1;           // 2 channels: intensity
     const float2 *lut32;         // ray tables, FP32

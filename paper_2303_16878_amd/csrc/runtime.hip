@@ -23,6 +23,7 @@ namespace {
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    const pba_config *via = nullptr;   // config whose allocator callbacks own p (nullptr: hipMalloc)
 };
 
 }  // namespace
@@ -112,27 +113,37 @@ pba_status fail(pba_ctx *c, pba_status s, const char *fmt, ...)
         if (e_ != hipSuccess) return fail(c, PBA_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));       \
     } while (0)
 
+void release(DevBuf &b)
+{
+    if (b.p) {
+        if (b.via) b.via->dev_free(b.p, b.bytes, b.via->alloc_user);
+        else (void)hipFree(b.p);
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+    b.via = nullptr;
+}
+
+// Device memory of at least `bytes` in b (kept if already large enough), through the caller's
+// allocator callbacks when the config has them, else hipMalloc.
 pba_status ensure(pba_ctx *c, DevBuf &b, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
     if (b.bytes >= bytes) return PBA_OK;
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
-    hipError_t e = hipMalloc(&b.p, bytes);
-    if (e != hipSuccess) {
-        b.p = nullptr;
-        return fail(c, PBA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    release(b);
+    if (c->cfg.dev_alloc) {
+        b.p = c->cfg.dev_alloc(bytes, c->cfg.alloc_user);
+        if (!b.p) return fail(c, PBA_ENOMEM, "allocator callback returned NULL for %zu bytes", bytes);
+        b.via = &c->cfg;
+    } else {
+        hipError_t e = hipMalloc(&b.p, bytes);
+        if (e != hipSuccess) {
+            b.p = nullptr;
+            return fail(c, PBA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        }
     }
     b.bytes = bytes;
     return PBA_OK;
-}
-
-void release(DevBuf &b)
-{
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
 }
 
 template <typename T>
@@ -533,6 +544,7 @@ pba_status enqueue_iteration(pba_ctx *c, hipStream_t st)
 {
     const int n = n_sys(c);
     double *totals = P_<double>(c->totals);   // [0..3] current, [4..7] candidate
+    launch_stamp(P_<LmState>(c->lm), P_<double>(c->logbuf), c->log_cap, 2, st);
     launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
                      P_<LmState>(c->lm), -1.0, st);
     double *Lf = P_<double>(c->A) + (size_t)n * n, *LTf = Lf + (size_t)n * n;
@@ -640,6 +652,7 @@ pba_status pba_create(const pba_config *cfg, pba_ctx **out)
     if (cfg->omega_intensity < 0 || cfg->omega_depth < 0 || cfg->omega_normal < 0) return PBA_EINVAL;
     if (!(cfg->occlusion_tau_pinhole > 0) || !(cfg->occlusion_tau_spherical > 0)) return PBA_EINVAL;
     if ((cfg->occlusion_zbuffer != 0 && cfg->occlusion_zbuffer != 1) || cfg->reserved != 0) return PBA_EINVAL;
+    if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return PBA_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return PBA_EDEVICE;
     if (hipSetDevice(cfg->device) != hipSuccess) return PBA_EDEVICE;
@@ -977,7 +990,7 @@ pba_status pba_iterate(pba_ctx *c, int32_t n_iters, int32_t use_lm, double lambd
     if (n_iters > c->log_cap) {
         const int cap = std::max(n_iters, 64);
         release(c->logbuf);
-        if ((s = ensure(c, c->logbuf, (size_t)cap * 8 * 8))) return s;
+        if ((s = ensure(c, c->logbuf, (size_t)cap * kLogRow * 8))) return s;
         c->log_cap = cap;
         drop_graph(c);   // the graph refers to the log buffer
     }
@@ -1018,7 +1031,7 @@ pba_status pba_iterate(pba_ctx *c, int32_t n_iters, int32_t use_lm, double lambd
             if ((s = enqueue_iteration(c, c->stream))) return s;
     }
     HIP_OK(hipEventRecord(c->ev1, c->stream));
-    std::vector<double> lg((size_t)n_iters * 8);
+    std::vector<double> lg((size_t)n_iters * kLogRow);
     HIP_OK(hipMemcpyAsync(lg.data(), c->logbuf.p, lg.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     float ms = 0.f;
@@ -1027,25 +1040,27 @@ pba_status pba_iterate(pba_ctx *c, int32_t n_iters, int32_t use_lm, double lambd
     c->iterations += n_iters;
     bool any_fail = false;
     for (int it = 0; it < n_iters; ++it) {
-        const double *r = &lg[8 * (size_t)it];
+        const double *r = &lg[kLogRow * (size_t)it];
+        uint64_t t0, t1, i0, i1;
+        std::memcpy(&t0, &r[6], 8);
+        std::memcpy(&t1, &r[7], 8);
+        std::memcpy(&i0, &r[8], 8);
+        std::memcpy(&i1, &r[9], 8);
         if (log) {
             log[it].F = r[0];
             log[it].lambda = r[1];
             log[it].step_norm = r[2];
             log[it].n_valid = (int64_t)r[3];
             log[it].accepted = r[4] != 0.0;
-            log[it].pad = 0;
+            log[it].ms = (c->wall_khz > 0.0 && i1 >= i0) ? (float)((double)(i1 - i0) / c->wall_khz) : -1.0f;
         }
         if (r[5] != 0.0) any_fail = true;
-        uint64_t t0, t1;
-        std::memcpy(&t0, &r[6], 8);
-        std::memcpy(&t1, &r[7], 8);
         if (c->wall_khz > 0.0 && t1 >= t0) {
             c->iter_eval_ms += (double)(t1 - t0) / c->wall_khz;
             c->iter_evals += 1;
         }
     }
-    if (use_lm) c->lam_carry = lg[8 * (size_t)(n_iters - 1) + 1];
+    if (use_lm) c->lam_carry = lg[kLogRow * (size_t)(n_iters - 1) + 1];
     if (any_fail && !use_lm) return fail(c, PBA_ENOTPD, "Gauss-Newton system not positive definite");
     return PBA_OK;
 }
@@ -1137,7 +1152,7 @@ pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float
     HIP_OK(hipGetLastError());
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (grad_delta) HIP_OK(hipMemcpyAsync(grad_delta, c->g_pose.p, (size_t)N * 24, kind, c->stream));
-    for (int k = 0; k < N; ++k) {
+    for (int k = 0; k < c->N; ++k) {   // every keyframe (pose variables may be shared)
         const size_t npx = (size_t)c->L().kfs_h[k].H * c->L().kfs_h[k].W;
         const int64_t off = c->L().kfs_h[k].off;
         if (grad_intensity && grad_intensity[k])

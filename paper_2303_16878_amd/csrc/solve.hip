@@ -592,7 +592,7 @@ __global__ void lm_finish_kernel(LmState *lm, const double *__restrict__ totals_
                                  double *logbuf, int log_cap)
 {
     // the row is chosen on the device so that every iteration launches identical arguments
-    double *log_row = logbuf + 8 * (int64_t)min(lm->iter, log_cap - 1);
+    double *log_row = logbuf + kLogRow * (int64_t)min(lm->iter, log_cap - 1);
     const double Fc = totals_cand[0];
     const bool solved = !lm->fail;
     const bool accept = solved && (!lm->use_lm || Fc < lm->F_cur);
@@ -611,6 +611,8 @@ __global__ void lm_finish_kernel(LmState *lm, const double *__restrict__ totals_
     log_row[3] = (double)lm->valid_cur;
     log_row[4] = accept ? 1.0 : 0.0;
     log_row[5] = solved ? 0.0 : 1.0;
+    // the last launch of an iteration: its end stamp
+    reinterpret_cast<uint64_t *>(log_row)[9] = (uint64_t)wall_clock64();
     lm->iter += 1;
 }
 
@@ -633,12 +635,13 @@ __global__ void copy_kernel(double *__restrict__ dst, const double *__restrict__
 }
 
 // Device wall-clock stamp (constant-rate counter) into slot 6 + which of the current iteration's
-// log row: the evaluation inside a captured iteration is bracketed by two of these, so every
-// replay of the graph leaves its own evaluation duration.
+// log row: the evaluation inside a captured iteration is bracketed by two of these (which = 0, 1)
+// and the iteration starts with one (which = 2), so every replay of the graph leaves its own
+// durations.
 __global__ void stamp_kernel(const LmState *lm, double *logbuf, int log_cap, int which)
 {
     if (threadIdx.x != 0) return;
-    uint64_t *row = reinterpret_cast<uint64_t *>(logbuf + 8 * (int64_t)min(lm->iter, log_cap - 1));
+    uint64_t *row = reinterpret_cast<uint64_t *>(logbuf + kLogRow * (int64_t)min(lm->iter, log_cap - 1));
     row[6 + which] = (uint64_t)wall_clock64();
 }
 

@@ -114,3 +114,36 @@ def test_pose_group_errors(rig, pba):
         ctx.set_poses(rig.kf_poses(rig.init_poses))
         ev = ctx.evaluate(want_system=True)
         assert ev["H"].shape == (24, 24)
+
+
+def test_loss_gradients_with_pose_groups(rig, pba):
+    """Loss adjoint with shared rig poses (two pose variables, four keyframes): the gradient per
+    pose variable and the image gradients of every keyframe -- including those whose index is
+    past the number of pose variables -- match the oracle's.  The outputs start as NaN, so a
+    keyframe the backward skips fails."""
+    pairs = np.array([(0, 2), (2, 0), (1, 3), (3, 1), (0, 1), (3, 2)], np.int32)
+    prob = synth.Problem(rig.name, rig.sensors, rig.kf_sensor, rig.gt_poses, rig.init_poses, pairs, dict(rig.params),
+                         rig.intensity, rig.depth, rig.normals, rig.scene, rig.pose_of)
+    nv = prob.n_poses
+    delta = (np.random.default_rng(11).normal(size=(nv, 6)) * 1e-3).astype(np.float32)
+    ref = oracle.loss_and_grad(prob, prob.init_poses, delta.astype(np.float64))
+    with pba.context_for_problem(prob) as ctx:
+        assert ctx.n_poses == nv == 2 and ctx.n == 4
+        F = ctx.loss_forward(delta)
+        gd = np.full((nv, 6), np.nan, np.float32)
+        gI = [np.full(prob.depth[k].shape, np.nan, np.float32) for k in range(prob.n)]
+        gD = [np.full(prob.depth[k].shape, np.nan, np.float32) for k in range(prob.n)]
+        gN = [np.full(prob.depth[k].shape + (3,), np.nan, np.float32) for k in range(prob.n)]
+        ctx.loss_backward(1.0, gd, (gI, gD, gN))
+    _log("grouped loss: F gpu %.9g oracle %.9g" % (F, ref["F"]))
+    assert abs(F - ref["F"]) <= 1e-5 * ref["F"]
+    assert np.abs(gd - ref["g_delta"]).max() <= 1e-4 * np.abs(ref["g_delta"]).max()
+    for name, g_gpu, g_orc in (("intensity", gI, ref["gI"]), ("depth", gD, ref["gD"]), ("normals", gN, ref["gN"])):
+        for k in range(prob.n):
+            assert np.all(np.isfinite(g_gpu[k])), (name, k)
+        a = np.concatenate([np.ravel(x) for x in g_gpu])
+        b = np.concatenate([np.ravel(x) for x in g_orc])
+        rel_l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+        frac_bad = np.mean(np.abs(a - b) > 1e-3 * np.abs(b).max())
+        _log("  %s: rel L2 %.2e, texels beyond 1e-3: %.2e" % (name, rel_l2, frac_bad))
+        assert rel_l2 < 1e-3 and frac_bad < 1e-3, name
