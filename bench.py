@@ -117,6 +117,9 @@ def main():
                     help="the z-buffer occlusion variant (an extra projection-only pass per evaluation)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate byte counters")
+    ap.add_argument("--profile-evals", type=int, default=0, metavar="K",
+                    help="only load the workload and run K evaluations at the initial poses on the FP32 path "
+                         "(default item size and grid): a short command for counter profiles")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -146,6 +149,12 @@ def main():
                                                              time.perf_counter() - t0))
     if args.zbuffer:
         prob.params["occlusion_zbuffer"] = 1
+    if args.profile_evals:
+        with pba.context_for_problem(prob, precision=pba.PBA_F32) as ctx:
+            for i in range(args.profile_evals):
+                ev = ctx.evaluate()
+                log("evaluation %d: %d px-pairs, %d valid" % (i, ev["n_evaluated"], ev["n_valid"]))
+        return
     ch = prob.params["channels"]
     sen = prob.sensors[0]
 

@@ -69,7 +69,8 @@ enum { PBA_F32 = 0, PBA_F64 = 1 };
 /* Length of one per-pair record written by pba_evaluate (pair_out):
  * [0,144)  H12, 12x12 row-major over [dx_s (6); dx_t (6)]
  * [144,156) b12
- * 156 F (sum of rho), 157 evaluated source pixels, 158 valid correspondences, 159 reserved (0). */
+ * 156 F (sum of rho), 157 evaluated source pixels, 158 valid correspondences, 159 boundary-band
+ * correspondences (see pba_eval_out.n_boundary_band). */
 #define PBA_PAIR_OUT_LEN 160
 
 /* A sensor model (Sec. III) and its rigid offset on the platform (Supplementary). */
@@ -160,6 +161,12 @@ typedef struct {
     double F;                    /* sum over pairs and pixels of rho(chi^2) */
     int64_t n_evaluated;         /* (pair, source pixel with valid depth) evaluations */
     int64_t n_valid;             /* valid correspondences */
+    int64_t n_boundary_band;     /* projected points whose stencil lies inside the target image and
+                                    whose coordinate u' (column or row) is within 1e-4 px of a cell
+                                    boundary: the integer cell floor(u') that decides the taps and
+                                    the mask (readings of Sec. IV-C's sampling) is then sensitive to
+                                    rounding, so such points may legitimately differ between the FP32
+                                    and FP64 paths or from an exact evaluation */
     double *H;                   /* nullable: 6N x 6N, raw (no gauge fix, no damping) */
     double *b;                   /* nullable: 6N */
     double *pair_out;            /* nullable: P x PBA_PAIR_OUT_LEN, in the platform frames */

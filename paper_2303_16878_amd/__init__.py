@@ -53,7 +53,7 @@ class pba_config(ctypes.Structure):
 
 class pba_eval_out(ctypes.Structure):
     _fields_ = [("F", ctypes.c_double), ("n_evaluated", ctypes.c_int64), ("n_valid", ctypes.c_int64),
-                ("H", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("n_boundary_band", ctypes.c_int64), ("H", ctypes.c_void_p), ("b", ctypes.c_void_p),
                 ("pair_out", ctypes.c_void_p), ("on_device", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
@@ -363,7 +363,7 @@ class Context:
             out.pair_out = po.ctypes.data
         out.on_device = 0
         self._check(self.lib.pba_evaluate(self.h, ctypes.byref(out)))
-        r = dict(F=out.F, n_evaluated=out.n_evaluated, n_valid=out.n_valid)
+        r = dict(F=out.F, n_evaluated=out.n_evaluated, n_valid=out.n_valid, n_boundary_band=out.n_boundary_band)
         if want_system:
             r.update(H=H, b=b)
         if want_pairs:

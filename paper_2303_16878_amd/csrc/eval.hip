@@ -511,7 +511,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         }
         const double st_fx = uni_d(st.fxd), st_fy = uni_d(st.fyd), st_cx = uni_d(st.cxd), st_cy = uni_d(st.cyd), st_dmin = uni_d(st.dmind);
         const T fx = (T)st_fx, fy = (T)st_fy;
-        const T tau = F32 ? (T)uni_f(st.tau) : (T)uni_d(st.taud);
+        const double taud_gate = uni_d(st.taud);   // occlusion bound, FP64 in both paths
         const T om_g = (T)a.omega_g, om_d = (T)a.omega_d, om_n = (T)a.omega_n, delta = (T)a.huber;
         // ray-table offsets of the source (unprojection) and target (projection) sensors in scalar
         // registers: read once per item, not from the sensor record in every chunk
@@ -523,7 +523,6 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         const float *satt1 = a.att1 + ks.off;
         // z-buffer occlusion variant: this pair's source z-buffer (FP32 depth bits per target cell)
         uint32_t *const zb = ZB ? a.zbuf + a.zoff[pair] : nullptr;
-        const double taud = ZB ? uni_d(st.taud) : 0.0;
         const uint32_t tnpx = (uint32_t)Ht * (uint32_t)Wt;
         const __amdgpu_buffer_rsrc_t r_tdep = plane_rsrc(uni_ptr(a.dep + kt.off), tnpx * 4u);
         const __amdgpu_buffer_rsrc_t r_tatt = NCH == 5 ? plane_rsrc(uni_ptr(a.att4 + kt.off), tnpx * 16u)
@@ -535,7 +534,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         double acc64[F32 ? 1 : ACC_F];   // FP64 path: the 27 sums per lane
 #pragma unroll
         for (int k = 0; k < (F32 ? 1 : ACC_F); ++k) acc64[k] = 0.0;
-        int n_eval = 0, n_valid = 0;
+        int n_eval = 0, n_valid = 0, n_band = 0;
         int head = 0, tail = 0;   // wave-uniform queue positions
 
         // phase 2: residuals, weights, Jacobian rows and accumulation of queue slot `slot`
@@ -768,14 +767,17 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         v = fma(st_fy, atan2(Z, sqrt(r2)), st_cy);
                     }
                 }
-                const T zeta_d = (T)zeta;
                 if (ok) {
                     if (DBG) { a.dbg_status[pix] = 3; a.dbg_uv[pix] = make_float2((float)u, (float)v); }
                     // the integer cell floor(u'), and the stencil inside the image
                     ok = near && u >= 1.0 && u < (double)(Wt - 2) && v >= 1.0 && v < (double)(Ht - 2);
                     if (ok) {
                         x0 = (int)u; y0 = (int)v;
-                        al = (T)(u - (double)x0); be = (T)(v - (double)y0);
+                        const double du = u - (double)x0, dv = v - (double)y0;
+                        al = (T)du; be = (T)dv;
+                        // the cell of a point this close to a boundary can differ between exact
+                        // arithmetic and any rounding of it: counted
+                        n_band += (du < kBandPx || du > 1.0 - kBandPx || dv < kBandPx || dv > 1.0 - kBandPx) ? 1 : 0;
                     }
                     if (ZB && ok && a.zpass) {
                         // z-buffer pass: keep the nearest predicted depth per target cell (depths are
@@ -791,15 +793,17 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         load_stencil<float, 4>(tD, [&](int vo, int so) { return ld_f32(r_tdep, vo, so); },
                                                ((y0 - 1) * Wt + (x0 - 1)) * 4, Wt * 4);
                         // invalid target depths hold a large negative sentinel, so one bound on the
-                        // largest |D - zeta| also rejects them
+                        // largest |D - zeta| also rejects them.  The bound is tested in FP64 in both
+                        // paths (the taps are exact in FP64): a mask decision then does not depend on
+                        // the evaluation precision, and the FP32 path keeps the FP64 path's points.
                         float dmin = tD[0], dmax = tD[0];
 #pragma unroll
                         for (int k = 1; k < 12; ++k) { dmin = fminf(dmin, tD[k]); dmax = fmaxf(dmax, tD[k]); }
-                        bool vis = fmax((T)dmax - zeta_d, zeta_d - (T)dmin) <= tau;
+                        bool vis = fmax((double)dmax - zeta, zeta - (double)dmin) <= taud_gate;
                         // z-buffer variant: also no more than tau behind the nearest of the pair's own
                         // points in this cell (both depths as FP32, compared in FP64)
                         if (ZB && vis)
-                            vis = (double)(float)zeta - (double)__uint_as_float(zb[y0 * Wt + x0]) <= taud;
+                            vis = (double)(float)zeta - (double)__uint_as_float(zb[y0 * Wt + x0]) <= taud_gate;
                         if (vis) {
                             const T w00 = (T(1) - al) * (T(1) - be), w01 = al * (T(1) - be);
                             const T w10 = (T(1) - al) * be, w11 = al * be;
@@ -846,7 +850,9 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
 #pragma unroll
         for (int k = ADJ ? ACC_B : (F32 ? ACC_F : 0); k < ACC_USED; ++k) {
             double v = k < ACC_F ? (ADJ ? acc_b[k - ACC_B] : acc64[F32 ? 0 : k])
-                                 : (k == ACC_F ? acc_F : (k == ACC_VALID ? (double)n_valid : (double)n_eval));
+                                 : (k == ACC_F ? acc_F
+                                               : (k == ACC_VALID ? (double)n_valid
+                                                                 : (k == ACC_EVAL ? (double)n_eval : (double)n_band)));
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
             if (lane == 0) s_red[wave][k] = v;
@@ -1070,7 +1076,7 @@ __global__ void __launch_bounds__(64) reduce_pairs_kernel(const double *__restri
         o[156] = sums[ACC_F];
         o[157] = sums[ACC_EVAL];
         o[158] = sums[ACC_VALID];
-        o[159] = 0.0;
+        o[159] = sums[ACC_BAND];
     }
 }
 
@@ -1124,7 +1130,7 @@ __global__ void __launch_bounds__(64) assemble_H_kernel(const double *__restrict
 
 // b per pose variable (bk_ent = 2 * pair + side, side 0 = source, 1 = target), one thread per
 // entry of b in the workgroups before the last, and the totals F, evaluated, valid (and the
-// reserved slot) summed over pairs in the last workgroup; every sum runs in a fixed order.
+// boundary-band count) summed over pairs in the last workgroup; every sum runs in a fixed order.
 __global__ void __launch_bounds__(256) assemble_b_kernel(const double *__restrict__ pair_out, int P,
                                                          const int32_t *__restrict__ bk_ptr,
                                                          const int32_t *__restrict__ bk_ent, int N,

@@ -9,8 +9,11 @@ namespace pba {
 
 constexpr int kBlock = 256;      // threads per evaluation workgroup (4 wave64)
 constexpr int kAcc = 32;         // accumulator slots per work item
-// accumulator layout: 21 upper-triangular H terms, 6 b terms, F, valid, evaluated
-enum { ACC_H = 0, ACC_B = 21, ACC_F = 27, ACC_VALID = 28, ACC_EVAL = 29, ACC_USED = 30 };
+// accumulator layout: 21 upper-triangular H terms, 6 b terms, F, valid, evaluated, boundary band
+enum { ACC_H = 0, ACC_B = 21, ACC_F = 27, ACC_VALID = 28, ACC_EVAL = 29, ACC_BAND = 30, ACC_USED = 31 };
+// boundary band: a correspondence whose projected coordinate lies within this many pixels of a
+// cell boundary (either coordinate), where the integer cell -- and so the mask -- is decided
+constexpr double kBandPx = 1e-4;
 constexpr int kPairOut = 160;    // PBA_PAIR_OUT_LEN
 // one row of the LM log per iteration: F, lambda, step norm, valid, accepted, solve failed, then
 // device wall-clock stamps: evaluation begin / end, iteration begin / end
@@ -24,7 +27,6 @@ enum { MODEL_PINHOLE = 0, MODEL_SPHERICAL = 1 };
 struct SensorDev {
     int32_t model, H, W, npx;
     uint32_t magic_w;            // ceil(2^32 / W): row = umulhi(pix, magic_w) for pix < 2^32 / W
-    float fx, fy, cx, cy, dmin, dmax, tau;
     double fxd, fyd, cxd, cyd, dmind, dmaxd, taud;
     double Ro[9], to[3];         // sensor -> platform
     int64_t lut_col, lut_row;    // element offsets into the ray tables

@@ -211,11 +211,8 @@ pba_status sensor_tables(pba_ctx *c, ImageSet &is)
         SensorDev &d = sd[i];
         d.model = S.model; d.H = S.height; d.W = S.width; d.npx = S.height * S.width;
         d.magic_w = (uint32_t)(((1ull << 32) + S.width - 1) / S.width);
-        d.fx = (float)S.fx; d.fy = (float)S.fy; d.cx = (float)S.cx; d.cy = (float)S.cy;
-        d.dmin = (float)S.min_depth; d.dmax = (float)S.max_depth;
         d.fxd = S.fx; d.fyd = S.fy; d.cxd = S.cx; d.cyd = S.cy; d.dmind = S.min_depth; d.dmaxd = S.max_depth;
         d.taud = S.model == PBA_PINHOLE ? c->cfg.occlusion_tau_pinhole : c->cfg.occlusion_tau_spherical;
-        d.tau = (float)d.taud;
         for (int k = 0; k < 9; ++k) d.Ro[k] = S.offset[k];
         for (int k = 0; k < 3; ++k) d.to[k] = S.offset[9 + k];
         d.lut_col = (int64_t)l32.size();
@@ -914,6 +911,7 @@ pba_status pba_evaluate(pba_ctx *c, pba_eval_out *out)
     out->F = tot[0];
     out->n_evaluated = (int64_t)tot[1];
     out->n_valid = (int64_t)tot[2];
+    out->n_boundary_band = (int64_t)tot[3];
     return PBA_OK;
 }
 

@@ -95,7 +95,8 @@ def test_graph_replays_match_eager_with_zbuffer(pba, lidar_mini):
             lg = cg.iterate(1, use_lm=True, lambda0=1e-4 if it == 0 else 0.0)
             le = ce.iterate(1, use_lm=True, lambda0=1e-4 if it == 0 else 0.0)
             assert np.array_equal(cg.get_poses(), ce.get_poses()), it
-            assert lg == le, it
+            # every field but the measured device time
+            assert [dict(l, ms=0) for l in lg] == [dict(l, ms=0) for l in le], it
 
 
 def test_zbuffer_config_errors(pba):
