@@ -177,6 +177,21 @@ typedef struct {
 /* Evaluate residuals, Jacobians and the normal equations at the current poses. */
 pba_status pba_evaluate(pba_ctx *ctx, pba_eval_out *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): pba_evaluate with the same arguments and bitwise the
+ * same results, whose evaluation working memory -- queue counters, per-item partial sums and
+ * per-pair records -- comes from a fixed array of PBA_NOALLOC_SCRATCH_BYTES in the library's
+ * device code instead of the context's buffers; the call allocates nothing (no hipMalloc or
+ * hipFree, no allocator callback).  The array exists once per GPU and lives until the process
+ * ends; every call on that GPU reuses it, so calls that overlap on one GPU (several streams or
+ * threads, any contexts) race and must be serialised by the caller.  The system is kept in the
+ * context as after pba_evaluate (pba_iterate and pba_solve_step reuse it).  Errors: those of
+ * pba_evaluate, and PBA_EINVAL (state unchanged) when the context's work queue needs more than
+ * the array: 256 B per work item (pba_timings.n_items) + 1280 B per pair + 256 B, each part
+ * rounded up to 256 B.  Not timed (pba_get_timings counts only pba_evaluate). */
+#define PBA_NOALLOC_SCRATCH_BYTES (64u << 20)
+pba_status pba_evaluate_noalloc(pba_ctx *ctx, pba_eval_out *out);
+
 /* Solve (H + lambda diag H) dx = -b at the current poses (anchor fixed), FP64 Cholesky.
  * dx (6N, N poses or pose variables, nullable) receives the step; it is also kept for
  * pba_apply_step. */

@@ -22,11 +22,13 @@ PBA_OK, PBA_EINVAL, PBA_ENOMEM, PBA_EDEVICE, PBA_ESTATE, PBA_ENOTPD, PBA_ENOVALI
 PBA_PINHOLE, PBA_SPHERICAL = 0, 1
 PBA_F32, PBA_F64 = 0, 1
 PBA_PAIR_OUT_LEN = 160
+PBA_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # names declared in include/pba.h
 ABI_FUNCTIONS = (
     "pba_config_default", "pba_create", "pba_destroy", "pba_add_sensor", "pba_load_keyframes",
-    "pba_set_poses", "pba_get_poses", "pba_set_pose_groups", "pba_set_pairs", "pba_evaluate", "pba_solve_step",
+    "pba_set_poses", "pba_get_poses", "pba_set_pose_groups", "pba_set_pairs", "pba_evaluate",
+    "pba_evaluate_noalloc", "pba_solve_step",
     "pba_apply_step", "pba_iterate", "pba_loss_forward", "pba_loss_backward", "pba_build_pyramid",
     "pba_set_level", "pba_optimize_pyramid", "pba_get_level_image", "pba_autotune", "pba_build_pairs", "pba_estimate_normals", "pba_debug_pair",
     "pba_get_timings", "pba_status_string", "pba_last_error",
@@ -151,6 +153,7 @@ def load_library(path: str = LIB_PATH):
         "pba_set_pairs": (i32, [vp, i32, vp, vp]),
         "pba_set_pose_groups": (i32, [vp, vp, i32]),
         "pba_evaluate": (i32, [vp, ctypes.POINTER(pba_eval_out)]),
+        "pba_evaluate_noalloc": (i32, [vp, ctypes.POINTER(pba_eval_out)]),
         "pba_solve_step": (i32, [vp, f64, vp, i32]),
         "pba_apply_step": (i32, [vp, vp, i32]),
         "pba_iterate": (i32, [vp, i32, i32, f64, vp]),
@@ -351,7 +354,9 @@ class Context:
         self._check(self.lib.pba_set_pairs(self.h, len(pairs), s.ctypes.data, t.ctypes.data))
         self.p = len(pairs)
 
-    def evaluate(self, want_system=False, want_pairs=False):
+    def evaluate(self, want_system=False, want_pairs=False, noalloc=False):
+        """pba_evaluate, or pba_evaluate_noalloc (noalloc=True: working memory from the library's fixed
+        scratch array; same results)."""
         out = pba_eval_out()
         H = b = po = None
         if want_system:
@@ -362,7 +367,8 @@ class Context:
             po = np.empty((self.p, PBA_PAIR_OUT_LEN), np.float64)
             out.pair_out = po.ctypes.data
         out.on_device = 0
-        self._check(self.lib.pba_evaluate(self.h, ctypes.byref(out)))
+        fn = self.lib.pba_evaluate_noalloc if noalloc else self.lib.pba_evaluate
+        self._check(fn(self.h, ctypes.byref(out)))
         r = dict(F=out.F, n_evaluated=out.n_evaluated, n_valid=out.n_valid, n_boundary_band=out.n_boundary_band)
         if want_system:
             r.update(H=H, b=b)

@@ -12,13 +12,25 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
 
 using namespace pba;
 
+// Working memory of pba_evaluate_noalloc: a fixed array in every GPU's copy of this library's code
+// object, held until the process ends.  Host code never passes its name to a kernel (on the host it
+// is only a stand-in for the symbol): the device address comes from hipGetSymbolAddress, once per
+// device at context creation, and is kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = PBA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
 
 struct DevBuf {
     void *p = nullptr;
@@ -475,7 +487,18 @@ EvalArgs make_args(pba_ctx *c)
 // z-buffer occlusion variant: every pair's z-buffer at the poses the last pair setup used (+inf, then
 // the nearest predicted depth per target cell by a projection-only pass of the evaluation kernel),
 // then the pair setup again, which clears the queue counters for the evaluation proper.
-void zbuffer_pass(pba_ctx *c, const double *poses, hipStream_t st)
+// Working memory of one evaluation: queue counters (kXcd per model group), per-item partial sums
+// and per-pair records.  The context's own buffers, or a caller-independent array (the
+// allocation-free entry point).
+struct WorkBufs {
+    uint32_t *counters;
+    void *partials;
+    double *pair_out;
+};
+
+WorkBufs ctx_work(pba_ctx *c) { return WorkBufs{P_<uint32_t>(c->counters), c->partials.p, P_<double>(c->pair_out)}; }
+
+void zbuffer_pass(pba_ctx *c, const double *poses, hipStream_t st, const WorkBufs &w)
 {
     if (!c->cfg.occlusion_zbuffer || c->P == 0) return;
     const uint64_t inf2 = 0x7F8000007F800000ull;   // two FP32 +inf (a finite double)
@@ -483,16 +506,17 @@ void zbuffer_pass(pba_ctx *c, const double *poses, hipStream_t st)
     std::memcpy(&fill, &inf2, 8);
     launch_fill(P_<double>(c->zbuf), (c->zcells + 1) / 2, fill, st);
     EvalArgs a = make_args(c);
+    a.partials = w.partials;
     a.zpass = 1;
     const int ngrp = (int)c->groups.size();
     for (int g = 0; g < ngrp; ++g) {
         const auto &G = c->groups[g];
-        a.counter = P_<uint32_t>(c->counters) + g * kXcd;
+        a.counter = w.counters + g * kXcd;
         launch_eval(a, c->cfg.precision, c->cfg.channels, c->cfg.grad_mode, G.sm, G.tm, false, G.base, G.count,
                     std::max(1, std::min(G.count, c->grid)), st);
     }
     launch_pair_setup(poses, P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->L().sensors_d), P_<KfDev>(c->L().kfs_d),
-                      P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ngrp * kXcd, st);
+                      P_<PairDev>(c->pair_dev), w.counters, ngrp * kXcd, st);
 }
 
 // Evaluate at `poses` into (H, b, totals).  Launch order on the context stream:
@@ -501,18 +525,20 @@ void zbuffer_pass(pba_ctx *c, const double *poses, hipStream_t st)
 // with the context's HIP events; `stamped` with wall-clock stamps into the LM log row (for
 // launches inside a captured iteration, where the events would only keep the last replay).
 pba_status run_eval(pba_ctx *c, const double *poses, double *H, double *b, double *totals, bool timed,
-                    hipStream_t st, bool stamped = false)
+                    hipStream_t st, bool stamped = false, const WorkBufs *work = nullptr)
 {
+    const WorkBufs w = work ? *work : ctx_work(c);
     const int ngrp = (int)c->groups.size();
     launch_pair_setup(poses, P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->L().sensors_d), P_<KfDev>(c->L().kfs_d),
-                      P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ngrp * kXcd, st);
-    zbuffer_pass(c, poses, st);
+                      P_<PairDev>(c->pair_dev), w.counters, ngrp * kXcd, st);
+    zbuffer_pass(c, poses, st, w);
     EvalArgs a = make_args(c);
+    a.partials = w.partials;
     if (timed) HIP_OK(hipEventRecord(c->ev0, st));
     if (stamped) launch_stamp(P_<LmState>(c->lm), P_<double>(c->logbuf), c->log_cap, 0, st);
     for (int g = 0; g < ngrp; ++g) {
         const auto &G = c->groups[g];
-        a.counter = P_<uint32_t>(c->counters) + g * kXcd;
+        a.counter = w.counters + g * kXcd;
         const int grid = std::max(1, std::min(G.count, c->grid));
         launch_eval(a, c->cfg.precision, c->cfg.channels, c->cfg.grad_mode, G.sm, G.tm, false, G.base, G.count, grid,
                     st);
@@ -520,9 +546,9 @@ pba_status run_eval(pba_ctx *c, const double *poses, double *H, double *b, doubl
     if (timed) HIP_OK(hipEventRecord(c->ev1, st));
     if (stamped) launch_stamp(P_<LmState>(c->lm), P_<double>(c->logbuf), c->log_cap, 1, st);
     HIP_OK(hipGetLastError());
-    launch_reduce_pairs(c->partials.p, c->cfg.precision, P_<int32_t>(c->pitems), P_<int32_t>(c->ibeg),
-                        P_<int32_t>(c->icnt), P_<PairDev>(c->pair_dev), P_<double>(c->pair_out), c->P, st);
-    launch_assemble(P_<double>(c->pair_out), c->P, P_<int2>(c->blk_rc), P_<int32_t>(c->blk_ptr),
+    launch_reduce_pairs(w.partials, c->cfg.precision, P_<int32_t>(c->pitems), P_<int32_t>(c->ibeg),
+                        P_<int32_t>(c->icnt), P_<PairDev>(c->pair_dev), w.pair_out, c->P, st);
+    launch_assemble(w.pair_out, c->P, P_<int2>(c->blk_rc), P_<int32_t>(c->blk_ptr),
                     P_<int32_t>(c->blk_ent), c->nblk, P_<int32_t>(c->bk_ptr), P_<int32_t>(c->bk_ent), c->NP, H, b,
                     totals, st);
     HIP_OK(hipGetLastError());
@@ -656,6 +682,16 @@ pba_status pba_create(const pba_config *cfg, pba_ctx **out)
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return PBA_EDEVICE;
     if (hipSetDevice(cfg->device) != hipSuccess) return PBA_EDEVICE;
+    if (cfg->device >= kMaxDevices) return PBA_EDEVICE;
+    {
+        // the device address of this GPU's copy of the scratch array (pba_evaluate_noalloc)
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[cfg->device]) {
+            void *p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PBA_EDEVICE;
+            g_scratch_ptr[cfg->device] = p;
+        }
+    }
     pba_ctx *c = new (std::nothrow) pba_ctx;
     if (!c) return PBA_ENOMEM;
     c->cfg = *cfg;
@@ -920,6 +956,44 @@ pba_status pba_evaluate(pba_ctx *c, pba_eval_out *out)
     return PBA_OK;
 }
 
+pba_status pba_evaluate_noalloc(pba_ctx *c, pba_eval_out *out)
+{
+    if (!c || !out) return fail(c, PBA_EINVAL, "null argument");
+    pba_status s;
+    if ((s = check_ready(c))) return s;
+    HIP_OK(hipSetDevice(c->cfg.device));
+    // carve the queue counters, per-item partials and per-pair records out of this device's array,
+    // each part 256-byte aligned
+    auto up = [](size_t n) { return (n + 255) & ~size_t(255); };
+    const size_t n_cnt = up((size_t)std::max<size_t>(1, c->groups.size()) * kXcd * 4);
+    const size_t n_part = up((size_t)std::max(1, c->n_items) * kAcc * 8);
+    const size_t n_pair = up((size_t)std::max(1, c->P) * kPairOut * 8);
+    if (n_cnt + n_part + n_pair > kScratchBytes)
+        return fail(c, PBA_EINVAL,
+                    "pba_evaluate_noalloc: %d work items and %d pairs need %zu bytes of scratch, more than its %zu",
+                    c->n_items, c->P, n_cnt + n_part + n_pair, kScratchBytes);
+    unsigned char *base = static_cast<unsigned char *>(g_scratch_ptr[c->cfg.device]);
+    if (!base) return fail(c, PBA_EDEVICE, "scratch array of device %d not resolved", c->cfg.device);
+    const WorkBufs w{reinterpret_cast<uint32_t *>(base), base + n_cnt, reinterpret_cast<double *>(base + n_cnt + n_part)};
+    if ((s = run_eval(c, P_<double>(c->poses), P_<double>(c->H), P_<double>(c->b), P_<double>(c->totals), false,
+                      c->stream, false, &w)))
+        return s;
+    const size_t n = (size_t)n_sys(c);
+    const hipMemcpyKind k = out->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (out->H) HIP_OK(hipMemcpyAsync(out->H, c->H.p, n * n * 8, k, c->stream));
+    if (out->b) HIP_OK(hipMemcpyAsync(out->b, c->b.p, n * 8, k, c->stream));
+    if (out->pair_out) HIP_OK(hipMemcpyAsync(out->pair_out, w.pair_out, (size_t)c->P * kPairOut * 8, k, c->stream));
+    double tot[4];
+    HIP_OK(hipMemcpyAsync(tot, c->totals.p, sizeof tot, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->system_valid = true;
+    out->F = tot[0];
+    out->n_evaluated = (int64_t)tot[1];
+    out->n_valid = (int64_t)tot[2];
+    out->n_boundary_band = (int64_t)tot[3];
+    return PBA_OK;
+}
+
 pba_status pba_solve_step(pba_ctx *c, double lambda, double *dx, int32_t on_device)
 {
     if (!c) return PBA_EINVAL;
@@ -1133,7 +1207,7 @@ pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float
     launch_pair_setup(P_<double>(c->loss_poses), P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->L().sensors_d),
                       P_<KfDev>(c->L().kfs_d), P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), ngrp * kXcd,
                       c->stream);
-    zbuffer_pass(c, P_<double>(c->loss_poses), c->stream);
+    zbuffer_pass(c, P_<double>(c->loss_poses), c->stream, ctx_work(c));
     EvalArgs a = make_args(c);
     a.g_int = P_<float>(c->g_int);
     a.g_dep = P_<float>(c->g_dep);
@@ -1453,7 +1527,7 @@ pba_status pba_debug_pair(pba_ctx *c, int32_t pair, uint8_t *status, float *uv, 
     // pair transforms at the current poses
     launch_pair_setup(P_<double>(c->poses), P_<int2>(c->pairs_d), c->P, P_<SensorDev>(c->L().sensors_d),
                       P_<KfDev>(c->L().kfs_d), P_<PairDev>(c->pair_dev), P_<uint32_t>(c->counters), 64, c->stream);
-    zbuffer_pass(c, P_<double>(c->poses), c->stream);
+    zbuffer_pass(c, P_<double>(c->poses), c->stream, ctx_work(c));
     int2 pr;
     HIP_OK(hipMemcpyAsync(&pr, P_<int2>(c->pairs_d) + pair, sizeof pr, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
