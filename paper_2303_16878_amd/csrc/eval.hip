@@ -363,8 +363,6 @@ struct Lut<double> {
 
 // Per-wave queue of valid correspondences found by phase 1, consumed by phase 2.
 // Structure of arrays, 128 slots per wave (a chunk appends at most 64; phase 2 drains 64 at a time).
-// (Two pixels per lane per drain, sharing one wave reduction, would keep the 27 sums live across a
-// whole pixel: 27 more VGPRs and one wave less per SIMD.)
 constexpr int kQ = 128;
 template <typename T>
 struct WaveQueue {
@@ -372,7 +370,7 @@ struct WaveQueue {
     int cell[kQ];          // x0 | y0 << 16
     T al[kQ], be[kQ];      // bilinear fractions
     T px[kQ], py[kQ], pz[kQ];   // p_bar
-    T ed0[kQ];             // zeta - D(x0, y0) (taken in FP64): the depth residual before interpolation
+    T ed[kQ], gxd[kQ], gyd[kQ]; // depth residual and depth-channel image Jacobian
 };
 
 // b-only accumulation for the loss adjoint, per lane in FP64: acc[i] += om * e * J_i
@@ -527,7 +525,6 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         uint32_t *const zb = ZB ? a.zbuf + a.zoff[pair] : nullptr;
         const uint32_t tnpx = (uint32_t)Ht * (uint32_t)Wt;
         const __amdgpu_buffer_rsrc_t r_tdep = plane_rsrc(uni_ptr(a.dep + kt.off), tnpx * 4u);
-        const __amdgpu_buffer_rsrc_t r_tbnd = plane_rsrc(uni_ptr(a.dbnd + kt.off), tnpx * 8u);
         const __amdgpu_buffer_rsrc_t r_tatt = NCH == 5 ? plane_rsrc(uni_ptr(a.att4 + kt.off), tnpx * 16u)
                                                        : plane_rsrc(uni_ptr(a.att1 + kt.off), tnpx * 4u);
 
@@ -540,31 +537,21 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         int n_eval = 0, n_valid = 0, n_band = 0;
         int head = 0, tail = 0;   // wave-uniform queue positions
 
-        // phase 2: residuals, weights, Jacobian rows and accumulation of queue slot `slot` into v
-        auto add_pixel = [&](T (&v)[32], int slot, bool active) __attribute__((always_inline)) {
+        // phase 2: residuals, weights, Jacobian rows and accumulation of queue slot `slot`
+        auto consume = [&](int slot, bool active) {
+          T v[32];
+#pragma unroll
+          for (int k = 0; k < 32; ++k) v[k] = T(0);
           if (active) {
             const int pix = Q.pix[slot];
             const int cellv = Q.cell[slot];
             const int x0 = cellv & 0xffff, y0 = cellv >> 16;
             const T al = Q.al[slot], be = Q.be[slot];
             const T px = Q.px[slot], py = Q.py[slot], pz = Q.pz[slot];
+            const T ed = Q.ed[slot], Gxd = Q.gxd[slot], Gyd = Q.gyd[slot];
             const int corner = (y0 - 1) * Wt + (x0 - 1);
             const T w00 = (T(1) - al) * (T(1) - be), w01 = al * (T(1) - be);
             const T w10 = (T(1) - al) * be, w11 = al * be;
-            // depth channel: e_d = zeta - D(u') taken relative to the tap at (x0, y0) -- the taps lie
-            // within tau of zeta, so their differences are exact and the large common part (zeta -
-            // D(x0, y0), queued) cancelled in FP64 before anything was rounded to the evaluation
-            // precision; the image Jacobian only takes differences of taps
-            T ed, Gxd, Gyd;
-            {
-                float tD[12];
-                load_stencil<float, 4>(tD, [&](int vo, int so) { return ld_f32(r_tdep, vo, so); }, corner * 4, Wt * 4);
-                const float d0 = tD[1];
-                const T Vr = w01 * (T)(tD[2] - d0) + w10 * (T)(tD[5] - d0) + w11 * (T)(tD[6] - d0);
-                sample_grad<T, GM>((T)tD[0], (T)tD[1], (T)tD[2], (T)tD[3], (T)tD[4], (T)tD[5], (T)tD[6], (T)tD[7],
-                                   (T)tD[8], (T)tD[9], (T)tD[10], (T)tD[11], w00, w01, w10, w11, al, be, Gxd, Gyd);
-                ed = Q.ed0[slot] - Vr;
-            }
             T Is, ns0 = T(0), ns1 = T(0), ns2 = T(0);
             T Vg, Gxg, Gyg;
             T Vn[3] = {T(0), T(0), T(0)}, Gxn[3] = {T(0), T(0), T(0)}, Gyn[3] = {T(0), T(0), T(0)};
@@ -713,13 +700,6 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 unsafeAtomicAdd(a.g_dep + so, (float)gd);
             }
           }
-        };
-        // one queue slot per lane, then the reduction of the wave's 64 pixels into the FP64 accumulators
-        auto consume = [&](int slot, bool active) {
-          T v[32];
-#pragma unroll
-          for (int k = 0; k < 32; ++k) v[k] = T(0);
-          add_pixel(v, slot, active);
           if (!ADJ && F32) acc_hb += (double)wave_reduce_scatter(v, lane);
         };
 
@@ -730,7 +710,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             // queued only where valid: elsewhere any value will do (no instructions to clear them)
             int x0 = any_value<int>(), y0 = any_value<int>();
             T al = any_value<T>(), be = any_value<T>(), px = any_value<T>(), py = any_value<T>();
-            T pz = any_value<T>(), ed0 = any_value<T>();
+            T pz = any_value<T>(), edv = any_value<T>(), gxd = any_value<T>(), gyd = any_value<T>();
             const float Ds = pix < px1 ? sdep[pix] : 0.f;
             if (DBG && pix < px1) a.dbg_status[pix] = 1;
             if (Ds > 0.f) {
@@ -807,23 +787,36 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                     }
                     if (ok) {
                         if (DBG) { a.dbg_status[pix] = 4; a.dbg_cell[pix] = make_int2(x0, y0); }
-                        // validity and occlusion suppression: every tap of the 12-tap stencil valid and
-                        // on the surface the point lands on.  Missing target depths hold a large
-                        // negative sentinel, so one bound on the largest |D - zeta| over the stencil
-                        // rejects them too; the stencil's smallest and largest depth come precomputed
-                        // per cell.  The bound is tested in FP64 in both paths (the depths are exact
-                        // in FP64): a mask decision then does not depend on the evaluation precision,
-                        // and the FP32 path keeps the FP64 path's points.
-                        const int cell = y0 * Wt + x0;
-                        const auto bv = __builtin_amdgcn_raw_buffer_load_b64(r_tbnd, cell * 8, 0, 0);
-                        const double dlo = (double)__uint_as_float(bv[0]), dhi = (double)__uint_as_float(bv[1]);
-                        bool vis = fmax(dhi - zeta, zeta - dlo) <= taud_gate;
+                        // the 12-tap depth stencil: validity and occlusion suppression -- every tap
+                        // valid and on the surface the point lands on
+                        float tD[12];
+                        load_stencil<float, 4>(tD, [&](int vo, int so) { return ld_f32(r_tdep, vo, so); },
+                                               ((y0 - 1) * Wt + (x0 - 1)) * 4, Wt * 4);
+                        // invalid target depths hold a large negative sentinel, so one bound on the
+                        // largest |D - zeta| also rejects them.  The bound is tested in FP64 in both
+                        // paths (the taps are exact in FP64): a mask decision then does not depend on
+                        // the evaluation precision, and the FP32 path keeps the FP64 path's points.
+                        float dmin = tD[0], dmax = tD[0];
+#pragma unroll
+                        for (int k = 1; k < 12; ++k) { dmin = fminf(dmin, tD[k]); dmax = fmaxf(dmax, tD[k]); }
+                        bool vis = fmax((double)dmax - zeta, zeta - (double)dmin) <= taud_gate;
                         // z-buffer variant: also no more than tau behind the nearest of the pair's own
                         // points in this cell (both depths as FP32, compared in FP64)
                         if (ZB && vis)
-                            vis = (double)(float)zeta - (double)__uint_as_float(zb[cell]) <= taud_gate;
+                            vis = (double)(float)zeta - (double)__uint_as_float(zb[y0 * Wt + x0]) <= taud_gate;
                         if (vis) {
-                            ed0 = (T)(zeta - (double)ld_f32(r_tdep, cell * 4, 0));
+                            const T w00 = (T(1) - al) * (T(1) - be), w01 = al * (T(1) - be);
+                            const T w10 = (T(1) - al) * be, w11 = al * be;
+                            // e_d = zeta - D(u') taken relative to the tap at (x0, y0): the taps lie within
+                            // tau of zeta, so their differences are exact and the large common part
+                            // cancels in FP64 before anything is rounded to the evaluation precision; the
+                            // image Jacobian only takes differences of taps
+                            const float d0 = tD[1];
+                            const T Vr = w01 * (T)(tD[2] - d0) + w10 * (T)(tD[5] - d0) + w11 * (T)(tD[6] - d0);
+                            sample_grad<T, GM>((T)tD[0], (T)tD[1], (T)tD[2], (T)tD[3], (T)tD[4], (T)tD[5], (T)tD[6],
+                                               (T)tD[7], (T)tD[8], (T)tD[9], (T)tD[10], (T)tD[11], w00, w01, w10, w11,
+                                               al, be, gxd, gyd);
+                            edv = (T)(zeta - (double)d0) - Vr;
                             valid = true;
                         }
                     }
@@ -839,7 +832,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 Q.cell[slot] = x0 | (y0 << 16);
                 Q.al[slot] = al; Q.be[slot] = be;
                 Q.px[slot] = px; Q.py[slot] = py; Q.pz[slot] = pz;
-                Q.ed0[slot] = ed0;
+                Q.ed[slot] = edv; Q.gxd[slot] = gxd; Q.gyd[slot] = gyd;
             }
             tail += __popcll(mask);
             __builtin_amdgcn_wave_barrier();

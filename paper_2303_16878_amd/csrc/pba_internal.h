@@ -56,7 +56,6 @@ struct EvalArgs {
     const float *dep;            // depth plane (pixels without a valid depth hold kNoDepth)
     const float4 *att4;          // 5 channels: {intensity, nx, ny, nz}
     const float *att1;           // 2 channels: intensity
-    const float2 *dbnd;          // per cell (x0, y0): smallest and largest depth of its 12-tap stencil
     const float2 *lut32;         // ray tables, FP32
     const double2 *lut64;        // ray tables, FP64
     const int32_t *item_pair;
@@ -125,10 +124,6 @@ struct CholPlan {
 // 64 x 64: all W, then all W^T).
 void launch_cholesky(double *A, double *L, double *LT, int n, double *Winv, const CholPlan &plan, int32_t *fail,
                      hipStream_t st);
-// Per cell (x0, y0) of one keyframe plane: the smallest and largest depth among the 12 taps of its
-// sampling stencil (kNoDepth included, so one missing tap fails every occlusion bound); cells whose
-// stencil leaves the image hold {kNoDepth, kNoDepth}.
-void launch_stencil_bounds(const float *dep, float2 *bnd, int H, int W, hipStream_t st);
 void launch_downsample(const float *dep, const float4 *att4, const float *att1, int H, int W, float *dep2,
                        float4 *att4_2, float *att1_2, int H2, int W2, double tau, hipStream_t st);
 void launch_unpack(const float *dep, const float4 *att4, const float *att1, int npx, float *I, float *D, float *N,

@@ -95,33 +95,4 @@ void launch_unpack(const float *dep, const float4 *att4, const float *att1, int 
     hipLaunchKernelGGL(unpack_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, dep, att4, att1, npx, I, D, N);
 }
 
-// One thread per cell: min / max over the stencil's taps -- row y0 cols x0-1..x0+2, row y0+1 cols
-// x0-1..x0+2, rows y0-1 and y0+2 cols x0, x0+1.  Pose-independent, so built once per level; the
-// evaluation then tests a cell's occlusion bound with one 8-byte load instead of 12 taps.
-__global__ void stencil_bounds_kernel(const float *__restrict__ dep, float2 *__restrict__ bnd, int H, int W)
-{
-    const int n = H * W;
-    for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < n; o += gridDim.x * blockDim.x) {
-        const int y = o / W, x = o - y * W;
-        float lo = kNoDepth, hi = kNoDepth;
-        if (x >= 1 && x <= W - 3 && y >= 1 && y <= H - 3) {
-            const float *r0 = dep + (int64_t)(y - 1) * W + x;   // row y0 - 1, col x0
-            const float t[12] = {r0[W - 1], r0[W], r0[W + 1], r0[W + 2],
-                                 r0[2 * W - 1], r0[2 * W], r0[2 * W + 1], r0[2 * W + 2],
-                                 r0[0], r0[1], r0[3 * W], r0[3 * W + 1]};
-            lo = hi = t[0];
-#pragma unroll
-            for (int k = 1; k < 12; ++k) { lo = fminf(lo, t[k]); hi = fmaxf(hi, t[k]); }
-        }
-        bnd[o] = make_float2(lo, hi);
-    }
-}
-
-void launch_stencil_bounds(const float *dep, float2 *bnd, int H, int W, hipStream_t st)
-{
-    const int n = H * W;
-    const int blocks = n / 256 + 1 < 4096 ? n / 256 + 1 : 4096;
-    hipLaunchKernelGGL(stencil_bounds_kernel, dim3(blocks), dim3(256), 0, st, dep, bnd, H, W);
-}
-
 }  // namespace pba

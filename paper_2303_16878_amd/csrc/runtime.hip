@@ -49,7 +49,6 @@ struct ImageSet {
     std::vector<KfDev> kfs_h;
     int64_t texels = 0;
     DevBuf sensors_d, kfs_d, dep, att4, att1, lut32, lut64;
-    DevBuf dbnd;   // per cell: depth bounds of its sampling stencil (launch_stencil_bounds)
 };
 
 struct pba_ctx {
@@ -208,7 +207,7 @@ __global__ void pack_kernel(const float *__restrict__ I, const float *__restrict
 
 void release_images(ImageSet &is)
 {
-    DevBuf *bufs[] = {&is.sensors_d, &is.kfs_d, &is.dep, &is.att4, &is.att1, &is.lut32, &is.lut64, &is.dbnd};
+    DevBuf *bufs[] = {&is.sensors_d, &is.kfs_d, &is.dep, &is.att4, &is.att1, &is.lut32, &is.lut64};
     for (DevBuf *b : bufs) release(*b);
 }
 
@@ -271,7 +270,6 @@ pba_status image_layout(pba_ctx *c, ImageSet &is, const std::vector<int32_t> &se
     pba_status s;
     if ((s = upload(c, is.kfs_d, is.kfs_h.data(), is.kfs_h.size() * sizeof(KfDev)))) return s;
     if ((s = ensure(c, is.dep, off * sizeof(float)))) return s;
-    if ((s = ensure(c, is.dbnd, off * sizeof(float2)))) return s;
     if (c->cfg.channels == 5) return ensure(c, is.att4, off * sizeof(float4));
     return ensure(c, is.att1, off * sizeof(float));
 }
@@ -466,7 +464,6 @@ EvalArgs make_args(pba_ctx *c)
     a.dep = P_<float>(c->L().dep);
     a.att4 = P_<float4>(c->L().att4);
     a.att1 = P_<float>(c->L().att1);
-    a.dbnd = P_<float2>(c->L().dbnd);
     a.lut32 = P_<float2>(c->L().lut32);
     a.lut64 = P_<double2>(c->L().lut64);
     a.item_pair = P_<int32_t>(c->item_pair);
@@ -806,8 +803,6 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
         hipLaunchKernelGGL(pack_kernel, dim3(blocks), dim3(256), 0, c->stream, dI, dD, five ? dN : nullptr,
                            P_<float>(c->L().dep) + kfs[k].off, five ? P_<float4>(c->L().att4) + kfs[k].off : nullptr,
                            five ? nullptr : P_<float>(c->L().att1) + kfs[k].off, npx, S.min_depth, S.max_depth);
-        launch_stencil_bounds(P_<float>(c->L().dep) + kfs[k].off, P_<float2>(c->L().dbnd) + kfs[k].off, kfs[k].H,
-                              kfs[k].W, c->stream);
         if (!on_device) HIP_OK(hipStreamSynchronize(c->stream));   // stage is reused
     }
     HIP_OK(hipGetLastError());
@@ -1420,7 +1415,6 @@ pba_status pba_build_pyramid(pba_ctx *c, int32_t n_levels)
                               five ? nullptr : P_<float>(lo.att1) + a.off, a.H, a.W, P_<float>(up.dep) + b.off,
                               five ? P_<float4>(up.att4) + b.off : nullptr, five ? nullptr : P_<float>(up.att1) + b.off,
                               b.H, b.W, tau, c->stream);
-            launch_stencil_bounds(P_<float>(up.dep) + b.off, P_<float2>(up.dbnd) + b.off, b.H, b.W, c->stream);
         }
         HIP_OK(hipGetLastError());
     }
