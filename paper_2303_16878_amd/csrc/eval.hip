@@ -177,9 +177,11 @@ __device__ __forceinline__ void sample_grad(T a0, T a1, T a2, T a3, T b0, T b1, 
                                             T w00, T w01, T w10, T w11, T al, T be, T &Gx, T &Gy)
 {
     if (GM == 0) {
-        // central differences 1/2 (I[x+1] - I[x-1]) at each tap, blended with the bilinear weights
-        Gx = T(0.5) * (w00 * (a2 - a0) + w01 * (a3 - a1) + w10 * (b2 - b0) + w11 * (b3 - b1));
-        Gy = T(0.5) * (w00 * (b1 - c1) + w01 * (b2 - c2) + w10 * (d1 - a1) + w11 * (d2 - a2));
+        // central differences 1/2 (I[x+1] - I[x-1]) at each tap, blended with the bilinear weights;
+        // returned without the factor 1/2, which the caller folds into the projective Jacobian
+        // (scaling by 1/2 is exact, so the products are the same)
+        Gx = w00 * (a2 - a0) + w01 * (a3 - a1) + w10 * (b2 - b0) + w11 * (b3 - b1);
+        Gy = w00 * (b1 - c1) + w01 * (b2 - c2) + w10 * (d1 - a1) + w11 * (d2 - a2);
     } else {
         Gx = (T(1) - be) * (a2 - a1) + be * (b2 - b1);
         Gy = (T(1) - al) * (b1 - a1) + al * (b2 - a2);
@@ -421,6 +423,11 @@ __device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, int voff, int 
 {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
+__device__ __forceinline__ double2 ld_f64x2(__amdgpu_buffer_rsrc_t r, int voff)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
+    return make_double2(__hiloint2double((int)v[1], (int)v[0]), __hiloint2double((int)v[3], (int)v[2]));
+}
 __device__ __forceinline__ float4 ld_f32x4(__amdgpu_buffer_rsrc_t r, int voff, int soff)
 {
     const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
@@ -455,7 +462,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
     __shared__ double s_red[kBlock / 64][kAcc];
     __shared__ WaveQueue<T> s_q[kBlock / 64];
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index: uniform
     WaveQueue<T> &Q = s_q[wave];
     typedef typename Lut<T>::type L2;
     const L2 *lut = Lut<T>::ptr(a);
@@ -510,7 +517,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             for (int k = 0; k < 3; ++k) cc[k] = (T)cd[k];
         }
         const double st_fx = uni_d(st.fxd), st_fy = uni_d(st.fyd), st_cx = uni_d(st.cxd), st_cy = uni_d(st.cyd), st_dmin = uni_d(st.dmind);
-        const T fx = (T)st_fx, fy = (T)st_fy;
+        // focal lengths of the projective Jacobian, halved for central differences (see sample_grad)
+        const T fx = (T)(GM == 0 ? 0.5 * st_fx : st_fx), fy = (T)(GM == 0 ? 0.5 * st_fy : st_fy);
         const double taud_gate = uni_d(st.taud);   // occlusion bound, FP64 in both paths
         const T om_g = (T)a.omega_g, om_d = (T)a.omega_d, om_n = (T)a.omega_n, delta = (T)a.huber;
         // ray-table offsets of the source (unprojection) and target (projection) sensors in scalar
@@ -518,13 +526,14 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         const int s_lcol = uni(ss.lut_col), s_lrow = uni(ss.lut_row);
         const int t_lcol = uni(st.lut_col), t_lrow = uni(st.lut_row);
         const L2 *lcol = lut + s_lcol, *lrow = lut + s_lrow;
-        const float *sdep = a.dep + ks.off;
         const float4 *satt4 = a.att4 + ks.off;
         const float *satt1 = a.att1 + ks.off;
         // z-buffer occlusion variant: this pair's source z-buffer (FP32 depth bits per target cell)
         uint32_t *const zb = ZB ? a.zbuf + a.zoff[pair] : nullptr;
         const uint32_t tnpx = (uint32_t)Ht * (uint32_t)Wt;
         const __amdgpu_buffer_rsrc_t r_tdep = plane_rsrc(uni_ptr(a.dep + kt.off), tnpx * 4u);
+        const __amdgpu_buffer_rsrc_t r_sdep = plane_rsrc(uni_ptr(a.dep + ks.off), (uint32_t)npx * 4u);
+        const __amdgpu_buffer_rsrc_t r_lut = plane_rsrc(uni_ptr(a.lut64), (uint32_t)a.lut64_bytes);
         const __amdgpu_buffer_rsrc_t r_tatt = NCH == 5 ? plane_rsrc(uni_ptr(a.att4 + kt.off), tnpx * 16u)
                                                        : plane_rsrc(uni_ptr(a.att1 + kt.off), tnpx * 4u);
 
@@ -534,7 +543,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         double acc64[F32 ? 1 : ACC_F];   // FP64 path: the 27 sums per lane
 #pragma unroll
         for (int k = 0; k < (F32 ? 1 : ACC_F); ++k) acc64[k] = 0.0;
-        int n_eval = 0, n_valid = 0, n_band = 0;
+        int n_eval = 0, n_valid = 0;   // per lane
+        int n_band = 0;                // per wave
         int head = 0, tail = 0;   // wave-uniform queue positions
 
         // phase 2: residuals, weights, Jacobian rows and accumulation of queue slot `slot`
@@ -711,19 +721,33 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             int x0 = any_value<int>(), y0 = any_value<int>();
             T al = any_value<T>(), be = any_value<T>(), px = any_value<T>(), py = any_value<T>();
             T pz = any_value<T>(), edv = any_value<T>(), gxd = any_value<T>(), gyd = any_value<T>();
-            const float Ds = pix < px1 ? sdep[pix] : 0.f;
+            bool in_band = false;
+            const float Ds_l = ld_f32(r_sdep, pix * 4, 0);
+            const float Ds = pix < px1 ? Ds_l : 0.f;
             if (DBG && pix < px1) a.dbg_status[pix] = 1;
             if (Ds > 0.f) {
                 ++n_eval;
                 if (DBG) a.dbg_status[pix] = 2;
-                int row = (int)__umulhi((uint32_t)pix, magic);
-                int col = pix - row * Ws;
-                if (col < 0) { row -= 1; col += Ws; }   // the reciprocal can only round up
+                int row, col;
+                if (Ws >= 64) {
+                    // the chunk's first pixel splits on the scalar unit; its 64 pixels span at most two rows
+                    int r0 = (int)__umulhi((uint32_t)cbase, magic);
+                    int c0 = cbase - r0 * Ws;
+                    if (c0 < 0) { r0 -= 1; c0 += Ws; }   // the reciprocal can only round up
+                    col = c0 + lane;
+                    const bool next = col >= Ws;
+                    row = next ? r0 + 1 : r0;
+                    col = next ? col - Ws : col;
+                } else {
+                    row = (int)__umulhi((uint32_t)pix, magic);
+                    col = pix - row * Ws;
+                    if (col < 0) { row -= 1; col += Ws; }
+                }
                 // Geometry in FP64 in both paths (on this chip FP64 vector arithmetic issues at the FP32
                 // rate): unprojection q = d * ray(u) from the FP64 ray table, p_bar = R q + t, the
                 // projected coordinates and the depth/range cue.  Cells, masks and the large-magnitude
                 // part of the depth residual then carry no FP32 rounding.
-                const double2 lcd = a.lut64[s_lcol + col], lrd = a.lut64[s_lrow + row];
+                const double2 lcd = ld_f64x2(r_lut, (s_lcol + col) * 16), lrd = ld_f64x2(r_lut, (s_lrow + row) * 16);
                 const double dd = (double)Ds;
                 double q0, q1, q2;
                 if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
@@ -756,7 +780,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         // pixel); inside, the nearest table ray is within 1 px, so the offset angle is small
                         near = ua > -1.f && ua < (float)Wt && va > -1.f && va < (float)Ht;
                         const int kc = min(max((int)rintf(ua), 0), Wt - 1), kr = min(max((int)rintf(va), 0), Ht - 1);
-                        const double2 cs = a.lut64[t_lcol + kc], rs = a.lut64[t_lrow + kr];
+                        const double2 cs = ld_f64x2(r_lut, (t_lcol + kc) * 16), rs = ld_f64x2(r_lut, (t_lrow + kr) * 16);
                         const double tu = fma(Y, cs.x, -X * cs.y) * rcp_f64(fma(X, cs.x, Y * cs.y));
                         const double tv = fma(Z, rs.x, -rho * rs.y) * rcp_f64(fma(rho, rs.x, Z * rs.y));
                         u = fma(st_fx, atan_small(tu), (double)kc);
@@ -776,8 +800,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         const double du = u - (double)x0, dv = v - (double)y0;
                         al = (T)du; be = (T)dv;
                         // the cell of a point this close to a boundary can differ between exact
-                        // arithmetic and any rounding of it: counted
-                        n_band += (du < kBandPx || du > 1.0 - kBandPx || dv < kBandPx || dv > 1.0 - kBandPx) ? 1 : 0;
+                        // arithmetic and any rounding of it: counted (per wave, on the scalar unit)
+                        in_band = fmax(fabs(du - 0.5), fabs(dv - 0.5)) > 0.5 - kBandPx;
                     }
                     if (ZB && ok && a.zpass) {
                         // z-buffer pass: keep the nearest predicted depth per target cell (depths are
@@ -822,6 +846,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                     }
                 }
             }
+            n_band += __popcll(__ballot(in_band));
             // append the valid lanes to the wave's queue in lane (= pixel) order
             const uint64_t mask = __ballot(valid);
             if (valid) {
@@ -852,7 +877,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             double v = k < ACC_F ? (ADJ ? acc_b[k - ACC_B] : acc64[F32 ? 0 : k])
                                  : (k == ACC_F ? acc_F
                                                : (k == ACC_VALID ? (double)n_valid
-                                                                 : (k == ACC_EVAL ? (double)n_eval : (double)n_band)));
+                                                                 : (k == ACC_EVAL ? (double)n_eval
+                                                                                  : (lane == 0 ? (double)n_band : 0.0))));
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
             if (lane == 0) s_red[wave][k] = v;

@@ -62,7 +62,7 @@ struct EvalArgs {
     const int32_t *item_px0;
     const int32_t *item_map;     // nullable: item = item_map[position] (per-pair launches)
     int32_t items_px;
-    int32_t pad;
+    int32_t lut64_bytes;         // size of the FP64 ray tables (bounds of their buffer loads)
     uint32_t *counter;           // kXcd queue counters of this launch
     void *partials;              // double[n_items][kAcc]
     double omega_g, omega_d, omega_n, huber;

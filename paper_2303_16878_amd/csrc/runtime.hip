@@ -466,6 +466,7 @@ EvalArgs make_args(pba_ctx *c)
     a.att1 = P_<float>(c->L().att1);
     a.lut32 = P_<float2>(c->L().lut32);
     a.lut64 = P_<double2>(c->L().lut64);
+    a.lut64_bytes = (int32_t)c->L().lut64.bytes;
     a.item_pair = P_<int32_t>(c->item_pair);
     a.item_px0 = P_<int32_t>(c->item_px0);
     a.items_px = c->items_px;
