@@ -231,7 +231,9 @@ def test_error_paths(rgbd_small, pba):
 # ---------------------------------------------------------------- full-size configurations, sampled pairs
 
 @pytest.mark.parametrize("name,sample", [("rgbd_room", [0, 17, 333, 640, 999]),
-                                         ("lidar128", [0, 401, 1202, 1800, 2405])])
+                                         ("lidar128", [0, 401, 1202, 1800, 2405]),
+                                         # loop closures: 0 -> 296 .. 299 and back, 3 -> 299
+                                         ("lidar128", [4, 7, 31, 2374, 2382])])
 def test_full_size_sampled_pairs(name, sample, pba):
     prob = synth.make(name)
     _log("generated", name, prob.n, "keyframes", len(prob.pairs), "pairs")
@@ -417,3 +419,41 @@ def test_boundary_band_counts(fixture, prec, request, pba):
     _log(fixture, prec, "boundary band", total, "of", ev["n_valid"], "valid")
     assert ev["n_boundary_band"] == total
     assert total > 0
+
+
+def test_full_size_lidar_lm_matches_oracle(pba):
+    """The full 128x2048 LiDAR loop (300 keyframes, 2406 pairs, n = 1800) on the FP64 path: two LM
+    iterations accept and reject as the oracle's do and end within 1e-6 m / 1e-6 rad of its poses
+    (the oracle needs three full evaluations of 6.2e8 px-pairs: about 100 s on 16 host cores)."""
+    prob = synth.make("lidar128")
+    iters = 2
+    with pba.context_for_problem(prob, precision=pba.PBA_F64) as ctx:
+        logs = ctx.iterate(iters, use_lm=True, lambda0=1e-4)
+        X = ctx.get_poses()
+    _log("GPU FP64 LM:", [(round(l["F"], 3), l["accepted"]) for l in logs])
+    X_or, log_or = oracle.optimize(prob, prob.init_poses, iters=iters, lm=True, lam0=1e-4)
+    _log("oracle LM:  ", [(round(l["F"], 3), l["accepted"]) for l in log_or])
+    dt, dr = _pose_err(X, X_or)
+    _log("full-size LM pose diff vs oracle: %.3g m %.3g rad" % (dt, dr))
+    assert [l["accepted"] for l in logs] == [l["accepted"] for l in log_or]
+    for a, b in zip(logs, log_or):
+        assert abs(a["F"] - b["F"]) <= 1e-7 * abs(b["F"])   # summation order; band points
+    assert dt < 1e-6 and dr < 1e-6
+
+
+def test_fp32_and_fp64_paths_reach_the_same_accuracy(pba):
+    """A 30-keyframe stretch of the 128x2048 LiDAR loop: after 25 LM iterations the FP32 evaluation
+    path's ATE RMSE equals the FP64 path's within 1e-6 m (both start from the same perturbed poses)."""
+    from paper_2303_16878_amd.metrics import ate_rmse
+    kfs = list(range(30))
+    prob = synth.make("lidar128", kfs=kfs).subset(kfs)
+    ate = {}
+    for name, prec in (("f32", pba.PBA_F32), ("f64", pba.PBA_F64)):
+        with pba.context_for_problem(prob, precision=prec) as ctx:
+            ctx.iterate(25, use_lm=True, lambda0=1e-4)
+            ate[name] = ate_rmse(ctx.get_poses(), prob.gt_poses)
+    a0 = ate_rmse(prob.init_poses, prob.gt_poses)
+    _log("30-keyframe segment ATE: start %.6f m, FP32 %.9f m, FP64 %.9f m, |diff| %.3g m" % (
+        a0, ate["f32"], ate["f64"], abs(ate["f32"] - ate["f64"])))
+    assert ate["f64"] < a0
+    assert abs(ate["f32"] - ate["f64"]) < 1e-6
