@@ -31,18 +31,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bytes_per_px_pair(channels):
-    # source texel + one target texel per evaluation, FP32 channels
-    return 2 * 4 * channels
+def bytes_per_px_pair(channels, bf16=0):
+    # source texel + one target texel per evaluation: FP32 depth plus the other cues in FP32 or BF16
+    return 2 * (4 + (2 if bf16 else 4) * (channels - 1))
 
 
-def flops_per_px_pair(channels, target_model):
-    """Algorithmic FLOPs (FMA = 2) per evaluated px-pair: transform, projection, bilinear samples with
-    central differences, residuals, Huber, Jacobian rows and the 27-term accumulation -- about 720
-    for 5 cue rows into a spherical target, 690 into a pinhole one, 300 for 2 rows."""
-    if channels == 2:
-        return 300
-    return 720 if target_model == 1 else 690
+def flops_split(channels, target_model):
+    """Algorithmic FLOPs (FMA = 2) of one px-pair: (every evaluated px-pair: transform 18, projection
+    36 spherical / 10 pinhole, the 12-tap occlusion bound 24; every valid correspondence: the rest --
+    bilinear samples with central differences, residuals, Huber, projective Jacobian, Jacobian rows
+    and the 27-term accumulation), totalling about 720 for 5 cue rows into a spherical target, 690
+    into a pinhole one, 300 for 2 rows."""
+    first = 18 + (36 if target_model == 1 else 10) + 24
+    total = 300 if channels == 2 else (720 if target_model == 1 else 690)
+    return first, total - first
 
 
 PROFILE_KERNEL = "void pba::eval_kernel<float, 5, 1, 1, 0, false, false, false>(pba::EvalArgs, int, int)"
@@ -74,10 +76,11 @@ def run_path(pba, prob, precision, warmup, steps, autotune=True, use_lm=True):
     with pba.context_for_problem(prob, precision=precision) as ctx:
         torch.cuda.synchronize()
         tune = ctx.autotune() if autotune else []
-        ev_init = ctx.evaluate(want_system=True)   # the system at the initial poses, for FP32 vs FP64
+        # the system at the initial poses, for FP32 vs FP64; per-pair counts for the FLOP figure
+        ev_init = ctx.evaluate(want_system=True, want_pairs=True)
         if warmup:
             ctx.iterate(warmup, use_lm=use_lm, lambda0=1e-4)
-        ev = ctx.evaluate()                      # system at the current poses; counts per evaluation
+        ev = ctx.evaluate(want_pairs=True)       # system at the current poses; counts per evaluation
         torch.cuda.synchronize()
         ctx.timings(reset=True)
         t0 = time.perf_counter()
@@ -95,8 +98,16 @@ def run_path(pba, prob, precision, warmup, steps, autotune=True, use_lm=True):
         tm = ctx.timings(reset=True)
         poses = ctx.get_poses()
     return dict(elapsed=elapsed, logs=logs, n_evaluated=ev["n_evaluated"], n_valid=ev["n_valid"], init=ev_init, tune=tune,
+                pair_eval=ev["pairs"][:, 157].copy(), pair_valid=ev["pairs"][:, 158].copy(),
                 eval_ms=tm_it["iter_eval_ms"] / steps, eval_ms_events=tm["eval_ms"] / n_eval_runs,
                 n_items=tm["n_items"], items_px=tm["items_px"], grid=tm["grid"], poses=poses, F=logs[-1]["F"])
+
+
+def bf16_round(x):
+    """float32 -> nearest-even BF16 values, held in float32 (input preparation for the FP64 path)."""
+    import numpy as np
+    b = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    return (((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16).astype(np.uint32).view(np.float32).reshape(np.shape(x))
 
 
 def cpu_model():
@@ -168,7 +179,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="lidar128", choices=["lidar128", "lidar64", "rgbd_room", "rgbd_small"])
+    ap.add_argument("--workload", default="lidar128",
+                    choices=["lidar128", "lidar64", "rgbd_room", "rgbd_small", "joint"])
+    ap.add_argument("--bf16", type=int, default=None, metavar="0|1",
+                    help="BF16 storage of intensity / normal images (default: 1 for joint, else 0); the FP64 "
+                         "path then reads the same images rounded to BF16, held in FP32")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--gn", action="store_true", help="Gauss-Newton iterations (every step taken) instead of LM")
     ap.add_argument("--no-cpu", action="store_true")
@@ -209,6 +224,8 @@ def main():
                                                              time.perf_counter() - t0))
     if args.zbuffer:
         prob.params["occlusion_zbuffer"] = 1
+    bf16 = args.bf16 if args.bf16 is not None else int(args.workload == "joint")
+    prob.params["storage_bf16"] = bf16
     if args.profile_evals:
         with pba.context_for_problem(prob, precision=pba.PBA_F32) as ctx:
             for i in range(args.profile_evals):
@@ -223,9 +240,13 @@ def main():
     ms_step = 1e3 * r32["elapsed"] / args.steps
     value = r32["n_evaluated"] * args.steps / r32["elapsed"]
     eval_s = r32["eval_ms"] / 1e3
-    achieved = bytes_per_px_pair(ch) * r32["n_evaluated"] / eval_s / 1e9
-    flop = flops_per_px_pair(ch, prob.sensors[0]["model"])
-    tflops = flop * r32["n_evaluated"] / eval_s / 1e12
+    achieved = bytes_per_px_pair(ch, bf16) * r32["n_evaluated"] / eval_s / 1e9
+    # algorithmic FLOPs of one evaluation at the poses the timed iterations start from, pair by pair
+    tmodel = [prob.sensors[prob.kf_sensor[int(t)]]["model"] for _, t in prob.pairs]
+    flop_launch = float(sum(e * flops_split(ch, m)[0] + v * flops_split(ch, m)[1]
+                            for e, v, m in zip(r32["pair_eval"], r32["pair_valid"], tmodel)))
+    flop = flop_launch / r32["n_evaluated"]
+    tflops = flop_launch / eval_s / 1e12
     log("FP32: %.2f ms/iter, %.3e px-pair/s; eval kernel %.3f ms in the iterations, %.3f ms alone "
         "(%.3e px-pair/s, %.0f GB/s algorithmic)" % (ms_step, value, r32["eval_ms"], r32["eval_ms_events"],
                                                      r32["n_evaluated"] / eval_s, achieved))
@@ -256,6 +277,9 @@ def main():
             "autotune": "item size and grid chosen by pba_autotune over %d points" % len(r32["tune"])
             if r32["tune"] else "off",
             "occlusion": "depth gate + z-buffer of the pair's source points" if args.zbuffer else "depth gate",
+            "image_storage": "BF16 intensity / normals, FP32 depth" if bf16 else "FP32",
+            "sensors": ["%s %dx%d" % ("spherical" if x["model"] == 1 else "pinhole", x["H"], x["W"])
+                        for x in prob.sensors],
         },
         "roofline": {
             # the evaluation kernel is bound by vector-ALU issue (measured VALU busy below); the HBM
@@ -267,11 +291,16 @@ def main():
             "frac": tflops / VALU_PEAK_TFLOPS,
             "traffic": None,
             "flop_per_px_pair": flop,
+            "flop_model": "per evaluated px-pair: transform + projection + 12-tap occlusion bound (78 spherical, "
+                          "52 pinhole); per valid correspondence: the rest of ~720 / 690 / 300 (5 rows spherical / "
+                          "pinhole, 2 rows)",
             "valu_busy_counter": None,
             "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "bytes_per_px_pair": bytes_per_px_pair(ch)},
-            "kernel": "eval_kernel<float,%d,%s,%s> (persistent)" % (
-                ch, "sph" if sen["model"] == 1 else "pin", "sph" if sen["model"] == 1 else "pin"),
+                    "bytes_per_px_pair": bytes_per_px_pair(ch, bf16)},
+            "kernel": ("eval_kernel<float,%d,%s,%s> (persistent)" % (
+                ch, "sph" if sen["model"] == 1 else "pin", "sph" if sen["model"] == 1 else "pin")
+                if len(prob.sensors) == 1 else
+                "eval_kernel<float,%d,*,*> (persistent; one launch per source/target model pair)" % ch),
             "kernel_ms": r32["eval_ms"],
             "kernel_ms_source": "mean over the timed iterations of device wall-clock stamps around the "
                                 "evaluation launches, on the library's stream",
@@ -287,12 +316,19 @@ def main():
         tb = pmc["traffic_bytes_per_launch"]
         out["roofline"]["traffic"] = tb / eval_s / 1e9
         out["roofline"]["traffic_bytes_per_launch"] = tb
-        out["roofline"]["algorithmic_bytes_per_launch"] = bytes_per_px_pair(ch) * r32["n_evaluated"]
+        out["roofline"]["algorithmic_bytes_per_launch"] = bytes_per_px_pair(ch, bf16) * r32["n_evaluated"]
         out["roofline"]["valu_busy_counter"] = pmc["valu_busy"]
         out["roofline"]["valu_insts_per_launch"] = pmc["valu_insts_per_launch"]
     if not args.no_fp64:
         log("FP64 path: warmup %d, timed %d iterations" % (args.warmup, args.steps))
-        r64 = run_path(pba, prob, pba.PBA_F64, args.warmup, args.steps, not args.no_autotune, use_lm=not args.gn)
+        prob64 = prob
+        if bf16:   # the FP64 path reads FP32 images: the same values, rounded to BF16 here
+            import copy
+            prob64 = copy.copy(prob)
+            prob64.params = dict(prob.params, storage_bf16=0)
+            prob64.intensity = [bf16_round(x) for x in prob.intensity]
+            prob64.normals = [bf16_round(x) for x in prob.normals]
+        r64 = run_path(pba, prob64, pba.PBA_F64, args.warmup, args.steps, not args.no_autotune, use_lm=not args.gn)
         out["s_per_iter"]["f64"] = r64["elapsed"] / args.steps
         out["eval_px_pairs_per_s"]["f64"] = r64["n_evaluated"] / (r64["eval_ms"] / 1e3)
         out["fp64_value"] = r64["n_evaluated"] * args.steps / r64["elapsed"]

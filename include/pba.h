@@ -106,7 +106,11 @@ typedef struct {
                                     FP32; Sec. IV-C occlusion suppression, z-buffer reading).  Costs
                                     one projection-only pass over every pair per evaluation and
                                     4 bytes per target pixel per pair of device memory; 0: off */
-    int32_t reserved;            /* must be 0 */
+    int32_t storage_bf16;        /* 1: intensity and normal images are kept on the device in BF16 (rounded
+                                    to nearest even when loaded, and when the pyramid or normal estimation
+                                    writes them); residuals, Jacobians and sums stay FP32/FP64.  FP32 path
+                                    only, without occlusion_zbuffer, and pba_loss_backward is then
+                                    PBA_EINVAL; 0: FP32 images */
     /* Device memory of the context (images, plans, systems, work buffers) comes from these
      * callbacks when both are set (e.g. a framework's caching allocator), else from hipMalloc.
      * dev_alloc(bytes, alloc_user) returns device memory of cfg->device usable on cfg->stream, or

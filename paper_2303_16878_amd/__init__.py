@@ -49,7 +49,7 @@ class pba_config(ctypes.Structure):
                 ("omega_depth", ctypes.c_double), ("omega_normal", ctypes.c_double),
                 ("huber_delta", ctypes.c_double), ("occlusion_tau_pinhole", ctypes.c_double),
                 ("occlusion_tau_spherical", ctypes.c_double), ("occlusion_zbuffer", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("dev_alloc", ctypes.c_void_p), ("dev_free", ctypes.c_void_p),
+                ("storage_bf16", ctypes.c_int32), ("dev_alloc", ctypes.c_void_p), ("dev_free", ctypes.c_void_p),
                 ("alloc_user", ctypes.c_void_p)]
 
 
@@ -215,7 +215,7 @@ class Context:
     def __init__(self, device=0, precision=PBA_F32, channels=5, grad_mode=0, anchor=0, stream=None,
                  omega_intensity=1.0, omega_depth=1.0, omega_normal=1.0, huber_delta=0.1,
                  occlusion_tau_pinhole=0.5, occlusion_tau_spherical=1.0, use_graph=True, occlusion_zbuffer=False,
-                 allocator="torch"):
+                 storage_bf16=False, allocator="torch"):
         """allocator: "torch" -- device memory from torch's caching allocator (when torch sees a GPU
         and no raw stream handle is given), "hip" -- the library's own hipMalloc."""
         self.lib = load_library()
@@ -243,6 +243,7 @@ class Context:
         cfg.huber_delta = huber_delta
         cfg.occlusion_tau_pinhole, cfg.occlusion_tau_spherical = occlusion_tau_pinhole, occlusion_tau_spherical
         cfg.occlusion_zbuffer = int(bool(occlusion_zbuffer))
+        cfg.storage_bf16 = int(bool(storage_bf16))
         self.cfg = cfg
         h = ctypes.c_void_p()
         self._check(self.lib.pba_create(ctypes.byref(cfg), ctypes.byref(h)), ctx=None)
@@ -531,7 +532,8 @@ def context_for_problem(prob, precision=PBA_F32, channels=None, grad_mode=0, dev
                   omega_intensity=prm["omega_intensity"], omega_depth=prm["omega_depth"],
                   omega_normal=prm["omega_normal"], huber_delta=prm["huber_delta"],
                   occlusion_tau_pinhole=prm["occ_tau_pinhole"], occlusion_tau_spherical=prm["occ_tau_spherical"],
-                  **dict(dict(occlusion_zbuffer=bool(prm.get("occlusion_zbuffer", 0))), **kw))
+                  **dict(dict(occlusion_zbuffer=bool(prm.get("occlusion_zbuffer", 0)),
+                              storage_bf16=bool(prm.get("storage_bf16", 0))), **kw))
     for s in prob.sensors:
         ctx.add_sensor(s["model"], s["H"], s["W"], s["fx"], s["fy"], s["cx"], s["cy"], s["min_depth"],
                        s["max_depth"], s["offset"])

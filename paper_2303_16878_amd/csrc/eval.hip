@@ -423,6 +423,17 @@ __device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, int voff, int 
 {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
+// BF16 texels: {I, nx, ny, nz} in two dwords (low half first), or one 16-bit intensity
+__device__ __forceinline__ float4 ld_bf16x4(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return make_float4(__uint_as_float(v[0] << 16), __uint_as_float(v[0] & 0xFFFF0000u), __uint_as_float(v[1] << 16),
+                       __uint_as_float(v[1] & 0xFFFF0000u));
+}
+__device__ __forceinline__ float ld_bf16(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    return bf16_to_f32((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
 __device__ __forceinline__ double2 ld_f64x2(__amdgpu_buffer_rsrc_t r, int voff)
 {
     const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
@@ -455,7 +466,8 @@ __device__ __forceinline__ void load_stencil(V (&t)[12], L ld, int voff, int row
 // the gradient arenas with hardware float atomics.
 // ZB: the z-buffer occlusion variant (a separate instantiation, so the plain evaluation carries
 // none of its code).
-template <typename T, int NCH, int SM, int TM, int GM, bool DBG, bool ADJ = false, bool ZB = false>
+// BF: intensity and normal planes stored as BF16 (a separate instantiation; FP32 path only).
+template <typename T, int NCH, int SM, int TM, int GM, bool DBG, bool ADJ = false, bool ZB = false, bool BF = false>
 __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base, int n_items)
 {
     __shared__ int s_item;
@@ -534,8 +546,9 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         const __amdgpu_buffer_rsrc_t r_tdep = plane_rsrc(uni_ptr(a.dep + kt.off), tnpx * 4u);
         const __amdgpu_buffer_rsrc_t r_sdep = plane_rsrc(uni_ptr(a.dep + ks.off), (uint32_t)npx * 4u);
         const __amdgpu_buffer_rsrc_t r_lut = plane_rsrc(uni_ptr(a.lut64), (uint32_t)a.lut64_bytes);
-        const __amdgpu_buffer_rsrc_t r_tatt = NCH == 5 ? plane_rsrc(uni_ptr(a.att4 + kt.off), tnpx * 16u)
-                                                       : plane_rsrc(uni_ptr(a.att1 + kt.off), tnpx * 4u);
+        const __amdgpu_buffer_rsrc_t r_tatt =
+            NCH == 5 ? (BF ? plane_rsrc(uni_ptr(a.att4h + kt.off), tnpx * 8u) : plane_rsrc(uni_ptr(a.att4 + kt.off), tnpx * 16u))
+                     : (BF ? plane_rsrc(uni_ptr(a.att1h + kt.off), tnpx * 2u) : plane_rsrc(uni_ptr(a.att1 + kt.off), tnpx * 4u));
 
         // FP64 accumulators: lanes 2k, 2k + 1 hold this wave's total of H/b sum k (k < 27); rho per
         // lane; the adjoint keeps b per lane
@@ -566,11 +579,19 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             T Vg, Gxg, Gyg;
             T Vn[3] = {T(0), T(0), T(0)}, Gxn[3] = {T(0), T(0), T(0)}, Gyn[3] = {T(0), T(0), T(0)};
             if (NCH == 5) {
-                const float4 s4 = satt4[pix];
-                Is = s4.x; ns0 = s4.y; ns1 = s4.z; ns2 = s4.w;
+                float4 s4;
                 float4 q4[12];
-                load_stencil<float4, 16>(q4, [&](int vo, int so) { return ld_f32x4(r_tatt, vo, so); }, corner * 16,
-                                         Wt * 16);
+                if (BF) {
+                    const ushort4 h = a.att4h[ks.off + pix];
+                    s4 = make_float4(bf16_to_f32(h.x), bf16_to_f32(h.y), bf16_to_f32(h.z), bf16_to_f32(h.w));
+                    load_stencil<float4, 8>(q4, [&](int vo, int so) { return ld_bf16x4(r_tatt, vo, so); }, corner * 8,
+                                            Wt * 8);
+                } else {
+                    s4 = satt4[pix];
+                    load_stencil<float4, 16>(q4, [&](int vo, int so) { return ld_f32x4(r_tatt, vo, so); }, corner * 16,
+                                             Wt * 16);
+                }
+                Is = s4.x; ns0 = s4.y; ns1 = s4.z; ns2 = s4.w;
                 float tI[12], tX[12], tY[12], tZ[12];
 #pragma unroll
                 for (int k = 0; k < 12; ++k) { tI[k] = q4[k].x; tX[k] = q4[k].y; tY[k] = q4[k].z; tZ[k] = q4[k].w; }
@@ -583,9 +604,16 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 SAMPLE(tY, Vn[1], Gxn[1], Gyn[1]);
                 SAMPLE(tZ, Vn[2], Gxn[2], Gyn[2]);
             } else {
-                Is = satt1[pix];
                 float tI[12];
-                load_stencil<float, 4>(tI, [&](int vo, int so) { return ld_f32(r_tatt, vo, so); }, corner * 4, Wt * 4);
+                if (BF) {
+                    Is = bf16_to_f32(a.att1h[ks.off + pix]);
+                    load_stencil<float, 2>(tI, [&](int vo, int so) { return ld_bf16(r_tatt, vo, so); }, corner * 2,
+                                           Wt * 2);
+                } else {
+                    Is = satt1[pix];
+                    load_stencil<float, 4>(tI, [&](int vo, int so) { return ld_f32(r_tatt, vo, so); }, corner * 4,
+                                           Wt * 4);
+                }
                 SAMPLE(tI, Vg, Gxg, Gyg);
 #undef SAMPLE
             }
@@ -978,6 +1006,13 @@ void launch_delta_to_dx(const float *delta, double *dx, int N, hipStream_t st)
 template <typename T, int NCH, int SM, int TM, int GM, bool DBG>
 static void launch_eval_t(const EvalArgs &a, int item_base, int n_items, int grid, hipStream_t st)
 {
+    if constexpr (std::is_same<T, float>::value) {
+        if (a.bf16) {
+            hipLaunchKernelGGL((eval_kernel<T, NCH, SM, TM, GM, DBG, false, false, true>), dim3(grid), dim3(kBlock), 0,
+                               st, a, item_base, n_items);
+            return;
+        }
+    }
     if (a.zbuf)
         hipLaunchKernelGGL((eval_kernel<T, NCH, SM, TM, GM, DBG, false, true>), dim3(grid), dim3(kBlock), 0, st, a,
                            item_base, n_items);

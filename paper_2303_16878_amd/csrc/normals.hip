@@ -61,7 +61,7 @@ __device__ static void smallest_eigvec(double (&a)[9], double (&v)[3], double &l
     v[2] = V[6 + i0];
 }
 
-__global__ void normals_kernel(const float *__restrict__ dep, float4 *__restrict__ att4, int H, int W,
+__global__ void normals_kernel(const float *__restrict__ dep, void *__restrict__ att4, int bf, int H, int W,
                                const double2 *__restrict__ lcol, const double2 *__restrict__ lrow, int spherical,
                                double scale, double min_px, double max_px, double tau, int min_count, int R)
 {
@@ -69,7 +69,7 @@ __global__ void normals_kernel(const float *__restrict__ dep, float4 *__restrict
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += gridDim.x * blockDim.x) {
         const int r = i / W, c = i - r * W;
         const double d = (double)dep[i];
-        float4 out = att4[i];
+        float4 out = att_get4(att4, bf, i);
         out.y = out.z = out.w = 0.f;
         if (d > 0.0) {
             const double rad = fmin(fmax(scale / d, min_px), max_px);
@@ -114,17 +114,17 @@ __global__ void normals_kernel(const float *__restrict__ dep, float4 *__restrict
                 out.w = (float)(sg * v[2]);
             }
         }
-        att4[i] = out;
+        att_put4(att4, bf, i, out);
     }
 }
 
-void launch_normals(const float *dep, float4 *att4, int H, int W, const double2 *lcol, const double2 *lrow,
+void launch_normals(const float *dep, void *att4, int bf, int H, int W, const double2 *lcol, const double2 *lrow,
                     int spherical, double scale, double min_px, double max_px, double tau, int min_count,
                     hipStream_t st)
 {
     const int npx = H * W;
     const int blocks = (npx + 255) / 256 < 4096 ? (npx + 255) / 256 : 4096;
-    hipLaunchKernelGGL(normals_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, dep, att4, H, W, lcol, lrow,
+    hipLaunchKernelGGL(normals_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, dep, att4, bf, H, W, lcol, lrow,
                        spherical, scale, min_px, max_px, tau, min_count, (int)floor(max_px));
 }
 

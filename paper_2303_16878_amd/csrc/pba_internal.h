@@ -24,6 +24,37 @@ constexpr float kNoDepth = -1e30f;
 constexpr int kXcd = 8;          // work queues per launch: one per accelerator complex die (XCD)
 enum { MODEL_PINHOLE = 0, MODEL_SPHERICAL = 1 };
 
+// BF16 storage of the intensity / normal planes: round to nearest even (finite values), and back.
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Attribute texel k of a plane: 5 cues {I, nx, ny, nz} as float4 or, with BF16 storage, ushort4;
+// 2 cues: I as float or uint16.
+__device__ __forceinline__ float4 att_get4(const void *p, int bf, int64_t k)
+{
+    if (!bf) return static_cast<const float4 *>(p)[k];
+    const ushort4 h = static_cast<const ushort4 *>(p)[k];
+    return make_float4(bf16_to_f32(h.x), bf16_to_f32(h.y), bf16_to_f32(h.z), bf16_to_f32(h.w));
+}
+__device__ __forceinline__ void att_put4(void *p, int bf, int64_t k, float4 v)
+{
+    if (!bf) { static_cast<float4 *>(p)[k] = v; return; }
+    static_cast<ushort4 *>(p)[k] = make_ushort4(f32_to_bf16(v.x), f32_to_bf16(v.y), f32_to_bf16(v.z), f32_to_bf16(v.w));
+}
+__device__ __forceinline__ float att_get1(const void *p, int bf, int64_t k)
+{
+    return bf ? bf16_to_f32(static_cast<const uint16_t *>(p)[k]) : static_cast<const float *>(p)[k];
+}
+__device__ __forceinline__ void att_put1(void *p, int bf, int64_t k, float v)
+{
+    if (bf) static_cast<uint16_t *>(p)[k] = f32_to_bf16(v);
+    else static_cast<float *>(p)[k] = v;
+}
+
 struct SensorDev {
     int32_t model, H, W, npx;
     uint32_t magic_w;            // ceil(2^32 / W): row = umulhi(pix, magic_w) for pix < 2^32 / W
@@ -56,6 +87,8 @@ struct EvalArgs {
     const float *dep;            // depth plane (pixels without a valid depth hold kNoDepth)
     const float4 *att4;          // 5 channels: {intensity, nx, ny, nz}
     const float *att1;           // 2 channels: intensity
+    const ushort4 *att4h;        // the same planes with BF16 storage
+    const uint16_t *att1h;
     const float2 *lut32;         // ray tables, FP32
     const double2 *lut64;        // ray tables, FP64
     const int32_t *item_pair;
@@ -74,7 +107,7 @@ struct EvalArgs {
     uint32_t *zbuf;
     const int64_t *zoff;
     int32_t zpass;
-    int32_t pad_z;
+    int32_t bf16;                // intensity / normal planes in BF16 (att4h, att1h)
     // per-pixel inspection outputs (debug launches only)
     uint8_t *dbg_status;
     float2 *dbg_uv;
@@ -124,11 +157,13 @@ struct CholPlan {
 // 64 x 64: all W, then all W^T).
 void launch_cholesky(double *A, double *L, double *LT, int n, double *Winv, const CholPlan &plan, int32_t *fail,
                      hipStream_t st);
-void launch_downsample(const float *dep, const float4 *att4, const float *att1, int H, int W, float *dep2,
-                       float4 *att4_2, float *att1_2, int H2, int W2, double tau, hipStream_t st);
-void launch_unpack(const float *dep, const float4 *att4, const float *att1, int npx, float *I, float *D, float *N,
+// att / att2: the attribute plane of one keyframe (att_get4 / att_get1 layout, `five` cues or one,
+// `bf` BF16 storage)
+void launch_downsample(const float *dep, const void *att, int five, int bf, int H, int W, float *dep2, void *att2,
+                       int H2, int W2, double tau, hipStream_t st);
+void launch_unpack(const float *dep, const void *att, int five, int bf, int npx, float *I, float *D, float *N,
                    hipStream_t st);
-void launch_normals(const float *dep, float4 *att4, int H, int W, const double2 *lcol, const double2 *lrow,
+void launch_normals(const float *dep, void *att4, int bf, int H, int W, const double2 *lcol, const double2 *lrow,
                     int spherical, double scale, double min_px, double max_px, double tau, int min_count,
                     hipStream_t st);
 // Solves L L^T x = x in place with the factor as launch_cholesky leaves it.

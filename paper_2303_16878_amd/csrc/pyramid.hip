@@ -7,15 +7,15 @@
 // for.  Intensity: the mean of the four.  Normals: the mean of the four scaled to unit length.
 // A texel without depth gets intensity and normal 0 (never read: source pixels need depth, and
 // so does every target tap).  Means and the normalisation run in FP64 with a fixed order of
-// operations and are rounded once to FP32.
+// operations and are rounded once to FP32 (or, with BF16 storage, once to BF16).
 
 #include "pba_internal.h"
 
 namespace pba {
 
-__global__ void downsample_kernel(const float *__restrict__ dep, const float4 *__restrict__ att4,
-                                  const float *__restrict__ att1, int H, int W, float *__restrict__ dep2,
-                                  float4 *__restrict__ att4_2, float *__restrict__ att1_2, int H2, int W2, double tau)
+__global__ void downsample_kernel(const float *__restrict__ dep, const void *__restrict__ att, int five, int bf,
+                                  int H, int W, float *__restrict__ dep2, void *__restrict__ att2, int H2, int W2,
+                                  double tau)
 {
     const int n2 = H2 * W2;
     for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < n2; o += gridDim.x * blockDim.x) {
@@ -36,10 +36,10 @@ __global__ void downsample_kernel(const float *__restrict__ dep, const float4 *_
             return __dmul_rn(__dadd_rn(__dadd_rn(__dadd_rn(a, b), c), e), 0.25);
         };
         dep2[o] = ok ? (float)mean4(d[0], d[1], d[2], d[3]) : kNoDepth;
-        if (att4) {
+        if (five) {
             float4 t[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) t[k] = att4[q[k]];
+            for (int k = 0; k < 4; ++k) t[k] = att_get4(att, bf, q[k]);
             float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
             if (ok) {
                 r.x = (float)mean4(t[0].x, t[1].x, t[2].x, t[3].x);
@@ -53,46 +53,49 @@ __global__ void downsample_kernel(const float *__restrict__ dep, const float4 *_
                     r.w = (float)__ddiv_rn(mz, nn);
                 }
             }
-            att4_2[o] = r;
+            att_put4(att2, bf, o, r);
         } else {
-            att1_2[o] = ok ? (float)mean4(att1[q[0]], att1[q[1]], att1[q[2]], att1[q[3]]) : 0.f;
+            att_put1(att2, bf, o,
+                     ok ? (float)mean4(att_get1(att, bf, q[0]), att_get1(att, bf, q[1]), att_get1(att, bf, q[2]),
+                                       att_get1(att, bf, q[3]))
+                        : 0.f);
         }
     }
 }
 
-void launch_downsample(const float *dep, const float4 *att4, const float *att1, int H, int W, float *dep2,
-                       float4 *att4_2, float *att1_2, int H2, int W2, double tau, hipStream_t st)
+void launch_downsample(const float *dep, const void *att, int five, int bf, int H, int W, float *dep2, void *att2,
+                       int H2, int W2, double tau, hipStream_t st)
 {
     const int n2 = H2 * W2;
     const int blocks = (n2 + 255) / 256 < 4096 ? (n2 + 255) / 256 : 4096;
-    hipLaunchKernelGGL(downsample_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, dep, att4, att1, H, W, dep2,
-                       att4_2, att1_2, H2, W2, tau);
+    hipLaunchKernelGGL(downsample_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, dep, att, five, bf, H, W,
+                       dep2, att2, H2, W2, tau);
 }
 
 // Packed planes of one keyframe back to the caller's layout: intensity [H][W], depth [H][W]
 // (0 where there is no measurement), normals [H][W][3] (may be null).
-__global__ void unpack_kernel(const float *__restrict__ dep, const float4 *__restrict__ att4,
-                              const float *__restrict__ att1, int npx, float *__restrict__ I, float *__restrict__ D,
-                              float *__restrict__ N)
+__global__ void unpack_kernel(const float *__restrict__ dep, const void *__restrict__ att, int five, int bf, int npx,
+                              float *__restrict__ I, float *__restrict__ D, float *__restrict__ N)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += gridDim.x * blockDim.x) {
         const float d = dep[i];
         D[i] = d > 0.f ? d : 0.f;
-        if (att4) {
-            const float4 t = att4[i];
+        if (five) {
+            const float4 t = att_get4(att, bf, i);
             I[i] = t.x;
             if (N) { N[3 * i] = t.y; N[3 * i + 1] = t.z; N[3 * i + 2] = t.w; }
         } else {
-            I[i] = att1[i];
+            I[i] = att_get1(att, bf, i);
         }
     }
 }
 
-void launch_unpack(const float *dep, const float4 *att4, const float *att1, int npx, float *I, float *D, float *N,
+void launch_unpack(const float *dep, const void *att, int five, int bf, int npx, float *I, float *D, float *N,
                    hipStream_t st)
 {
     const int blocks = (npx + 255) / 256 < 4096 ? (npx + 255) / 256 : 4096;
-    hipLaunchKernelGGL(unpack_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, dep, att4, att1, npx, I, D, N);
+    hipLaunchKernelGGL(unpack_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, dep, att, five, bf, npx, I, D,
+                       N);
 }
 
 }  // namespace pba

@@ -188,22 +188,26 @@ int pose_var(const pba_ctx *c, int kf) { return c->pose_of.empty() ? kf : c->pos
 // texel preparation: sanitise depth (invalid -> 0; the depth test is made in FP64, as the
 // sensor's limits are given) and split into the depth plane and the attribute plane
 __global__ void pack_kernel(const float *__restrict__ I, const float *__restrict__ D, const float *__restrict__ Nn,
-                            float *__restrict__ dep, float4 *__restrict__ att4, float *__restrict__ att1, int npx,
-                            double dmin, double dmax)
+                            float *__restrict__ dep, void *__restrict__ att, int five, int bf, int npx, double dmin,
+                            double dmax)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += gridDim.x * blockDim.x) {
         const float d = D[i];
         const bool ok = isfinite(d) && d > 0.f && (double)d >= dmin && (double)d <= dmax;
         const float in = I[i];
         dep[i] = ok ? d : kNoDepth;
-        if (att4) {
+        if (five) {
             const float n0 = Nn[3 * (int64_t)i], n1 = Nn[3 * (int64_t)i + 1], n2 = Nn[3 * (int64_t)i + 2];
-            att4[i] = ok ? make_float4(in, n0, n1, n2) : make_float4(0.f, 0.f, 0.f, 0.f);
+            att_put4(att, bf, i, ok ? make_float4(in, n0, n1, n2) : make_float4(0.f, 0.f, 0.f, 0.f));
         } else {
-            att1[i] = ok ? in : 0.f;
+            att_put1(att, bf, i, ok ? in : 0.f);
         }
     }
 }
+
+// The attribute plane of a level (5 cues: att4, 2 cues: att1; element size per the storage).
+void *att_plane(pba_ctx *c, ImageSet &is);
+size_t att_bytes(const pba_ctx *c);
 
 void release_images(ImageSet &is)
 {
@@ -270,8 +274,8 @@ pba_status image_layout(pba_ctx *c, ImageSet &is, const std::vector<int32_t> &se
     pba_status s;
     if ((s = upload(c, is.kfs_d, is.kfs_h.data(), is.kfs_h.size() * sizeof(KfDev)))) return s;
     if ((s = ensure(c, is.dep, off * sizeof(float)))) return s;
-    if (c->cfg.channels == 5) return ensure(c, is.att4, off * sizeof(float4));
-    return ensure(c, is.att1, off * sizeof(float));
+    if (c->cfg.channels == 5) return ensure(c, is.att4, off * att_bytes(c));
+    return ensure(c, is.att1, off * att_bytes(c));
 }
 
 // Tiles (64 x 64) of the Cholesky factor of the 6 NP x 6 NP system that can be nonzero: those
@@ -464,6 +468,9 @@ EvalArgs make_args(pba_ctx *c)
     a.dep = P_<float>(c->L().dep);
     a.att4 = P_<float4>(c->L().att4);
     a.att1 = P_<float>(c->L().att1);
+    a.att4h = P_<ushort4>(c->L().att4);
+    a.att1h = P_<uint16_t>(c->L().att1);
+    a.bf16 = c->cfg.storage_bf16;
     a.lut32 = P_<float2>(c->L().lut32);
     a.lut64 = P_<double2>(c->L().lut64);
     a.lut64_bytes = (int32_t)c->L().lut64.bytes;
@@ -596,6 +603,14 @@ pba_status accumulate_eval_time(pba_ctx *c)
     return PBA_OK;
 }
 
+void *att_plane(pba_ctx *c, ImageSet &is) { return c->cfg.channels == 5 ? is.att4.p : is.att1.p; }
+
+size_t att_bytes(const pba_ctx *c)
+{
+    if (c->cfg.channels == 5) return c->cfg.storage_bf16 ? sizeof(ushort4) : sizeof(float4);
+    return c->cfg.storage_bf16 ? sizeof(uint16_t) : sizeof(float);
+}
+
 pba_status check_ready(pba_ctx *c)
 {
     if (c->N == 0) return fail(c, PBA_ESTATE, "no keyframes loaded");
@@ -675,7 +690,10 @@ pba_status pba_create(const pba_config *cfg, pba_ctx **out)
         if (!std::isfinite(x)) return PBA_EINVAL;
     if (cfg->omega_intensity < 0 || cfg->omega_depth < 0 || cfg->omega_normal < 0) return PBA_EINVAL;
     if (!(cfg->occlusion_tau_pinhole > 0) || !(cfg->occlusion_tau_spherical > 0)) return PBA_EINVAL;
-    if ((cfg->occlusion_zbuffer != 0 && cfg->occlusion_zbuffer != 1) || cfg->reserved != 0) return PBA_EINVAL;
+    if (cfg->occlusion_zbuffer != 0 && cfg->occlusion_zbuffer != 1) return PBA_EINVAL;
+    // BF16 storage: FP32 evaluation path only, without the z-buffer variant
+    if (cfg->storage_bf16 != 0 && cfg->storage_bf16 != 1) return PBA_EINVAL;
+    if (cfg->storage_bf16 && (cfg->precision != PBA_F32 || cfg->occlusion_zbuffer)) return PBA_EINVAL;
     if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return PBA_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return PBA_EDEVICE;
@@ -802,8 +820,9 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
         const int blocks = std::min((npx + 255) / 256, 4096);
         const bool five = c->cfg.channels == 5;
         hipLaunchKernelGGL(pack_kernel, dim3(blocks), dim3(256), 0, c->stream, dI, dD, five ? dN : nullptr,
-                           P_<float>(c->L().dep) + kfs[k].off, five ? P_<float4>(c->L().att4) + kfs[k].off : nullptr,
-                           five ? nullptr : P_<float>(c->L().att1) + kfs[k].off, npx, S.min_depth, S.max_depth);
+                           P_<float>(c->L().dep) + kfs[k].off,
+                           static_cast<char *>(att_plane(c, c->L())) + kfs[k].off * att_bytes(c), five ? 1 : 0,
+                           c->cfg.storage_bf16, npx, S.min_depth, S.max_depth);
         if (!on_device) HIP_OK(hipStreamSynchronize(c->stream));   // stage is reused
     }
     HIP_OK(hipGetLastError());
@@ -1179,6 +1198,8 @@ pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float
     pba_status s;
     if ((s = check_ready(c))) return s;
     if (!c->loss_ready) return fail(c, PBA_ESTATE, "pba_loss_backward needs a preceding pba_loss_forward");
+    if (c->cfg.storage_bf16)
+        return fail(c, PBA_EINVAL, "the loss adjoint reads FP32 images: not available with BF16 storage");
     HIP_OK(hipSetDevice(c->cfg.device));
     const int N = c->NP;   // pose variables
     const int64_t tx = c->L().texels;
@@ -1262,7 +1283,8 @@ pba_status pba_estimate_normals(pba_ctx *c, double radius_m, double min_px, doub
         const pba_sensor &S = is.sensors[f.sensor];
         const SensorDev &sd = is.sensors_dev_h[f.sensor];
         const double tau = S.model == PBA_PINHOLE ? c->cfg.occlusion_tau_pinhole : c->cfg.occlusion_tau_spherical;
-        launch_normals(P_<float>(is.dep) + f.off, P_<float4>(is.att4) + f.off, f.H, f.W,
+        launch_normals(P_<float>(is.dep) + f.off, static_cast<char *>(is.att4.p) + f.off * att_bytes(c),
+                       c->cfg.storage_bf16, f.H, f.W,
                        P_<double2>(is.lut64) + sd.lut_col, P_<double2>(is.lut64) + sd.lut_row,
                        S.model == PBA_SPHERICAL, radius_m * std::fabs(S.fx), min_px, max_px, tau, min_count,
                        c->stream);
@@ -1412,10 +1434,10 @@ pba_status pba_build_pyramid(pba_ctx *c, int32_t n_levels)
             const KfDev &a = lo.kfs_h[k], &b = up.kfs_h[k];
             const double tau = lo.sensors[a.sensor].model == PBA_PINHOLE ? c->cfg.occlusion_tau_pinhole
                                                                           : c->cfg.occlusion_tau_spherical;
-            launch_downsample(P_<float>(lo.dep) + a.off, five ? P_<float4>(lo.att4) + a.off : nullptr,
-                              five ? nullptr : P_<float>(lo.att1) + a.off, a.H, a.W, P_<float>(up.dep) + b.off,
-                              five ? P_<float4>(up.att4) + b.off : nullptr, five ? nullptr : P_<float>(up.att1) + b.off,
-                              b.H, b.W, tau, c->stream);
+            launch_downsample(P_<float>(lo.dep) + a.off,
+                              static_cast<char *>(att_plane(c, lo)) + a.off * att_bytes(c), five ? 1 : 0,
+                              c->cfg.storage_bf16, a.H, a.W, P_<float>(up.dep) + b.off,
+                              static_cast<char *>(att_plane(c, up)) + b.off * att_bytes(c), b.H, b.W, tau, c->stream);
         }
         HIP_OK(hipGetLastError());
     }
@@ -1497,8 +1519,8 @@ pba_status pba_get_level_image(pba_ctx *c, int32_t level, int32_t kf, float *int
     if ((s = ensure(c, tmp, npx * 5 * 4))) return s;
     float *I = P_<float>(tmp), *D = I + npx, *N = D + npx;
     const bool five = c->cfg.channels == 5;
-    launch_unpack(P_<float>(is.dep) + f.off, five ? P_<float4>(is.att4) + f.off : nullptr,
-                  five ? nullptr : P_<float>(is.att1) + f.off, (int)npx, I, D, five ? N : nullptr, c->stream);
+    launch_unpack(P_<float>(is.dep) + f.off, static_cast<char *>(att_plane(c, is)) + f.off * att_bytes(c), five ? 1 : 0,
+                  c->cfg.storage_bf16, (int)npx, I, D, five ? N : nullptr, c->stream);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && intensity) e = hipMemcpyAsync(intensity, I, npx * 4, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess && depth) e = hipMemcpyAsync(depth, D, npx * 4, hipMemcpyDeviceToHost, c->stream);

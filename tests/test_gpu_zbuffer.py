@@ -106,5 +106,5 @@ def test_zbuffer_config_errors(pba):
     h = ctypes.c_void_p()
     assert pba.load_library().pba_create(ctypes.byref(cfg), ctypes.byref(h)) == pba.PBA_EINVAL
     cfg.occlusion_zbuffer = 1
-    cfg.reserved = 1
+    cfg.storage_bf16 = 1          # the z-buffer variant has no BF16 instantiation
     assert pba.load_library().pba_create(ctypes.byref(cfg), ctypes.byref(h)) == pba.PBA_EINVAL
