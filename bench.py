@@ -47,7 +47,7 @@ def flops_split(channels, target_model):
     return first, total - first
 
 
-PROFILE_KERNEL = "void pba::eval_kernel<float, 5, 1, 1, 0, false, false, false>(pba::EvalArgs, int, int)"
+PROFILE_KERNEL = "void pba::eval_kernel<float, 5, 1, 1, 0, false, false, false, false>(pba::EvalArgs, int, int)"
 
 
 def measured_counters(root):

@@ -538,13 +538,18 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         const int s_lcol = uni(ss.lut_col), s_lrow = uni(ss.lut_row);
         const int t_lcol = uni(st.lut_col), t_lrow = uni(st.lut_row);
         const L2 *lcol = lut + s_lcol, *lrow = lut + s_lrow;
-        const float4 *satt4 = a.att4 + ks.off;
-        const float *satt1 = a.att1 + ks.off;
         // z-buffer occlusion variant: this pair's source z-buffer (FP32 depth bits per target cell)
         uint32_t *const zb = ZB ? a.zbuf + a.zoff[pair] : nullptr;
         const uint32_t tnpx = (uint32_t)Ht * (uint32_t)Wt;
         const __amdgpu_buffer_rsrc_t r_tdep = plane_rsrc(uni_ptr(a.dep + kt.off), tnpx * 4u);
         const __amdgpu_buffer_rsrc_t r_sdep = plane_rsrc(uni_ptr(a.dep + ks.off), (uint32_t)npx * 4u);
+        // the source keyframe's attribute plane (its own texels of the queued pixels)
+        const uint32_t att_e = NCH == 5 ? (BF ? 8u : 16u) : (BF ? 2u : 4u);
+        const __amdgpu_buffer_rsrc_t r_satt =
+            NCH == 5 ? (BF ? plane_rsrc(uni_ptr(a.att4h + ks.off), (uint32_t)npx * att_e)
+                           : plane_rsrc(uni_ptr(a.att4 + ks.off), (uint32_t)npx * att_e))
+                     : (BF ? plane_rsrc(uni_ptr(a.att1h + ks.off), (uint32_t)npx * att_e)
+                           : plane_rsrc(uni_ptr(a.att1 + ks.off), (uint32_t)npx * att_e));
         const __amdgpu_buffer_rsrc_t r_lut = plane_rsrc(uni_ptr(a.lut64), (uint32_t)a.lut64_bytes);
         const __amdgpu_buffer_rsrc_t r_tatt =
             NCH == 5 ? (BF ? plane_rsrc(uni_ptr(a.att4h + kt.off), tnpx * 8u) : plane_rsrc(uni_ptr(a.att4 + kt.off), tnpx * 16u))
@@ -582,12 +587,11 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 float4 s4;
                 float4 q4[12];
                 if (BF) {
-                    const ushort4 h = a.att4h[ks.off + pix];
-                    s4 = make_float4(bf16_to_f32(h.x), bf16_to_f32(h.y), bf16_to_f32(h.z), bf16_to_f32(h.w));
+                    s4 = ld_bf16x4(r_satt, pix * 8, 0);
                     load_stencil<float4, 8>(q4, [&](int vo, int so) { return ld_bf16x4(r_tatt, vo, so); }, corner * 8,
                                             Wt * 8);
                 } else {
-                    s4 = satt4[pix];
+                    s4 = ld_f32x4(r_satt, pix * 16, 0);
                     load_stencil<float4, 16>(q4, [&](int vo, int so) { return ld_f32x4(r_tatt, vo, so); }, corner * 16,
                                              Wt * 16);
                 }
@@ -606,11 +610,11 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             } else {
                 float tI[12];
                 if (BF) {
-                    Is = bf16_to_f32(a.att1h[ks.off + pix]);
+                    Is = ld_bf16(r_satt, pix * 2, 0);
                     load_stencil<float, 2>(tI, [&](int vo, int so) { return ld_bf16(r_tatt, vo, so); }, corner * 2,
                                            Wt * 2);
                 } else {
-                    Is = satt1[pix];
+                    Is = ld_f32(r_satt, pix * 4, 0);
                     load_stencil<float, 4>(tI, [&](int vo, int so) { return ld_f32(r_tatt, vo, so); }, corner * 4,
                                            Wt * 4);
                 }
