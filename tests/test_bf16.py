@@ -13,9 +13,6 @@ import oracle
 import synth
 from parity import compare_pair_masks, compare_pair_sums, forced_oracle
 
-pytestmark = pytest.mark.gpu
-
-
 @pytest.fixture(scope="module")
 def pba():
     import torch
@@ -59,6 +56,7 @@ def test_bf16_rounding_pin():
     assert np.array_equal(bf16_round(r), r)
 
 
+@pytest.mark.gpu
 @pytest.mark.parametrize("fixture", ["lidar_mini", "joint_mini", "rgbd_small"])
 def test_bf16_pairs_match_oracle_on_rounded_images(fixture, request, pba):
     prob = request.getfixturevalue(fixture)
@@ -83,6 +81,7 @@ def test_bf16_pairs_match_oracle_on_rounded_images(fixture, request, pba):
         assert np.array_equal(N, ref.normals[1])
 
 
+@pytest.mark.gpu
 def test_bf16_lm_and_pyramid(lidar_mini, pba):
     """LM on BF16 storage reaches the poses LM reaches on the BF16-rounded images held in FP32 (the
     same values, the same FP32 arithmetic); the pyramid built from BF16 storage holds BF16 values
@@ -108,6 +107,7 @@ def test_bf16_lm_and_pyramid(lidar_mini, pba):
     assert len(log) > 0
 
 
+@pytest.mark.gpu
 def test_bf16_config_errors(pba):
     import ctypes
     lib = pba.load_library()
