@@ -119,3 +119,23 @@ def test_bf16_config_errors(pba):
     cfg.precision = pba.PBA_F32
     cfg.storage_bf16 = 2
     assert lib.pba_create(ctypes.byref(cfg), ctypes.byref(h)) == pba.PBA_EINVAL
+
+
+@pytest.mark.gpu
+def test_bf16_full_size_joint_sampled_pairs(pba):
+    """The full joint configuration (200 spherical 128x1024 + 400 pinhole 640x480 keyframes, 7200
+    pairs) on BF16 storage, in the launch bench.py times: sampled pairs of all four source/target
+    sensor combinations against the oracle given the BF16-rounded images."""
+    prob = synth.make("joint")
+    ref = _rounded(prob)
+    sample = [0, 1200, 4, 1204, 2400, 4800, 2404, 7199]   # LiDAR->LiDAR, LiDAR->cam, cam->LiDAR, cam->cam
+    with pba.context_for_problem(prob, storage_bf16=True) as ctx:
+        ctx.autotune()
+        ev = ctx.evaluate(want_pairs=True)
+        for k in sample:
+            m = compare_pair_masks(ctx, ref, ref.init_poses, k)
+            assert m["n_bad"] == 0, (k, m["n_mismatch"], m["bad_idx"])
+            fo = forced_oracle(ref, ref.init_poses, k, m["gpu"])
+            c = compare_pair_sums(ev["pairs"][k], fo, 1e-5)
+            _log("joint pair", k, "valid", m["n_valid"], "band", m["n_band"], "H err %.2e b err %.2e" % (c["H"], c["b"]))
+            assert c["ok"], (k, c)
