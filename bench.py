@@ -70,10 +70,10 @@ def measured_counters(root):
         return {}
 
 
-def run_path(pba, prob, precision, warmup, steps, autotune=True, use_lm=True):
+def run_path(pba, prob, precision, warmup, steps, autotune=True, use_lm=True, solve_order=0):
     import numpy as np
     import torch
-    with pba.context_for_problem(prob, precision=precision) as ctx:
+    with pba.context_for_problem(prob, precision=precision, solve_order=solve_order) as ctx:
         torch.cuda.synchronize()
         tune = ctx.autotune() if autotune else []
         # the system at the initial poses, for FP32 vs FP64; per-pair counts for the FLOP figure
@@ -100,7 +100,8 @@ def run_path(pba, prob, precision, warmup, steps, autotune=True, use_lm=True):
     return dict(elapsed=elapsed, logs=logs, n_evaluated=ev["n_evaluated"], n_valid=ev["n_valid"], init=ev_init, tune=tune,
                 pair_eval=ev["pairs"][:, 157].copy(), pair_valid=ev["pairs"][:, 158].copy(),
                 eval_ms=tm_it["iter_eval_ms"] / steps, eval_ms_events=tm["eval_ms"] / n_eval_runs,
-                n_items=tm["n_items"], items_px=tm["items_px"], grid=tm["grid"], poses=poses, F=logs[-1]["F"])
+                n_items=tm["n_items"], items_px=tm["items_px"], grid=tm["grid"], poses=poses, F=logs[-1]["F"],
+                solve_n=tm["solve_n"], solve_steps=tm["solve_steps"], solve_nd=tm["solve_nd"])
 
 
 def bf16_round(x):
@@ -192,6 +193,9 @@ def main():
                     help="the z-buffer occlusion variant (an extra projection-only pass per evaluation)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to calibrate byte counters")
+    ap.add_argument("--solve-order", default="auto", choices=["auto", "natural", "nd"],
+                    help="elimination order of the step's Cholesky solve (auto: nested dissection when it at "
+                         "least halves the factorisation's dependent steps)")
     ap.add_argument("--profile-evals", type=int, default=0, metavar="K",
                     help="only load the workload and run K evaluations at the initial poses on the FP32 path "
                          "(default item size and grid): a short command for counter profiles")
@@ -236,7 +240,9 @@ def main():
     sen = prob.sensors[0]
 
     log("FP32 path: warmup %d, timed %d iterations" % (args.warmup, args.steps))
-    r32 = run_path(pba, prob, pba.PBA_F32, args.warmup, args.steps, not args.no_autotune, use_lm=not args.gn)
+    order = {"auto": pba.PBA_ORDER_AUTO, "natural": pba.PBA_ORDER_NATURAL, "nd": pba.PBA_ORDER_ND}[args.solve_order]
+    r32 = run_path(pba, prob, pba.PBA_F32, args.warmup, args.steps, not args.no_autotune, use_lm=not args.gn,
+                   solve_order=order)
     ms_step = 1e3 * r32["elapsed"] / args.steps
     value = r32["n_evaluated"] * args.steps / r32["elapsed"]
     eval_s = r32["eval_ms"] / 1e3
@@ -280,6 +286,8 @@ def main():
             "image_storage": "BF16 intensity / normals, FP32 depth" if bf16 else "FP32",
             "sensors": ["%s %dx%d" % ("spherical" if x["model"] == 1 else "pinhole", x["H"], x["W"])
                         for x in prob.sensors],
+            "solve": "%s order: FP64 Cholesky of order %d in %d dependent steps" % (
+                "nested-dissection" if r32["solve_nd"] else "natural", r32["solve_n"], r32["solve_steps"]),
         },
         "roofline": {
             # the evaluation kernel is bound by vector-ALU issue (measured VALU busy below); the HBM
@@ -307,6 +315,9 @@ def main():
             "kernel_ms_hip_events": r32["eval_ms_events"],
         },
         "s_per_iter": {"f32": r32["elapsed"] / args.steps},
+        # the rest of an iteration besides the evaluation launches: damped copy, factorisation,
+        # triangular solves, pose update, per-pair reduction, assembly, accept/reject, launch gaps
+        "ms_per_iter_outside_eval": {"f32": ms_step - r32["eval_ms"]},
         "eval_px_pairs_per_s": {"f32": r32["n_evaluated"] / eval_s},
         "final_ate_rmse": {"f32": ate_rmse(r32["poses"], prob.gt_poses),
                            "init": ate_rmse(prob.init_poses, prob.gt_poses)},
@@ -328,7 +339,8 @@ def main():
             prob64.params = dict(prob.params, storage_bf16=0)
             prob64.intensity = [bf16_round(x) for x in prob.intensity]
             prob64.normals = [bf16_round(x) for x in prob.normals]
-        r64 = run_path(pba, prob64, pba.PBA_F64, args.warmup, args.steps, not args.no_autotune, use_lm=not args.gn)
+        r64 = run_path(pba, prob64, pba.PBA_F64, args.warmup, args.steps, not args.no_autotune, use_lm=not args.gn,
+                       solve_order=order)
         out["s_per_iter"]["f64"] = r64["elapsed"] / args.steps
         out["eval_px_pairs_per_s"]["f64"] = r64["n_evaluated"] / (r64["eval_ms"] / 1e3)
         out["fp64_value"] = r64["n_evaluated"] * args.steps / r64["elapsed"]

@@ -65,6 +65,8 @@ enum {
 
 enum { PBA_PINHOLE = 0, PBA_SPHERICAL = 1 };
 enum { PBA_F32 = 0, PBA_F64 = 1 };
+/* Elimination order of the pose system's Cholesky factorisation (pba_config.solve_order). */
+enum { PBA_ORDER_AUTO = 0, PBA_ORDER_NATURAL = 1, PBA_ORDER_ND = 2 };
 
 /* Length of one per-pair record written by pba_evaluate (pair_out):
  * [0,144)  H12, 12x12 row-major over [dx_s (6); dx_t (6)]
@@ -111,6 +113,15 @@ typedef struct {
                                     writes them); residuals, Jacobians and sums stay FP32/FP64.  FP32 path
                                     only, without occlusion_zbuffer, and pba_loss_backward is then
                                     PBA_EINVAL; 0: FP32 images */
+    int32_t solve_order;         /* elimination order of the damped system's Cholesky factorisation (the
+                                    solve of Sec. IV's Gauss-Newton / Levenberg-Marquardt step; the step
+                                    is the same up to rounding in every order):
+                                    PBA_ORDER_NATURAL: pose order, one dependent step per 64-row block
+                                    column; PBA_ORDER_ND: nested dissection of the pose graph, each
+                                    dissection block padded to 64 rows, one step per elimination-tree
+                                    level; PBA_ORDER_AUTO (default): nested dissection when it at least
+                                    halves the number of dependent steps and at most doubles the
+                                    system's order (the factor takes 24 n^2 bytes at order n) */
     /* Device memory of the context (images, plans, systems, work buffers) comes from these
      * callbacks when both are set (e.g. a framework's caching allocator), else from hipMalloc.
      * dev_alloc(bytes, alloc_user) returns device memory of cfg->device usable on cfg->stream, or
@@ -122,12 +133,14 @@ typedef struct {
 } pba_config;
 
 /* Fill *cfg with defaults: F32, 5 channels, grad_mode 0, anchor 0, graphs on, Omega 1,
- * Huber 0.1, tau 0.5 m (pinhole) / 1.0 m (spherical), no z-buffer. */
+ * Huber 0.1, tau 0.5 m (pinhole) / 1.0 m (spherical), no z-buffer, FP32 images, automatic
+ * solve order. */
 void pba_config_default(pba_config *cfg);
 
 /* Create a context on cfg->device.  *out receives the handle.  PBA_EINVAL for an unknown
  * precision, channel count or grad_mode, a negative anchor, negative or non-finite Omega,
- * non-finite Huber threshold, or tau <= 0; PBA_EDEVICE for a device that does not exist. */
+ * non-finite Huber threshold, tau <= 0 or an unknown solve_order; PBA_EDEVICE for a device
+ * that does not exist. */
 pba_status pba_create(const pba_config *cfg, pba_ctx **out);
 pba_status pba_destroy(pba_ctx *ctx);
 
@@ -327,6 +340,12 @@ typedef struct {
                                     wall-clock stamps before and after the evaluation launches of
                                     each iteration, also under graph replay) */
     int64_t iter_evals;
+    int32_t solve_n;             /* order of the factored system (6 x pose variables, more with the
+                                    padding of a nested-dissection order); 0 before the first plan */
+    int32_t solve_steps;         /* dependent steps of the factorisation: block columns (natural order)
+                                    or elimination-tree levels (nested dissection) */
+    int32_t solve_nd;            /* 1 if the nested-dissection order is in use */
+    int32_t reserved;
 } pba_timings;
 
 /* Kernel timing counters; reset = 1 clears them after reading. */

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpba.so")
 PBA_OK, PBA_EINVAL, PBA_ENOMEM, PBA_EDEVICE, PBA_ESTATE, PBA_ENOTPD, PBA_ENOVALID = 0, -1, -2, -3, -4, -5, -6
 PBA_PINHOLE, PBA_SPHERICAL = 0, 1
 PBA_F32, PBA_F64 = 0, 1
+PBA_ORDER_AUTO, PBA_ORDER_NATURAL, PBA_ORDER_ND = 0, 1, 2
 PBA_PAIR_OUT_LEN = 160
 PBA_NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -49,7 +50,8 @@ class pba_config(ctypes.Structure):
                 ("omega_depth", ctypes.c_double), ("omega_normal", ctypes.c_double),
                 ("huber_delta", ctypes.c_double), ("occlusion_tau_pinhole", ctypes.c_double),
                 ("occlusion_tau_spherical", ctypes.c_double), ("occlusion_zbuffer", ctypes.c_int32),
-                ("storage_bf16", ctypes.c_int32), ("dev_alloc", ctypes.c_void_p), ("dev_free", ctypes.c_void_p),
+                ("storage_bf16", ctypes.c_int32), ("solve_order", ctypes.c_int32), ("dev_alloc", ctypes.c_void_p),
+                ("dev_free", ctypes.c_void_p),
                 ("alloc_user", ctypes.c_void_p)]
 
 
@@ -71,7 +73,9 @@ class pba_tune_point(ctypes.Structure):
 class pba_timings(ctypes.Structure):
     _fields_ = [("eval_ms", ctypes.c_double), ("eval_launches", ctypes.c_int64), ("iterate_ms", ctypes.c_double),
                 ("iterations", ctypes.c_int64), ("n_items", ctypes.c_int64), ("items_px", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("iter_eval_ms", ctypes.c_double), ("iter_evals", ctypes.c_int64)]
+                ("grid", ctypes.c_int32), ("iter_eval_ms", ctypes.c_double), ("iter_evals", ctypes.c_int64),
+                ("solve_n", ctypes.c_int32), ("solve_steps", ctypes.c_int32), ("solve_nd", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -215,9 +219,10 @@ class Context:
     def __init__(self, device=0, precision=PBA_F32, channels=5, grad_mode=0, anchor=0, stream=None,
                  omega_intensity=1.0, omega_depth=1.0, omega_normal=1.0, huber_delta=0.1,
                  occlusion_tau_pinhole=0.5, occlusion_tau_spherical=1.0, use_graph=True, occlusion_zbuffer=False,
-                 storage_bf16=False, allocator="torch"):
+                 storage_bf16=False, solve_order=PBA_ORDER_AUTO, allocator="torch"):
         """allocator: "torch" -- device memory from torch's caching allocator (when torch sees a GPU
-        and no raw stream handle is given), "hip" -- the library's own hipMalloc."""
+        and no raw stream handle is given), "hip" -- the library's own hipMalloc.  solve_order:
+        PBA_ORDER_AUTO, PBA_ORDER_NATURAL or PBA_ORDER_ND (elimination order of the step's solve)."""
         self.lib = load_library()
         self.h = None
         self.allocator = None
@@ -244,6 +249,7 @@ class Context:
         cfg.occlusion_tau_pinhole, cfg.occlusion_tau_spherical = occlusion_tau_pinhole, occlusion_tau_spherical
         cfg.occlusion_zbuffer = int(bool(occlusion_zbuffer))
         cfg.storage_bf16 = int(bool(storage_bf16))
+        cfg.solve_order = int(solve_order)
         self.cfg = cfg
         h = ctypes.c_void_p()
         self._check(self.lib.pba_create(ctypes.byref(cfg), ctypes.byref(h)), ctx=None)
@@ -516,7 +522,8 @@ class Context:
         self._check(self.lib.pba_get_timings(self.h, ctypes.byref(t), int(bool(reset))))
         return dict(eval_ms=t.eval_ms, eval_launches=t.eval_launches, iterate_ms=t.iterate_ms,
                     iterations=t.iterations, n_items=t.n_items, items_px=t.items_px, grid=t.grid,
-                    iter_eval_ms=t.iter_eval_ms, iter_evals=t.iter_evals)
+                    iter_eval_ms=t.iter_eval_ms, iter_evals=t.iter_evals, solve_n=t.solve_n,
+                    solve_steps=t.solve_steps, solve_nd=bool(t.solve_nd))
 
 
 def context_for_problem(prob, precision=PBA_F32, channels=None, grad_mode=0, device=0, poses=None, images=None,
@@ -528,7 +535,8 @@ def context_for_problem(prob, precision=PBA_F32, channels=None, grad_mode=0, dev
     CUDA tensors).  Only argument marshalling happens here."""
     prm = prob.params
     ch = channels if channels is not None else prm["channels"]
-    ctx = Context(device=device, precision=precision, channels=ch, grad_mode=grad_mode, anchor=prm.get("anchor", 0),
+    ctx = Context(device=device, precision=precision, channels=ch, grad_mode=grad_mode,
+                  anchor=kw.pop("anchor", prm.get("anchor", 0)),
                   omega_intensity=prm["omega_intensity"], omega_depth=prm["omega_depth"],
                   omega_normal=prm["omega_normal"], huber_delta=prm["huber_delta"],
                   occlusion_tau_pinhole=prm["occ_tau_pinhole"], occlusion_tau_spherical=prm["occ_tau_spherical"],

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 namespace pba {
@@ -140,6 +141,12 @@ struct LmState {
 };
 void launch_damp_copy(const double *H, const double *b, double *A, double *rhs, int n, int anchor,
                       const LmState *lm, double lam_override, hipStream_t st);
+struct CholPlan;
+// The same into the plan's nested-dissection order (plan.n rows, pattern tiles only); also
+// clears *fail.
+void launch_damp_copy_perm(const double *H, const double *b, double *A, double *rhs, int n0, int anchor,
+                           const LmState *lm, double lam_override, const CholPlan &plan, int32_t *fail,
+                           hipStream_t st);
 // Tiles of the Cholesky factor that can be nonzero (host-built from the pair graph with the
 // factorisation's symbolic fill): for block column k, rcnt[k] tile rows i > k at rows + rbeg[k]
 // (device, ascending); for block row k, ccnt[k] tile columns j < k at cols + cbeg[k] (device).
@@ -151,7 +158,47 @@ constexpr int kCholPre = 4;
 struct CholPlan {
     const int32_t *rows = nullptr, *cols = nullptr, *meta = nullptr;
     std::vector<int> rbeg, rcnt, cbeg, ccnt;
+    int np = -1;      // pose variables the plan was built for
+    int n = 0;        // order of the factored system (6 NP, or more with nested dissection)
+    // Nested-dissection order (nd): the factor works on a permuted system whose dissection blocks
+    // are padded to 64-row boundaries, and the factorisation and solves run one elimination-tree
+    // level per launch.  Device arrays:
+    bool nd = false;
+    const int32_t *perm = nullptr;      // n: the 6 NP-system index of each factor row, -1 = padding
+    const int32_t *pose_off = nullptr;  // NP: first factor row of each pose variable
+    const int32_t *dtiles = nullptr;    // 2 ndt: (tile row, tile column) of the lower tiles of the pattern
+    int ndt = 0;
+    const int32_t *lcols = nullptr;     // block columns grouped by level: level l at lcols + lbeg[l]
+    std::vector<int> lbeg, lcnt;
+    const int32_t *tasks = nullptr;     // update tasks, 4 ints each: target tile (a, b), first
+    const int32_t *contrib = nullptr;   //   contributing column in contrib, count (ascending columns)
+    std::vector<int> tbeg, tcnt;        // level l's tasks at tasks + 4 tbeg[l]
 };
+
+// Block pattern of the factor of an n x n system with pose variable v at rows pos[v] .. pos[v] + 5,
+// coupled along `edges` (pose-variable pairs): for each 64-wide block column k its tile rows
+// below the diagonal (ascending, symbolic fill included) and for each block row its tile columns
+// left of the diagonal, and each column's level in the elimination tree (0 = no predecessor).
+struct TilePattern {
+    int n = 0, nt = 0, nlev = 0;
+    std::vector<std::vector<int>> rows, cols;
+    std::vector<int> level;
+};
+TilePattern tile_pattern(int n, const std::vector<int> &pos, const std::vector<std::pair<int, int>> &edges);
+// Nested-dissection blocks of the pose graph (nv vertices): leaves of at most `leaf` vertices and
+// separators, each block's vertices ascending, every separator after the two parts it separates.
+std::vector<std::vector<int>> nd_blocks(int nv, const std::vector<std::pair<int, int>> &edges, int leaf);
+// First row of each vertex with the blocks laid out in order, each padded to a multiple of 64 rows;
+// n_pad receives the padded order.
+std::vector<int> nd_positions(int nv, const std::vector<std::vector<int>> &blocks, int &n_pad);
+// The level-scheduled factorisation's lists for a pattern in a nested-dissection order (the
+// CholPlan fields of the same names, host side): perm, dtiles, lcols / lbeg / lcnt, and tasks /
+// contrib / tbeg / tcnt.
+struct NdArrays {
+    std::vector<int32_t> perm, dtiles, lcols, tasks, contrib;
+    std::vector<int> lbeg, lcnt, tbeg, tcnt;
+};
+NdArrays nd_arrays(const TilePattern &tp, const std::vector<int> &pos);
 // A (n x n, lower triangle used) is overwritten; the factor's panel tiles go to L and, transposed,
 // to LT (n x n each), the inverted diagonal blocks W and their transposes to Winv (2 nblk blocks of
 // 64 x 64: all W, then all W^T).
@@ -169,8 +216,10 @@ void launch_normals(const float *dep, void *att4, int bf, int H, int W, const do
 // Solves L L^T x = x in place with the factor as launch_cholesky leaves it.
 void launch_chol_solve(const double *L, const double *LT, double *Winv, double *x, int n, const CholPlan &plan,
                        const int32_t *fail, hipStream_t st);
-void launch_boxplus(const double *X, const double *dx, double *Xout, int N, const int32_t *fail,
+// off: first element of each pose variable's 6 in dx (nested-dissection layout), nullptr = 6 k.
+void launch_boxplus(const double *X, const double *dx, const int32_t *off, double *Xout, int N, const int32_t *fail,
                     LmState *lm, hipStream_t st);
+void launch_gather_step(double *dst, const double *src, const int32_t *off, int N, hipStream_t st);
 void launch_stamp(const LmState *lm, double *logbuf, int log_cap, int which, hipStream_t st);
 void launch_lm_decide(LmState *lm, const double *totals_cand, int64_t nH, double *H_cur, const double *H_cand,
                       double *b_cur, const double *b_cand, double *X_cur, const double *X_cand, int N,

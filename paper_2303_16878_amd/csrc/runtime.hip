@@ -81,6 +81,7 @@ struct pba_ctx {
     DevBuf poses, poses_cand, pairs_d, pair_dev, item_pair, item_px0, pitems, ibeg, icnt, counters, partials, pair_out;
     DevBuf blk_rc, blk_ptr, blk_ent, bk_ptr, bk_ent;
     DevBuf chol_rows, chol_cols, chol_meta;
+    DevBuf nd_perm, nd_off, nd_dtiles, nd_lcols, nd_tasks, nd_contrib, dx_nat;
     CholPlan chol;   // tiles of the Cholesky factor that can be nonzero
     DevBuf zbuf, zoff;   // z-buffer occlusion variant: per pair, one FP32 depth per target pixel
     int64_t zcells = 0;
@@ -283,22 +284,37 @@ pba_status image_layout(pba_ctx *c, ImageSet &is, const std::vector<int32_t> &se
 // factorisation fills (tile (i, j), i >= j, once tiles (i, k) and (j, k) are nonzero for some
 // k < j).  The damped, gauge-fixed matrix has no nonzero outside this pattern, so the panel,
 // trailing update and triangular solves may skip every other tile.
+//
+// In the natural order the factorisation is a chain of one dependent step per block column.  A
+// nested-dissection order of the pose graph (blocks padded to 64 rows) lets the columns of one
+// elimination-tree level factor in one launch; it is taken (solve_order auto) when it at least
+// halves the chain without more than doubling the system's order, or always (solve_order nd).
 void drop_graph(pba_ctx *c);
+
+constexpr int kNdLeaf = 20;   // pose variables per dissection leaf (120 rows: two tiles)
 
 // (A captured iteration holds the list pointers and launch counts, so it is dropped.)
 pba_status build_chol_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt)
 {
     drop_graph(c);
-    const int nt = (n_sys(c) + 63) / 64;
-    std::vector<char> occ((size_t)nt * nt, 0);   // lower triangle: occ[i * nt + j], i >= j
-    auto mark = [&](int a, int b) {
-        const int ta[2] = {6 * a / 64, (6 * a + 5) / 64}, tb[2] = {6 * b / 64, (6 * b + 5) / 64};
-        for (int x : ta)
-            for (int y : tb) occ[(size_t)std::max(x, y) * nt + std::min(x, y)] = 1;
-    };
-    for (int v = 0; v < c->NP; ++v) mark(v, v);
-    for (size_t p = 0; p < src.size(); ++p) mark(pose_var(c, src[p]), pose_var(c, tgt[p]));
-    for (int k = 0; k < nt; ++k) occ[(size_t)k * nt + k] = 1;
+    const int np = c->NP, n0 = n_sys(c);
+    std::vector<std::pair<int, int>> edges(src.size());
+    for (size_t p = 0; p < src.size(); ++p) edges[p] = {pose_var(c, src[p]), pose_var(c, tgt[p])};
+    std::vector<int> pos(np);
+    for (int v = 0; v < np; ++v) pos[v] = 6 * v;
+    TilePattern tp = tile_pattern(n0, pos, edges);
+    bool nd = false;
+    if (c->cfg.solve_order != PBA_ORDER_NATURAL && np > 1) {
+        int n_pad = 0;
+        std::vector<int> pnd = nd_positions(np, nd_blocks(np, edges, kNdLeaf), n_pad);
+        TilePattern t2 = tile_pattern(n_pad, pnd, edges);
+        if (c->cfg.solve_order == PBA_ORDER_ND || (2 * t2.nlev <= tp.nt && n_pad <= 2 * n0 + 64)) {
+            tp = std::move(t2);
+            pos = std::move(pnd);
+            nd = true;
+        }
+    }
+    const int nt = tp.nt, n = tp.n;
     std::vector<int32_t> rows, cols;
     CholPlan &pl = c->chol;
     pl.rbeg.assign(nt, 0);
@@ -307,19 +323,13 @@ pba_status build_chol_plan(pba_ctx *c, const std::vector<int32_t> &src, const st
     pl.ccnt.assign(nt, 0);
     for (int k = 0; k < nt; ++k) {
         pl.rbeg[k] = (int)rows.size();
-        for (int i = k + 1; i < nt; ++i)
-            if (occ[(size_t)i * nt + k]) rows.push_back(i);
-        pl.rcnt[k] = (int)rows.size() - pl.rbeg[k];
-        // symbolic fill of this column's update
-        for (int a = pl.rbeg[k]; a < (int)rows.size(); ++a)
-            for (int b = pl.rbeg[k]; b <= a; ++b) occ[(size_t)rows[a] * nt + rows[b]] = 1;
-    }
-    for (int k = 0; k < nt; ++k) {
+        rows.insert(rows.end(), tp.rows[k].begin(), tp.rows[k].end());
+        pl.rcnt[k] = (int)tp.rows[k].size();
         pl.cbeg[k] = (int)cols.size();
-        for (int j = 0; j < k; ++j)
-            if (occ[(size_t)k * nt + j]) cols.push_back(j);
-        pl.ccnt[k] = (int)cols.size() - pl.cbeg[k];
+        cols.insert(cols.end(), tp.cols[k].begin(), tp.cols[k].end());
+        pl.ccnt[k] = (int)tp.cols[k].size();
     }
+    const std::vector<int32_t> crows = rows, ccols = cols;
     rows.push_back(0);   // keep the device arrays non-empty
     cols.push_back(0);
     pba_status s;
@@ -330,13 +340,52 @@ pba_status build_chol_plan(pba_ctx *c, const std::vector<int32_t> &src, const st
     // the first kCholPre tile rows of each block column, then the first tile columns of each block
     // row, -1 padded
     for (int k = 0; k < nt; ++k)
-        for (int e = 0; e < kCholPre; ++e) meta.push_back(e < pl.rcnt[k] ? rows[pl.rbeg[k] + e] : -1);
+        for (int e = 0; e < kCholPre; ++e) meta.push_back(e < pl.rcnt[k] ? crows[pl.rbeg[k] + e] : -1);
     for (int k = 0; k < nt; ++k)
-        for (int e = 0; e < kCholPre; ++e) meta.push_back(e < pl.ccnt[k] ? cols[pl.cbeg[k] + e] : -1);
+        for (int e = 0; e < kCholPre; ++e) meta.push_back(e < pl.ccnt[k] ? ccols[pl.cbeg[k] + e] : -1);
     if ((s = upload(c, c->chol_meta, meta.data(), meta.size() * 4))) return s;
     pl.rows = P_<int32_t>(c->chol_rows);
     pl.cols = P_<int32_t>(c->chol_cols);
     pl.meta = P_<int32_t>(c->chol_meta);
+    pl.np = np;
+    pl.n = n;
+    pl.nd = nd;
+    pl.lbeg.clear();
+    pl.lcnt.clear();
+    pl.tbeg.clear();
+    pl.tcnt.clear();
+    pl.ndt = 0;
+    if (nd) {
+        const NdArrays a = nd_arrays(tp, pos);
+        pl.lbeg = a.lbeg;
+        pl.lcnt = a.lcnt;
+        pl.tbeg = a.tbeg;
+        pl.tcnt = a.tcnt;
+        std::vector<int32_t> perm = a.perm, dtiles = a.dtiles, lcols = a.lcols, tasks = a.tasks, contrib = a.contrib;
+        pl.ndt = (int)dtiles.size() / 2;
+        contrib.push_back(0);
+        tasks.insert(tasks.end(), {0, 0, 0, 0});
+        if ((s = upload(c, c->nd_perm, perm.data(), perm.size() * 4))) return s;
+        if ((s = upload(c, c->nd_off, pos.data(), pos.size() * 4))) return s;
+        if ((s = upload(c, c->nd_dtiles, dtiles.data(), dtiles.size() * 4))) return s;
+        if ((s = upload(c, c->nd_lcols, lcols.data(), lcols.size() * 4))) return s;
+        if ((s = upload(c, c->nd_tasks, tasks.data(), tasks.size() * 4))) return s;
+        if ((s = upload(c, c->nd_contrib, contrib.data(), contrib.size() * 4))) return s;
+        if ((s = ensure(c, c->dx_nat, (size_t)n0 * 8))) return s;
+        pl.perm = P_<int32_t>(c->nd_perm);
+        pl.pose_off = P_<int32_t>(c->nd_off);
+        pl.dtiles = P_<int32_t>(c->nd_dtiles);
+        pl.lcols = P_<int32_t>(c->nd_lcols);
+        pl.tasks = P_<int32_t>(c->nd_tasks);
+        pl.contrib = P_<int32_t>(c->nd_contrib);
+    }
+    // the factorisation's buffers at the factored order: working matrix, the factor's panels and
+    // their transposes; the inverted diagonal blocks (64 x 64 each, zero-padded) then their
+    // transposes; the step
+    const size_t nz = (size_t)n;
+    if ((s = ensure(c, c->A, 3 * nz * nz * 8))) return s;
+    if ((s = ensure(c, c->Winv, 2 * (size_t)nt * 64 * 64 * 8))) return s;
+    if ((s = ensure(c, c->dx, nz * 8))) return s;
     return PBA_OK;
 }
 
@@ -344,7 +393,7 @@ pba_status build_chol_plan(pba_ctx *c, const std::vector<int32_t> &src, const st
 // from the pairs as set (none before any are set).
 pba_status ensure_chol_plan(pba_ctx *c)
 {
-    if (c->chol.rows && (int)c->chol.rcnt.size() == (n_sys(c) + 63) / 64) return PBA_OK;
+    if (c->chol.rows && c->chol.np == c->NP) return PBA_OK;
     const std::vector<int32_t> none;
     return c->P > 0 ? build_chol_plan(c, c->src_h, c->tgt_h) : build_chol_plan(c, none, none);
 }
@@ -569,6 +618,23 @@ void drop_graph(pba_ctx *c)
     c->graph_valid = false;
 }
 
+// Damped, gauge-fixed solve of the current system into dx (the plan's order and layout): lambda
+// from lm, or lam_override when >= 0.
+void enqueue_solve(pba_ctx *c, const LmState *lm, double lam_override, hipStream_t st)
+{
+    const CholPlan &pl = c->chol;
+    const int n = pl.n;
+    double *A = P_<double>(c->A), *Lf = A + (size_t)n * n, *LTf = Lf + (size_t)n * n;
+    if (pl.nd)
+        launch_damp_copy_perm(P_<double>(c->H), P_<double>(c->b), A, P_<double>(c->dx), n_sys(c), c->cfg.anchor, lm,
+                              lam_override, pl, P_<int32_t>(c->fail), st);
+    else
+        launch_damp_copy(P_<double>(c->H), P_<double>(c->b), A, P_<double>(c->dx), n, c->cfg.anchor, lm,
+                         lam_override, st);
+    launch_cholesky(A, Lf, LTf, n, P_<double>(c->Winv), pl, P_<int32_t>(c->fail), st);
+    launch_chol_solve(Lf, LTf, P_<double>(c->Winv), P_<double>(c->dx), n, pl, P_<int32_t>(c->fail), st);
+}
+
 // Enqueue one LM / GN iteration on `st`: damped solve at the current poses, candidate poses,
 // evaluation at the candidate, device-side accept/reject.  Identical launches every iteration.
 pba_status enqueue_iteration(pba_ctx *c, hipStream_t st)
@@ -576,13 +642,9 @@ pba_status enqueue_iteration(pba_ctx *c, hipStream_t st)
     const int n = n_sys(c);
     double *totals = P_<double>(c->totals);   // [0..3] current, [4..7] candidate
     launch_stamp(P_<LmState>(c->lm), P_<double>(c->logbuf), c->log_cap, 2, st);
-    launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
-                     P_<LmState>(c->lm), -1.0, st);
-    double *Lf = P_<double>(c->A) + (size_t)n * n, *LTf = Lf + (size_t)n * n;
-    launch_cholesky(P_<double>(c->A), Lf, LTf, n, P_<double>(c->Winv), c->chol, P_<int32_t>(c->fail), st);
-    launch_chol_solve(Lf, LTf, P_<double>(c->Winv), P_<double>(c->dx), n, c->chol, P_<int32_t>(c->fail), st);
-    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->NP, P_<int32_t>(c->fail),
-                   P_<LmState>(c->lm), st);
+    enqueue_solve(c, P_<LmState>(c->lm), -1.0, st);
+    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), c->chol.nd ? c->chol.pose_off : nullptr,
+                   P_<double>(c->poses_cand), c->NP, P_<int32_t>(c->fail), P_<LmState>(c->lm), st);
     pba_status s = run_eval(c, P_<double>(c->poses_cand), P_<double>(c->H_cand), P_<double>(c->b_cand), totals + 4,
                             false, st, true);
     if (s) return s;
@@ -694,6 +756,7 @@ pba_status pba_create(const pba_config *cfg, pba_ctx **out)
     // BF16 storage: FP32 evaluation path only, without the z-buffer variant
     if (cfg->storage_bf16 != 0 && cfg->storage_bf16 != 1) return PBA_EINVAL;
     if (cfg->storage_bf16 && (cfg->precision != PBA_F32 || cfg->occlusion_zbuffer)) return PBA_EINVAL;
+    if (cfg->solve_order < PBA_ORDER_AUTO || cfg->solve_order > PBA_ORDER_ND) return PBA_EINVAL;
     if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return PBA_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return PBA_EDEVICE;
@@ -738,7 +801,8 @@ pba_status pba_destroy(pba_ctx *c)
                       &c->bk_ent, &c->H, &c->b, &c->H_cand, &c->b_cand, &c->totals, &c->A, &c->Winv, &c->dx, &c->lm,
                       &c->fail, &c->logbuf, &c->dbg_status, &c->dbg_uv, &c->dbg_cell, &c->dbg_res,
                       &c->loss_delta, &c->loss_poses, &c->g_int, &c->g_dep, &c->g_nrm, &c->g_pose,
-                      &c->chol_rows, &c->chol_cols, &c->chol_meta, &c->zbuf, &c->zoff};
+                      &c->chol_rows, &c->chol_cols, &c->chol_meta, &c->zbuf, &c->zoff, &c->nd_perm,
+                      &c->nd_off, &c->nd_dtiles, &c->nd_lcols, &c->nd_tasks, &c->nd_contrib, &c->dx_nat};
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : bufs) release(*b);
@@ -1024,17 +1088,20 @@ pba_status pba_solve_step(pba_ctx *c, double lambda, double *dx, int32_t on_devi
             return s;
         c->system_valid = true;
     }
-    launch_damp_copy(P_<double>(c->H), P_<double>(c->b), P_<double>(c->A), P_<double>(c->dx), n, c->cfg.anchor,
-                     P_<LmState>(c->lm), lambda, c->stream);
-    double *Lf = P_<double>(c->A) + (size_t)n * n, *LTf = Lf + (size_t)n * n;
-    launch_cholesky(P_<double>(c->A), Lf, LTf, n, P_<double>(c->Winv), c->chol, P_<int32_t>(c->fail), c->stream);
-    launch_chol_solve(Lf, LTf, P_<double>(c->Winv), P_<double>(c->dx), n, c->chol, P_<int32_t>(c->fail),
-                      c->stream);
+    enqueue_solve(c, P_<LmState>(c->lm), lambda, c->stream);
+    // the step in pose order
+    const double *step = P_<double>(c->dx);
+    if (c->chol.nd && dx) {
+        double *dst = on_device ? dx : P_<double>(c->dx_nat);
+        launch_gather_step(dst, step, c->chol.pose_off, c->NP, c->stream);
+        step = dst;
+    }
     HIP_OK(hipGetLastError());
     int32_t f = 0;
     HIP_OK(hipMemcpyAsync(&f, c->fail.p, 4, hipMemcpyDeviceToHost, c->stream));
-    if (dx) HIP_OK(hipMemcpyAsync(dx, c->dx.p, (size_t)n * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                                  c->stream));
+    if (dx && step != dx)
+        HIP_OK(hipMemcpyAsync(dx, step, (size_t)n * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                              c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     if (f) return fail(c, PBA_ENOTPD, "damped system is not positive definite (lambda = %g)", lambda);
     return PBA_OK;
@@ -1059,8 +1126,8 @@ pba_status pba_apply_step(pba_ctx *c, const double *dx, int32_t on_device)
             if (!std::isfinite(v)) return fail(c, PBA_EINVAL, "non-finite step");
         if ((s = upload(c, c->dx, h.data(), (size_t)n * 8))) return s;
     }
-    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->poses_cand), c->NP, nullptr, nullptr,
-                   c->stream);
+    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), nullptr, P_<double>(c->poses_cand), c->NP, nullptr,
+                   nullptr, c->stream);
     launch_copy(P_<double>(c->poses), P_<double>(c->poses_cand), (int64_t)c->NP * 12, c->stream);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(c->stream));
@@ -1175,8 +1242,8 @@ pba_status pba_loss_forward(pba_ctx *c, const float *delta, int32_t on_device, d
     }
     // X = X0 boxplus delta (the step buffer is scratch here)
     launch_delta_to_dx(P_<float>(c->loss_delta), P_<double>(c->dx), N, c->stream);
-    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), P_<double>(c->loss_poses), N, nullptr, nullptr,
-                   c->stream);
+    launch_boxplus(P_<double>(c->poses), P_<double>(c->dx), nullptr, P_<double>(c->loss_poses), N, nullptr,
+                   nullptr, c->stream);
     double *tot = P_<double>(c->totals) + 4;
     if ((s = run_eval(c, P_<double>(c->loss_poses), P_<double>(c->H_cand), P_<double>(c->b_cand), tot, false,
                       c->stream)))
@@ -1587,6 +1654,10 @@ pba_status pba_get_timings(pba_ctx *c, pba_timings *out, int32_t reset)
     out->grid = c->grid;
     out->iter_eval_ms = c->iter_eval_ms;
     out->iter_evals = c->iter_evals;
+    out->solve_n = c->chol.rows ? c->chol.n : 0;
+    out->solve_steps = !c->chol.rows ? 0 : c->chol.nd ? (int32_t)c->chol.lcnt.size() : (int32_t)c->chol.rcnt.size();
+    out->solve_nd = c->chol.rows && c->chol.nd ? 1 : 0;
+    out->reserved = 0;
     if (reset) {
         c->eval_ms = c->iterate_ms = c->iter_eval_ms = 0.0;
         c->eval_launches = c->iterations = c->iter_evals = 0;

@@ -33,6 +33,44 @@ __global__ void damp_copy_kernel(const double *__restrict__ H, const double *__r
     }
 }
 
+// The same system in a nested-dissection order: factor row R holds row perm[R] of the 6 NP system
+// (perm[R] < 0: padding, a unit diagonal and no coupling).  Only the lower tiles of the factor's
+// pattern are written (one workgroup per tile, dtiles), the diagonal tiles in full; rhs is the
+// permuted -b.  Also clears the failure flag ahead of the level launches.
+__global__ void __launch_bounds__(256) damp_copy_perm_kernel(const double *__restrict__ H,
+                                                             const double *__restrict__ b, double *__restrict__ A,
+                                                             double *__restrict__ rhs, int n0, int n,
+                                                             const int32_t *__restrict__ perm,
+                                                             const int32_t *__restrict__ dtiles, int anchor,
+                                                             const LmState *lm, double lam_override, int32_t *fail)
+{
+    const double lam = lam_override >= 0.0 ? lam_override : lm->lam;
+    const int a0 = 6 * anchor, a1 = a0 + 6;
+    const int ti = dtiles[2 * blockIdx.x], tj = dtiles[2 * blockIdx.x + 1];
+    const int C = tj * NB + (threadIdx.x & 63), oc = perm[C];
+    const bool ac = oc >= a0 && oc < a1;
+    for (int r = threadIdx.x >> 6; r < NB; r += 4) {
+        const int R = ti * NB + r, orow = perm[R];
+        const bool ar = orow >= a0 && orow < a1;
+        double v = (orow >= 0 && oc >= 0) ? H[(int64_t)orow * n0 + oc] : 0.0;
+        if (orow < 0 || oc < 0 || ar || ac) v = (R == C) ? 1.0 : 0.0;
+        if (R == C) v += lam * v;
+        A[(int64_t)R * n + C] = v;
+    }
+    if (ti == tj && threadIdx.x < NB) {
+        const int R = ti * NB + threadIdx.x, o = perm[R];
+        rhs[R] = (o < 0 || (o >= a0 && o < a1)) ? 0.0 : -b[o];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *fail = 0;
+}
+
+void launch_damp_copy_perm(const double *H, const double *b, double *A, double *rhs, int n0, int anchor,
+                           const LmState *lm, double lam_override, const CholPlan &plan, int32_t *fail, hipStream_t st)
+{
+    hipLaunchKernelGGL(damp_copy_perm_kernel, dim3(plan.ndt), dim3(256), 0, st, H, b, A, rhs, n0, plan.n, plan.perm,
+                       plan.dtiles, anchor, lm, lam_override, fail);
+}
+
 void launch_damp_copy(const double *H, const double *b, double *A, double *rhs, int n, int anchor,
                       const LmState *lm, double lam_override, hipStream_t st)
 {
@@ -89,7 +127,14 @@ __device__ __forceinline__ double rsqrt_f64(double d)
 // in order.  No step branches on the lane or the wave.  (Broadcasting the 16 values by readlane
 // instead of LDS, skipping the column ranges a step cannot change, or eight pivots per barrier
 // all measured slower; keeping V with lane = row, which needs 32 readlanes per pivot, cost 30%.)
-__global__ void __launch_bounds__(256) chol_diag_kernel(const double *A, int n, int k0, double *Winv, int32_t *fail)
+//
+// kList: the launch factors the block columns cols[blockIdx.x] (one tree level of a nested-dissection
+// order; the failure flag was cleared before the factorisation), else the single block at k0, the
+// first of which (k0 = 0) clears the flag.
+template <bool kList>
+__global__ void __launch_bounds__(256) chol_diag_kernel(const double *A, int n, int k0_arg,
+                                                        const int32_t *__restrict__ cols, double *Winv,
+                                                        int32_t *fail)
 {
     __shared__ double cb[2][4][NB];   // the four columns c of a pivot group (double-buffered)
     __shared__ double rb[2][4][NB];   // the four rows r of V at their pivots
@@ -97,7 +142,9 @@ __global__ void __launch_bounds__(256) chol_diag_kernel(const double *A, int n, 
     __shared__ double qb[2][4];       // their reciprocals
     __shared__ double piv[NB];
     __shared__ double Ts[NB][NB + 1];   // W, transposed on the way out
-    if (k0 > 0 && *fail) return;   // the first block starts the factorisation and clears the flag
+    const int k0 = kList ? cols[blockIdx.x] * NB : k0_arg;
+    const bool clears = !kList && k0 == 0;
+    if (!clears && *fail) return;
     const int nb = min(NB, n - k0);
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -176,7 +223,7 @@ __global__ void __launch_bounds__(256) chol_diag_kernel(const double *A, int n, 
     __syncthreads();
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) Wtb[(c0 + jj) * NB + lane] = Ts[c0 + jj][lane];
-    if (threadIdx.x == 0 && (bad || k0 == 0)) *fail = bad ? 1 : 0;
+    if (threadIdx.x == 0 && (bad || clears)) *fail = bad ? 1 : 0;
 }
 
 // C += P Q^T over k = 0..63 for tiles in LDS (rows padded to 65 doubles), 16 x 16 threads,
@@ -288,13 +335,88 @@ __global__ void __launch_bounds__(256) chol_panel_update_kernel(double *A, doubl
         }
 }
 
+// One elimination-tree level of a nested-dissection factorisation, after its diagonal blocks: every
+// block column k of the level contributes A_ab -= X_a X_b^T, X = A_(., k) W_k^T, to the tiles (a, b),
+// b <= a, of its tile rows, and writes X as its panel of the factor.  The tiles a level writes
+// belong to higher levels, so no tile is both read as a panel and updated here.  One task per
+// target tile lists its contributing columns (ascending); workgroup (task, qi, qj) owns one
+// 32 x 32 quarter of the target and sums the contributions in registers, column by column in
+// that order, before subtracting them: the result does not depend on the schedule.  The
+// workgroups of a diagonal target with qj = 0 write their rows of each contributor's panel to L
+// and L^T.
+__global__ void __launch_bounds__(256) chol_level_update_kernel(double *A, double *L, double *LT, int n,
+                                                                const double *__restrict__ Winv,
+                                                                const int32_t *__restrict__ tasks,
+                                                                const int32_t *__restrict__ contrib,
+                                                                const int32_t *fail)
+{
+    constexpr int H = NB / 2;
+    __shared__ double Ws[NB][NB + 1];
+    __shared__ double Xi[H][NB + 1];
+    __shared__ double Xj[H][NB + 1];
+    if (*fail) return;
+    const int4 tk = reinterpret_cast<const int4 *>(tasks)[blockIdx.x >> 2];
+    const int qi = (blockIdx.x >> 1) & 1, qj = blockIdx.x & 1;
+    const bool diag = tk.x == tk.y;
+    if (diag && qj > qi) return;   // uniform over the workgroup
+    const bool same = diag && qi == qj, write_l = diag && qj == 0;
+    const int ri = tk.x * NB + H * qi, rj = tk.y * NB + H * qj;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    double c[2][2] = {};
+    for (int e = 0; e < tk.w; ++e) {
+        const int kb = contrib[tk.z + e], k0 = kb * NB;
+        load_tile<NB>(Ws, Winv + (int64_t)kb * NB * NB, NB, NB, 0, 0, NB);
+        load_tile<H>(Xi, A, n, n, ri, k0, NB);
+        if (!same) load_tile<H>(Xj, A, n, n, rj, k0, NB);
+        __syncthreads();
+        double ci[2][4] = {}, cj[2][4] = {};
+        tile_nt(Xi, Ws, tx, ty, ci);
+        if (!same) tile_nt(Xj, Ws, tx, ty, cj);
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = ty + 16 * a, j = tx + 16 * q;
+                Xi[i][j] = ci[a][q];
+                if (!same) Xj[i][j] = cj[a][q];
+                if (write_l) L[(int64_t)(ri + i) * n + k0 + j] = ci[a][q];
+            }
+        __syncthreads();
+        if (write_l)
+            for (int e2 = tid; e2 < H * NB; e2 += 256) {
+                const int i = e2 % H, j = e2 / H;
+                LT[(int64_t)(k0 + j) * n + ri + i] = Xi[i][j];
+            }
+        tile_nt(Xi, same ? Xi : Xj, tx, ty, c);
+        __syncthreads();   // the next contributor's tiles overwrite the LDS
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int i = ty + 16 * a, j = tx + 16 * q;
+            if (!diag || H * qj + j <= H * qi + i) A[(int64_t)(ri + i) * n + rj + j] -= c[a][q];
+        }
+}
+
 void launch_cholesky(double *A, double *L, double *LT, int n, double *Winv, const CholPlan &plan, int32_t *fail,
                      hipStream_t st)
 {
+    if (plan.nd) {
+        for (size_t l = 0; l < plan.lcnt.size(); ++l) {
+            hipLaunchKernelGGL(chol_diag_kernel<true>, dim3(plan.lcnt[l]), dim3(256), 0, st, A, n, 0,
+                               plan.lcols + plan.lbeg[l], Winv, fail);
+            if (plan.tcnt[l] > 0)
+                hipLaunchKernelGGL(chol_level_update_kernel, dim3(4 * plan.tcnt[l]), dim3(256), 0, st, A, L, LT, n,
+                                   Winv, plan.tasks + 4 * (int64_t)plan.tbeg[l], plan.contrib, fail);
+        }
+        return;
+    }
     const int nblk = (n + NB - 1) / NB;
     for (int kb = 0; kb < nblk; ++kb) {
         const int k0 = kb * NB;
-        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, A, n, k0, Winv, fail);
+        hipLaunchKernelGGL(chol_diag_kernel<false>, dim3(1), dim3(256), 0, st, A, n, k0, nullptr, Winv, fail);
         const int m = plan.rcnt[kb];
         if (m > 0)
             hipLaunchKernelGGL(chol_panel_update_kernel, dim3(4 * (m * (m + 1) / 2)), dim3(256), 0, st, A, L, LT, n, k0, Winv,
@@ -478,9 +600,71 @@ __global__ void __launch_bounds__(64 * LPR) trsv_band_kernel(const double *__res
         for (int e = t; e < n; e += blockDim.x) x[e] = vs[e];
 }
 
+// One elimination-tree level of the triangular solves in a nested-dissection order, one workgroup
+// per block column k of the level, gathering what the finished levels contribute:
+//   forward   y_k = W_k (r_k - sum_j L_kj y_j)      over the tile columns j < k of block row k,
+//   backward  x_k = W_k^T (y_k - sum_i L_ik^T x_i)  over the tile rows i > k of block column k,
+// with F = L (tile (k, j)) or F = L^T (tile (k, i), rows of L^T) and M = W_k or W_k^T.  The tiles
+// gathered belong to lower levels (forward) or higher ones (backward), finished by earlier
+// launches.  Four lanes per row, 16 columns each; the sums of a row's lanes by quad permutes.
+// x is zeroed instead if the factorisation failed.
+__global__ void __launch_bounds__(256) trsv_level_kernel(const double *__restrict__ F, const double *__restrict__ M,
+                                                         double *x, int n, const int32_t *__restrict__ lcols,
+                                                         const int32_t *__restrict__ adj,
+                                                         const int32_t *__restrict__ beg,
+                                                         const int32_t *__restrict__ cnt, const int32_t *fail)
+{
+    __shared__ double sv[NB];
+    const int kb = lcols[blockIdx.x], k0 = kb * NB;
+    const int t = threadIdx.x, row = t >> 2, c16 = (t & 3) * 16;
+    const bool lead = (t & 3) == 0;
+    if (*fail) {
+        if (t < NB) x[k0 + t] = 0.0;
+        return;
+    }
+    double z = 0.0;
+    const int b0 = beg[kb], m = cnt[kb];
+    for (int e = 0; e < m; ++e) {
+        const int j0 = adj[b0 + e] * NB;
+        const double2 *Fr = reinterpret_cast<const double2 *>(F + (int64_t)(k0 + row) * n + j0 + c16);
+        const double2 *xr = reinterpret_cast<const double2 *>(x + j0 + c16);
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const double2 f = Fr[h], v = xr[h];
+            z = fma(f.x, v.x, z);
+            z = fma(f.y, v.y, z);
+        }
+    }
+    z = group_sum<4>(z);
+    if (lead) sv[row] = x[k0 + row] - z;
+    __syncthreads();
+    const double2 *Mr = reinterpret_cast<const double2 *>(M + ((int64_t)kb * NB + row) * NB + c16);
+    double u = 0.0;
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+        const double2 w = Mr[h];
+        u = fma(w.x, sv[c16 + 2 * h], u);
+        u = fma(w.y, sv[c16 + 2 * h + 1], u);
+    }
+    u = group_sum<4>(u);
+    if (lead) x[k0 + row] = u;
+}
+
 void launch_chol_solve(const double *L, const double *LT, double *Winv, double *x, int n, const CholPlan &plan,
                        const int32_t *fail, hipStream_t st)
 {
+    if (plan.nd) {
+        const int nblk = n / NB, nlev = (int)plan.lcnt.size();
+        const int32_t *rbeg = plan.meta, *rcnt = rbeg + nblk, *cbeg = rcnt + nblk, *ccnt = cbeg + nblk;
+        for (int l = 0; l < nlev; ++l)
+            hipLaunchKernelGGL(trsv_level_kernel, dim3(plan.lcnt[l]), dim3(256), 0, st, L, Winv, x, n,
+                               plan.lcols + plan.lbeg[l], plan.cols, cbeg, ccnt, fail);
+        for (int l = nlev - 1; l >= 0; --l)
+            hipLaunchKernelGGL(trsv_level_kernel, dim3(plan.lcnt[l]), dim3(256), 0, st, LT,
+                               Winv + (int64_t)nblk * NB * NB, x, n, plan.lcols + plan.lbeg[l], plan.rows, rbeg,
+                               rcnt, fail);
+        return;
+    }
     // PBA_TRSV_LDS_MAX (doubles, at most kTrsvLds) lowers the size up to which the vector is kept
     // in LDS; 0 selects the global-memory variant for every size.  PBA_TRSV_LPR (4, 8 or 16) sets
     // the lanes per row of the products.
@@ -521,9 +705,10 @@ __device__ static void quat_rot(double qx, double qy, double qz, double *R)
 }
 
 // Xout_k = X_k exp(dx_k); also the step norm into lm (one workgroup reduces it).
+// off: first element of each pose's 6 in dx (a nested-dissection solve's layout), nullptr = 6 k.
 __global__ void __launch_bounds__(256) boxplus_kernel(const double *__restrict__ X, const double *__restrict__ dx,
-                                                      double *__restrict__ Xo, int N, const int32_t *fail,
-                                                      LmState *lm)
+                                                      const int32_t *__restrict__ off, double *__restrict__ Xo,
+                                                      int N, const int32_t *fail, LmState *lm)
 {
     const int tid = threadIdx.x;
     const bool f = fail && *fail;
@@ -536,7 +721,7 @@ __global__ void __launch_bounds__(256) boxplus_kernel(const double *__restrict__
             for (int i = 0; i < 12; ++i) o[i] = x[i];
             continue;
         }
-        const double *d = dx + 6 * (int64_t)k;
+        const double *d = dx + (off ? (int64_t)off[k] : 6 * (int64_t)k);
         for (int i = 0; i < 6; ++i) ss += d[i] * d[i];
         double E[9];
         quat_rot(d[3], d[4], d[5], E);
@@ -558,10 +743,24 @@ __global__ void __launch_bounds__(256) boxplus_kernel(const double *__restrict__
     }
 }
 
-void launch_boxplus(const double *X, const double *dx, double *Xout, int N, const int32_t *fail, LmState *lm,
-                    hipStream_t st)
+void launch_boxplus(const double *X, const double *dx, const int32_t *off, double *Xout, int N, const int32_t *fail,
+                    LmState *lm, hipStream_t st)
 {
-    hipLaunchKernelGGL(boxplus_kernel, dim3(1), dim3(256), 0, st, X, dx, Xout, N, fail, lm);
+    hipLaunchKernelGGL(boxplus_kernel, dim3(1), dim3(256), 0, st, X, dx, off, Xout, N, fail, lm);
+}
+
+// dst[6 k + i] = src[off[k] + i]: a nested-dissection solve's step in pose order.
+__global__ void gather_step_kernel(double *__restrict__ dst, const double *__restrict__ src,
+                                   const int32_t *__restrict__ off, int N)
+{
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 6 * N; e += gridDim.x * blockDim.x)
+        dst[e] = src[off[e / 6] + e % 6];
+}
+
+void launch_gather_step(double *dst, const double *src, const int32_t *off, int N, hipStream_t st)
+{
+    const int blocks = std::max(1, std::min(1024, (6 * N + 255) / 256));
+    hipLaunchKernelGGL(gather_step_kernel, dim3(blocks), dim3(256), 0, st, dst, src, off, N);
 }
 
 // Accept/reject the candidate: totals_cand = {F, evaluated, valid, 0} at the candidate

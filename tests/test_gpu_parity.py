@@ -277,7 +277,8 @@ def test_scattered_pattern_solve(pba, lds_max, lpr, monkeypatch):
     each 64-wide block to most others and the factorisation fills in, so block columns carry more
     tiles than the triangular solve prefetches.  The solve matches a dense solve of the same
     system, with the vector of the triangular solves in LDS and (PBA_TRSV_LDS_MAX=0) in global
-    memory, for each supported number of lanes per row of their products (PBA_TRSV_LPR)."""
+    memory, for each supported number of lanes per row of their products (PBA_TRSV_LPR), in the
+    natural order (whose single-workgroup triangular solve these settings tune)."""
     if lds_max is not None:
         monkeypatch.setenv("PBA_TRSV_LDS_MAX", lds_max)
     monkeypatch.setenv("PBA_TRSV_LPR", lpr)
@@ -286,7 +287,7 @@ def test_scattered_pattern_solve(pba, lds_max, lpr, monkeypatch):
     perm = np.random.default_rng(7).permutation(n_kf).astype(np.int32)
     X_var = np.empty_like(prob.init_poses)
     X_var[perm] = prob.init_poses
-    with pba.context_for_problem(prob, precision=pba.PBA_F64) as ctx:
+    with pba.context_for_problem(prob, precision=pba.PBA_F64, solve_order=pba.PBA_ORDER_NATURAL) as ctx:
         ctx.set_pose_groups(perm)
         ctx.set_poses(X_var)
         ev = ctx.evaluate(want_system=True)
