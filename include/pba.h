@@ -178,17 +178,12 @@ typedef struct {
     double F;                    /* sum over pairs and pixels of rho(chi^2) */
     int64_t n_evaluated;         /* (pair, source pixel with valid depth) evaluations */
     int64_t n_valid;             /* valid correspondences */
-    int64_t n_boundary_band;     /* projected points whose stencil lies inside the target image,
+    int64_t n_boundary_band;     /* projected points whose stencil lies inside the target image and
                                     whose coordinate u' (column or row) is within 1e-4 px of a cell
-                                    boundary and whose four central taps (floor(u') and the next
-                                    column, in the cell's row and the next) all hold valid depths
-                                    within tau of the predicted depth: the integer cell floor(u')
-                                    that decides the taps and the mask (readings of Sec. IV-C's
-                                    sampling) is then sensitive to rounding, so such points may
-                                    legitimately differ between the FP32 and FP64 paths or from an
-                                    exact evaluation.  (A point with a central tap off the surface is
-                                    rejected in that cell and in each cell one step away along one
-                                    axis, whose stencils hold the same four taps.) */
+                                    boundary: the integer cell floor(u') that decides the taps and
+                                    the mask (readings of Sec. IV-C's sampling) is then sensitive to
+                                    rounding, so such points may legitimately differ between the FP32
+                                    and FP64 paths or from an exact evaluation */
     double *H;                   /* nullable: 6N x 6N, raw (no gauge fix, no damping) */
     double *b;                   /* nullable: 6N */
     double *pair_out;            /* nullable: P x PBA_PAIR_OUT_LEN, in the platform frames */

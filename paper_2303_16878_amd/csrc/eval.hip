@@ -532,12 +532,6 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         // focal lengths of the projective Jacobian, halved for central differences (see sample_grad)
         const T fx = (T)(GM == 0 ? 0.5 * st_fx : st_fx), fy = (T)(GM == 0 ? 0.5 * st_fy : st_fy);
         const double taud_gate = uni_d(st.taud);   // occlusion bound, FP64 in both paths
-        // one-tap rejection ahead of the exact projection (spherical target, FP32 path): allowed
-        // when the coarse estimate is within half a pixel of the exact coordinates wherever the
-        // exact cell lies inside the image (host check on the sensor); not in the debug and
-        // z-buffer instantiations, whose outputs cover points the gate rejects
-        constexpr bool kPre = F32 && TM == MODEL_SPHERICAL && !DBG && !ZB;
-        const bool st_pre = kPre && uni(st.pretest) != 0;
         const T om_g = (T)a.omega_g, om_d = (T)a.omega_d, om_n = (T)a.omega_n, delta = (T)a.huber;
         // ray-table offsets of the source (unprojection) and target (projection) sensors in scalar
         // registers: read once per item, not from the sensor record in every chunk
@@ -819,24 +813,10 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         near = ua > -1.f && ua < (float)Wt && va > -1.f && va < (float)Ht;
                         const int kc = min(max((int)rintf(ua), 0), Wt - 1), kr = min(max((int)rintf(va), 0), Ht - 1);
                         const double2 cs = ld_f64x2(r_lut, (t_lcol + kc) * 16), rs = ld_f64x2(r_lut, (t_lrow + kr) * 16);
-                        if (kPre && st_pre) {
-                            // (kc, kr) rounds a coarse estimate within half a pixel of (u', v'), so
-                            // where the exact cell (x0, y0) is inside the image it is one of the
-                            // stencil's four central taps (x0 or x0 + 1, y0 or y0 + 1): a tap off
-                            // the surface by more than tau fails the gate below, by the same FP64
-                            // comparison, before the exact offsets, the stencil and the depth
-                            // sampling (skipped by a wave whose lanes all fail here)
-                            const float Dn = ld_f32(r_tdep, (kr * Wt + kc) * 4, 0);
-                            near = near && fabs((double)Dn - zeta) <= taud_gate;
-                        }
-                        if (!kPre || near) {
-                            const double tu = fma(Y, cs.x, -X * cs.y) * rcp_f64(fma(X, cs.x, Y * cs.y));
-                            const double tv = fma(Z, rs.x, -rho * rs.y) * rcp_f64(fma(rho, rs.x, Z * rs.y));
-                            u = fma(st_fx, atan_small(tu), (double)kc);
-                            v = fma(st_fy, atan_small(tv), (double)kr);
-                        } else {
-                            u = v = -1.0;
-                        }
+                        const double tu = fma(Y, cs.x, -X * cs.y) * rcp_f64(fma(X, cs.x, Y * cs.y));
+                        const double tv = fma(Z, rs.x, -rho * rs.y) * rcp_f64(fma(rho, rs.x, Z * rs.y));
+                        u = fma(st_fx, atan_small(tu), (double)kc);
+                        v = fma(st_fy, atan_small(tv), (double)kr);
                     } else {
                         zeta = sqrt(n2);
                         u = fma(st_fx, atan2(Y, X), st_cx);
@@ -853,7 +833,6 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         al = (T)du; be = (T)dv;
                         // the cell of a point this close to a boundary can differ between exact
                         // arithmetic and any rounding of it: counted (per wave, on the scalar unit)
-                        // if its four central taps are also on the surface (below)
                         in_band = fmax(fabs(du - 0.5), fabs(dv - 0.5)) > 0.5 - kBandPx;
                     }
                     if (ZB && ok && a.zpass) {
@@ -873,18 +852,9 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         // largest |D - zeta| also rejects them.  The bound is tested in FP64 in both
                         // paths (the taps are exact in FP64): a mask decision then does not depend on
                         // the evaluation precision, and the FP32 path keeps the FP64 path's points.
-                        // the four central taps (x0 or x0 + 1, y0 or y0 + 1) first: they belong to the
-                        // stencil of the cell and of each cell one step away along one axis, so a
-                        // point with one of them off the surface is rejected whichever of those
-                        // cells rounding picks; the boundary band counts only the others
-                        const float cmin = fminf(fminf(tD[1], tD[2]), fminf(tD[5], tD[6]));
-                        const float cmax = fmaxf(fmaxf(tD[1], tD[2]), fmaxf(tD[5], tD[6]));
-                        // (unconditional: a wave-uniform branch around it measured slower)
-                        in_band = in_band && fmax((double)cmax - zeta, zeta - (double)cmin) <= taud_gate;
-                        float dmin = cmin, dmax = cmax;
-                        constexpr int kOuter[8] = {0, 3, 4, 7, 8, 9, 10, 11};
+                        float dmin = tD[0], dmax = tD[0];
 #pragma unroll
-                        for (int k : kOuter) { dmin = fminf(dmin, tD[k]); dmax = fmaxf(dmax, tD[k]); }
+                        for (int k = 1; k < 12; ++k) { dmin = fminf(dmin, tD[k]); dmax = fmaxf(dmax, tD[k]); }
                         bool vis = fmax((double)dmax - zeta, zeta - (double)dmin) <= taud_gate;
                         // z-buffer variant: also no more than tau behind the nearest of the pair's own
                         // points in this cell (both depths as FP32, compared in FP64)

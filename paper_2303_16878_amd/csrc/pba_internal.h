@@ -59,8 +59,6 @@ __device__ __forceinline__ void att_put1(void *p, int bf, int64_t k, float v)
 struct SensorDev {
     int32_t model, H, W, npx;
     uint32_t magic_w;            // ceil(2^32 / W): row = umulhi(pix, magic_w) for pix < 2^32 / W
-    int32_t pretest;             // spherical: the coarse projection is within half a pixel of the
-                                 // exact one wherever the exact cell is inside the image
     double fxd, fyd, cxd, cyd, dmind, dmaxd, taud;
     double Ro[9], to[3];         // sensor -> platform
     int64_t lut_col, lut_row;    // element offsets into the ray tables

@@ -230,20 +230,6 @@ pba_status sensor_tables(pba_ctx *c, ImageSet &is)
         d.magic_w = (uint32_t)(((1ull << 32) + S.width - 1) / S.width);
         d.fxd = S.fx; d.fyd = S.fy; d.cxd = S.cx; d.cyd = S.cy; d.dmind = S.min_depth; d.dmaxd = S.max_depth;
         d.taud = S.model == PBA_PINHOLE ? c->cfg.occlusion_tau_pinhole : c->cfg.occlusion_tau_spherical;
-        // The evaluation's coarse spherical projection: FP32 atan2 within 6.1e-4 rad of each angle
-        // (checked against the FP64 atan2 on 4e6 directions: 6.09e-4), scaled by |fx| or |fy| in
-        // pixels, plus the FP32 rounding of u' = fx a + cx (a few ulps of |cx| + |fx| pi).  The
-        // azimuth wraps at a = +-pi, i.e. at u' = cx -+ |fx| pi, where the estimate may be off by a
-        // whole turn; a wrap position at least half a pixel outside the cells [1, W - 3] leaves every
-        // in-image point within reach.
-        d.pretest = 0;
-        if (S.model == PBA_SPHERICAL) {
-            const double pi = 3.14159265358979323846, afx = std::fabs(S.fx), afy = std::fabs(S.fy);
-            const double eu = afx * 6.1e-4 + 4.0 * std::ldexp(std::fabs(S.cx) + afx * pi, -24) + 1e-6;
-            const double ev = afy * 6.1e-4 + 4.0 * std::ldexp(std::fabs(S.cy) + afy * pi, -24) + 1e-6;
-            auto off_cells = [&](double w) { return w <= 0.5 || w >= S.width - 1.5; };
-            d.pretest = eu < 0.49 && ev < 0.49 && off_cells(S.cx - afx * pi) && off_cells(S.cx + afx * pi);
-        }
         for (int k = 0; k < 9; ++k) d.Ro[k] = S.offset[k];
         for (int k = 0; k < 3; ++k) d.to[k] = S.offset[9 + k];
         d.lut_col = (int64_t)l32.size();

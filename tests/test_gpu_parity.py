@@ -396,49 +396,25 @@ def test_build_pairs_matches_oracle(pba):
         assert ev["n_evaluated"] > 0
 
 
-def _predicted_depth(prob, poses, s, t):
-    """zeta of every source pixel of pair (s, t): range (spherical target) or depth (pinhole) of the
-    source point in the target sensor frame, FP64 (Sec. III, the sensor offsets of the Supplementary)."""
-    ss, st = prob.sensors[prob.kf_sensor[s]], prob.sensors[prob.kf_sensor[t]]
-    q = oracle.unproject_image(ss, prob.depth[s].astype(np.float64))
-    frame = lambda X: (np.asarray(X[:9], np.float64).reshape(3, 3), np.asarray(X[9:12], np.float64))
-    (Ros, tos), (Rot, tot) = frame(ss["offset"]), frame(st["offset"])
-    (Rs, ts), (Rt, tt) = frame(poses[s]), frame(poses[t])
-    p = (((q @ Ros.T + tos) @ Rs.T + ts - tt) @ Rt - tot) @ Rot
-    return np.linalg.norm(p, axis=-1) if st["model"] == 1 else p[..., 2]
-
-
 @pytest.mark.parametrize("fixture,prec", [("rgbd_small", "F32"), ("lidar_mini", "F32"), ("lidar_mini", "F64"),
                                           ("joint_mini", "F32")])
 def test_boundary_band_counts(fixture, prec, request, pba):
     """The evaluation counts, per pair and in total, the points whose stencil lies inside the target
-    image, whose projected coordinate is within 1e-4 px of a cell boundary and whose four central
-    taps all hold valid depths within tau of the predicted depth zeta.  The same count from the
-    oracle's FP64 projections (cells from its u', taps from the target depth image, zeta recomputed
-    here in FP64), with no point at 1e-4 +- 1e-11 px or at tau +- 1e-9 m aside, where rounding could
-    tip a side."""
+    image and whose projected coordinate is within 1e-4 px of a cell boundary; the oracle's FP64
+    projections give the same count (a point at 1e-4 +- 1e-11 px aside, which FP64 rounding could
+    tip, and there are none)."""
     prob = request.getfixturevalue(fixture)
     precision = pba.PBA_F64 if prec == "F64" else pba.PBA_F32
     with pba.context_for_problem(prob, precision=precision) as ctx:
         ev = ctx.evaluate(want_pairs=True)
     total = 0
     for k, (s, t) in enumerate(prob.pairs):
-        s, t = int(s), int(t)
-        o = oracle.eval_pair(prob, prob.init_poses, s, t, pixels=True)
+        o = oracle.eval_pair(prob, prob.init_poses, int(s), int(t), pixels=True)
         reached = (o["status"] == 0) | (o["status"] == 4) | (o["status"] == 5)   # passed the stencil test
-        uv = o["uv"][reached]
-        frac = uv - np.floor(uv)
+        frac = o["uv"][reached] - np.floor(o["uv"][reached])
         near = np.minimum(frac, 1.0 - frac).min(axis=-1)
         assert not np.any(np.abs(near - 1e-4) < 1e-11)
-        st = prob.sensors[prob.kf_sensor[t]]
-        Dt = prob.depth[t].astype(np.float64)
-        Dt = np.where(np.isfinite(Dt) & (Dt > 0) & (Dt >= st["min_depth"]) & (Dt <= st["max_depth"]), Dt, -1e30)
-        x0, y0 = np.floor(uv[:, 0]).astype(int), np.floor(uv[:, 1]).astype(int)
-        zeta = _predicted_depth(prob, prob.init_poses, s, t)[reached]
-        tau = prob.params["occ_tau_spherical" if st["model"] == 1 else "occ_tau_pinhole"]
-        dev = np.stack([np.abs(Dt[y0 + dy, x0 + dx] - zeta) for dy in (0, 1) for dx in (0, 1)], -1).max(-1)
-        assert not np.any(np.abs(dev - tau) < 1e-9)
-        n = int(((near < 1e-4) & (dev <= tau)).sum())
+        n = int((near < 1e-4).sum())
         assert int(ev["pairs"][k][159]) == n, (k, ev["pairs"][k][159], n)
         total += n
     _log(fixture, prec, "boundary band", total, "of", ev["n_valid"], "valid")
