@@ -116,17 +116,32 @@ void launch_pair_setup(const double *poses, const int2 *pairs, int P, const Sens
 
 // ------------------------------------------------------------------ per-pixel evaluation
 
-// 1/x and 1/sqrt(x): exact division in FP64; the hardware reciprocal and reciprocal square root
-// (about 1 ulp) in FP32, where they feed Jacobians and weights whose own FP32 rounding is of the
-// same order.
+// 1/x and 1/sqrt(x) for x > 0 (finite): in FP32 the hardware reciprocal and reciprocal square root
+// (about 1 ulp), where they feed Jacobians and weights whose own FP32 rounding is of the same
+// order; in FP64 the hardware estimates (relative error below 2^-24) refined by two Newton steps,
+// within a few ulps (an IEEE division or square root costs several times the instructions).
 template <typename T>
-__device__ __forceinline__ T fast_rcp(T x) { return T(1) / x; }
+__device__ __forceinline__ T fast_rcp(T x);
 template <>
 __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double fast_rcp<double>(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
 template <typename T>
-__device__ __forceinline__ T fast_rsq(T x) { return T(1) / sqrt(x); }
+__device__ __forceinline__ T fast_rsq(T x);
 template <>
 __device__ __forceinline__ float fast_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <>
+__device__ __forceinline__ double fast_rsq<double>(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y * fma(-0.5 * x * y, y, 1.5);
+}
 
 // 1/x in FP64: the hardware estimate (relative error below 2^-24, measured on this target) refined
 // by one Newton step, which squares the error: below 3e-15.  The geometry needs far less (a
@@ -800,7 +815,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 } else {
                     const double r2 = fma(X, X, Y * Y), n2 = fma(Z, Z, r2);
                     ok = (r2 > 0.0) && (n2 >= st_dmin * st_dmin);
-                    if (F32) {
+                    {   // the same FP64 arithmetic in both paths: cells and masks do not depend on the path
                         zeta = sqrt_f64(n2);
                         const double rho = sqrt_f64(r2);
                         // nearest column / row from a coarse FP32 estimate, then the exact angular offset
@@ -817,10 +832,6 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                         const double tv = fma(Z, rs.x, -rho * rs.y) * rcp_f64(fma(rho, rs.x, Z * rs.y));
                         u = fma(st_fx, atan_small(tu), (double)kc);
                         v = fma(st_fy, atan_small(tv), (double)kr);
-                    } else {
-                        zeta = sqrt(n2);
-                        u = fma(st_fx, atan2(Y, X), st_cx);
-                        v = fma(st_fy, atan2(Z, sqrt(r2)), st_cy);
                     }
                 }
                 if (ok) {
