@@ -202,8 +202,11 @@ NdArrays nd_arrays(const TilePattern &tp, const std::vector<int> &pos);
 // A (n x n, lower triangle used) is overwritten; the factor's panel tiles go to L and, transposed,
 // to LT (n x n each), the inverted diagonal blocks W and their transposes to Winv (2 nblk blocks of
 // 64 x 64: all W, then all W^T).
+// With a nested-dissection plan and x (the right-hand side, factor order), the forward substitution
+// runs with the factorisation and x ends up holding y with L y = rhs (launch_chol_solve then runs
+// only the backward sweeps); x is ignored in the natural order.
 void launch_cholesky(double *A, double *L, double *LT, int n, double *Winv, const CholPlan &plan, int32_t *fail,
-                     hipStream_t st);
+                     hipStream_t st, double *x);
 // att / att2: the attribute plane of one keyframe (att_get4 / att_get1 layout, `five` cues or one,
 // `bf` BF16 storage)
 void launch_downsample(const float *dep, const void *att, int five, int bf, int H, int W, float *dep2, void *att2,
@@ -213,7 +216,8 @@ void launch_unpack(const float *dep, const void *att, int five, int bf, int npx,
 void launch_normals(const float *dep, void *att4, int bf, int H, int W, const double2 *lcol, const double2 *lrow,
                     int spherical, double scale, double min_px, double max_px, double tau, int min_count,
                     hipStream_t st);
-// Solves L L^T x = x in place with the factor as launch_cholesky leaves it.
+// Solves L L^T x = x in place with the factor as launch_cholesky leaves it (nested dissection: x
+// holds y from launch_cholesky, and only L^T x = y remains).
 void launch_chol_solve(const double *L, const double *LT, double *Winv, double *x, int n, const CholPlan &plan,
                        const int32_t *fail, hipStream_t st);
 // off: first element of each pose variable's 6 in dx (nested-dissection layout), nullptr = 6 k.

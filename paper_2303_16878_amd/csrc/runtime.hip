@@ -631,7 +631,7 @@ void enqueue_solve(pba_ctx *c, const LmState *lm, double lam_override, hipStream
     else
         launch_damp_copy(P_<double>(c->H), P_<double>(c->b), A, P_<double>(c->dx), n, c->cfg.anchor, lm,
                          lam_override, st);
-    launch_cholesky(A, Lf, LTf, n, P_<double>(c->Winv), pl, P_<int32_t>(c->fail), st);
+    launch_cholesky(A, Lf, LTf, n, P_<double>(c->Winv), pl, P_<int32_t>(c->fail), st, P_<double>(c->dx));
     launch_chol_solve(Lf, LTf, P_<double>(c->Winv), P_<double>(c->dx), n, pl, P_<int32_t>(c->fail), st);
 }
 

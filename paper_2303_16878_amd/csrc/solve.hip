@@ -130,11 +130,13 @@ __device__ __forceinline__ double rsqrt_f64(double d)
 //
 // kList: the launch factors the block columns cols[blockIdx.x] (one tree level of a nested-dissection
 // order; the failure flag was cleared before the factorisation), else the single block at k0, the
-// first of which (k0 = 0) clears the flag.
+// first of which (k0 = 0) clears the flag.  With x (kList only), the forward substitution's step
+// of the block rides along: x_k holds r_k, the right-hand side with every earlier column's
+// contribution already subtracted (by the update launches), and becomes y_k = W r_k.
 template <bool kList>
 __global__ void __launch_bounds__(256) chol_diag_kernel(const double *A, int n, int k0_arg,
                                                         const int32_t *__restrict__ cols, double *Winv,
-                                                        int32_t *fail)
+                                                        int32_t *fail, double *x)
 {
     __shared__ double cb[2][4][NB];   // the four columns c of a pivot group (double-buffered)
     __shared__ double rb[2][4][NB];   // the four rows r of V at their pivots
@@ -224,6 +226,18 @@ __global__ void __launch_bounds__(256) chol_diag_kernel(const double *A, int n, 
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) Wtb[(c0 + jj) * NB + lane] = Ts[c0 + jj][lane];
     if (threadIdx.x == 0 && (bad || clears)) *fail = bad ? 1 : 0;
+    if (kList && x) {   // y_k = W r_k: row i = t / 4, columns 16 (t % 4) .. +15 (Ts[j][i] = W(i, j))
+        double *rk = x + k0;
+        if (threadIdx.x < NB) piv[threadIdx.x] = rk[threadIdx.x];   // r_k (the pivots are no longer needed)
+        __syncthreads();
+        const int i = threadIdx.x >> 2, j0 = (threadIdx.x & 3) * 16;
+        double y = 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) y = fma(Ts[j0 + j][i], piv[j0 + j], y);
+        y += __shfl_xor(y, 1, 64);
+        y += __shfl_xor(y, 2, 64);
+        if ((threadIdx.x & 3) == 0) rk[i] = y;
+    }
 }
 
 // C += P Q^T over k = 0..63 for tiles in LDS (rows padded to 65 doubles), 16 x 16 threads,
@@ -344,11 +358,16 @@ __global__ void __launch_bounds__(256) chol_panel_update_kernel(double *A, doubl
 // that order, before subtracting them: the result does not depend on the schedule.  The
 // workgroups of a diagonal target with qj = 0 write their rows of each contributor's panel to L
 // and L^T.
+//
+// The forward substitution rides along: the diagonal targets' workgroups, which form each
+// contributor's panel rows X_a = L_ak anyway, subtract L_ak y_k from their rows r_a of x (y_k was
+// written by this level's diagonal launch; r_a belongs to a higher level and only this task
+// writes it).
 __global__ void __launch_bounds__(256) chol_level_update_kernel(double *A, double *L, double *LT, int n,
                                                                 const double *__restrict__ Winv,
                                                                 const int32_t *__restrict__ tasks,
                                                                 const int32_t *__restrict__ contrib,
-                                                                const int32_t *fail)
+                                                                const int32_t *fail, double *x)
 {
     constexpr int H = NB / 2;
     __shared__ double Ws[NB][NB + 1];
@@ -363,6 +382,7 @@ __global__ void __launch_bounds__(256) chol_level_update_kernel(double *A, doubl
     const int ri = tk.x * NB + H * qi, rj = tk.y * NB + H * qj;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     double c[2][2] = {};
+    double z = 0.0;   // write_l: sum over the contributors of L_ak y_k, row tid / 8 of the quarter
     for (int e = 0; e < tk.w; ++e) {
         const int kb = contrib[tk.z + e], k0 = kb * NB;
         load_tile<NB>(Ws, Winv + (int64_t)kb * NB * NB, NB, NB, 0, 0, NB);
@@ -383,11 +403,15 @@ __global__ void __launch_bounds__(256) chol_level_update_kernel(double *A, doubl
                 if (write_l) L[(int64_t)(ri + i) * n + k0 + j] = ci[a][q];
             }
         __syncthreads();
-        if (write_l)
+        if (write_l) {
             for (int e2 = tid; e2 < H * NB; e2 += 256) {
                 const int i = e2 % H, j = e2 / H;
                 LT[(int64_t)(k0 + j) * n + ri + i] = Xi[i][j];
             }
+            const int i = tid >> 3, j0 = (tid & 7) * 8;   // 8 lanes per row, 8 columns each
+#pragma unroll
+            for (int j = 0; j < 8; ++j) z = fma(Xi[i][j0 + j], x[k0 + j0 + j], z);
+        }
         tile_nt(Xi, same ? Xi : Xj, tx, ty, c);
         __syncthreads();   // the next contributor's tiles overwrite the LDS
     }
@@ -398,25 +422,32 @@ __global__ void __launch_bounds__(256) chol_level_update_kernel(double *A, doubl
             const int i = ty + 16 * a, j = tx + 16 * q;
             if (!diag || H * qj + j <= H * qi + i) A[(int64_t)(ri + i) * n + rj + j] -= c[a][q];
         }
+    if (write_l && x) {   // uniform over the workgroup
+        z += __shfl_xor(z, 1, 64);
+        z += __shfl_xor(z, 2, 64);
+        z += __shfl_xor(z, 4, 64);
+        if ((tid & 7) == 0) x[ri + (tid >> 3)] -= z;
+    }
 }
 
 void launch_cholesky(double *A, double *L, double *LT, int n, double *Winv, const CholPlan &plan, int32_t *fail,
-                     hipStream_t st)
+                     hipStream_t st, double *x)
 {
     if (plan.nd) {
         for (size_t l = 0; l < plan.lcnt.size(); ++l) {
             hipLaunchKernelGGL(chol_diag_kernel<true>, dim3(plan.lcnt[l]), dim3(256), 0, st, A, n, 0,
-                               plan.lcols + plan.lbeg[l], Winv, fail);
+                               plan.lcols + plan.lbeg[l], Winv, fail, x);
             if (plan.tcnt[l] > 0)
                 hipLaunchKernelGGL(chol_level_update_kernel, dim3(4 * plan.tcnt[l]), dim3(256), 0, st, A, L, LT, n,
-                                   Winv, plan.tasks + 4 * (int64_t)plan.tbeg[l], plan.contrib, fail);
+                                   Winv, plan.tasks + 4 * (int64_t)plan.tbeg[l], plan.contrib, fail, x);
         }
         return;
     }
     const int nblk = (n + NB - 1) / NB;
     for (int kb = 0; kb < nblk; ++kb) {
         const int k0 = kb * NB;
-        hipLaunchKernelGGL(chol_diag_kernel<false>, dim3(1), dim3(256), 0, st, A, n, k0, nullptr, Winv, fail);
+        hipLaunchKernelGGL(chol_diag_kernel<false>, dim3(1), dim3(256), 0, st, A, n, k0, nullptr, Winv, fail,
+                           nullptr);
         const int m = plan.rcnt[kb];
         if (m > 0)
             hipLaunchKernelGGL(chol_panel_update_kernel, dim3(4 * (m * (m + 1) / 2)), dim3(256), 0, st, A, L, LT, n, k0, Winv,
@@ -601,7 +632,8 @@ __global__ void __launch_bounds__(64 * LPR) trsv_band_kernel(const double *__res
 }
 
 // One elimination-tree level of the triangular solves in a nested-dissection order, one workgroup
-// per block column k of the level, gathering what the finished levels contribute:
+// per block column k of the level, gathering what the finished levels contribute (the library
+// runs the forward sweep with the factorisation instead, and this kernel for the backward one):
 //   forward   y_k = W_k (r_k - sum_j L_kj y_j)      over the tile columns j < k of block row k,
 //   backward  x_k = W_k^T (y_k - sum_i L_ik^T x_i)  over the tile rows i > k of block column k,
 // with F = L (tile (k, j)) or F = L^T (tile (k, i), rows of L^T) and M = W_k or W_k^T.  The tiles
@@ -653,12 +685,9 @@ __global__ void __launch_bounds__(256) trsv_level_kernel(const double *__restric
 void launch_chol_solve(const double *L, const double *LT, double *Winv, double *x, int n, const CholPlan &plan,
                        const int32_t *fail, hipStream_t st)
 {
-    if (plan.nd) {
+    if (plan.nd) {   // the forward substitution ran with the factorisation (launch_cholesky with x)
         const int nblk = n / NB, nlev = (int)plan.lcnt.size();
-        const int32_t *rbeg = plan.meta, *rcnt = rbeg + nblk, *cbeg = rcnt + nblk, *ccnt = cbeg + nblk;
-        for (int l = 0; l < nlev; ++l)
-            hipLaunchKernelGGL(trsv_level_kernel, dim3(plan.lcnt[l]), dim3(256), 0, st, L, Winv, x, n,
-                               plan.lcols + plan.lbeg[l], plan.cols, cbeg, ccnt, fail);
+        const int32_t *rbeg = plan.meta, *rcnt = rbeg + nblk;
         for (int l = nlev - 1; l >= 0; --l)
             hipLaunchKernelGGL(trsv_level_kernel, dim3(plan.lcnt[l]), dim3(256), 0, st, LT,
                                Winv + (int64_t)nblk * NB * NB, x, n, plan.lcols + plan.lbeg[l], plan.rows, rbeg,

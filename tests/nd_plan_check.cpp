@@ -6,8 +6,9 @@
 // (target tile, contributing column) pair of the factorisation appears in exactly one task of the
 // column's level, contributors ascending; the damped-copy tile list has no duplicate) and then runs
 // the level-scheduled factorisation and triangular solves on the CPU in the order the device
-// launches take (damped copy of the pattern tiles, per level: diagonal blocks, then the update
-// tasks; forward sweeps by ascending level, backward by descending level), with every matrix entry
+// launches take (damped copy of the pattern tiles; per level: diagonal blocks with their forward
+// step y_k = W_k r_k, then the update tasks, whose diagonal targets also subtract L_ak y_k from
+// r_a; backward sweeps by descending level), with every matrix entry
 // outside the pattern set to NaN so that a read outside it shows in the result.
 //
 // stdin (binary, little endian): int32 np, int32 ne, ne x (int32 s, int32 t) pose-variable pairs,
@@ -98,6 +99,9 @@ int main() {
             for (int c = 0; c < 64; ++c) for (int i = 0; i < 64; ++i) {   // W = Lk^-1 by forward substitution
                 double s = (i == c); for (int m = 0; m < i; ++m) s -= Lk[i][m] * Wk[m][c]; Wk[i][c] = s / Lk[i][i]; }
             for (int i = 0; i < 64; ++i) for (int j = 0; j < 64; ++j) { W.at((long)k*4096 + i*64 + j) = Wk[i][j]; W.at((long)(nt + k)*4096 + i*64 + j) = Wk[j][i]; }
+            double y[64];   // forward step with the factorisation: y_k = W_k r_k
+            for (int i = 0; i < 64; ++i) { y[i] = 0; for (int j = 0; j < 64; ++j) y[i] += Wk[i][j] * x.at(k0 + j); }
+            for (int i = 0; i < 64; ++i) x.at(k0 + i) = y[i];
         }
         for (int t = a.tbeg[l]; t < a.tbeg[l] + a.tcnt[l]; ++t) for (int q = 0; q < 4; ++q) {
             int qi = (q >> 1) & 1, qj = q & 1, ta = a.tasks[4*t], tb = a.tasks[4*t+1], cb = a.tasks[4*t+2], cc = a.tasks[4*t+3];
@@ -105,6 +109,7 @@ int main() {
             bool write_l = diag && qj == 0;
             int ri = ta*64 + 32*qi, rj = tb*64 + 32*qj;
             static double acc[32][32]; for (auto &r : acc) for (double &v : r) v = 0;
+            double z[32] = {};
             for (int e = 0; e < cc; ++e) {
                 int kb = a.contrib[cb + e], k0 = kb*64;
                 static double Xi[32][64], Xj[32][64];
@@ -115,9 +120,12 @@ int main() {
                     Xi[i][j] = si; Xj[i][j] = sj;
                     if (write_l) { A.at(L0 + (long)(ri+i)*n + k0 + j) = si; A.at(LT0 + (long)(k0+j)*n + ri + i) = si; }
                 }
+                if (write_l)   // r_a -= L_ak y_k for the quarter's rows
+                    for (int i = 0; i < 32; ++i) for (int j = 0; j < 64; ++j) z[i] += Xi[i][j] * x.at(k0 + j);
                 for (int i = 0; i < 32; ++i) for (int j = 0; j < 32; ++j) { double s = 0; for (int m = 0; m < 64; ++m) s += Xi[i][m] * Xj[j][m]; acc[i][j] += s; }
             }
             for (int i = 0; i < 32; ++i) for (int j = 0; j < 32; ++j) if (!diag || 32*qj + j <= 32*qi + i) A.at((long)(ri+i)*n + rj + j) -= acc[i][j];
+            if (write_l) for (int i = 0; i < 32; ++i) x.at(ri + i) -= z[i];
         }
     }
     // meta as in the runtime
@@ -137,7 +145,7 @@ int main() {
             for (int row = 0; row < 64; ++row) { double u = 0; for (int c = 0; c < 64; ++c) u += W.at(M + ((long)kb*64 + row)*64 + c) * sv[c]; x.at(k0 + row) = u; }
         }
     };
-    for (int l = 0; l < tp.nlev; ++l) trsv(true, l);
+    // the forward sweep ran with the factorisation; the backward sweeps by descending level
     for (int l = tp.nlev - 1; l >= 0; --l) trsv(false, l);
     std::vector<double> out(n0);
     for (int v = 0; v < np; ++v) for (int i = 0; i < 6; ++i) out[6*v+i] = x.at(pos[v] + i);
