@@ -314,10 +314,10 @@ typedef struct {
 } pba_tune_point;
 
 /* Autotuner of the persistent evaluation launch (work-item size and grid): times one evaluation
- * at the current poses and level for every item size in {4096, 8192, 16384, 32768} and grid in
- * {2, 4, 8} x (compute units) workgroups, keeps the fastest for this context (until keyframes or
- * pairs change the plan again) and reports the measured points (points nullable, up to
- * max_points; *n_points nullable).  Results of evaluations do not depend on the choice except in
+ * at the current poses and level for every item size in {2048, 4096, 8192, 16384} (the source
+ * pixels one wave takes at a time) and grid in {2, 4, 8} x (compute units) workgroups, keeps the
+ * fastest for this context (until keyframes or pairs change the plan again) and reports the
+ * measured points (points nullable, up to max_points; *n_points nullable).  Results of evaluations do not depend on the choice except in
  * the summation order of the per-pair sums. */
 pba_status pba_autotune(pba_ctx *ctx, pba_tune_point *points, int32_t max_points, int32_t *n_points);
 

@@ -174,6 +174,13 @@ __device__ __forceinline__ float atan2_coarse(float y, float x)
     return y < 0.f ? -a : a;
 }
 
+// atan(t) for |t| <= 1 by the same quadratic in t^2 (error below 6.1e-4 rad)
+__device__ __forceinline__ float atan_unit(float t)
+{
+    const float s = t * t;
+    return t * fmaf(fmaf(0.07933887839317322f, s, -0.28869009017944336f), s, 0.9953579306602478f);
+}
+
 // atan(t) for small |t| by its Taylor series to t^5 (remainder below t^7 / 7: 2.4e-19 rad at 3e-3,
 // about the largest offset from the nearest ray of a 2048 x 128 spherical image; 1.1e-10 rad at
 // 0.05, the offset of a 64-column image).
@@ -390,6 +397,15 @@ struct WaveQueue {
     T ed[kQ], gxd[kQ], gyd[kQ]; // depth residual and depth-channel image Jacobian
 };
 
+// Per-wave queue of the points that pass phase 1a (the first projection and the depth-interval test),
+// consumed 64 at a time by phase 1b: the pixel, the first projection's table column and row, and the point
+// in the target sensor frame (FP64).
+struct WaveQueueA {
+    int pix[kQ];
+    int kcr[kQ];           // column | row << 16; debug launches: bit 15 = interval test passed, bit 31 = near
+    double X[kQ], Y[kQ], Z[kQ];
+};
+
 // b-only accumulation for the loss adjoint, per lane in FP64: acc[i] += om * e * J_i
 template <typename T>
 __device__ __forceinline__ void accumulate_row_b(double *acc, const T (&J)[6], T e, T om)
@@ -449,6 +465,11 @@ __device__ __forceinline__ float ld_bf16(__amdgpu_buffer_rsrc_t r, int voff, int
 {
     return bf16_to_f32((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
 }
+__device__ __forceinline__ float2 ld_f32x2(__amdgpu_buffer_rsrc_t r, int voff)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
+    return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+}
 __device__ __forceinline__ double2 ld_f64x2(__amdgpu_buffer_rsrc_t r, int voff)
 {
     const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
@@ -485,24 +506,24 @@ __device__ __forceinline__ void load_stencil(V (&t)[12], L ld, int voff, int row
 template <typename T, int NCH, int SM, int TM, int GM, bool DBG, bool ADJ = false, bool ZB = false, bool BF = false>
 __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base, int n_items)
 {
-    __shared__ int s_item;
-    __shared__ double s_red[kBlock / 64][kAcc];
     __shared__ WaveQueue<T> s_q[kBlock / 64];
+    __shared__ WaveQueueA s_qa[kBlock / 64];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index: uniform
     WaveQueue<T> &Q = s_q[wave];
+    WaveQueueA &QA = s_qa[wave];
     typedef typename Lut<T>::type L2;
     const L2 *lut = Lut<T>::ptr(a);
     constexpr bool F32 = std::is_same<T, float>::value;
 
     // The items of a launch form kXcd contiguous queues; workgroups are dispatched round-robin
-    // over the XCDs, so workgroup w drains queue w % kXcd first (items that share target images
-    // stay on one XCD's L2), then helps with the others.  Every workgroup leaves once all
-    // queues are exhausted.
-    int q = 0;   // thread 0: queues tried so far
+    // over the XCDs, so the waves of workgroup w drain queue w % kXcd first (items that share target
+    // images stay on one XCD's L2), then help with the others.  Each wave takes items on its own
+    // and leaves once all queues are exhausted: no wave waits for another.
+    int q = 0;   // lane 0: queues tried so far
     for (;;) {
-        if (tid == 0) {
-            int got = -1;
+        int got = -1;
+        if (lane == 0) {
             while (q < kXcd) {
                 const int x = ((int)blockIdx.x + q) % kXcd;
                 const int lo = (int)((int64_t)n_items * x / kXcd), hi = (int)((int64_t)n_items * (x + 1) / kXcd);
@@ -510,11 +531,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 if (v < hi - lo) { got = lo + v; break; }
                 ++q;
             }
-            s_item = got;
         }
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(got);   // lane 0's
         if (it < 0) break;
         const int item = a.item_map ? a.item_map[item_base + it] : item_base + it;
         const int pair = __builtin_amdgcn_readfirstlane(a.item_pair[item]);
@@ -566,6 +584,11 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                      : (BF ? plane_rsrc(uni_ptr(a.att1h + ks.off), (uint32_t)npx * att_e)
                            : plane_rsrc(uni_ptr(a.att1 + ks.off), (uint32_t)npx * att_e));
         const __amdgpu_buffer_rsrc_t r_lut = plane_rsrc(uni_ptr(a.lut64), (uint32_t)a.lut64_bytes);
+        const __amdgpu_buffer_rsrc_t r_gate = plane_rsrc(uni_ptr(a.gate + kt.off), tnpx * 8u);
+        // the depth-interval test may run: the target's first projection is within half a pixel (and not in
+        // the z-buffer fill pass, which needs every point inside the image)
+        const bool early = uni(st.early) != 0 && !(ZB && a.zpass);
+        const bool el45 = uni(st.el45) != 0;
         const __amdgpu_buffer_rsrc_t r_tatt =
             NCH == 5 ? (BF ? plane_rsrc(uni_ptr(a.att4h + kt.off), tnpx * 8u) : plane_rsrc(uni_ptr(a.att4 + kt.off), tnpx * 16u))
                      : (BF ? plane_rsrc(uni_ptr(a.att1h + kt.off), tnpx * 2u) : plane_rsrc(uni_ptr(a.att1 + kt.off), tnpx * 4u));
@@ -578,13 +601,15 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         for (int k = 0; k < (F32 ? 1 : ACC_F); ++k) acc64[k] = 0.0;
         int n_eval = 0, n_valid = 0;   // per lane
         int n_band = 0;                // per wave
-        int head = 0, tail = 0;   // wave-uniform queue positions
+        int headA = 0, tailA = 0, head = 0, tail = 0;   // wave-uniform queue positions (A, and phase 2's)
 
         // phase 2: residuals, weights, Jacobian rows and accumulation of queue slot `slot`
         auto consume = [&](int slot, bool active) {
+          // 27 H / b sums; slots 27..31 only pad the butterfly, whose lanes keep each slot apart, so any value
+          // will do there.  rho is summed per lane in FP64 (finite differences of F resolve small changes).
           T v[32];
 #pragma unroll
-          for (int k = 0; k < 32; ++k) v[k] = T(0);
+          for (int k = 0; k < 32; ++k) v[k] = k < ACC_F ? T(0) : any_value<T>();
           if (active) {
             const int pix = Q.pix[slot];
             const int cellv = Q.cell[slot];
@@ -592,7 +617,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             const T al = Q.al[slot], be = Q.be[slot];
             const T px = Q.px[slot], py = Q.py[slot], pz = Q.pz[slot];
             const T ed = Q.ed[slot], Gxd = Q.gxd[slot], Gyd = Q.gyd[slot];
-            const int corner = (y0 - 1) * Wt + (x0 - 1);
+            const int corner = (int)__umul24((uint32_t)(y0 - 1), (uint32_t)Wt) + (x0 - 1);
             const T w00 = (T(1) - al) * (T(1) - be), w01 = al * (T(1) - be);
             const T w10 = (T(1) - al) * be, w11 = al * be;
             T Is, ns0 = T(0), ns1 = T(0), ns2 = T(0);
@@ -683,10 +708,17 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             }
             const T y2x = T(2) * (px + cc[0]), y2y = T(2) * (py + cc[1]), y2z = T(2) * (pz + cc[2]);
             T J[6];
+            // a = -(Gx Pi0 + Gy Pi1), leaving out the projective Jacobian's structural zeros (spherical:
+            // d u' / d z = 0; pinhole: d u' / d y = d v' / d x = 0)
+            auto proj_a = [&](T Gx, T Gy, T &a0, T &a1, T &a2) {
+                if (TM == MODEL_PINHOLE) { a0 = -(Gx * P00); a1 = -(Gy * P11); a2 = -(Gx * P02 + Gy * P12); }
+                else { a0 = -(Gx * P00 + Gy * P10); a1 = -(Gx * P01 + Gy * P11); a2 = -(Gy * P12); }
+            };
             // point-space derivatives a^c = d e^c / d p_bar
-            const T ag0 = -(Gxg * P00 + Gyg * P10), ag1 = -(Gxg * P01 + Gyg * P11), ag2 = -(Gxg * P02 + Gyg * P12);
-            const T ad0 = zx - (Gxd * P00 + Gyd * P10), ad1 = zy - (Gxd * P01 + Gyd * P11);
-            const T ad2 = zz - (Gxd * P02 + Gyd * P12);
+            T ag0, ag1, ag2, ad0, ad1, ad2;
+            proj_a(Gxg, Gyg, ag0, ag1, ag2);
+            proj_a(Gxd, Gyd, ad0, ad1, ad2);
+            ad0 += zx; ad1 += zy; ad2 += zz;
             // intensity: a = -(Gx Pi0 + Gy Pi1)
             row_from_a(J, ag0, ag1, ag2, y2x, y2y, y2z);
             if (ADJ) accumulate_row_b(acc_b, J, eg, w * om_g);
@@ -699,8 +731,9 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 // normal rows: image term plus the rotation-only term 2 (e_k x n')
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    row_from_a(J, -(Gxn[k] * P00 + Gyn[k] * P10), -(Gxn[k] * P01 + Gyn[k] * P11),
-                               -(Gxn[k] * P02 + Gyn[k] * P12), y2x, y2y, y2z);
+                    T an0, an1, an2;
+                    proj_a(Gxn[k], Gyn[k], an0, an1, an2);
+                    row_from_a(J, an0, an1, an2, y2x, y2y, y2z);
                     if (k == 0) { J[4] -= T(2) * nr[2]; J[5] += T(2) * nr[1]; }
                     if (k == 1) { J[3] += T(2) * nr[2]; J[5] -= T(2) * nr[0]; }
                     if (k == 2) { J[3] -= T(2) * nr[1]; J[4] += T(2) * nr[0]; }
@@ -760,15 +793,14 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
           if (!ADJ && F32) acc_hb += (double)wave_reduce_scatter(v, lane);
         };
 
-        for (int cbase = px0 + wave * 64; cbase < px1; cbase += kBlock) {
-            // ---------------- phase 1: projection, cell, validity and occlusion, depth channel
+        // phase 1a: every source pixel of a chunk -- unprojection, transform, a first projection good to a
+        // fraction of a pixel, and the depth-interval test; survivors are appended to queue A in pixel order
+        auto stage_a = [&](int cbase) {
             const int pix = cbase + lane;
-            bool valid = false;
-            // queued only where valid: elsewhere any value will do (no instructions to clear them)
-            int x0 = any_value<int>(), y0 = any_value<int>();
-            T al = any_value<T>(), be = any_value<T>(), px = any_value<T>(), py = any_value<T>();
-            T pz = any_value<T>(), edv = any_value<T>(), gxd = any_value<T>(), gyd = any_value<T>();
-            bool in_band = false;
+            bool keep = false;
+            // queued only where kept: elsewhere any value will do (no instructions to clear them)
+            int kcr = any_value<int>();
+            double X = any_value<double>(), Y = any_value<double>(), Z = any_value<double>();
             const float Ds_l = ld_f32(r_sdep, pix * 4, 0);
             const float Ds = pix < px1 ? Ds_l : 0.f;
             if (DBG && pix < px1) a.dbg_status[pix] = 1;
@@ -791,106 +823,186 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                     if (col < 0) { row -= 1; col += Ws; }
                 }
                 // Geometry in FP64 in both paths (on this chip FP64 vector arithmetic issues at the FP32
-                // rate): unprojection q = d * ray(u) from the FP64 ray table, p_bar = R q + t, the
-                // projected coordinates and the depth/range cue.  Cells, masks and the large-magnitude
-                // part of the depth residual then carry no FP32 rounding.
+                // rate): unprojection q = d * ray(u) from the FP64 ray table, p_bar = R q + t, and the
+                // predicted depth/range.  Cells, masks and the large-magnitude part of the depth residual then
+                // carry no FP32 rounding.
                 const double2 lcd = ld_f64x2(r_lut, (s_lcol + col) * 16), lrd = ld_f64x2(r_lut, (s_lrow + row) * 16);
                 const double dd = (double)Ds;
                 double q0, q1, q2;
                 if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
                 else { q0 = dd * lcd.x; q1 = dd * lrd.x; q2 = dd; }
-                const double X = fma(Rd[0], q0, fma(Rd[1], q1, fma(Rd[2], q2, td[0])));
-                const double Y = fma(Rd[3], q0, fma(Rd[4], q1, fma(Rd[5], q2, td[1])));
-                const double Z = fma(Rd[6], q0, fma(Rd[7], q1, fma(Rd[8], q2, td[2])));
-                px = (T)X; py = (T)Y; pz = (T)Z;
-                // projection (Sec. III) and predicted depth/range cue
-                double u, v, zeta;
-                bool ok, near = true;
+                X = fma(Rd[0], q0, fma(Rd[1], q1, fma(Rd[2], q2, td[0])));
+                Y = fma(Rd[3], q0, fma(Rd[4], q1, fma(Rd[5], q2, td[1])));
+                Z = fma(Rd[6], q0, fma(Rd[7], q1, fma(Rd[8], q2, td[2])));
+                // first projection (Sec. III): pinhole exact; spherical a coarse FP32 estimate (within 0.49 px,
+                // checked per sensor on the host), which names the table rays of phase 1b's exact offsets
+                bool ok, near;
+                float zf, ua, va;   // predicted depth/range in FP32 (within 2e-7 relative) for the interval test
                 if (TM == MODEL_PINHOLE) {
                     ok = Z >= st_dmin;
+                    const double iz = rcp_f64(Z);
+                    const double u = fma(st_fx * X, iz, st_cx), v = fma(st_fy * Y, iz, st_cy);
+                    near = u >= 1.0 && u < (double)(Wt - 2) && v >= 1.0 && v < (double)(Ht - 2);
+                    ua = (float)u; va = (float)v;
+                    zf = (float)Z;
+                } else {
+                    const double r2 = fma(X, X, Y * Y), n2 = fma(Z, Z, r2);
+                    ok = (r2 > 0.0) && (n2 >= st_dmin * st_dmin);
+                    const float n2f = (float)n2, r2f = (float)r2, irho = __builtin_amdgcn_rsqf(r2f);
+                    zf = n2f * __builtin_amdgcn_rsqf(n2f);
+                    ua = (float)st_fx * atan2_coarse((float)Y, (float)X) + (float)st_cx;
+                    if (el45) {
+                        // every elevation the image can reach is below 45 degrees: atan of tan(el) = Z / rho
+                        // by the coarse quadratic, no division; beyond 45 degrees the point is outside
+                        const float te = (float)Z * irho, tc = fminf(fmaxf(te, -1.f), 1.f);
+                        va = fabsf(te) <= 1.f ? fmaf((float)st_fy, atan_unit(tc), (float)st_cy) : -2.f;
+                    } else {
+                        va = (float)st_fy * atan2_coarse((float)Z, r2f * irho) + (float)st_cy;
+                    }
+                    // far outside the image the estimate decides alone (it is good to a fraction of a pixel);
+                    // inside, the nearest table ray is within 1 px, so the offset angle is small
+                    near = ua > -1.f && ua < (float)Wt && va > -1.f && va < (float)Ht;
+                }
+                const int kc = (int)fminf(fmaxf(rintf(ua), 0.f), (float)(Wt - 1));
+                const int kr = (int)fminf(fmaxf(rintf(va), 0.f), (float)(Ht - 1));
+                // The exact cell is one of {kc - 1, kc} x {kr - 1, kr} (|u' - ua| < 0.5) or outside the cells
+                // whose stencil lies inside the image.  The plane holds the range of predicted depths for which
+                // one of them can pass the occlusion gate, widened beyond the FP32 error of zf; outside it the gate
+                // fails in every one, so a rejected point changes nothing.
+                bool pass = true;
+                if (early) {
+                    const float2 g = ld_f32x2(r_gate, (int)(__umul24((uint32_t)kr, (uint32_t)Wt) + kc) * 8);
+                    pass = zf >= g.x && zf <= g.y;
+                }
+                // debug launches take every projected point through phase 1b (complete per-pixel statuses) and
+                // apply the interval test's verdict at the end
+                keep = DBG ? ok : (ok && near && pass);
+                kcr = kc | (kr << 16);
+                if (DBG) kcr |= (pass ? 0x8000 : 0) | (near ? (int)0x80000000 : 0);
+            }
+            const uint64_t mask = __ballot(keep);
+            if (keep) {
+                const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                const int slot = (tailA + rank) & (kQ - 1);
+                QA.pix[slot] = pix;
+                QA.kcr[slot] = kcr;
+                QA.X[slot] = X; QA.Y[slot] = Y; QA.Z[slot] = Z;
+            }
+            tailA += __popcll(mask);
+            __builtin_amdgcn_wave_barrier();
+        };
+
+        // The 12-tap occlusion gate of cell (x0, y0) inside the image: every tap valid and on the surface the
+        // point lands on.  Invalid target depths hold a large negative sentinel, so one bound on the largest
+        // |D - zeta| also rejects them.  Tested in FP64 in both paths (the taps are exact in FP64): a mask
+        // decision does not depend on the evaluation precision.
+        auto gate_at = [&](float (&tD)[12], int x0, int y0, double zeta) {
+            load_stencil<float, 4>(tD, [&](int vo, int so) { return ld_f32(r_tdep, vo, so); },
+                                   ((int)__umul24((uint32_t)(y0 - 1), (uint32_t)Wt) + (x0 - 1)) * 4, Wt * 4);
+            float dmin = tD[0], dmax = tD[0];
+#pragma unroll
+            for (int k = 1; k < 12; ++k) { dmin = fminf(dmin, tD[k]); dmax = fmaxf(dmax, tD[k]); }
+            return fmax((double)dmax - zeta, zeta - (double)dmin) <= taud_gate;
+        };
+
+        // phase 1b: 64 queued points at a time -- the exact projection and cell, the stencil inside the image,
+        // the occlusion gate and the depth channel; valid correspondences are appended to phase 2's queue
+        auto stage_b = [&](int slot_a, bool active) {
+            bool valid = false, band = false;
+            int pix = any_value<int>(), x0 = any_value<int>(), y0 = any_value<int>();
+            T al = any_value<T>(), be = any_value<T>(), px = any_value<T>(), py = any_value<T>();
+            T pz = any_value<T>(), edv = any_value<T>(), gxd = any_value<T>(), gyd = any_value<T>();
+            if (active) {
+                pix = QA.pix[slot_a];
+                const int kcr = QA.kcr[slot_a];
+                const double X = QA.X[slot_a], Y = QA.Y[slot_a], Z = QA.Z[slot_a];
+                px = (T)X; py = (T)Y; pz = (T)Z;
+                const int kc = kcr & 0x7fff, kr = (kcr >> 16) & 0x7fff;
+                const bool near = !DBG || TM == MODEL_PINHOLE || kcr < 0;
+                const bool pass = !DBG || (kcr & 0x8000) != 0;
+                double u, v, zeta;
+                if (TM == MODEL_PINHOLE) {
                     const double iz = rcp_f64(Z);
                     u = fma(st_fx * X, iz, st_cx);
                     v = fma(st_fy * Y, iz, st_cy);
                     zeta = Z;
                 } else {
+                    // exact angular offset from the table ray the first projection named:
+                    // az - az_k = atan2(Y cos az_k - X sin az_k, X cos az_k + Y sin az_k), a small angle, and
+                    // likewise for the elevation
                     const double r2 = fma(X, X, Y * Y), n2 = fma(Z, Z, r2);
-                    ok = (r2 > 0.0) && (n2 >= st_dmin * st_dmin);
-                    {   // the same FP64 arithmetic in both paths: cells and masks do not depend on the path
-                        zeta = sqrt_f64(n2);
-                        const double rho = sqrt_f64(r2);
-                        // nearest column / row from a coarse FP32 estimate, then the exact angular offset
-                        // from that ray of the FP64 table: az - az_k = atan2(Y cos az_k - X sin az_k,
-                        // X cos az_k + Y sin az_k), a small angle, and likewise for the elevation
-                        const float ua = (float)st_fx * atan2_coarse((float)Y, (float)X) + (float)st_cx;
-                        const float va = (float)st_fy * atan2_coarse((float)Z, (float)rho) + (float)st_cy;
-                        // far outside the image the estimate decides alone (it is good to a fraction of a
-                        // pixel); inside, the nearest table ray is within 1 px, so the offset angle is small
-                        near = ua > -1.f && ua < (float)Wt && va > -1.f && va < (float)Ht;
-                        const int kc = min(max((int)rintf(ua), 0), Wt - 1), kr = min(max((int)rintf(va), 0), Ht - 1);
-                        const double2 cs = ld_f64x2(r_lut, (t_lcol + kc) * 16), rs = ld_f64x2(r_lut, (t_lrow + kr) * 16);
-                        const double tu = fma(Y, cs.x, -X * cs.y) * rcp_f64(fma(X, cs.x, Y * cs.y));
-                        const double tv = fma(Z, rs.x, -rho * rs.y) * rcp_f64(fma(rho, rs.x, Z * rs.y));
-                        u = fma(st_fx, atan_small(tu), (double)kc);
-                        v = fma(st_fy, atan_small(tv), (double)kr);
-                    }
+                    zeta = sqrt_f64(n2);
+                    const double rho = sqrt_f64(r2);
+                    const double2 cs = ld_f64x2(r_lut, (t_lcol + kc) * 16), rs = ld_f64x2(r_lut, (t_lrow + kr) * 16);
+                    const double tu = fma(Y, cs.x, -X * cs.y) * rcp_f64(fma(X, cs.x, Y * cs.y));
+                    const double tv = fma(Z, rs.x, -rho * rs.y) * rcp_f64(fma(rho, rs.x, Z * rs.y));
+                    u = fma(st_fx, atan_small(tu), (double)kc);
+                    v = fma(st_fy, atan_small(tv), (double)kr);
+                }
+                if (DBG) { a.dbg_status[pix] = 3; a.dbg_uv[pix] = make_float2((float)u, (float)v); }
+                // the integer cell floor(u'), and the stencil inside the image
+                bool ok = near && u >= 1.0 && u < (double)(Wt - 2) && v >= 1.0 && v < (double)(Ht - 2);
+                double du = 0.0, dv = 0.0;
+                if (ok) {
+                    x0 = (int)u; y0 = (int)v;
+                    du = u - (double)x0; dv = v - (double)y0;
+                    al = (T)du; be = (T)dv;
+                }
+                if (ZB && ok && a.zpass) {
+                    // z-buffer pass: keep the nearest predicted depth per target cell (depths are positive, so
+                    // their FP32 bit patterns order like the values); nothing queued
+                    atomicMin(zb + y0 * Wt + x0, __float_as_uint((float)zeta));
+                    ok = false;
                 }
                 if (ok) {
-                    if (DBG) { a.dbg_status[pix] = 3; a.dbg_uv[pix] = make_float2((float)u, (float)v); }
-                    // the integer cell floor(u'), and the stencil inside the image
-                    ok = near && u >= 1.0 && u < (double)(Wt - 2) && v >= 1.0 && v < (double)(Ht - 2);
-                    if (ok) {
-                        x0 = (int)u; y0 = (int)v;
-                        const double du = u - (double)x0, dv = v - (double)y0;
-                        al = (T)du; be = (T)dv;
-                        // the cell of a point this close to a boundary can differ between exact
-                        // arithmetic and any rounding of it: counted (per wave, on the scalar unit)
-                        in_band = fmax(fabs(du - 0.5), fabs(dv - 0.5)) > 0.5 - kBandPx;
-                    }
-                    if (ZB && ok && a.zpass) {
-                        // z-buffer pass: keep the nearest predicted depth per target cell (depths are
-                        // positive, so their FP32 bit patterns order like the values); nothing queued
-                        atomicMin(zb + y0 * Wt + x0, __float_as_uint((float)zeta));
-                        ok = false;
-                    }
-                    if (ok) {
-                        if (DBG) { a.dbg_status[pix] = 4; a.dbg_cell[pix] = make_int2(x0, y0); }
-                        // the 12-tap depth stencil: validity and occlusion suppression -- every tap
-                        // valid and on the surface the point lands on
-                        float tD[12];
-                        load_stencil<float, 4>(tD, [&](int vo, int so) { return ld_f32(r_tdep, vo, so); },
-                                               ((y0 - 1) * Wt + (x0 - 1)) * 4, Wt * 4);
-                        // invalid target depths hold a large negative sentinel, so one bound on the
-                        // largest |D - zeta| also rejects them.  The bound is tested in FP64 in both
-                        // paths (the taps are exact in FP64): a mask decision then does not depend on
-                        // the evaluation precision, and the FP32 path keeps the FP64 path's points.
-                        float dmin = tD[0], dmax = tD[0];
-#pragma unroll
-                        for (int k = 1; k < 12; ++k) { dmin = fminf(dmin, tD[k]); dmax = fmaxf(dmax, tD[k]); }
-                        bool vis = fmax((double)dmax - zeta, zeta - (double)dmin) <= taud_gate;
-                        // z-buffer variant: also no more than tau behind the nearest of the pair's own
-                        // points in this cell (both depths as FP32, compared in FP64)
-                        if (ZB && vis)
-                            vis = (double)(float)zeta - (double)__uint_as_float(zb[y0 * Wt + x0]) <= taud_gate;
-                        if (vis) {
-                            const T w00 = (T(1) - al) * (T(1) - be), w01 = al * (T(1) - be);
-                            const T w10 = (T(1) - al) * be, w11 = al * be;
-                            // e_d = zeta - D(u') taken relative to the tap at (x0, y0): the taps lie within
-                            // tau of zeta, so their differences are exact and the large common part
-                            // cancels in FP64 before anything is rounded to the evaluation precision; the
-                            // image Jacobian only takes differences of taps
-                            const float d0 = tD[1];
-                            const T Vr = w01 * (T)(tD[2] - d0) + w10 * (T)(tD[5] - d0) + w11 * (T)(tD[6] - d0);
-                            sample_grad<T, GM>((T)tD[0], (T)tD[1], (T)tD[2], (T)tD[3], (T)tD[4], (T)tD[5], (T)tD[6],
-                                               (T)tD[7], (T)tD[8], (T)tD[9], (T)tD[10], (T)tD[11], w00, w01, w10, w11,
-                                               al, be, gxd, gyd);
-                            edv = (T)(zeta - (double)d0) - Vr;
-                            valid = true;
+                    if (DBG) { a.dbg_status[pix] = 4; a.dbg_cell[pix] = make_int2(x0, y0); }
+                    float tD[12];
+                    const bool gate = gate_at(tD, x0, y0, zeta);
+                    // boundary band: the coordinate is within kBandPx of a cell boundary, where floor(u') can
+                    // differ between exact arithmetic and any rounding of it, and the point passes the gate in
+                    // its cell or in a cell across that boundary (otherwise no rounding changes its outcome)
+                    const bool bu = fabs(du - 0.5) > 0.5 - kBandPx, bv = fabs(dv - 0.5) > 0.5 - kBandPx;
+                    band = (bu || bv) && pass && (ZB ? !a.zpass : true);
+                    // (rare: a wave-uniform branch, so the common path carries none of it)
+                    if (__builtin_expect(__ballot(band && !gate) != 0, 0)) {
+                        if (band && !gate) {
+                            bool other = false;
+                            const int su = du < 0.5 ? -1 : 1, sv = dv < 0.5 ? -1 : 1;
+                            for (int k = 1; k < 4; ++k) {
+                                const int cx = x0 + ((k & 1) ? su : 0), cy = y0 + ((k & 2) ? sv : 0);
+                                if (((k & 1) && !bu) || ((k & 2) && !bv)) continue;
+                                if (cx < 1 || cx > Wt - 3 || cy < 1 || cy > Ht - 3) continue;
+                                float tA[12];
+                                other = other || gate_at(tA, cx, cy, zeta);
+                            }
+                            band = other;
                         }
+                    }
+                    bool vis = gate && pass;
+                    // z-buffer variant: also no more than tau behind the nearest of the pair's own points in this
+                    // cell (both depths as FP32, compared in FP64)
+                    if (ZB && vis)
+                        vis = (double)(float)zeta - (double)__uint_as_float(zb[y0 * Wt + x0]) <= taud_gate;
+                    if (vis) {
+                        const T w00 = (T(1) - al) * (T(1) - be), w01 = al * (T(1) - be);
+                        const T w10 = (T(1) - al) * be, w11 = al * be;
+                        // e_d = zeta - D(u') taken relative to the tap at (x0, y0): the taps lie within tau of
+                        // zeta, so their differences are exact and the large common part cancels in FP64 before
+                        // anything is rounded to the evaluation precision; the image Jacobian only takes
+                        // differences of taps
+                        const float d0 = tD[1];
+                        const T Vr = w01 * (T)(tD[2] - d0) + w10 * (T)(tD[5] - d0) + w11 * (T)(tD[6] - d0);
+                        sample_grad<T, GM>((T)tD[0], (T)tD[1], (T)tD[2], (T)tD[3], (T)tD[4], (T)tD[5], (T)tD[6],
+                                           (T)tD[7], (T)tD[8], (T)tD[9], (T)tD[10], (T)tD[11], w00, w01, w10, w11,
+                                           al, be, gxd, gyd);
+                        edv = (T)(zeta - (double)d0) - Vr;
+                        valid = true;
                     }
                 }
             }
-            n_band += __popcll(__ballot(in_band));
-            // append the valid lanes to the wave's queue in lane (= pixel) order
+            n_band += __popcll(__ballot(band));
+            // append the valid lanes to phase 2's queue in lane (= pixel) order
             const uint64_t mask = __ballot(valid);
             if (valid) {
                 const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -904,17 +1016,41 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             }
             tail += __popcll(mask);
             __builtin_amdgcn_wave_barrier();
-            // ---------------- phase 2: drain full waves of queued correspondences
+        };
+
+        // The wave's chunks go through phase 1a; each later stage takes 64 queued entries at a time (every lane
+        // busy), and after the last chunk the partial remainders (inactive lanes join the butterfly with
+        // zeros).  Queue occupancy stays below 128: at most 63 wait before a stage appends at most 64.
+        for (int cbase = px0; cbase < px1; cbase += 64) {
+            stage_a(cbase);
+            if (tailA - headA >= 64) {
+                stage_b((headA + lane) & (kQ - 1), true);
+                headA += 64;
+                __builtin_amdgcn_wave_barrier();
+            }
             if (tail - head >= 64) {
                 consume((head + lane) & (kQ - 1), true);
                 head += 64;
                 __builtin_amdgcn_wave_barrier();
             }
         }
-        if (tail > head) consume((head + lane) & (kQ - 1), lane < tail - head);   // every lane joins the butterfly
+        if (tailA > headA) {
+            stage_b((headA + lane) & (kQ - 1), lane < tailA - headA);
+            headA = tailA;
+            __builtin_amdgcn_wave_barrier();
+        }
+        while (tail > head) {   // at most two rounds (up to 126 entries)
+            consume((head + lane) & (kQ - 1), lane < tail - head);
+            head += min(tail - head, 64);
+            __builtin_amdgcn_wave_barrier();
+        }
 
-        // workgroup reduction of the accumulators (fixed order: deterministic)
-        if (!ADJ && F32 && (lane & 1) == 0 && (lane >> 1) < ACC_F) s_red[wave][lane >> 1] = acc_hb;
+        // the wave's totals (fixed order: deterministic), value k in lane k, one store per item
+        double outv = 0.0;
+        if (!ADJ && F32) {
+            const double t = __shfl(acc_hb, (2 * lane) & 63, 64);   // lanes 2k, 2k + 1 hold sum k
+            if (lane < ACC_F) outv = t;
+        }
 #pragma unroll
         for (int k = ADJ ? ACC_B : (F32 ? ACC_F : 0); k < ACC_USED; ++k) {
             double v = k < ACC_F ? (ADJ ? acc_b[k - ACC_B] : acc64[F32 ? 0 : k])
@@ -924,20 +1060,65 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                                                                                   : (lane == 0 ? (double)n_band : 0.0))));
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0) s_red[wave][k] = v;
+            if (lane == k) outv = v;
         }
-        if (ADJ && lane < ACC_B) s_red[wave][lane] = 0.0;
-        __syncthreads();
-        if (tid < kAcc) {
-            double v = 0.0;
-            if (tid < ACC_USED) {
-#pragma unroll
-                for (int w = 0; w < kBlock / 64; ++w) v += s_red[w][tid];
-            }
-            static_cast<double *>(a.partials)[(int64_t)item * kAcc + tid] = v;
-        }
-        __syncthreads();
+        if (lane < kAcc) static_cast<double *>(a.partials)[(int64_t)item * kAcc + lane] = outv;
     }
+}
+
+// Depth-interval plane of one keyframe (one thread per texel (kc, kr)): over the cells (x0, y0) in
+// {kc - 1, kc} x {kr - 1, kr} with the stencil inside the image, those whose 12 depth taps span at most
+// 2 tau + 1e-6 m (a wider span fails the gate max(dmax - zeta, zeta - dmin) <= tau for every zeta, FP64
+// rounding included) give lo = min of their largest taps and hi = max of their smallest taps.  A point
+// passing the gate in one of them has dmax - zeta <= tau and zeta - dmin <= tau there, hence, rounding
+// being monotone, lo - zeta <= tau and zeta - hi <= tau.
+__global__ void gate_plane_kernel(const float *__restrict__ dep, float2 *__restrict__ out, int H, int W, double tau)
+{
+    const int kc = blockIdx.x * blockDim.x + threadIdx.x, kr = blockIdx.y;
+    if (kc >= W) return;
+    // the 5 x 5 texels rows kr - 2 .. kr + 2, columns kc - 2 .. kc + 2 hold every tap of the four cells
+    float d[5][5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int y = kr - 2 + i, x = kc - 2 + j;
+            d[i][j] = (y >= 0 && y < H && x >= 0 && x < W) ? dep[(int64_t)y * W + x] : kNoDepth;
+        }
+    float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+    for (int dy = -1; dy <= 0; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 0; ++dx) {
+            const int x0 = kc + dx, y0 = kr + dy;
+            if (x0 < 1 || x0 > W - 3 || y0 < 1 || y0 > H - 3) continue;
+            // in d, row y0 of cell (x0, y0) is index dy + 2 and its column x0 index dx + 2
+            const int r = dy + 2, c = dx + 2;
+            const float t[12] = {d[r][c - 1], d[r][c], d[r][c + 1], d[r][c + 2], d[r + 1][c - 1], d[r + 1][c],
+                                 d[r + 1][c + 1], d[r + 1][c + 2], d[r - 1][c], d[r - 1][c + 1], d[r + 2][c],
+                                 d[r + 2][c + 1]};
+            float mn = t[0], mx = t[0];
+#pragma unroll
+            for (int k = 1; k < 12; ++k) { mn = fminf(mn, t[k]); mx = fmaxf(mx, t[k]); }
+            if ((double)mx - (double)mn > 2.0 * tau + 1e-6) continue;
+            lo = fminf(lo, mx);
+            hi = fmaxf(hi, mn);
+        }
+    // Predicted depths zeta that can pass: zeta >= lo - tau and zeta <= hi + tau (up to FP64 rounding).  The
+    // evaluation tests an FP32 zf within 2e-7 relative of zeta, so the bounds are widened by 1e-6 relative
+    // and 1e-9 m and rounded outwards to FP32.
+    float2 r = make_float2(INFINITY, -INFINITY);
+    if (lo < INFINITY) {
+        const double l = (double)lo - tau, h = (double)hi + tau;
+        r.x = __double2float_rd(l - 1e-6 * fabs(l) - 1e-9);
+        r.y = __double2float_ru(h + 1e-6 * fabs(h) + 1e-9);
+    }
+    out[(int64_t)kr * W + kc] = r;
+}
+
+void launch_gate_plane(const float *dep, float2 *gate, int H, int W, double tau, hipStream_t st)
+{
+    hipLaunchKernelGGL(gate_plane_kernel, dim3((W + 127) / 128, H), dim3(128), 0, st, dep, gate, H, W, tau);
 }
 
 template <int NCH, int SM, int TM>

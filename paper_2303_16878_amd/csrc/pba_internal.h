@@ -59,6 +59,9 @@ __device__ __forceinline__ void att_put1(void *p, int bf, int64_t k, float v)
 struct SensorDev {
     int32_t model, H, W, npx;
     uint32_t magic_w;            // ceil(2^32 / W): row = umulhi(pix, magic_w) for pix < 2^32 / W
+    int32_t early;               // as a target: the evaluation's first projection is within half a pixel of
+                                 // the exact one, so the depth-interval plane may reject points early
+    int32_t el45;                // spherical: every elevation of the image is below 45 degrees
     double fxd, fyd, cxd, cyd, dmind, dmaxd, taud;
     double Ro[9], to[3];         // sensor -> platform
     int64_t lut_col, lut_row;    // element offsets into the ray tables
@@ -92,6 +95,7 @@ struct EvalArgs {
     const uint16_t *att1h;
     const float2 *lut32;         // ray tables, FP32
     const double2 *lut64;        // ray tables, FP64
+    const float2 *gate;          // depth-interval plane (launch_gate_plane), laid out like dep
     const int32_t *item_pair;
     const int32_t *item_px0;
     const int32_t *item_map;     // nullable: item = item_map[position] (per-pair launches)
@@ -207,6 +211,12 @@ NdArrays nd_arrays(const TilePattern &tp, const std::vector<int> &pos);
 // only the backward sweeps); x is ignored in the natural order.
 void launch_cholesky(double *A, double *L, double *LT, int n, double *Winv, const CholPlan &plan, int32_t *fail,
                      hipStream_t st, double *x);
+// Depth-interval plane of one keyframe (H x W depth plane `dep`, occlusion bound tau): texel (kc, kr)
+// holds, over the cells (x0, y0) in {kc - 1, kc} x {kr - 1, kr} whose stencil lies inside the image and
+// whose 12 depth taps span at most 2 tau (+1e-6 m), with lo = the smallest of their largest taps and
+// hi = the largest of their smallest taps, the predicted-depth range [lo - tau, hi + tau] widened by
+// 1e-6 relative and 1e-9 m and rounded outwards to FP32 (+inf / -inf where there is no such cell).
+void launch_gate_plane(const float *dep, float2 *gate, int H, int W, double tau, hipStream_t st);
 // att / att2: the attribute plane of one keyframe (att_get4 / att_get1 layout, `five` cues or one,
 // `bf` BF16 storage)
 void launch_downsample(const float *dep, const void *att, int five, int bf, int H, int W, float *dep2, void *att2,

@@ -49,6 +49,7 @@ struct ImageSet {
     std::vector<KfDev> kfs_h;
     int64_t texels = 0;
     DevBuf sensors_d, kfs_d, dep, att4, att1, lut32, lut64;
+    DevBuf gate;   // depth-interval plane (launch_gate_plane), one float2 per texel
 };
 
 struct pba_ctx {
@@ -70,7 +71,7 @@ struct pba_ctx {
     double lam_carry = -1.0;     // LM damping left by the previous pba_iterate call
 
     // items
-    int items_px = 16384;
+    int items_px = 4096;    // source pixels per work item (one wave's)
     int n_items = 0;
     struct Group { int sm, tm, base, count; };
     std::vector<Group> groups;
@@ -212,7 +213,7 @@ size_t att_bytes(const pba_ctx *c);
 
 void release_images(ImageSet &is)
 {
-    DevBuf *bufs[] = {&is.sensors_d, &is.kfs_d, &is.dep, &is.att4, &is.att1, &is.lut32, &is.lut64};
+    DevBuf *bufs[] = {&is.sensors_d, &is.kfs_d, &is.dep, &is.att4, &is.att1, &is.lut32, &is.lut64, &is.gate};
     for (DevBuf *b : bufs) release(*b);
 }
 
@@ -230,6 +231,28 @@ pba_status sensor_tables(pba_ctx *c, ImageSet &is)
         d.magic_w = (uint32_t)(((1ull << 32) + S.width - 1) / S.width);
         d.fxd = S.fx; d.fyd = S.fy; d.cxd = S.cx; d.cyd = S.cy; d.dmind = S.min_depth; d.dmaxd = S.max_depth;
         d.taud = S.model == PBA_PINHOLE ? c->cfg.occlusion_tau_pinhole : c->cfg.occlusion_tau_spherical;
+        // As a target, the evaluation's first projection must lie within half a pixel of the exact one
+        // for the depth-interval rejection.  Pinhole: the exact FP64 coordinate rounded to FP32.  Spherical:
+        // the coarse FP32 atan2 is within 6.1e-4 rad of each angle (6.09e-4 measured against the FP64
+        // atan2 over 4e6 directions), scaled by |fx| or |fy| pixels per radian, plus the FP32 rounding of
+        // fx a + cx (a few ulps of |cx| + |fx| pi).  The azimuth wraps at a = +-pi, i.e. at u' = cx -+ |fx| pi,
+        // where the estimate may be a whole turn off; a wrap at least half a pixel outside the cells
+        // [1, W - 3] leaves every point that can be valid within reach.
+        d.early = 1;
+        if (S.model == PBA_SPHERICAL) {
+            const double pi = 3.14159265358979323846, afx = std::fabs(S.fx), afy = std::fabs(S.fy);
+            const double eu = afx * 6.1e-4 + 4.0 * std::ldexp(std::fabs(S.cx) + afx * pi, -24) + 1e-6;
+            const double ev = afy * 6.1e-4 + 4.0 * std::ldexp(std::fabs(S.cy) + afy * pi, -24) + 1e-6;
+            auto off_cells = [&](double w) { return w <= 0.5 || w >= S.width - 1.5; };
+            d.early = eu < 0.49 && ev < 0.49 && off_cells(S.cx - afx * pi) && off_cells(S.cx + afx * pi);
+        }
+        // the division-free coarse elevation: every row the image can reach (v' in (-1, H)) is below 45
+        // degrees, so a point at 45 degrees or more is outside
+        d.el45 = 0;
+        if (S.model == PBA_SPHERICAL) {
+            const double e0 = std::fabs((-1.0 - S.cy) / S.fy), e1 = std::fabs((S.height - S.cy) / S.fy);
+            d.el45 = std::max(e0, e1) < 0.76;   // 43.5 degrees
+        }
         for (int k = 0; k < 9; ++k) d.Ro[k] = S.offset[k];
         for (int k = 0; k < 3; ++k) d.to[k] = S.offset[9 + k];
         d.lut_col = (int64_t)l32.size();
@@ -275,8 +298,18 @@ pba_status image_layout(pba_ctx *c, ImageSet &is, const std::vector<int32_t> &se
     pba_status s;
     if ((s = upload(c, is.kfs_d, is.kfs_h.data(), is.kfs_h.size() * sizeof(KfDev)))) return s;
     if ((s = ensure(c, is.dep, off * sizeof(float)))) return s;
+    if ((s = ensure(c, is.gate, off * sizeof(float2)))) return s;
     if (c->cfg.channels == 5) return ensure(c, is.att4, off * att_bytes(c));
     return ensure(c, is.att1, off * att_bytes(c));
+}
+
+// The depth-interval plane of every keyframe of a level, from its depth plane (enqueued on the context
+// stream; rebuilt whenever the depth plane is written).
+void build_gate(pba_ctx *c, ImageSet &is)
+{
+    for (const KfDev &f : is.kfs_h)
+        launch_gate_plane(P_<float>(is.dep) + f.off, P_<float2>(is.gate) + f.off, f.H, f.W,
+                          is.sensors_dev_h[f.sensor].taud, c->stream);
 }
 
 // Tiles (64 x 64) of the Cholesky factor of the 6 NP x 6 NP system that can be nonzero: those
@@ -523,6 +556,7 @@ EvalArgs make_args(pba_ctx *c)
     a.lut32 = P_<float2>(c->L().lut32);
     a.lut64 = P_<double2>(c->L().lut64);
     a.lut64_bytes = (int32_t)c->L().lut64.bytes;
+    a.gate = P_<float2>(c->L().gate);
     a.item_pair = P_<int32_t>(c->item_pair);
     a.item_px0 = P_<int32_t>(c->item_px0);
     a.items_px = c->items_px;
@@ -889,6 +923,7 @@ pba_status pba_load_keyframes(pba_ctx *c, int32_t n, const int32_t *sensor_id, c
                            c->cfg.storage_bf16, npx, S.min_depth, S.max_depth);
         if (!on_device) HIP_OK(hipStreamSynchronize(c->stream));   // stage is reused
     }
+    build_gate(c, is);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(c->stream));
     release(stage);
@@ -1436,7 +1471,7 @@ pba_status pba_autotune(pba_ctx *c, pba_tune_point *points, int32_t max_points, 
     pba_status s;
     if ((s = check_ready(c))) return s;
     HIP_OK(hipSetDevice(c->cfg.device));
-    const int sizes[4] = {4096, 8192, 16384, 32768};
+    const int sizes[4] = {2048, 4096, 8192, 16384};
     const int mult[3] = {2, 4, 8};
     int best_px = c->items_px, best_grid = c->grid, n = 0;
     double best = 1e300;
@@ -1506,6 +1541,7 @@ pba_status pba_build_pyramid(pba_ctx *c, int32_t n_levels)
                               c->cfg.storage_bf16, a.H, a.W, P_<float>(up.dep) + b.off,
                               static_cast<char *>(att_plane(c, up)) + b.off * att_bytes(c), b.H, b.W, tau, c->stream);
         }
+        build_gate(c, up);
         HIP_OK(hipGetLastError());
     }
     HIP_OK(hipStreamSynchronize(c->stream));

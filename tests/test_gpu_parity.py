@@ -396,25 +396,70 @@ def test_build_pairs_matches_oracle(pba):
         assert ev["n_evaluated"] > 0
 
 
+def _predicted_depth(prob, poses, s, t):
+    """zeta of every source pixel of pair (s, t): range (spherical target) or depth (pinhole) of the
+    source point in the target sensor frame, FP64 (Sec. III, the sensor offsets of the Supplementary)."""
+    ss, st = prob.sensors[prob.kf_sensor[s]], prob.sensors[prob.kf_sensor[t]]
+    q = oracle.unproject_image(ss, prob.depth[s].astype(np.float64))
+    frame = lambda X: (np.asarray(X[:9], np.float64).reshape(3, 3), np.asarray(X[9:12], np.float64))
+    Xk = prob.kf_poses(poses)
+    (Ros, tos), (Rot, tot) = frame(ss["offset"]), frame(st["offset"])
+    (Rs, ts), (Rt, tt) = frame(Xk[s]), frame(Xk[t])
+    p = (((q @ Ros.T + tos) @ Rs.T + ts - tt) @ Rt - tot) @ Rot
+    return np.linalg.norm(p, axis=-1) if st["model"] == 1 else p[..., 2]
+
+
+def _gate_dev(Dt, x0, y0, zeta):
+    """max |D - zeta| over the 12-tap stencil of cells (x0, y0) (invalid depths: a -1e30 sentinel)."""
+    taps = [(0, -1), (0, 0), (0, 1), (0, 2), (1, -1), (1, 0), (1, 1), (1, 2), (-1, 0), (-1, 1), (2, 0), (2, 1)]
+    return np.stack([np.abs(Dt[y0 + dy, x0 + dx] - zeta) for dy, dx in taps], -1).max(-1)
+
+
 @pytest.mark.parametrize("fixture,prec", [("rgbd_small", "F32"), ("lidar_mini", "F32"), ("lidar_mini", "F64"),
                                           ("joint_mini", "F32")])
 def test_boundary_band_counts(fixture, prec, request, pba):
     """The evaluation counts, per pair and in total, the points whose stencil lies inside the target
-    image and whose projected coordinate is within 1e-4 px of a cell boundary; the oracle's FP64
-    projections give the same count (a point at 1e-4 +- 1e-11 px aside, which FP64 rounding could
-    tip, and there are none)."""
+    image, whose projected coordinate is within 1e-4 px of a cell boundary, and which pass the
+    occlusion gate in their cell or in a cell across that boundary (the cells a rounding of u' could
+    pick; a point failing in all of them keeps its outcome under any rounding).  The same count from
+    the oracle's FP64 projections (cells from its u', taps from the target depth image, zeta
+    recomputed here in FP64), with no point at 1e-4 +- 1e-11 px or at tau +- 1e-9 m aside, where
+    rounding could tip a side."""
     prob = request.getfixturevalue(fixture)
     precision = pba.PBA_F64 if prec == "F64" else pba.PBA_F32
     with pba.context_for_problem(prob, precision=precision) as ctx:
         ev = ctx.evaluate(want_pairs=True)
     total = 0
     for k, (s, t) in enumerate(prob.pairs):
-        o = oracle.eval_pair(prob, prob.init_poses, int(s), int(t), pixels=True)
+        s, t = int(s), int(t)
+        o = oracle.eval_pair(prob, prob.init_poses, s, t, pixels=True)
         reached = (o["status"] == 0) | (o["status"] == 4) | (o["status"] == 5)   # passed the stencil test
-        frac = o["uv"][reached] - np.floor(o["uv"][reached])
-        near = np.minimum(frac, 1.0 - frac).min(axis=-1)
-        assert not np.any(np.abs(near - 1e-4) < 1e-11)
-        n = int((near < 1e-4).sum())
+        uv = o["uv"][reached]
+        frac = uv - np.floor(uv)
+        dist = np.minimum(frac, 1.0 - frac)
+        assert not np.any(np.abs(dist - 1e-4) < 1e-11)
+        inb = dist < 1e-4                      # per axis: within the band of a boundary
+        band = inb.any(-1)
+        st = prob.sensors[prob.kf_sensor[t]]
+        Ht, Wt = st["H"], st["W"]
+        Dt = prob.depth[t].astype(np.float64)
+        Dt = np.where(np.isfinite(Dt) & (Dt > 0) & (Dt >= st["min_depth"]) & (Dt <= st["max_depth"]), Dt, -1e30)
+        zeta = _predicted_depth(prob, prob.init_poses, s, t)[reached][band]
+        tau = prob.params["occ_tau_spherical" if st["model"] == 1 else "occ_tau_pinhole"]
+        x0, y0 = np.floor(uv[band, 0]).astype(int), np.floor(uv[band, 1]).astype(int)
+        su = np.where(frac[band, 0] < 0.5, -1, 1)
+        sv = np.where(frac[band, 1] < 0.5, -1, 1)
+        reach = np.zeros(len(x0), bool)
+        for cu in (0, 1):
+            for cv in (0, 1):
+                cx, cy = x0 + cu * su, y0 + cv * sv
+                use = ((cu == 0) | inb[band, 0]) & ((cv == 0) | inb[band, 1])
+                use &= (cx >= 1) & (cx <= Wt - 3) & (cy >= 1) & (cy <= Ht - 3)
+                dev = np.full(len(x0), np.inf)
+                dev[use] = _gate_dev(Dt, cx[use], cy[use], zeta[use])
+                assert not np.any(np.abs(dev - tau) < 1e-9)
+                reach |= dev <= tau
+        n = int(reach.sum())
         assert int(ev["pairs"][k][159]) == n, (k, ev["pairs"][k][159], n)
         total += n
     _log(fixture, prec, "boundary band", total, "of", ev["n_valid"], "valid")
