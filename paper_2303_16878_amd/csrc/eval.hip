@@ -795,38 +795,55 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
 
         // phase 1a: every source pixel of a chunk -- unprojection, transform, a first projection good to a
         // fraction of a pixel, and the depth-interval test; survivors are appended to queue A in pixel order
+        // A chunk's source depth and ray-table entries, loaded one chunk ahead so that phase 1a finds them in
+        // registers (lanes past the item's end read harmless in-buffer values and are discarded)
+        struct ChunkLoads {
+            float d;
+            double2 lc, lr;
+        };
+        auto fetch = [&](int cbase) {
+            int row, col;
+            if (Ws >= 64) {
+                // the chunk's first pixel splits on the scalar unit; its 64 pixels span at most two rows
+                int r0 = (int)__umulhi((uint32_t)cbase, magic);
+                int c0 = cbase - r0 * Ws;
+                if (c0 < 0) { r0 -= 1; c0 += Ws; }   // the reciprocal can only round up
+                col = c0 + lane;
+                const bool next = col >= Ws;
+                row = next ? r0 + 1 : r0;
+                col = next ? col - Ws : col;
+            } else {
+                const int pix = cbase + lane;
+                row = (int)__umulhi((uint32_t)pix, magic);
+                col = pix - row * Ws;
+                if (col < 0) { row -= 1; col += Ws; }
+            }
+            ChunkLoads L;
+            L.d = ld_f32(r_sdep, (cbase + lane) * 4, 0);
+            L.lc = ld_f64x2(r_lut, (s_lcol + col) * 16);
+            L.lr = ld_f64x2(r_lut, (s_lrow + row) * 16);
+            return L;
+        };
+        ChunkLoads cur = fetch(px0);
+
         auto stage_a = [&](int cbase) {
             const int pix = cbase + lane;
             bool keep = false;
             // queued only where kept: elsewhere any value will do (no instructions to clear them)
             int kcr = any_value<int>();
             double X = any_value<double>(), Y = any_value<double>(), Z = any_value<double>();
-            const float Ds_l = ld_f32(r_sdep, pix * 4, 0);
-            const float Ds = pix < px1 ? Ds_l : 0.f;
+            const ChunkLoads L = cur;
+            if (cbase + 64 < px1) cur = fetch(cbase + 64);
+            const float Ds = pix < px1 ? L.d : 0.f;
             if (DBG && pix < px1) a.dbg_status[pix] = 1;
             if (Ds > 0.f) {
                 ++n_eval;
                 if (DBG) a.dbg_status[pix] = 2;
-                int row, col;
-                if (Ws >= 64) {
-                    // the chunk's first pixel splits on the scalar unit; its 64 pixels span at most two rows
-                    int r0 = (int)__umulhi((uint32_t)cbase, magic);
-                    int c0 = cbase - r0 * Ws;
-                    if (c0 < 0) { r0 -= 1; c0 += Ws; }   // the reciprocal can only round up
-                    col = c0 + lane;
-                    const bool next = col >= Ws;
-                    row = next ? r0 + 1 : r0;
-                    col = next ? col - Ws : col;
-                } else {
-                    row = (int)__umulhi((uint32_t)pix, magic);
-                    col = pix - row * Ws;
-                    if (col < 0) { row -= 1; col += Ws; }
-                }
                 // Geometry in FP64 in both paths (on this chip FP64 vector arithmetic issues at the FP32
                 // rate): unprojection q = d * ray(u) from the FP64 ray table, p_bar = R q + t, and the
                 // predicted depth/range.  Cells, masks and the large-magnitude part of the depth residual then
                 // carry no FP32 rounding.
-                const double2 lcd = ld_f64x2(r_lut, (s_lcol + col) * 16), lrd = ld_f64x2(r_lut, (s_lrow + row) * 16);
+                const double2 lcd = L.lc, lrd = L.lr;
                 const double dd = (double)Ds;
                 double q0, q1, q2;
                 if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
