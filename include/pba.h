@@ -314,7 +314,7 @@ typedef struct {
 } pba_tune_point;
 
 /* Autotuner of the persistent evaluation launch (work-item size and grid): times one evaluation
- * at the current poses and level for every item size in {2048, 4096, 8192, 16384} (the source
+ * at the current poses and level for every item size in {512, ..., 16384} (powers of 2; the source
  * pixels one wave takes at a time) and grid in {2, 4, 8} x (compute units) workgroups, keeps the
  * fastest for this context (until keyframes or pairs change the plan again) and reports the
  * measured points (points nullable, up to max_points; *n_points nullable).  Results of evaluations do not depend on the choice except in

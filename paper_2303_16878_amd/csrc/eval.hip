@@ -58,7 +58,7 @@ __global__ void pair_setup_kernel(const double *__restrict__ poses, const int2 *
                                   PairDev *__restrict__ out, uint32_t *counters, int ncounters)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < ncounters) counters[p] = 0u;
+    if (p < ncounters) counters[(int64_t)p * kCtrStride] = 0u;
     if (p >= P) return;
     const int s = pairs[p].x, t = pairs[p].y;
     const SensorDev &ss = sensors[kfs[s].sensor];
@@ -527,8 +527,13 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             while (q < kXcd) {
                 const int x = ((int)blockIdx.x + q) % kXcd;
                 const int lo = (int)((int64_t)n_items * x / kXcd), hi = (int)((int64_t)n_items * (x + 1) / kXcd);
-                const int v = (int)atomicAdd(a.counter + x, 1u);
-                if (v < hi - lo) { got = lo + v; break; }
+                // a plain read first: an exhausted queue costs no atomic (thousands of waves leave at the end)
+                uint32_t *const ctr = a.counter + x * kCtrStride;
+                const uint32_t seen = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (seen < (uint32_t)(hi - lo)) {
+                    const int v = (int)atomicAdd(ctr, 1u);
+                    if (v < hi - lo) { got = lo + v; break; }
+                }
                 ++q;
             }
         }
@@ -587,7 +592,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         const __amdgpu_buffer_rsrc_t r_gate = plane_rsrc(uni_ptr(a.gate + kt.off), tnpx * 8u);
         // the depth-interval test may run: the target's first projection is within half a pixel (and not in
         // the z-buffer fill pass, which needs every point inside the image)
-        const bool early = uni(st.early) != 0 && !(ZB && a.zpass);
+        const bool early = TM == MODEL_SPHERICAL && uni(st.early) != 0 && !(ZB && a.zpass);
         const bool el45 = uni(st.el45) != 0;
         const __amdgpu_buffer_rsrc_t r_tatt =
             NCH == 5 ? (BF ? plane_rsrc(uni_ptr(a.att4h + kt.off), tnpx * 8u) : plane_rsrc(uni_ptr(a.att4 + kt.off), tnpx * 16u))
@@ -795,121 +800,6 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
 
         // phase 1a: every source pixel of a chunk -- unprojection, transform, a first projection good to a
         // fraction of a pixel, and the depth-interval test; survivors are appended to queue A in pixel order
-        // A chunk's source depth and ray-table entries, loaded one chunk ahead so that phase 1a finds them in
-        // registers (lanes past the item's end read harmless in-buffer values and are discarded)
-        struct ChunkLoads {
-            float d;
-            double2 lc, lr;
-        };
-        auto fetch = [&](int cbase) {
-            int row, col;
-            if (Ws >= 64) {
-                // the chunk's first pixel splits on the scalar unit; its 64 pixels span at most two rows
-                int r0 = (int)__umulhi((uint32_t)cbase, magic);
-                int c0 = cbase - r0 * Ws;
-                if (c0 < 0) { r0 -= 1; c0 += Ws; }   // the reciprocal can only round up
-                col = c0 + lane;
-                const bool next = col >= Ws;
-                row = next ? r0 + 1 : r0;
-                col = next ? col - Ws : col;
-            } else {
-                const int pix = cbase + lane;
-                row = (int)__umulhi((uint32_t)pix, magic);
-                col = pix - row * Ws;
-                if (col < 0) { row -= 1; col += Ws; }
-            }
-            ChunkLoads L;
-            L.d = ld_f32(r_sdep, (cbase + lane) * 4, 0);
-            L.lc = ld_f64x2(r_lut, (s_lcol + col) * 16);
-            L.lr = ld_f64x2(r_lut, (s_lrow + row) * 16);
-            return L;
-        };
-        ChunkLoads cur = fetch(px0);
-
-        auto stage_a = [&](int cbase) {
-            const int pix = cbase + lane;
-            bool keep = false;
-            // queued only where kept: elsewhere any value will do (no instructions to clear them)
-            int kcr = any_value<int>();
-            double X = any_value<double>(), Y = any_value<double>(), Z = any_value<double>();
-            const ChunkLoads L = cur;
-            if (cbase + 64 < px1) cur = fetch(cbase + 64);
-            const float Ds = pix < px1 ? L.d : 0.f;
-            if (DBG && pix < px1) a.dbg_status[pix] = 1;
-            if (Ds > 0.f) {
-                ++n_eval;
-                if (DBG) a.dbg_status[pix] = 2;
-                // Geometry in FP64 in both paths (on this chip FP64 vector arithmetic issues at the FP32
-                // rate): unprojection q = d * ray(u) from the FP64 ray table, p_bar = R q + t, and the
-                // predicted depth/range.  Cells, masks and the large-magnitude part of the depth residual then
-                // carry no FP32 rounding.
-                const double2 lcd = L.lc, lrd = L.lr;
-                const double dd = (double)Ds;
-                double q0, q1, q2;
-                if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
-                else { q0 = dd * lcd.x; q1 = dd * lrd.x; q2 = dd; }
-                X = fma(Rd[0], q0, fma(Rd[1], q1, fma(Rd[2], q2, td[0])));
-                Y = fma(Rd[3], q0, fma(Rd[4], q1, fma(Rd[5], q2, td[1])));
-                Z = fma(Rd[6], q0, fma(Rd[7], q1, fma(Rd[8], q2, td[2])));
-                // first projection (Sec. III): pinhole exact; spherical a coarse FP32 estimate (within 0.49 px,
-                // checked per sensor on the host), which names the table rays of phase 1b's exact offsets
-                bool ok, near;
-                float zf, ua, va;   // predicted depth/range in FP32 (within 2e-7 relative) for the interval test
-                if (TM == MODEL_PINHOLE) {
-                    ok = Z >= st_dmin;
-                    const double iz = rcp_f64(Z);
-                    const double u = fma(st_fx * X, iz, st_cx), v = fma(st_fy * Y, iz, st_cy);
-                    near = u >= 1.0 && u < (double)(Wt - 2) && v >= 1.0 && v < (double)(Ht - 2);
-                    ua = (float)u; va = (float)v;
-                    zf = (float)Z;
-                } else {
-                    const double r2 = fma(X, X, Y * Y), n2 = fma(Z, Z, r2);
-                    ok = (r2 > 0.0) && (n2 >= st_dmin * st_dmin);
-                    const float n2f = (float)n2, r2f = (float)r2, irho = __builtin_amdgcn_rsqf(r2f);
-                    zf = n2f * __builtin_amdgcn_rsqf(n2f);
-                    ua = (float)st_fx * atan2_coarse((float)Y, (float)X) + (float)st_cx;
-                    if (el45) {
-                        // every elevation the image can reach is below 45 degrees: atan of tan(el) = Z / rho
-                        // by the coarse quadratic, no division; beyond 45 degrees the point is outside
-                        const float te = (float)Z * irho, tc = fminf(fmaxf(te, -1.f), 1.f);
-                        va = fabsf(te) <= 1.f ? fmaf((float)st_fy, atan_unit(tc), (float)st_cy) : -2.f;
-                    } else {
-                        va = (float)st_fy * atan2_coarse((float)Z, r2f * irho) + (float)st_cy;
-                    }
-                    // far outside the image the estimate decides alone (it is good to a fraction of a pixel);
-                    // inside, the nearest table ray is within 1 px, so the offset angle is small
-                    near = ua > -1.f && ua < (float)Wt && va > -1.f && va < (float)Ht;
-                }
-                const int kc = (int)fminf(fmaxf(rintf(ua), 0.f), (float)(Wt - 1));
-                const int kr = (int)fminf(fmaxf(rintf(va), 0.f), (float)(Ht - 1));
-                // The exact cell is one of {kc - 1, kc} x {kr - 1, kr} (|u' - ua| < 0.5) or outside the cells
-                // whose stencil lies inside the image.  The plane holds the range of predicted depths for which
-                // one of them can pass the occlusion gate, widened beyond the FP32 error of zf; outside it the gate
-                // fails in every one, so a rejected point changes nothing.
-                bool pass = true;
-                if (early) {
-                    const float2 g = ld_f32x2(r_gate, (int)(__umul24((uint32_t)kr, (uint32_t)Wt) + kc) * 8);
-                    pass = zf >= g.x && zf <= g.y;
-                }
-                // debug launches take every projected point through phase 1b (complete per-pixel statuses) and
-                // apply the interval test's verdict at the end
-                keep = DBG ? ok : (ok && near && pass);
-                kcr = kc | (kr << 16);
-                if (DBG) kcr |= (pass ? 0x8000 : 0) | (near ? (int)0x80000000 : 0);
-            }
-            const uint64_t mask = __ballot(keep);
-            if (keep) {
-                const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                const int slot = (tailA + rank) & (kQ - 1);
-                QA.pix[slot] = pix;
-                QA.kcr[slot] = kcr;
-                QA.X[slot] = X; QA.Y[slot] = Y; QA.Z[slot] = Z;
-            }
-            tailA += __popcll(mask);
-            __builtin_amdgcn_wave_barrier();
-        };
-
         // The 12-tap occlusion gate of cell (x0, y0) inside the image: every tap valid and on the surface the
         // point lands on.  Invalid target depths hold a large negative sentinel, so one bound on the largest
         // |D - zeta| also rejects them.  Tested in FP64 in both paths (the taps are exact in FP64): a mask
@@ -925,19 +815,19 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
 
         // phase 1b: 64 queued points at a time -- the exact projection and cell, the stencil inside the image,
         // the occlusion gate and the depth channel; valid correspondences are appended to phase 2's queue
-        auto stage_b = [&](int slot_a, bool active) {
+        // (Pinhole targets take it in place, for the lanes of a chunk, from phase 1a's registers: their exact
+        // projection costs little, so they keep no queue A and no interval test.)
+        auto stage_b_core = [&](int pix_in, int kcr, double X, double Y, double Z, bool active) {
             bool valid = false, band = false;
             int pix = any_value<int>(), x0 = any_value<int>(), y0 = any_value<int>();
             T al = any_value<T>(), be = any_value<T>(), px = any_value<T>(), py = any_value<T>();
             T pz = any_value<T>(), edv = any_value<T>(), gxd = any_value<T>(), gyd = any_value<T>();
             if (active) {
-                pix = QA.pix[slot_a];
-                const int kcr = QA.kcr[slot_a];
-                const double X = QA.X[slot_a], Y = QA.Y[slot_a], Z = QA.Z[slot_a];
+                pix = pix_in;
                 px = (T)X; py = (T)Y; pz = (T)Z;
                 const int kc = kcr & 0x7fff, kr = (kcr >> 16) & 0x7fff;
                 const bool near = !DBG || TM == MODEL_PINHOLE || kcr < 0;
-                const bool pass = !DBG || (kcr & 0x8000) != 0;
+                const bool pass = !DBG || TM == MODEL_PINHOLE || (kcr & 0x8000) != 0;
                 double u, v, zeta;
                 if (TM == MODEL_PINHOLE) {
                     const double iz = rcp_f64(Z);
@@ -1034,13 +924,139 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             tail += __popcll(mask);
             __builtin_amdgcn_wave_barrier();
         };
+        auto stage_b = [&](int slot_a, bool active) {
+            int pix = any_value<int>(), kcr = any_value<int>();
+            double X = any_value<double>(), Y = any_value<double>(), Z = any_value<double>();
+            if (active) {
+                pix = QA.pix[slot_a];
+                kcr = QA.kcr[slot_a];
+                X = QA.X[slot_a]; Y = QA.Y[slot_a]; Z = QA.Z[slot_a];
+            }
+            stage_b_core(pix, kcr, X, Y, Z, active);
+        };
+
+        // A chunk's source depth and ray-table entries, loaded one chunk ahead so that phase 1a finds them in
+        // registers (lanes past the item's end read harmless in-buffer values and are discarded)
+        struct ChunkLoads {
+            float d;
+            double2 lc, lr;
+        };
+        auto fetch = [&](int cbase) {
+            int row, col;
+            if (Ws >= 64) {
+                // the chunk's first pixel splits on the scalar unit; its 64 pixels span at most two rows
+                int r0 = (int)__umulhi((uint32_t)cbase, magic);
+                int c0 = cbase - r0 * Ws;
+                if (c0 < 0) { r0 -= 1; c0 += Ws; }   // the reciprocal can only round up
+                col = c0 + lane;
+                const bool next = col >= Ws;
+                row = next ? r0 + 1 : r0;
+                col = next ? col - Ws : col;
+            } else {
+                const int pix = cbase + lane;
+                row = (int)__umulhi((uint32_t)pix, magic);
+                col = pix - row * Ws;
+                if (col < 0) { row -= 1; col += Ws; }
+            }
+            ChunkLoads L;
+            L.d = ld_f32(r_sdep, (cbase + lane) * 4, 0);
+            L.lc = ld_f64x2(r_lut, (s_lcol + col) * 16);
+            L.lr = ld_f64x2(r_lut, (s_lrow + row) * 16);
+            return L;
+        };
+        ChunkLoads cur = fetch(px0);
+
+        auto stage_a = [&](int cbase) {
+            const int pix = cbase + lane;
+            bool keep = false;
+            // queued only where kept: elsewhere any value will do (no instructions to clear them)
+            int kcr = any_value<int>();
+            double X = any_value<double>(), Y = any_value<double>(), Z = any_value<double>();
+            const ChunkLoads L = cur;
+            if (cbase + 64 < px1) cur = fetch(cbase + 64);
+            const float Ds = pix < px1 ? L.d : 0.f;
+            if (DBG && pix < px1) a.dbg_status[pix] = 1;
+            if (Ds > 0.f) {
+                ++n_eval;
+                if (DBG) a.dbg_status[pix] = 2;
+                // Geometry in FP64 in both paths (on this chip FP64 vector arithmetic issues at the FP32
+                // rate): unprojection q = d * ray(u) from the FP64 ray table, p_bar = R q + t, and the
+                // predicted depth/range.  Cells, masks and the large-magnitude part of the depth residual then
+                // carry no FP32 rounding.
+                const double2 lcd = L.lc, lrd = L.lr;
+                const double dd = (double)Ds;
+                double q0, q1, q2;
+                if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
+                else { q0 = dd * lcd.x; q1 = dd * lrd.x; q2 = dd; }
+                X = fma(Rd[0], q0, fma(Rd[1], q1, fma(Rd[2], q2, td[0])));
+                Y = fma(Rd[3], q0, fma(Rd[4], q1, fma(Rd[5], q2, td[1])));
+                Z = fma(Rd[6], q0, fma(Rd[7], q1, fma(Rd[8], q2, td[2])));
+                // first projection (Sec. III): pinhole exact; spherical a coarse FP32 estimate (within 0.49 px,
+                // checked per sensor on the host), which names the table rays of phase 1b's exact offsets
+                bool ok, near;
+                float zf, ua, va;   // predicted depth/range in FP32 (within 2e-7 relative) for the interval test
+                if (TM == MODEL_PINHOLE) {
+                    ok = Z >= st_dmin;
+                    near = true;
+                    ua = 0.f; va = 0.f; zf = 0.f;
+                } else {
+                    const double r2 = fma(X, X, Y * Y), n2 = fma(Z, Z, r2);
+                    ok = (r2 > 0.0) && (n2 >= st_dmin * st_dmin);
+                    const float n2f = (float)n2, r2f = (float)r2, irho = __builtin_amdgcn_rsqf(r2f);
+                    zf = n2f * __builtin_amdgcn_rsqf(n2f);
+                    ua = (float)st_fx * atan2_coarse((float)Y, (float)X) + (float)st_cx;
+                    if (el45) {
+                        // every elevation the image can reach is below 45 degrees: atan of tan(el) = Z / rho
+                        // by the coarse quadratic, no division; beyond 45 degrees the point is outside
+                        const float te = (float)Z * irho, tc = fminf(fmaxf(te, -1.f), 1.f);
+                        va = fabsf(te) <= 1.f ? fmaf((float)st_fy, atan_unit(tc), (float)st_cy) : -2.f;
+                    } else {
+                        va = (float)st_fy * atan2_coarse((float)Z, r2f * irho) + (float)st_cy;
+                    }
+                    // far outside the image the estimate decides alone (it is good to a fraction of a pixel);
+                    // inside, the nearest table ray is within 1 px, so the offset angle is small
+                    near = ua > -1.f && ua < (float)Wt && va > -1.f && va < (float)Ht;
+                }
+                const int kc = (int)fminf(fmaxf(rintf(ua), 0.f), (float)(Wt - 1));
+                const int kr = (int)fminf(fmaxf(rintf(va), 0.f), (float)(Ht - 1));
+                // The exact cell is one of {kc - 1, kc} x {kr - 1, kr} (|u' - ua| < 0.5) or outside the cells
+                // whose stencil lies inside the image.  The plane holds the range of predicted depths for which
+                // one of them can pass the occlusion gate, widened beyond the FP32 error of zf; outside it the gate
+                // fails in every one, so a rejected point changes nothing.
+                bool pass = true;
+                if (early) {
+                    const float2 g = ld_f32x2(r_gate, (int)(__umul24((uint32_t)kr, (uint32_t)Wt) + kc) * 8);
+                    pass = zf >= g.x && zf <= g.y;
+                }
+                // debug launches take every projected point through phase 1b (complete per-pixel statuses) and
+                // apply the interval test's verdict at the end
+                keep = DBG ? ok : (ok && near && pass);
+                kcr = kc | (kr << 16);
+                if (DBG) kcr |= (pass ? 0x8000 : 0) | (near ? (int)0x80000000 : 0);
+            }
+            if (TM == MODEL_PINHOLE) {   // phase 1b in place
+                stage_b_core(pix, kcr, X, Y, Z, keep);
+                return;
+            }
+            const uint64_t mask = __ballot(keep);
+            if (keep) {
+                const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                const int slot = (tailA + rank) & (kQ - 1);
+                QA.pix[slot] = pix;
+                QA.kcr[slot] = kcr;
+                QA.X[slot] = X; QA.Y[slot] = Y; QA.Z[slot] = Z;
+            }
+            tailA += __popcll(mask);
+            __builtin_amdgcn_wave_barrier();
+        };
 
         // The wave's chunks go through phase 1a; each later stage takes 64 queued entries at a time (every lane
         // busy), and after the last chunk the partial remainders (inactive lanes join the butterfly with
         // zeros).  Queue occupancy stays below 128: at most 63 wait before a stage appends at most 64.
         for (int cbase = px0; cbase < px1; cbase += 64) {
             stage_a(cbase);
-            if (tailA - headA >= 64) {
+            if (TM == MODEL_SPHERICAL && tailA - headA >= 64) {
                 stage_b((headA + lane) & (kQ - 1), true);
                 headA += 64;
                 __builtin_amdgcn_wave_barrier();
@@ -1051,7 +1067,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 __builtin_amdgcn_wave_barrier();
             }
         }
-        if (tailA > headA) {
+        if (TM == MODEL_SPHERICAL && tailA > headA) {
             stage_b((headA + lane) & (kQ - 1), lane < tailA - headA);
             headA = tailA;
             __builtin_amdgcn_wave_barrier();

@@ -23,6 +23,7 @@ constexpr int kLogRow = 10;
 // and every occlusion bound |D - zeta| <= tau
 constexpr float kNoDepth = -1e30f;
 constexpr int kXcd = 8;          // work queues per launch: one per accelerator complex die (XCD)
+constexpr int kCtrStride = 32;   // queue counters 128 bytes apart: one L2 line each, no shared-line contention
 enum { MODEL_PINHOLE = 0, MODEL_SPHERICAL = 1 };
 
 // BF16 storage of the intensity / normal planes: round to nearest even (finite values), and back.
@@ -101,7 +102,7 @@ struct EvalArgs {
     const int32_t *item_map;     // nullable: item = item_map[position] (per-pair launches)
     int32_t items_px;
     int32_t lut64_bytes;         // size of the FP64 ray tables (bounds of their buffer loads)
-    uint32_t *counter;           // kXcd queue counters of this launch
+    uint32_t *counter;           // kXcd queue counters of this launch, kCtrStride apart
     void *partials;              // double[n_items][kAcc]
     double omega_g, omega_d, omega_n, huber;
     // loss adjoint outputs (adjoint launches only): arenas laid out like the images

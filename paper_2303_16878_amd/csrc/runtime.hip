@@ -526,7 +526,7 @@ pba_status build_plan(pba_ctx *c, const std::vector<int32_t> &src, const std::ve
     if ((s = upload(c, c->blk_ent, ent.data(), ent.size() * 4))) return s;
     if ((s = upload(c, c->bk_ptr, bptr.data(), bptr.size() * 4))) return s;
     if ((s = upload(c, c->bk_ent, bent.data(), bent.size() * 4))) return s;
-    if ((s = ensure(c, c->counters, 64 * 4))) return s;
+    if ((s = ensure(c, c->counters, 64 * 4 * kCtrStride))) return s;
     if (c->cfg.occlusion_zbuffer) {   // one z-buffer per pair, sized for its target at this level
         std::vector<int64_t> zo(std::max(P, 1), 0);
         int64_t tot = 0;
@@ -599,7 +599,7 @@ void zbuffer_pass(pba_ctx *c, const double *poses, hipStream_t st, const WorkBuf
     const int ngrp = (int)c->groups.size();
     for (int g = 0; g < ngrp; ++g) {
         const auto &G = c->groups[g];
-        a.counter = w.counters + g * kXcd;
+        a.counter = w.counters + g * kXcd * kCtrStride;
         launch_eval(a, c->cfg.precision, c->cfg.channels, c->cfg.grad_mode, G.sm, G.tm, false, G.base, G.count,
                     std::max(1, std::min(G.count, c->grid)), st);
     }
@@ -626,7 +626,7 @@ pba_status run_eval(pba_ctx *c, const double *poses, double *H, double *b, doubl
     if (stamped) launch_stamp(P_<LmState>(c->lm), P_<double>(c->logbuf), c->log_cap, 0, st);
     for (int g = 0; g < ngrp; ++g) {
         const auto &G = c->groups[g];
-        a.counter = w.counters + g * kXcd;
+        a.counter = w.counters + g * kXcd * kCtrStride;
         const int grid = std::max(1, std::min(G.count, c->grid));
         launch_eval(a, c->cfg.precision, c->cfg.channels, c->cfg.grad_mode, G.sm, G.tm, false, G.base, G.count, grid,
                     st);
@@ -1079,7 +1079,7 @@ pba_status pba_evaluate_noalloc(pba_ctx *c, pba_eval_out *out)
     // carve the queue counters, per-item partials and per-pair records out of this device's array,
     // each part 256-byte aligned
     auto up = [](size_t n) { return (n + 255) & ~size_t(255); };
-    const size_t n_cnt = up((size_t)std::max<size_t>(1, c->groups.size()) * kXcd * 4);
+    const size_t n_cnt = up((size_t)std::max<size_t>(1, c->groups.size()) * kXcd * kCtrStride * 4);
     const size_t n_part = up((size_t)std::max(1, c->n_items) * kAcc * 8);
     const size_t n_pair = up((size_t)std::max(1, c->P) * kPairOut * 8);
     if (n_cnt + n_part + n_pair > kScratchBytes)
@@ -1334,7 +1334,7 @@ pba_status pba_loss_backward(pba_ctx *c, double grad_F, float *grad_delta, float
     a.adj_scale = grad_F;
     for (int g = 0; g < ngrp; ++g) {
         const auto &G = c->groups[g];
-        a.counter = P_<uint32_t>(c->counters) + g * kXcd;
+        a.counter = P_<uint32_t>(c->counters) + g * kXcd * kCtrStride;
         launch_eval_adjoint(a, c->cfg.channels, G.sm, G.tm, G.base, G.count, std::max(1, std::min(G.count, c->grid)),
                             c->stream);
     }
@@ -1471,11 +1471,11 @@ pba_status pba_autotune(pba_ctx *c, pba_tune_point *points, int32_t max_points, 
     pba_status s;
     if ((s = check_ready(c))) return s;
     HIP_OK(hipSetDevice(c->cfg.device));
-    const int sizes[4] = {2048, 4096, 8192, 16384};
+    const int sizes[6] = {512, 1024, 2048, 4096, 8192, 16384};
     const int mult[3] = {2, 4, 8};
     int best_px = c->items_px, best_grid = c->grid, n = 0;
     double best = 1e300;
-    for (int si = 0; si < 4; ++si) {
+    for (int si = 0; si < 6; ++si) {
         c->items_px = sizes[si];
         if ((s = build_plan(c, c->src_h, c->tgt_h))) return s;
         for (int gi = 0; gi < 3; ++gi) {

@@ -364,7 +364,7 @@ def test_autotune_keeps_results(lidar_mini, pba):
     with pba.context_for_problem(lidar_mini) as ctx:
         a = ctx.evaluate(want_system=True)
         pts = ctx.autotune()
-        assert len(pts) == 12 and all(ms > 0 for _, _, ms in pts)
+        assert len(pts) == 18 and all(ms > 0 for _, _, ms in pts)
         t = ctx.timings()
         assert (t["items_px"], t["grid"]) in [(p, g) for p, g, _ in pts]
         b = ctx.evaluate(want_system=True)
