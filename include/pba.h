@@ -322,7 +322,9 @@ typedef struct {
 pba_status pba_autotune(pba_ctx *ctx, pba_tune_point *points, int32_t max_points, int32_t *n_points);
 
 /* Per-pixel view of one pair for inspection (host outputs, each nullable, source-image sized):
- * status (0 valid, 1 no depth, 2 not projectable, 3 outside, 4 invalid or occluded tap),
+ * status (0 valid, 1 no depth, 2 not projectable, 3 outside, 4 invalid or occluded tap; 5 flags a
+ * point the evaluation's early depth-interval rejection would drop although it passes the
+ * occlusion gate in a cell its projection can reach -- a check that should never fire),
  * uv (2 floats: projected column, row), cell (2 ints: integer cell x0, y0) and residuals
  * (5 floats).  Same kernels as pba_evaluate. */
 pba_status pba_debug_pair(pba_ctx *ctx, int32_t pair, uint8_t *status, float *uv, int32_t *cell,

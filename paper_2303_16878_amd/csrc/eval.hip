@@ -870,7 +870,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                     // differ between exact arithmetic and any rounding of it, and the point passes the gate in
                     // its cell or in a cell across that boundary (otherwise no rounding changes its outcome)
                     const bool bu = fabs(du - 0.5) > 0.5 - kBandPx, bv = fabs(dv - 0.5) > 0.5 - kBandPx;
-                    band = (bu || bv) && pass && (ZB ? !a.zpass : true);
+                    band = (bu || bv) && (DBG || pass) && (ZB ? !a.zpass : true);
                     // (rare: a wave-uniform branch, so the common path carries none of it)
                     if (__builtin_expect(__ballot(band && !gate) != 0, 0)) {
                         if (band && !gate) {
@@ -886,6 +886,10 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                             band = other;
                         }
                     }
+                    // debug launches: status 5 marks a point the interval test dropped although it passes the
+                    // gate in a cell it can reach (never expected; the parity tests check for it)
+                    if (DBG && !pass && (gate || band)) a.dbg_status[pix] = 5;
+                    band = band && pass;
                     bool vis = gate && pass;
                     // z-buffer variant: also no more than tau behind the nearest of the pair's own points in this
                     // cell (both depths as FP32, compared in FP64)

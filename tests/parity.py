@@ -19,6 +19,9 @@ def compare_pair_masks(ctx, prob, poses, k, band=1e-4, gate=1e-5, params=None, g
     s, t = (int(v) for v in prob.pairs[k])
     sen = prob.sensors[prob.kf_sensor[s]]
     g = ctx.debug_pair(k, (sen["H"], sen["W"]))
+    # status 5: the early depth-interval rejection would drop a point that passes the occlusion gate in
+    # a cell it can reach (a band point's too, which the mask comparison below exempts)
+    assert not np.any(g["status"] == 5), ("interval test drops a point", k, np.argwhere(g["status"] == 5)[:5])
     o = oracle.eval_pair(prob, poses, s, t, params or prob.params, pixels=True, grad_mode=grad_mode)
     gv = g["status"] == 0
     ov = o["status"] == 0
