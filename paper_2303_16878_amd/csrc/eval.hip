@@ -592,8 +592,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         const __amdgpu_buffer_rsrc_t r_gate = plane_rsrc(uni_ptr(a.gate + kt.off), tnpx * 8u);
         // the depth-interval test may run: the target's first projection is within half a pixel (and not in
         // the z-buffer fill pass, which needs every point inside the image)
-        const bool early = TM == MODEL_SPHERICAL && uni(st.early) != 0 && !(ZB && a.zpass);
-        const bool el45 = uni(st.el45) != 0;
+        // uniform flags as one scalar word (bit 0: the interval test runs, bit 1: the division-free elevation)
+        const int flags = uni((TM == MODEL_SPHERICAL && st.early != 0 && !(ZB && a.zpass) ? 1 : 0) | (st.el45 != 0 ? 2 : 0));
         const __amdgpu_buffer_rsrc_t r_tatt =
             NCH == 5 ? (BF ? plane_rsrc(uni_ptr(a.att4h + kt.off), tnpx * 8u) : plane_rsrc(uni_ptr(a.att4 + kt.off), tnpx * 16u))
                      : (BF ? plane_rsrc(uni_ptr(a.att1h + kt.off), tnpx * 2u) : plane_rsrc(uni_ptr(a.att1 + kt.off), tnpx * 4u));
@@ -1009,7 +1009,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                     const float n2f = (float)n2, r2f = (float)r2, irho = __builtin_amdgcn_rsqf(r2f);
                     zf = n2f * __builtin_amdgcn_rsqf(n2f);
                     ua = (float)st_fx * atan2_coarse((float)Y, (float)X) + (float)st_cx;
-                    if (el45) {
+                    if (flags & 2) {
                         // every elevation the image can reach is below 45 degrees: atan of tan(el) = Z / rho
                         // by the coarse quadratic, no division; beyond 45 degrees the point is outside
                         const float te = (float)Z * irho, tc = fminf(fmaxf(te, -1.f), 1.f);
@@ -1028,7 +1028,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 // one of them can pass the occlusion gate, widened beyond the FP32 error of zf; outside it the gate
                 // fails in every one, so a rejected point changes nothing.
                 bool pass = true;
-                if (early) {
+                if (flags & 1) {
                     const float2 g = ld_f32x2(r_gate, (int)(__umul24((uint32_t)kr, (uint32_t)Wt) + kc) * 8);
                     pass = zf >= g.x && zf <= g.y;
                 }
