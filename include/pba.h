@@ -144,7 +144,11 @@ void pba_config_default(pba_config *cfg);
 pba_status pba_create(const pba_config *cfg, pba_ctx **out);
 pba_status pba_destroy(pba_ctx *ctx);
 
-/* Register a sensor; *sensor_id receives its index (0, 1, ...).  Before any keyframe is loaded. */
+/* Register a sensor; *sensor_id receives its index (0, 1, ...).  Before any keyframe is loaded.
+ * PBA_EINVAL for an image size outside 4 <= H, W, H W^2 < 2^32, H W <= 2^26, non-finite or zero
+ * intrinsics, a bad depth interval or offset, and for a spherical sensor finer than 1550 px/rad
+ * (|fx| or |fy|; a full turn in about 9700 columns): the evaluation's first projection, which
+ * names the table rays of the exact one, must land within a pixel. */
 pba_status pba_add_sensor(pba_ctx *ctx, const pba_sensor *sensor, int32_t *sensor_id);
 
 /* Load n keyframes: per keyframe its sensor id and pointers to its intensity [H][W], depth [H][W]

@@ -385,7 +385,7 @@ struct Lut<double> {
     __device__ static const double2 *ptr(const EvalArgs &a) { return a.lut64; }
 };
 
-// Per-wave queue of valid correspondences found by phase 1, consumed by phase 2.
+// Per-wave queue of valid correspondences found by phase 1b, consumed by phase 2.
 // Structure of arrays, 128 slots per wave (a chunk appends at most 64; phase 2 drains 64 at a time).
 constexpr int kQ = 128;
 template <typename T>
@@ -590,9 +590,9 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                            : plane_rsrc(uni_ptr(a.att1 + ks.off), (uint32_t)npx * att_e));
         const __amdgpu_buffer_rsrc_t r_lut = plane_rsrc(uni_ptr(a.lut64), (uint32_t)a.lut64_bytes);
         const __amdgpu_buffer_rsrc_t r_gate = plane_rsrc(uni_ptr(a.gate + kt.off), tnpx * 8u);
-        // the depth-interval test may run: the target's first projection is within half a pixel (and not in
-        // the z-buffer fill pass, which needs every point inside the image)
-        // uniform flags as one scalar word (bit 0: the interval test runs, bit 1: the division-free elevation)
+        // uniform flags as one scalar word.  Bit 0: the depth-interval test runs (spherical targets whose first
+        // projection is within half a pixel, and not in the z-buffer fill pass, which needs every point inside
+        // the image).  Bit 1: the division-free coarse elevation.
         const int flags = uni((TM == MODEL_SPHERICAL && st.early != 0 && !(ZB && a.zpass) ? 1 : 0) | (st.el45 != 0 ? 2 : 0));
         const __amdgpu_buffer_rsrc_t r_tatt =
             NCH == 5 ? (BF ? plane_rsrc(uni_ptr(a.att4h + kt.off), tnpx * 8u) : plane_rsrc(uni_ptr(a.att4 + kt.off), tnpx * 16u))

@@ -861,6 +861,9 @@ pba_status pba_add_sensor(pba_ctx *c, const pba_sensor *s, int32_t *sensor_id)
     for (double x : v)
         if (!std::isfinite(x)) return fail(c, PBA_EINVAL, "non-finite intrinsics");
     if (s->fx == 0.0 || s->fy == 0.0) return fail(c, PBA_EINVAL, "zero focal length / resolution");
+    // the evaluation's coarse FP32 projection (within 6.1e-4 rad) must land within a pixel of the exact one
+    if (s->model == PBA_SPHERICAL && std::max(std::fabs(s->fx), std::fabs(s->fy)) * 6.1e-4 >= 0.95)
+        return fail(c, PBA_EINVAL, "spherical resolution %.0f px/rad above 1550", std::max(std::fabs(s->fx), std::fabs(s->fy)));
     if (!(s->min_depth > 0.0 && s->max_depth > s->min_depth)) return fail(c, PBA_EINVAL, "bad depth interval");
     if (!pose_ok(s->offset)) return fail(c, PBA_EINVAL, "sensor offset is not a rigid transform");
     c->sensors.push_back(*s);

@@ -80,6 +80,42 @@ def test_pairs_match_oracle(fixture, prec, ch, gm, request, pba):
         assert np.array_equal(ev["H"], ev["H"].T)
 
 
+def _lidar_variant(H, W, up=8.0, down=-25.0):
+    """Three keyframes of the LiDAR loop seen by an H x W spherical sensor with elevations up..down."""
+    full = synth.make("lidar128", render_images=False, H=H, W=W)
+    full.sensors = [synth.spherical_sensor(H, W, el_up_deg=up, el_down_deg=down)]
+    synth.render(full, kfs=[0, 1, 2])
+    synth._mask_source(full)
+    return full.subset([0, 1, 2])
+
+
+@pytest.mark.parametrize("variant,prec", [("wide", "F32"), ("wide", "F64"), ("fine", "F32")])
+def test_spherical_sensor_variants_match_oracle(variant, prec, pba):
+    """The first projection's other branches: elevations beyond 45 degrees inside the image (the
+    coarse elevation by the general atan2), and 8192 columns, where the coarse estimate can be more
+    than half a pixel off (no depth-interval rejection, only the exact path).  Masks, codes and pair
+    sums against the oracle, as for the other fixtures."""
+    if variant == "wide":
+        prob = _lidar_variant(48, 768, up=50.0, down=-50.0)
+    else:
+        prob = _lidar_variant(16, 8192)
+    precision = pba.PBA_F64 if prec == "F64" else pba.PBA_F32
+    tol = 1e-9 if prec == "F64" else 1e-5
+    with pba.context_for_problem(prob, precision=precision) as ctx:
+        ev = ctx.evaluate(want_pairs=True)
+        for k in range(len(prob.pairs)):
+            m = compare_pair_masks(ctx, prob, prob.init_poses, k)
+            assert m["n_bad"] == 0 and m["n_code"] == 0, (k, m["n_mismatch"], m["bad_idx"])
+            fo = forced_oracle(prob, prob.init_poses, k, m["gpu"])
+            c = compare_pair_sums(ev["pairs"][k], fo, tol)
+            assert c["ok"], (k, c)
+        o = oracle.evaluate(prob, prob.init_poses)
+        assert ev["n_evaluated"] == o["n_eval"]
+        assert abs(ev["n_valid"] - o["n_valid"]) <= 20
+        assert ev["n_valid"] > 1000
+    _log(variant, prec, "valid", ev["n_valid"], "oracle", o["n_valid"])
+
+
 def test_evaluation_is_deterministic(lidar_mini, pba):
     with pba.context_for_problem(lidar_mini) as ctx:
         a = ctx.evaluate(want_system=True, want_pairs=True)
@@ -191,6 +227,11 @@ def test_error_paths(rgbd_small, pba):
     s = prob.sensors[0]
     with pytest.raises(pba.PbaError) as e:
         ctx.add_sensor(7, s["H"], s["W"], s["fx"], s["fy"], s["cx"], s["cy"], 0.1, 10.0)
+    assert e.value.status == pba.PBA_EINVAL
+    # a spherical sensor finer than 1550 px/rad (the first projection must land within a pixel)
+    fine = synth.spherical_sensor(4, 16384)
+    with pytest.raises(pba.PbaError) as e:
+        ctx.add_sensor(fine["model"], 4, 16384, fine["fx"], fine["fy"], fine["cx"], fine["cy"], 0.5, 80.0)
     assert e.value.status == pba.PBA_EINVAL
     ctx.add_sensor(s["model"], s["H"], s["W"], s["fx"], s["fy"], s["cx"], s["cy"], s["min_depth"], s["max_depth"])
     with pytest.raises(pba.PbaError) as e:
