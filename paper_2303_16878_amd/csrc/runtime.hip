@@ -303,13 +303,14 @@ pba_status image_layout(pba_ctx *c, ImageSet &is, const std::vector<int32_t> &se
     return ensure(c, is.att1, off * att_bytes(c));
 }
 
-// The depth-interval plane of every keyframe of a level, from its depth plane (enqueued on the context
-// stream; rebuilt whenever the depth plane is written).
+// The depth-interval plane of every spherical keyframe of a level (only spherical targets read it), from
+// its depth plane (enqueued on the context stream; rebuilt whenever the depth plane is written).
 void build_gate(pba_ctx *c, ImageSet &is)
 {
     for (const KfDev &f : is.kfs_h)
-        launch_gate_plane(P_<float>(is.dep) + f.off, P_<float2>(is.gate) + f.off, f.H, f.W,
-                          is.sensors_dev_h[f.sensor].taud, c->stream);
+        if (is.sensors_dev_h[f.sensor].model == MODEL_SPHERICAL)
+            launch_gate_plane(P_<float>(is.dep) + f.off, P_<float2>(is.gate) + f.off, f.H, f.W,
+                              is.sensors_dev_h[f.sensor].taud, c->stream);
 }
 
 // Tiles (64 x 64) of the Cholesky factor of the 6 NP x 6 NP system that can be nonzero: those
