@@ -210,7 +210,7 @@ pba_status pba_evaluate(pba_ctx *ctx, pba_eval_out *out);
  * pba_evaluate, and PBA_EINVAL (state unchanged) when the context's work queue needs more than
  * the array: 256 B per work item (pba_timings.n_items) + 1280 B per pair + 1 KiB per (source,
  * target) sensor-model group (its queue counters), each part rounded up to 256 B.  Not timed (pba_get_timings counts only pba_evaluate). */
-#define PBA_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define PBA_NOALLOC_SCRATCH_BYTES (128u << 20)
 pba_status pba_evaluate_noalloc(pba_ctx *ctx, pba_eval_out *out);
 
 /* Solve (H + lambda diag H) dx = -b at the current poses (anchor fixed), FP64 Cholesky.

@@ -23,7 +23,7 @@ PBA_PINHOLE, PBA_SPHERICAL = 0, 1
 PBA_F32, PBA_F64 = 0, 1
 PBA_ORDER_AUTO, PBA_ORDER_NATURAL, PBA_ORDER_ND = 0, 1, 2
 PBA_PAIR_OUT_LEN = 160
-PBA_NOALLOC_SCRATCH_BYTES = 64 << 20
+PBA_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 # names declared in include/pba.h
 ABI_FUNCTIONS = (

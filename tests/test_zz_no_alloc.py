@@ -54,7 +54,8 @@ def test_noalloc_fp64_path(rgbd_small, pba):
 
 
 def test_noalloc_refuses_a_queue_beyond_the_array(rgbd_small, pba):
-    """60000 pairs of 160x120 keyframes: 120000 work items and 60000 pair records need ~107 MB."""
+    """60000 pairs of 160x120 keyframes: 300000 work items (4096 source pixels per wave) and 60000 pair
+    records need ~154 MB, more than the 128 MiB array."""
     pairs = np.tile(np.asarray(rgbd_small.pairs, np.int32), (3000, 1))
     with pba.context_for_problem(rgbd_small) as ctx:
         ctx.set_pairs(pairs)
