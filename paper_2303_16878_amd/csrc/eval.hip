@@ -604,7 +604,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
         double acc64[F32 ? 1 : ACC_F];   // FP64 path: the 27 sums per lane
 #pragma unroll
         for (int k = 0; k < (F32 ? 1 : ACC_F); ++k) acc64[k] = 0.0;
-        int n_eval = 0, n_valid = 0;   // per lane
+        int n_valid = 0;               // per lane
+        int n_eval = 0;                // per wave
         int n_band = 0;                // per wave
         int headA = 0, tailA = 0, head = 0, tail = 0;   // wave-uniform queue positions (A, and phase 2's)
 
@@ -945,17 +946,21 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             float d;
             double2 lc, lr;
         };
+        // row and column of the first pixel of the chunk fetched next (rows of 64 or more pixels): split once per
+        // item on the scalar unit, then advanced by 64 pixels per chunk (at most one row boundary)
+        int f_r0 = (int)__umulhi((uint32_t)px0, magic);
+        int f_c0 = px0 - f_r0 * Ws;
+        if (f_c0 < 0) { f_r0 -= 1; f_c0 += Ws; }   // the reciprocal can only round up
         auto fetch = [&](int cbase) {
             int row, col;
             if (Ws >= 64) {
-                // the chunk's first pixel splits on the scalar unit; its 64 pixels span at most two rows
-                int r0 = (int)__umulhi((uint32_t)cbase, magic);
-                int c0 = cbase - r0 * Ws;
-                if (c0 < 0) { r0 -= 1; c0 += Ws; }   // the reciprocal can only round up
-                col = c0 + lane;
+                // the chunk's 64 pixels span at most two rows
+                col = f_c0 + lane;
                 const bool next = col >= Ws;
-                row = next ? r0 + 1 : r0;
+                row = next ? f_r0 + 1 : f_r0;
                 col = next ? col - Ws : col;
+                f_c0 += 64;
+                if (f_c0 >= Ws) { f_c0 -= Ws; f_r0 += 1; }
             } else {
                 const int pix = cbase + lane;
                 row = (int)__umulhi((uint32_t)pix, magic);
@@ -977,12 +982,12 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             int kcr = any_value<int>();
             double X = any_value<double>(), Y = any_value<double>(), Z = any_value<double>();
             const ChunkLoads L = cur;
-            if (cbase + 64 < px1) cur = fetch(cbase + 64);
             const float Ds = pix < px1 ? L.d : 0.f;
-            if (DBG && pix < px1) a.dbg_status[pix] = 1;
-            if (Ds > 0.f) {
-                ++n_eval;
-                if (DBG) a.dbg_status[pix] = 2;
+            if (DBG && pix < px1) a.dbg_status[pix] = Ds > 0.f ? 2 : 1;
+            // computed on every lane (nearly every source pixel has a depth, so a branch would skip no chunk);
+            // lanes without one are dropped at the end
+            {
+                n_eval += __popcll(__ballot(Ds > 0.f));
                 // Geometry in FP64 in both paths (on this chip FP64 vector arithmetic issues at the FP32
                 // rate): unprojection q = d * ray(u) from the FP64 ray table, p_bar = R q + t, and the
                 // predicted depth/range.  Cells, masks and the large-magnitude part of the depth residual then
@@ -992,6 +997,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 double q0, q1, q2;
                 if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
                 else { q0 = dd * lcd.x; q1 = dd * lrd.x; q2 = dd; }
+                // the next chunk's loads (one chunk ahead)
+                if (cbase + 64 < px1) cur = fetch(cbase + 64);
                 X = fma(Rd[0], q0, fma(Rd[1], q1, fma(Rd[2], q2, td[0])));
                 Y = fma(Rd[3], q0, fma(Rd[4], q1, fma(Rd[5], q2, td[1])));
                 Z = fma(Rd[6], q0, fma(Rd[7], q1, fma(Rd[8], q2, td[2])));
@@ -1034,7 +1041,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                 }
                 // debug launches take every projected point through phase 1b (complete per-pixel statuses) and
                 // apply the interval test's verdict at the end
-                keep = DBG ? ok : (ok && near && pass);
+                keep = Ds > 0.f && (DBG ? ok : (ok && near && pass));
                 kcr = kc | (kr << 16);
                 if (DBG) kcr |= (pass ? 0x8000 : 0) | (near ? (int)0x80000000 : 0);
             }
@@ -1093,8 +1100,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
             double v = k < ACC_F ? (ADJ ? acc_b[k - ACC_B] : acc64[F32 ? 0 : k])
                                  : (k == ACC_F ? acc_F
                                                : (k == ACC_VALID ? (double)n_valid
-                                                                 : (k == ACC_EVAL ? (double)n_eval
-                                                                                  : (lane == 0 ? (double)n_band : 0.0))));
+                                                                 : (lane == 0 ? (double)(k == ACC_EVAL ? n_eval : n_band)
+                                                                              : 0.0)));
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
             if (lane == k) outv = v;
