@@ -1019,8 +1019,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(EvalArgs a, int item_base,
                     if (flags & 2) {
                         // every elevation the image can reach is below 45 degrees: atan of tan(el) = Z / rho
                         // by the coarse quadratic, no division; beyond 45 degrees the point is outside
-                        const float te = (float)Z * irho, tc = fminf(fmaxf(te, -1.f), 1.f);
-                        va = fabsf(te) <= 1.f ? fmaf((float)st_fy, atan_unit(tc), (float)st_cy) : -2.f;
+                        const float te = (float)Z * irho;
+                        va = fabsf(te) <= 1.f ? fmaf((float)st_fy, atan_unit(te), (float)st_cy) : -2.f;
                     } else {
                         va = (float)st_fy * atan2_coarse((float)Z, r2f * irho) + (float)st_cy;
                     }
