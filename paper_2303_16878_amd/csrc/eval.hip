@@ -988,17 +988,18 @@ __global__ void __launch_bounds__(kBlock)
             int kcr = any_value<int>();
             double X = any_value<double>(), Y = any_value<double>(), Z = any_value<double>();
             const ChunkLoads L = cur;
-            // the next chunk's loads, one chunk ahead (the z-buffer variants issue them here, the others once the
-            // unprojection has its operands: the register allocation each compiles to best); never inside a
-            // branch on the lanes, since fetch also advances the row and column of the next chunk
-            if (ZB && cbase + 64 < px1) cur = fetch(cbase + 64);
+            // Phase 1a runs on every lane (nearly every source pixel has a depth, so a branch on it skips no
+            // chunk; lanes without one are dropped at the end), except where the branch measured faster: the
+            // z-buffer variants (whose register allocation fits four waves per SIMD only with it) and the FP64
+            // kernels into pinhole targets.  The next chunk's loads, one chunk ahead, go ahead of that branch
+            // (never inside it: fetch also advances the next chunk's row and column), elsewhere after the
+            // unprojection has its operands.
+            constexpr bool kDepthBranch = ZB || (!F32 && TM == MODEL_PINHOLE);
+            if (kDepthBranch && cbase + 64 < px1) cur = fetch(cbase + 64);
             const float Ds = pix < px1 ? L.d : 0.f;
             if (DBG && pix < px1) a.dbg_status[pix] = Ds > 0.f ? 2 : 1;
             n_eval += __popcll(__ballot(Ds > 0.f));
-            // computed on every lane (nearly every source pixel has a depth, so a branch would skip no chunk;
-            // lanes without one are dropped at the end), except in the z-buffer variants, whose register
-            // allocation fits four waves per SIMD only with the branch
-            if (!ZB || Ds > 0.f) {
+            if (!kDepthBranch || Ds > 0.f) {
                 // Geometry in FP64 in both paths (on this chip FP64 vector arithmetic issues at the FP32
                 // rate): unprojection q = d * ray(u) from the FP64 ray table, p_bar = R q + t, and the
                 // predicted depth/range.  Cells, masks and the large-magnitude part of the depth residual then
@@ -1008,7 +1009,7 @@ __global__ void __launch_bounds__(kBlock)
                 double q0, q1, q2;
                 if (SM == MODEL_SPHERICAL) { q0 = dd * (lrd.x * lcd.x); q1 = dd * (lrd.x * lcd.y); q2 = dd * lrd.y; }
                 else { q0 = dd * lcd.x; q1 = dd * lrd.x; q2 = dd; }
-                if (!ZB && cbase + 64 < px1) cur = fetch(cbase + 64);
+                if (!kDepthBranch && cbase + 64 < px1) cur = fetch(cbase + 64);
                 X = fma(Rd[0], q0, fma(Rd[1], q1, fma(Rd[2], q2, td[0])));
                 Y = fma(Rd[3], q0, fma(Rd[4], q1, fma(Rd[5], q2, td[1])));
                 Z = fma(Rd[6], q0, fma(Rd[7], q1, fma(Rd[8], q2, td[2])));
